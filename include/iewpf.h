@@ -1,0 +1,183 @@
+/*
+ * iewpf.h -- C ABI of the MI355X (gfx950) IEWPF ensemble forecast + analysis library.
+ *
+ * Method: the two-stage implicit equal-weights particle filter applied to an ensemble of
+ * rotating shallow-water models with SOAR-correlated, geostrophically balanced model
+ * error (arXiv:1910.01031, Sections "The data-assimilation problem", "Simplified ocean
+ * model for massively parallel architectures", "Efficient implementation of the IEWPF
+ * scheme", Appendix A).
+ *
+ * Conventions shared by every call
+ *   - State layout: float32, structure of arrays [n_particles][3][ny][nx], x fastest; the
+ *     three fields are eta, hu, hv (eq. swe_full).  Cell (j, k) is centred at
+ *     ((j + 1/2) dx, (k + 1/2) dy) (eq. cell_center); all boundaries are periodic.
+ *   - Device pointers are plain HIP device pointers owned by the caller; `stream` is a
+ *     hipStream_t passed as void* (NULL = the default stream).  Calls enqueue work on the
+ *     stream and return without waiting unless stated otherwise.
+ *   - Random numbers: counter-based Philox4x64-10 (Salmon et al., SC'11), key (seed, 0),
+ *     counter (block, step_or_analysis_index, (tag << 32) | ensemble_id, particle), four
+ *     normals per block by Box-Muller in float64 (tags: model error 1, IEWPF xi 2,
+ *     IEWPF nu 3, observation noise 4, initial state 5, resampling 6).  Results are a
+ *     pure function of (config, indices, inputs): no atomics touch results.
+ *   - Return value: 0 on success, a negative IEWPF_E_* code on failure (nothing is
+ *     thrown across the ABI); iewpf_last_error() returns a thread-local message.
+ *   - Host precompute (SOAR weights, pull windows, S, the local A^{1/2}) happens once in
+ *     iewpf_create; no later call allocates device memory.
+ *   - The context owns its constants and workspaces; calls on one context must not
+ *     overlap in time (they share the workspaces).
+ */
+#ifndef IEWPF_H
+#define IEWPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IEWPF_OK 0
+#define IEWPF_E_ARG (-1)        /* invalid argument or NULL pointer                      */
+#define IEWPF_E_SHAPE (-2)      /* grid not divisible by c_omega or < 7 coarse points      */
+#define IEWPF_E_CFL (-3)        /* scheme step exceeds the CFL limit (eq. swecfl)          */
+#define IEWPF_E_NONFINITE (-4)  /* non-finite value found in a particle                    */
+#define IEWPF_E_BETA (-5)       /* beta <= 0: ensemble violates N_psi >> N_y (eq. betaTwoStage) */
+#define IEWPF_E_HIP (-6)        /* a HIP runtime call failed                               */
+#define IEWPF_E_CAPACITY (-7)   /* more observations/drifters than the context was built for */
+
+typedef struct iewpf_ctx iewpf_ctx;
+
+/* Grid, physics, model-error and filter constants of one ensemble.
+ *   nx, ny, dx, dy     grid of nx x ny cells of dx x dy metres (eq. cell_center)
+ *   H, g, f            equilibrium depth, gravity, Coriolis parameter (eq. swe_full)
+ *   dt, n_sub          model step and its number of equal scheme steps (eq. swecfl)
+ *   theta              generalized-minmod limiter parameter of the scheme (1 <= theta <= 2)
+ *   c_omega            coarsening of the random grid Omega^R (Section "Small scale model errors")
+ *   me_std, me_L0      model error: pointwise std of the coarse SOAR field and SOAR length
+ *                      scale L0 (eq. soar_function); q0 = me_std / ||k||_2
+ *   init_std, init_L0  same for the initial-state perturbation of iewpf_init_ensemble
+ *   obs_sigma          observation error std, R = obs_sigma^2 I
+ *   n_particles        ensemble size N_e
+ *   max_obs            capacity for observations / drifters per call
+ *   seed, ensemble_id  Philox key word 0 and counter word 2 (low half)          */
+typedef struct {
+  int32_t nx, ny;
+  double dx, dy, H, g, f, dt;
+  int32_t n_sub;
+  double theta;
+  int32_t c_omega;
+  double me_std, me_L0;
+  double init_std, init_L0;
+  double obs_sigma;
+  int32_t n_particles;
+  int32_t max_obs;
+  uint64_t seed;
+  uint32_t ensemble_id;
+} iewpf_config;
+
+/* One (hu, hv) observation in cell (j, k) (eq. stateObservation). */
+typedef struct {
+  int32_t j, k;
+  double y_hu, y_hv;
+} iewpf_obs;
+
+/* Scalars of one analysis (Appendix A): cbar = w_target = mean c_i, beta, and ranges. */
+typedef struct {
+  double cbar, beta;
+  double alpha_min, alpha_max;
+  double cstar_max;
+  double c_min, c_max;
+  int32_t argmin_beta;
+  int32_t n_obs;
+} iewpf_stats;
+
+/* Create a context: validates the config (nx, ny divisible by c_omega, >= 7 coarse points
+ * per direction, obs/drifter capacity), computes in float64 on the host the SOAR stencils,
+ * the pull windows Q^{1/2} Q^{1/2,T} H^T e_b (eq. detailedOPDUpdate), S = (H Q H^T + R)^-1
+ * by Cholesky (eq. S_extended), the local 49x49 A^{1/2} (eq. svdOfParenthesis), uploads
+ * them and allocates the workspaces (one state-sized scratch buffer + coarse fields).
+ * *out receives the context; destroy with iewpf_destroy.  Uses the current HIP device. */
+int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out);
+void iewpf_destroy(iewpf_ctx* ctx);
+
+/* Initial ensemble (Section "Small scale model errors" applied with the init_* constants):
+ * state[i] = base + Q_init^{1/2} xi_i, xi_i from stream (stream_index, tag 5, particle i).
+ * base: device [3][ny][nx] or NULL (zero).  state: device [n_particles][3][ny][nx]. */
+int iewpf_init_ensemble(iewpf_ctx* ctx, float* state, const float* base, uint64_t stream_index,
+                        void* stream);
+
+/* n_model_steps stochastic model steps (eq. model_equation): each is n_sub SSP-RK2 scheme
+ * steps followed by the model error beta = Q^{1/2} xi with xi from stream (first_step + s,
+ * tag 1); when noise_on_last is 0 the error is not added after the last step (the
+ * forecast into an observation time is deterministic, Section "Observations and
+ * innovations").  In place on state. */
+int iewpf_step_ensemble(iewpf_ctx* ctx, float* state, int n_model_steps, uint64_t first_step,
+                        int noise_on_last, void* stream);
+
+/* Add one model-error draw (stream step_index, tag 1) to every particle, in place. */
+int iewpf_perturb(iewpf_ctx* ctx, float* state, uint64_t step_index, void* stream);
+
+/* Two-stage IEWPF analysis of the forecast ensemble in place (Section "Efficient
+ * implementation of the IEWPF scheme"): innovations, pull, perpendicular xi/nu (streams
+ * (analysis_index, tags 2 and 3)), beta, alpha (Lambert W_0), local P^{1/2} and the
+ * posterior update.  obs_host: n_obs host records (copied; the pointer may be reused
+ * when the call returns).  stats_out: host pointer or NULL; when non-NULL the call waits
+ * for the stream and fills it.  beta <= 0 is reported through stats (beta) and by the
+ * return code IEWPF_E_BETA only when stats_out is non-NULL. */
+int iewpf_assimilate(iewpf_ctx* ctx, float* state, const iewpf_obs* obs_host, int n_obs,
+                     uint64_t analysis_index, iewpf_stats* stats_out, void* stream);
+
+/* Per-particle scalars of the last analysis, copied to host after a stream sync:
+ * out[i*8 + {0..7}] = c_i, gamma_i, zeta_i, alpha_i, c*_i, xi.xi, nu~.nu~, nu~.xi. */
+int iewpf_particle_scalars(iewpf_ctx* ctx, double* out, void* stream);
+
+/* Mooring observations of a truth state (eq. buoyObservation): for each cell (j, k) of
+ * cells_host [2*n_obs], y = (hu, hv) H / (H + eta) + obs_sigma * n, n from stream
+ * (analysis_index, tag 4, ensemble_id, particle 0), normals 2o and 2o+1.  truth: device
+ * [3][ny][nx].  Writes n_obs records to obs_host (waits for the stream). */
+int iewpf_observe_moorings(iewpf_ctx* ctx, const float* truth, const int32_t* cells_host,
+                           int n_obs, uint64_t analysis_index, iewpf_obs* obs_host,
+                           void* stream);
+
+/* Drifter forecast: n_model_steps stochastic model steps (model error after every step,
+ * stream first_step + s) while n_drifters drifters per particle are advected by Heun's
+ * method with bilinear velocity u = (hu, hv)/(H + eta) from psi^n and psi^{n+1}.
+ * pos: device float64 [n_particles][n_drifters][2] unwrapped metres, updated in place;
+ * traj: device float64 [n_model_steps + 1][n_particles][n_drifters][2] or NULL. */
+int iewpf_forecast_drifters(iewpf_ctx* ctx, float* state, double* pos, int n_drifters,
+                            int n_model_steps, uint64_t first_step, double* traj, void* stream);
+
+/* Advect drifters over one model step between two given states (no model stepping):
+ * pos += dt/2 (u(pos; psi_n) + u(pos + dt u(pos; psi_n); psi_np1)). */
+int iewpf_advect_drifters(iewpf_ctx* ctx, const float* psi_n, const float* psi_np1, double* pos,
+                          int n_drifters, void* stream);
+
+/* SIR residual resampling (Section "Standard particle filter"): from natural log-weights
+ * logw (device float64 [n_particles]) draw parents (device int32 [n_particles], ascending)
+ * with uniforms from stream (analysis_index, tag 6) and copy the parent states into state
+ * (in place, via the context's scratch buffer). */
+int iewpf_resample(iewpf_ctx* ctx, float* state, const double* logw, uint64_t analysis_index,
+                   int32_t* parents, void* stream);
+
+/* Largest admissible scheme step of the current ensemble by eq. swecfl with Courant 0.8:
+ * 0.8 * 1/4 * min(dx / max(|u| + c), dy / max(|v| + c)).  Waits for the stream.  Returns
+ * IEWPF_E_CFL (and still writes *dt_out) when dt / n_sub exceeds it. */
+int iewpf_check_cfl(iewpf_ctx* ctx, const float* state, double* dt_out, void* stream);
+
+/* Copies a context constant or workspace to host for inspection (waits for the stream).
+ * which: 0 xi [Ne][NR] f32, 1 nu~ [Ne][NR] f32, 2 r' [Ne][NR] f32, 3 S 2x2 f64,
+ * 4 S_c 2x2 f64, 5 A^{1/2} 49x49 f64, 6 pull windows [2][3][W][W] f32 with W given by
+ * iewpf_window_size, 7 S d of the last analysis [Ne][n_obs][2] f64, 8 model-error SOAR
+ * stencil 5x5 f64.  bytes must equal the buffer size. */
+int iewpf_read_buffer(iewpf_ctx* ctx, int which, void* host_out, size_t bytes, void* stream);
+
+/* Window extents (x, y) of the stored pull windows (2r+1 or the folded grid size). */
+int iewpf_window_size(iewpf_ctx* ctx, int32_t* wx, int32_t* wy);
+
+const char* iewpf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IEWPF_H */

@@ -1,0 +1,9 @@
+"""MI355X-native IEWPF ensemble forecast + analysis (arXiv:1910.01031).
+
+The compute path is libiewpf.so (HIP kernels for gfx950, C ABI in include/iewpf.h);
+this package is its ctypes binding (`abi`) and the in-tree build step (`build`).
+"""
+from . import abi
+from .abi import Context, IewpfError, load
+
+__all__ = ["abi", "Context", "IewpfError", "load"]

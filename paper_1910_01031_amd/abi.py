@@ -1,0 +1,237 @@
+"""ctypes binding of libiewpf.so (include/iewpf.h): argument marshalling only.
+
+Device buffers are passed as torch tensors (their data pointers) and the HIP stream as
+torch's current stream; every step of the forecast and analysis runs in the library's
+HIP kernels.  Loading fails loudly when the library has not been built: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libiewpf.so")
+
+IEWPF_OK = 0
+IEWPF_E_ARG = -1
+IEWPF_E_SHAPE = -2
+IEWPF_E_CFL = -3
+IEWPF_E_NONFINITE = -4
+IEWPF_E_BETA = -5
+IEWPF_E_HIP = -6
+IEWPF_E_CAPACITY = -7
+
+EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_ensemble",
+            "iewpf_perturb", "iewpf_assimilate", "iewpf_particle_scalars",
+            "iewpf_observe_moorings", "iewpf_forecast_drifters", "iewpf_advect_drifters",
+            "iewpf_resample", "iewpf_check_cfl", "iewpf_read_buffer", "iewpf_window_size",
+            "iewpf_last_error")
+
+
+class IewpfConfig(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("H", ctypes.c_double),
+                ("g", ctypes.c_double), ("f", ctypes.c_double), ("dt", ctypes.c_double),
+                ("n_sub", ctypes.c_int32), ("theta", ctypes.c_double),
+                ("c_omega", ctypes.c_int32), ("me_std", ctypes.c_double),
+                ("me_L0", ctypes.c_double), ("init_std", ctypes.c_double),
+                ("init_L0", ctypes.c_double), ("obs_sigma", ctypes.c_double),
+                ("n_particles", ctypes.c_int32), ("max_obs", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("ensemble_id", ctypes.c_uint32)]
+
+
+class IewpfObs(ctypes.Structure):
+    _fields_ = [("j", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("y_hu", ctypes.c_double), ("y_hv", ctypes.c_double)]
+
+
+class IewpfStats(ctypes.Structure):
+    _fields_ = [("cbar", ctypes.c_double), ("beta", ctypes.c_double),
+                ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
+                ("cstar_max", ctypes.c_double), ("c_min", ctypes.c_double),
+                ("c_max", ctypes.c_double), ("argmin_beta", ctypes.c_int32),
+                ("n_obs", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1910_01031_amd/build.py "
+                           "(the HIP library is required; there is no fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i32, u64, f64p = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p
+    lib.iewpf_create.argtypes = [ctypes.POINTER(IewpfConfig), ctypes.POINTER(vp)]
+    lib.iewpf_destroy.argtypes = [vp]
+    lib.iewpf_destroy.restype = None
+    lib.iewpf_init_ensemble.argtypes = [vp, vp, vp, u64, vp]
+    lib.iewpf_step_ensemble.argtypes = [vp, vp, i32, u64, i32, vp]
+    lib.iewpf_perturb.argtypes = [vp, vp, u64, vp]
+    lib.iewpf_assimilate.argtypes = [vp, vp, ctypes.POINTER(IewpfObs), i32, u64,
+                                     ctypes.POINTER(IewpfStats), vp]
+    lib.iewpf_particle_scalars.argtypes = [vp, f64p, vp]
+    lib.iewpf_observe_moorings.argtypes = [vp, vp, vp, i32, u64, ctypes.POINTER(IewpfObs), vp]
+    lib.iewpf_forecast_drifters.argtypes = [vp, vp, vp, i32, i32, u64, vp, vp]
+    lib.iewpf_advect_drifters.argtypes = [vp, vp, vp, vp, i32, vp]
+    lib.iewpf_resample.argtypes = [vp, vp, vp, u64, vp, vp]
+    lib.iewpf_check_cfl.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.iewpf_read_buffer.argtypes = [vp, i32, vp, ctypes.c_size_t, vp]
+    lib.iewpf_window_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]
+    lib.iewpf_last_error.restype = ctypes.c_char_p
+    lib.iewpf_last_error.argtypes = []
+    for name in EXPORTED:
+        if name not in ("iewpf_destroy", "iewpf_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class IewpfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"iewpf error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise IewpfError(rc, load().iewpf_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_config(cfg, max_obs: int = 256) -> IewpfConfig:
+    """iewpf_config from a workloads.Config-like object."""
+    return IewpfConfig(nx=cfg.nx, ny=cfg.ny, dx=cfg.dx, dy=cfg.dy, H=cfg.H, g=cfg.g, f=cfg.f,
+                       dt=cfg.dt, n_sub=cfg.n_sub, theta=cfg.theta, c_omega=cfg.c_omega,
+                       me_std=cfg.me_std, me_L0=cfg.L0, init_std=cfg.init_std,
+                       init_L0=cfg.init_L, obs_sigma=cfg.obs_sigma,
+                       n_particles=cfg.n_particles, max_obs=max_obs, seed=cfg.seed,
+                       ensemble_id=cfg.ensemble_id)
+
+
+def obs_array(cells: np.ndarray, y: np.ndarray):
+    n = len(cells)
+    arr = (IewpfObs * max(n, 1))()
+    for o in range(n):
+        arr[o].j = int(cells[o, 0])
+        arr[o].k = int(cells[o, 1])
+        arr[o].y_hu = float(y[o, 0])
+        arr[o].y_hv = float(y[o, 1])
+    return arr
+
+
+class Context:
+    """Owns one iewpf_ctx; methods mirror the C entry points."""
+
+    def __init__(self, cfg, max_obs: int = 256):
+        lib = load()
+        self.cfg = cfg
+        self.max_obs = max_obs
+        self._c = make_config(cfg, max_obs)
+        h = ctypes.c_void_p()
+        _check(lib.iewpf_create(ctypes.byref(self._c), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().iewpf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_ensemble(self, state, base=None, stream_index: int = 0, stream=None):
+        _check(load().iewpf_init_ensemble(self.h, _ptr(state), _ptr(base), stream_index,
+                                          _stream(stream)))
+
+    def step_ensemble(self, state, n_model_steps: int, first_step: int = 0,
+                      noise_on_last: bool = True, stream=None):
+        _check(load().iewpf_step_ensemble(self.h, _ptr(state), n_model_steps, first_step,
+                                          int(noise_on_last), _stream(stream)))
+
+    def perturb(self, state, step_index: int, stream=None):
+        _check(load().iewpf_perturb(self.h, _ptr(state), step_index, _stream(stream)))
+
+    def assimilate(self, state, cells: np.ndarray, y: np.ndarray, analysis_index: int,
+                   want_stats: bool = True, stream=None, obs=None):
+        if obs is None:
+            obs = obs_array(cells, y)
+        n = len(cells) if cells is not None else len(obs)
+        st = IewpfStats()
+        _check(load().iewpf_assimilate(self.h, _ptr(state), obs, n, analysis_index,
+                                       ctypes.byref(st) if want_stats else None,
+                                       _stream(stream)))
+        return st.as_dict() if want_stats else None
+
+    def particle_scalars(self, stream=None) -> np.ndarray:
+        out = np.zeros((self.cfg.n_particles, 8))
+        _check(load().iewpf_particle_scalars(self.h, out.ctypes.data, _stream(stream)))
+        return out
+
+    def observe_moorings(self, truth, cells: np.ndarray, analysis_index: int, stream=None):
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        n = len(cells)
+        arr = (IewpfObs * max(n, 1))()
+        _check(load().iewpf_observe_moorings(self.h, _ptr(truth), cells.ctypes.data, n,
+                                             analysis_index, arr, _stream(stream)))
+        return np.array([[arr[o].y_hu, arr[o].y_hv] for o in range(n)])
+
+    def forecast_drifters(self, state, pos, n_model_steps: int, first_step: int, traj=None,
+                          stream=None):
+        nd = pos.shape[1]
+        _check(load().iewpf_forecast_drifters(self.h, _ptr(state), _ptr(pos), nd, n_model_steps,
+                                              first_step, _ptr(traj), _stream(stream)))
+
+    def advect_drifters(self, psi_n, psi_np1, pos, stream=None):
+        _check(load().iewpf_advect_drifters(self.h, _ptr(psi_n), _ptr(psi_np1), _ptr(pos),
+                                            pos.shape[1], _stream(stream)))
+
+    def resample(self, state, logw, analysis_index: int, parents, stream=None):
+        _check(load().iewpf_resample(self.h, _ptr(state), _ptr(logw), analysis_index,
+                                     _ptr(parents), _stream(stream)))
+
+    def check_cfl(self, state, stream=None):
+        """Returns (dt_cfl, ok)."""
+        dt = ctypes.c_double()
+        rc = load().iewpf_check_cfl(self.h, _ptr(state), ctypes.byref(dt), _stream(stream))
+        if rc not in (0, IEWPF_E_CFL):
+            _check(rc)
+        return dt.value, rc == 0
+
+    def window_size(self):
+        wx, wy = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().iewpf_window_size(self.h, ctypes.byref(wx), ctypes.byref(wy)))
+        return wx.value, wy.value
+
+    def read_buffer(self, which: int, shape, dtype, stream=None) -> np.ndarray:
+        out = np.zeros(shape, dtype=dtype)
+        _check(load().iewpf_read_buffer(self.h, which, out.ctypes.data, out.nbytes,
+                                        _stream(stream)))
+        return out

@@ -1,0 +1,533 @@
+// IEWPF analysis kernels (Section "Efficient implementation of the IEWPF scheme",
+// Appendix A) plus observation synthesis, the CFL check, drifters and residual resampling.
+//
+//   innovation_kernel     stage 1-2: d = y (H + eta)/H - (hu, hv) (eq. etaCompensatedInnovation),
+//                         S d, c_i = sum_o d^T S d (eq. ciMultiDrifter), float64
+//   rand_dots_kernel      stage 3: xi, nu~ ~ N(0, I) on Omega^R and xi.xi, nu~.nu~, nu~.xi
+//   sync_kernel           stages 4-5, the only ensemble-wide step: cbar, beta
+//                         (eq. betaTwoStage), c*_i (eq. cistarTwoStage), alpha_i by the
+//                         principal Lambert W branch (eq. iewpfAlphaSol)
+//   posterior_coarse      stage 6 on Omega^R: r = beta^{1/2} nu + alpha^{1/2} xi with nu
+//                         from eq. nuPerpendicular, then r' = r + sum_o (A^{1/2} - I) r on
+//                         the 7x7 block of every observation (gathered, order fixed)
+// All reductions use fixed trees, so results do not depend on scheduling.
+#include "internal.hpp"
+#include "philox_dev.hpp"
+
+namespace iewpf {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// Fixed-order block sum of one double per thread (blockDim.x == kThreads).
+__device__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+struct Mat2 {
+  double a[4];
+};
+
+__global__ __launch_bounds__(kThreads) void innovation_kernel(
+    int n_obs, int max_obs, int nx, int ny, double H, Mat2 S, const float* __restrict__ psi,
+    const int32_t* __restrict__ cells, const double* __restrict__ y, double* __restrict__ sd,
+    double* __restrict__ cval) {
+  __shared__ double sh[kThreads];
+  const int i = blockIdx.x;
+  const size_t ncell = (size_t)nx * ny;
+  const float* E = psi + (size_t)i * 3 * ncell;
+  double phi = 0.0;
+  for (int o = threadIdx.x; o < n_obs; o += kThreads) {
+    const int j = cells[2 * o], k = cells[2 * o + 1];
+    const size_t c = (size_t)k * nx + j;
+    const double eta = E[c], hu = E[ncell + c], hv = E[2 * ncell + c];
+    const double scale = (H + eta) / H;
+    const double d0 = y[2 * o] * scale - hu;
+    const double d1 = y[2 * o + 1] * scale - hv;
+    const double s0 = S.a[0] * d0 + S.a[1] * d1;
+    const double s1 = S.a[2] * d0 + S.a[3] * d1;
+    sd[((size_t)i * max_obs + o) * 2] = s0;
+    sd[((size_t)i * max_obs + o) * 2 + 1] = s1;
+    phi += d0 * s0 + d1 * s1;
+  }
+  phi = block_sum(phi, sh);
+  if (threadIdx.x == 0) cval[i] = phi;
+}
+
+__global__ __launch_bounds__(kThreads) void rand_dots_kernel(int nr, uint64_t seed, uint64_t step,
+                                                             uint32_t ens, float* __restrict__ xi,
+                                                             float* __restrict__ nu,
+                                                             double* __restrict__ dots) {
+  __shared__ double sh[kThreads];
+  const int i = blockIdx.x;
+  float* X = xi + (size_t)i * nr;
+  float* N = nu + (size_t)i * nr;
+  double xx = 0.0, nn = 0.0, nxv = 0.0;
+  const int nblk = (nr + 3) / 4;
+  for (int b = threadIdx.x; b < nblk; b += kThreads) {
+    double zx[4], zn[4];
+    normals4(b, step, 2u, ens, i, seed, zx);
+    normals4(b, step, 3u, ens, i, seed, zn);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int p = 4 * b + l;
+      if (p < nr) {
+        const float fx = static_cast<float>(zx[l]), fn = static_cast<float>(zn[l]);
+        X[p] = fx;
+        N[p] = fn;
+        xx += (double)fx * fx;
+        nn += (double)fn * fn;
+        nxv += (double)fn * fx;
+      }
+    }
+  }
+  xx = block_sum(xx, sh);
+  nn = block_sum(nn, sh);
+  nxv = block_sum(nxv, sh);
+  if (threadIdx.x == 0) {
+    dots[3 * i] = xx;
+    dots[3 * i + 1] = nn;
+    dots[3 * i + 2] = nxv;
+  }
+}
+
+// (x - 1) - ln x for x = 1 + e, accurate for small e.
+__device__ double xm1_minus_log(double e) {
+  if (fabs(e) < 1e-2) {
+    double s = 0.0, term = e * e;
+    for (int k = 2; k < 24; ++k) {
+      s += (k & 1) ? -term / k : term / k;
+      term *= e;
+    }
+    return s;
+  }
+  return e - log1p(e);
+}
+
+// alpha solving (alpha - 1) gamma - N ln alpha = c* on the principal branch, i.e.
+// alpha = -(N/gamma) W_0(-(gamma/N) e^{-gamma/N} e^{-c*/N}).  With y = -W_0 = alpha gamma/N:
+// y - ln y = 1 + rho, rho = (gamma/N - 1 - ln(gamma/N)) + c*/N.  Halley iterations on
+// delta = 1 - y near the branch point (rho < 1/2), on y otherwise.
+__device__ double alpha_solve(double gamma, double cstar, double N) {
+  const double x = gamma / N;
+  const double cn = fmax(cstar, 0.0) / N;
+  if (cn == 0.0 && x <= 1.0) return 1.0;
+  const double rho = xm1_minus_log((gamma - N) / N) + cn;
+  double y;
+  if (rho <= 0.0) {
+    y = 1.0;
+  } else if (rho < 0.5) {
+    const double p = sqrt(2.0 * rho);
+    double d = p - p * p / 3.0 + 11.0 / 72.0 * p * p * p;  // branch-point series start
+    for (int it = 0; it < 60; ++it) {
+      const double om = 1.0 - d;
+      const double f = -d - log1p(-d) - rho;
+      const double f1 = d / om;
+      const double f2 = 1.0 / (om * om);
+      const double den = 2.0 * f1 * f1 - f * f2;
+      const double step = den != 0.0 ? 2.0 * f * f1 / den : 0.0;
+      double dn = d - step;
+      if (dn <= 0.0) dn = 0.5 * d;
+      if (dn >= 1.0) dn = 0.5 * (d + 1.0);
+      const bool done = fabs(dn - d) <= 1e-16 * d;
+      d = dn;
+      if (done) break;
+    }
+    y = 1.0 - d;
+  } else {
+    const double R = 1.0 + rho;
+    y = exp(-R);
+    for (int it = 0; it < 100; ++it) {
+      const double g = y - log(y) - R;
+      const double g1 = 1.0 - 1.0 / y;
+      const double g2 = 1.0 / (y * y);
+      const double den = 2.0 * g1 * g1 - g * g2;
+      const double step = den != 0.0 ? 2.0 * g * g1 / den : 0.0;
+      double yn = y - step;
+      if (yn <= 0.0) yn = 0.5 * y;
+      if (yn >= 1.0) yn = 0.5 * (y + 1.0);
+      const bool done = fabs(yn - y) <= 1e-16 * y;
+      y = yn;
+      if (done) break;
+    }
+  }
+  return y / x;
+}
+
+__global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, double n_r,
+                                                        const double* __restrict__ cval,
+                                                        const double* __restrict__ dots,
+                                                        double* __restrict__ alpha,
+                                                        double* __restrict__ cstar,
+                                                        double* __restrict__ scal) {
+  __shared__ double sh[kThreads];
+  __shared__ double shb[kThreads];
+  __shared__ int shi[kThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < ne; i += kThreads) s += cval[i];
+  const double cbar = block_sum(s, sh) / ne;
+  const double scale = n_psi / n_r;
+  // beta = min_i ((cbar - c_i)/zeta_i + 1), argmin with the smallest index on ties
+  double bmin = 1e300;
+  int imin = 0x7fffffff;
+  for (int i = threadIdx.x; i < ne; i += kThreads) {
+    const double zeta = dots[3 * i + 1] * scale;
+    const double b = (cbar - cval[i]) / zeta + 1.0;
+    if (b < bmin || (b == bmin && i < imin)) {
+      bmin = b;
+      imin = i;
+    }
+  }
+  shb[threadIdx.x] = bmin;
+  shi[threadIdx.x] = imin;
+  __syncthreads();
+  for (int st = kThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      const double b2 = shb[threadIdx.x + st];
+      const int i2 = shi[threadIdx.x + st];
+      if (b2 < shb[threadIdx.x] || (b2 == shb[threadIdx.x] && i2 < shi[threadIdx.x])) {
+        shb[threadIdx.x] = b2;
+        shi[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  const double beta = shb[0];
+  const int argmin = shi[0];
+  __syncthreads();
+  double amin = 1e300, amax = -1e300, csmax = 0.0, cmin = 1e300, cmax = -1e300;
+  for (int i = threadIdx.x; i < ne; i += kThreads) {
+    const double gamma = dots[3 * i] * scale;
+    const double zeta = dots[3 * i + 1] * scale;
+    const double cs = fmax(0.0, cbar - cval[i] - (beta - 1.0) * zeta);
+    const double a = beta > 0.0 ? alpha_solve(gamma, cs, n_psi) : 0.0;
+    cstar[i] = cs;
+    alpha[i] = a;
+    amin = fmin(amin, a);
+    amax = fmax(amax, a);
+    csmax = fmax(csmax, cs);
+    cmin = fmin(cmin, cval[i]);
+    cmax = fmax(cmax, cval[i]);
+  }
+  // min / max reductions (order independent)
+  double vals[5] = {amin, -amax, -csmax, cmin, -cmax};
+  double outv[5];
+  for (int q = 0; q < 5; ++q) {
+    sh[threadIdx.x] = vals[q];
+    __syncthreads();
+    for (int st = kThreads / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + st]);
+      __syncthreads();
+    }
+    outv[q] = sh[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    scal[0] = cbar;
+    scal[1] = beta;
+    scal[2] = outv[0];
+    scal[3] = -outv[1];
+    scal[4] = -outv[2];
+    scal[5] = outv[3];
+    scal[6] = -outv[4];
+    scal[7] = static_cast<double>(argmin);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void posterior_coarse_kernel(
+    CoarseConst C, const float* __restrict__ xi, const float* __restrict__ nu,
+    const double* __restrict__ dots, const double* __restrict__ alpha,
+    const double* __restrict__ scal, const float* __restrict__ dmat,
+    const int32_t* __restrict__ pt_off, const int32_t* __restrict__ pt_ent,
+    const int32_t* __restrict__ cells, float* __restrict__ rout) {
+  const int nr = C.nrx * C.nry;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (p >= nr) return;
+  const double xx = dots[3 * i], nn = dots[3 * i + 1], nxv = dots[3 * i + 2];
+  const double a = nxv / xx;
+  const double sperp = sqrt(nn / (nn - a * nxv));
+  const double beta = scal[1];
+  const double sb = sqrt(fmax(beta, 0.0)) * sperp, sa = sqrt(alpha[i]);
+  const float* X = xi + (size_t)i * nr;
+  const float* N = nu + (size_t)i * nr;
+  auto r_at = [&](int q) -> double {
+    const double xv = X[q], nv = N[q];
+    return sb * (nv - a * xv) + sa * xv;
+  };
+  double acc = r_at(p);
+  const int b = p / C.nrx, av = p - b * C.nrx;
+  (void)b;
+  (void)av;
+  for (int t = pt_off[p]; t < pt_off[p + 1]; ++t) {
+    const int e = pt_ent[t];
+    const int o = e >> 8, row = e & 255;
+    const int ao = cells[2 * o] / C.c, bo = cells[2 * o + 1] / C.c;
+    const float* drow = dmat + row * kBlockN;
+    double s = 0.0;
+    for (int q = 0; q < kBlockN; ++q) {
+      const int dk = q / 7 - 3, dj = q % 7 - 3;
+      const int pq = wrapi(bo + dk, C.nry) * C.nrx + wrapi(ao + dj, C.nrx);
+      s += (double)drow[q] * r_at(pq);
+    }
+    acc += s;
+  }
+  rout[(size_t)i * nr + p] = static_cast<float>(acc);
+}
+
+__global__ void observe_kernel(int n_obs, int nx, int ny, double H, double sigma, uint64_t seed,
+                               uint64_t step, uint32_t ens, const float* __restrict__ truth,
+                               const int32_t* __restrict__ cells, double* __restrict__ y) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_obs) return;
+  const size_t ncell = (size_t)nx * ny;
+  const int j = cells[2 * o], k = cells[2 * o + 1];
+  const size_t c = (size_t)k * nx + j;
+  const double eta = truth[c], hu = truth[ncell + c], hv = truth[2 * ncell + c];
+  const double s = H / (H + eta);
+  double z[4];
+  normals4((2 * o) / 4, step, 4u, ens, 0, seed, z);
+  const int l = (2 * o) % 4;
+  y[2 * o] = hu * s + sigma * z[l];
+  y[2 * o + 1] = hv * s + sigma * z[l + 1];
+}
+
+__global__ __launch_bounds__(256) void cfl_kernel(size_t n_cells_total, size_t ncell, float H, float g,
+                                                  const float* __restrict__ psi,
+                                                  unsigned* __restrict__ out) {
+  float sx = 0.0f, sy = 0.0f;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n_cells_total;
+       t += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = t / ncell, c = t - i * ncell;
+    const float* E = psi + i * 3 * ncell;
+    const float h = H + E[c];
+    const float cw = sqrtf(g * h);
+    sx = fmaxf(sx, fabsf(E[ncell + c] / h) + cw);
+    sy = fmaxf(sy, fabsf(E[2 * ncell + c] / h) + cw);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sx = fmaxf(sx, __shfl_down(sx, off, 64));
+    sy = fmaxf(sy, __shfl_down(sy, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, __float_as_uint(sx));
+    atomicMax(out + 1, __float_as_uint(sy));
+  }
+}
+
+// Bilinear velocity of one particle's state at position (px, py) (metres, unwrapped).
+__device__ void velocity_at(const float* __restrict__ E, int nx, int ny, double dx, double dy,
+                            double H, double px, double py, double& u, double& v) {
+  const size_t ncell = (size_t)nx * ny;
+  const double fx = px / dx - 0.5, fy = py / dy - 0.5;
+  const double fj = floor(fx), fk = floor(fy);
+  const double tx = fx - fj, ty = fy - fk;
+  long long j0 = (long long)fj, k0 = (long long)fk;
+  j0 %= nx;
+  if (j0 < 0) j0 += nx;
+  k0 %= ny;
+  if (k0 < 0) k0 += ny;
+  const int j1 = (int)((j0 + 1) % nx), k1 = (int)((k0 + 1) % ny);
+  const int js[2] = {(int)j0, j1}, ks[2] = {(int)k0, k1};
+  const double wxs[2] = {1.0 - tx, tx}, wys[2] = {1.0 - ty, ty};
+  u = 0.0;
+  v = 0.0;
+  for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 2; ++a) {
+      const size_t c = (size_t)ks[b] * nx + js[a];
+      const double h = H + (double)E[c];
+      const double w = wxs[a] * wys[b];
+      u += w * ((double)E[ncell + c] / h);
+      v += w * ((double)E[2 * ncell + c] / h);
+    }
+}
+
+__global__ void drift_k1_kernel(int ne, int nd, int nx, int ny, double dx, double dy, double H,
+                                double dt, const float* __restrict__ psi,
+                                const double* __restrict__ pos, double* __restrict__ k1,
+                                double* __restrict__ pstar) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ne * nd) return;
+  const int i = t / nd;
+  const float* E = psi + (size_t)i * 3 * nx * ny;
+  double u, v;
+  velocity_at(E, nx, ny, dx, dy, H, pos[2 * t], pos[2 * t + 1], u, v);
+  k1[2 * t] = u;
+  k1[2 * t + 1] = v;
+  pstar[2 * t] = pos[2 * t] + dt * u;
+  pstar[2 * t + 1] = pos[2 * t + 1] + dt * v;
+}
+
+__global__ void drift_k2_kernel(int ne, int nd, int nx, int ny, double dx, double dy, double H,
+                                double dt, const float* __restrict__ psi, double* __restrict__ pos,
+                                const double* __restrict__ k1, const double* __restrict__ pstar,
+                                double* __restrict__ traj) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ne * nd) return;
+  const int i = t / nd;
+  const float* E = psi + (size_t)i * 3 * nx * ny;
+  double u, v;
+  velocity_at(E, nx, ny, dx, dy, H, pstar[2 * t], pstar[2 * t + 1], u, v);
+  const double px = pos[2 * t] + 0.5 * dt * (k1[2 * t] + u);
+  const double py = pos[2 * t + 1] + 0.5 * dt * (k1[2 * t + 1] + v);
+  pos[2 * t] = px;
+  pos[2 * t + 1] = py;
+  if (traj) {
+    traj[2 * t] = px;
+    traj[2 * t + 1] = py;
+  }
+}
+
+// Residual resampling (Section "Standard particle filter"), one work-item: the decisions
+// are integer and sequential over at most a few thousand particles.
+__global__ void resample_kernel(int ne, uint64_t seed, uint64_t step, uint32_t ens,
+                                const double* __restrict__ logw, int32_t* __restrict__ parents,
+                                int32_t* __restrict__ counts) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double m = logw[0];
+  for (int i = 1; i < ne; ++i) m = fmax(m, logw[i]);
+  double s = 0.0;
+  for (int i = 0; i < ne; ++i) s += exp(logw[i] - m);
+  if (!(s > 0.0) || !isfinite(s)) {  // no usable weights: keep the ensemble as it is
+    for (int i = 0; i < ne; ++i) parents[i] = i;
+    return;
+  }
+  int used = 0;
+  double total = 0.0;
+  for (int i = 0; i < ne; ++i) {
+    const double x = (double)ne * exp(logw[i] - m) / s;
+    const double n = (x >= 0.0 && x <= (double)ne) ? floor(x) : 0.0;
+    counts[i] = (int)n;
+    used += (int)n;
+    total += (x >= 0.0 && x <= (double)ne) ? x - n : 0.0;
+  }
+  const int n_res = used <= ne ? ne - used : 0;
+  for (int kdraw = 0; kdraw < n_res; ++kdraw) {
+    const U64x4 w = philox4x64_10((uint64_t)(kdraw / 4), step, stream_word(6u, ens), 0, seed, 0);
+    const uint64_t words[4] = {w.x0, w.x1, w.x2, w.x3};
+    const double u = (double)(words[kdraw % 4] >> 11) * 0x1.0p-53;
+    const double target = u * total;
+    int pick = ne - 1;
+    double acc = 0.0;
+    for (int i = 0; i < ne; ++i) {
+      const double x = (double)ne * exp(logw[i] - m) / s;
+      acc += x - floor(x);
+      if (target < acc) {
+        pick = i;
+        break;
+      }
+    }
+    counts[pick] += 1;
+  }
+  int t = 0;
+  for (int i = 0; i < ne; ++i)
+    for (int c = 0; c < counts[i] && t < ne; ++c) parents[t++] = i;
+  for (; t < ne; ++t) parents[t] = ne - 1;  // unreachable when the counts sum to ne
+}
+
+__global__ void gather_kernel(size_t per_particle4, const int32_t* __restrict__ parents,
+                              const float4* __restrict__ in, float4* __restrict__ out) {
+  const int i = blockIdx.y;
+  const float4* src = in + (size_t)parents[i] * per_particle4;
+  float4* dst = out + (size_t)i * per_particle4;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < per_particle4;
+       t += (size_t)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+
+}  // namespace
+
+void launch_innovation(int ne, int n_obs, int max_obs, int nx, int ny, double H, const double S[4],
+                       const float* psi, const int32_t* cells, const double* y, double* sd,
+                       double* cval, hipStream_t s) {
+  Mat2 M{{S[0], S[1], S[2], S[3]}};
+  hipLaunchKernelGGL(innovation_kernel, dim3(ne), dim3(kThreads), 0, s, n_obs, max_obs, nx, ny, H,
+                     M, psi, cells, y, sd, cval);
+}
+
+void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens, float* xi,
+                      float* nu, double* dots, hipStream_t s) {
+  hipLaunchKernelGGL(rand_dots_kernel, dim3(ne), dim3(kThreads), 0, s, nr, seed, step, ens, xi, nu,
+                     dots);
+}
+
+void launch_sync(int ne, double n_psi, double n_r, const double* cval, const double* dots,
+                 double* alpha, double* cstar, double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(sync_kernel, dim3(1), dim3(kThreads), 0, s, ne, n_psi, n_r, cval, dots, alpha,
+                     cstar, scal);
+}
+
+void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,
+                             const double* dots, const double* alpha, const double* scal,
+                             const float* dmat, const int32_t* pt_off, const int32_t* pt_ent,
+                             const int32_t* cells, float* rout, hipStream_t s) {
+  const int nr = C.nrx * C.nry;
+  hipLaunchKernelGGL(posterior_coarse_kernel, dim3((nr + kThreads - 1) / kThreads, ne),
+                     dim3(kThreads), 0, s, C, xi, nu, dots, alpha, scal, dmat, pt_off, pt_ent,
+                     cells, rout);
+}
+
+void launch_observe(int n_obs, int nx, int ny, double H, double sigma, uint64_t seed,
+                    uint64_t step, uint32_t ens, const float* truth, const int32_t* cells,
+                    double* y, hipStream_t s) {
+  hipLaunchKernelGGL(observe_kernel, dim3((n_obs + 127) / 128), dim3(128), 0, s, n_obs, nx, ny, H,
+                     sigma, seed, step, ens, truth, cells, y);
+}
+
+void launch_cfl(int ne, int nx, int ny, float H, float g, const float* psi, unsigned* out,
+                hipStream_t s) {
+  const size_t total = (size_t)ne * nx * ny;
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(cfl_kernel, dim3((unsigned)blocks), dim3(256), 0, s, total, (size_t)nx * ny,
+                     H, g, psi, out);
+}
+
+void launch_drift_k1(int ne, int nd, int nx, int ny, double dx, double dy, double H, double dt,
+                     const float* psi, const double* pos, double* k1, double* pstar,
+                     hipStream_t s) {
+  const int n = ne * nd;
+  hipLaunchKernelGGL(drift_k1_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ne, nd, nx, ny, dx, dy,
+                     H, dt, psi, pos, k1, pstar);
+}
+
+void launch_drift_k2(int ne, int nd, int nx, int ny, double dx, double dy, double H, double dt,
+                     const float* psi, double* pos, const double* k1, const double* pstar,
+                     double* traj, hipStream_t s) {
+  const int n = ne * nd;
+  hipLaunchKernelGGL(drift_k2_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ne, nd, nx, ny, dx, dy,
+                     H, dt, psi, pos, k1, pstar, traj);
+}
+
+void launch_resample(int ne, uint64_t seed, uint64_t step, uint32_t ens, const double* logw,
+                     int32_t* parents, int32_t* counts, hipStream_t s);
+
+void launch_gather_particles(int ne, size_t per_particle, const int32_t* parents, const float* in,
+                             float* out, hipStream_t s) {
+  const size_t n4 = per_particle / 4;
+  size_t bx = (n4 + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)bx, ne), dim3(256), 0, s, n4, parents,
+                     reinterpret_cast<const float4*>(in), reinterpret_cast<float4*>(out));
+}
+
+void launch_resample(int ne, uint64_t seed, uint64_t step, uint32_t ens, const double* logw,
+                     int32_t* parents, int32_t* counts, hipStream_t s) {
+  hipLaunchKernelGGL(resample_kernel, dim3(1), dim3(64), 0, s, ne, seed, step, ens, logw, parents,
+                     counts);
+}
+
+}  // namespace iewpf

@@ -1,0 +1,624 @@
+// extern "C" entry points of libiewpf.so (declared in include/iewpf.h).
+//
+// The host side validates arguments, keeps the float64 precompute, builds the per-call
+// observation index lists (which observation windows touch which fine strip, which 7x7
+// blocks touch which coarse point) and enqueues kernels; every arithmetic step of the
+// forecast and the analysis runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace iewpf {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+namespace {
+
+constexpr uint32_t kTagModelError = 1;
+constexpr uint32_t kTagInit = 5;
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+template <class T>
+int dev_alloc(T** p, size_t n) {
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+  if (e != hipSuccess) return fail(IEWPF_E_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return 0;
+}
+
+int env_int(const char* name, int def) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return def;
+  return std::atoi(v);
+}
+
+void free_ctx(iewpf_ctx* c) {
+  if (!c) return;
+  void* bufs[] = {c->scratch, c->xi,     c->nu,     c->coarse, c->coarse2, c->windows,
+                  c->dmat,    c->sd,     c->cval,   c->dots,   c->alpha,   c->cstar,
+                  c->scal,    c->obs_cells, c->obs_y, c->pt_off, c->pt_ent, c->st_off,
+                  c->st_ent,  c->dk1,    c->dpstar, c->dobs,   c->cflmax,  c->dparents};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  if (c->h_small) (void)hipHostFree(c->h_small);
+  if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
+  delete c;
+}
+
+// Circular distance from point p to the half-open interval [a, a + len) on Z_n.
+int circ_interval_dist(int p, int a, int len, int n) {
+  int d = (p - a) % n;
+  if (d < 0) d += n;
+  if (d < len) return 0;
+  return std::min(d - (len - 1), n - d);
+}
+
+size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+struct StageLayout {
+  size_t cells, y, pt_off, pt_ent, st_off, st_ent, total;
+};
+
+StageLayout stage_layout(const iewpf_ctx& c) {
+  StageLayout L;
+  size_t o = 0;
+  L.cells = o; o = align16(o + sizeof(int32_t) * 2 * c.max_obs);
+  L.y = o; o = align16(o + sizeof(double) * 2 * c.max_obs);
+  L.pt_off = o; o = align16(o + sizeof(int32_t) * (c.nr + 1));
+  L.pt_ent = o; o = align16(o + sizeof(int32_t) * (size_t)c.max_obs * kBlockN);
+  L.st_off = o; o = align16(o + sizeof(int32_t) * (c.n_upd_strips + 1));
+  L.st_ent = o; o = align16(o + sizeof(int32_t) * (size_t)c.n_upd_strips * c.max_obs);
+  L.total = o;
+  return L;
+}
+
+int wait_stage(iewpf_ctx* c) {
+  if (c->stage_pending) {
+    IEWPF_HIP_TRY(hipEventSynchronize(c->stage_ev));
+    c->stage_pending = false;
+  }
+  return 0;
+}
+
+int check_cells(const iewpf_ctx* c, const int32_t* cells, int n) {
+  for (int o = 0; o < n; ++o) {
+    if (cells[2 * o] < 0 || cells[2 * o] >= c->nx || cells[2 * o + 1] < 0 ||
+        cells[2 * o + 1] >= c->ny)
+      return fail(IEWPF_E_ARG, "observation cell out of the grid");
+  }
+  return 0;
+}
+
+int model_steps(iewpf_ctx* c, float* state, int n_steps, uint64_t first_step, int noise_on_last,
+                hipStream_t s) {
+  float* cur = state;
+  float* other = c->scratch;
+  for (int st = 0; st < n_steps; ++st) {
+    for (int sub = 0; sub < c->cfg.n_sub; ++sub) {
+      launch_swe_substep(c->swe, c->ne, cur, other, s);
+      std::swap(cur, other);
+    }
+    const bool noise = (st < n_steps - 1) || noise_on_last;
+    if (noise) {
+      launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, first_step + st, kTagModelError,
+                     c->cfg.ensemble_id, s);
+      launch_soar(c->cc, c->soar_me_f, c->ne, c->xi, c->coarse, s);
+      launch_gb_add(c->cc, c->ne, c->coarse, nullptr, cur, c->upd_strip_h, s);
+    }
+  }
+  if (cur != state)
+    IEWPF_HIP_TRY(hipMemcpyAsync(state, cur, sizeof(float) * 3 * c->ncell * c->ne,
+                                 hipMemcpyDeviceToDevice, s));
+  IEWPF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+}  // namespace
+}  // namespace iewpf
+
+using namespace iewpf;
+
+extern "C" {
+
+const char* iewpf_last_error(void) { return g_last_error.c_str(); }
+
+int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
+  if (!cfg || !out) return fail(IEWPF_E_ARG, "NULL argument");
+  *out = nullptr;
+  const iewpf_config& f = *cfg;
+  if (f.nx <= 0 || f.ny <= 0 || f.c_omega <= 0 || f.n_particles <= 0 || f.n_sub <= 0 ||
+      !(f.dt > 0) || !(f.dx > 0) || !(f.dy > 0) || !(f.H > 0) || !(f.g > 0) || f.f == 0.0 ||
+      !(f.obs_sigma > 0) || f.max_obs <= 0 || f.max_obs >= (1 << 22) || !(f.theta >= 1.0) ||
+      !(f.theta <= 2.0) || f.me_std < 0 || f.init_std < 0)
+    return fail(IEWPF_E_ARG, "invalid configuration value");
+  if (f.nx % f.c_omega || f.ny % f.c_omega)
+    return fail(IEWPF_E_SHAPE, "nx and ny must be divisible by c_omega");
+  if (f.nx / f.c_omega < 7 || f.ny / f.c_omega < 7)
+    return fail(IEWPF_E_SHAPE, "the coarse grid needs at least 7 points per direction");
+  iewpf_ctx* c = new iewpf_ctx();
+  c->cfg = f;
+  c->nx = f.nx;
+  c->ny = f.ny;
+  c->c = f.c_omega;
+  c->nrx = f.nx / f.c_omega;
+  c->nry = f.ny / f.c_omega;
+  c->nr = c->nrx * c->nry;
+  c->ne = f.n_particles;
+  c->max_obs = f.max_obs;
+  c->ncell = (size_t)f.nx * f.ny;
+  c->n_psi = 3.0 * (double)c->ncell;
+  const double dxc = c->c * f.dx, dyc = c->c * f.dy;
+  if (!(c->cfg.me_L0 > 0)) c->cfg.me_L0 = 0.75 * dxc;
+  if (!(c->cfg.init_L0 > 0)) c->cfg.init_L0 = 0.75 * dxc;
+  c->q0_me = soar_q0(f.me_std, c->cfg.me_L0, dxc, dyc);
+  c->q0_init = soar_q0(f.init_std, c->cfg.init_L0, dxc, dyc);
+  soar_stencil(c->q0_me, c->cfg.me_L0, dxc, dyc, c->soar_me);
+  soar_stencil(c->q0_init, c->cfg.init_L0, dxc, dyc, c->soar_init);
+  for (int i = 0; i < 25; ++i) {
+    c->soar_me_f[i] = (float)c->soar_me[i];
+    c->soar_init_f[i] = (float)c->soar_init[i];
+  }
+  // scheme constants
+  SweConst& S = c->swe;
+  S.nx = f.nx;
+  S.ny = f.ny;
+  S.strip_h = std::max(4, env_int("IEWPF_SWE_STRIP", 32));
+  S.n_strip_x = (f.nx + kSweOut - 1) / kSweOut;
+  S.n_strip_y = (f.ny + S.strip_h - 1) / S.strip_h;
+  S.H = (float)f.H;
+  S.g = (float)f.g;
+  S.inv2g = (float)(1.0 / (2.0 * f.g));
+  S.f = (float)f.f;
+  S.hfdx = (float)(0.5 * f.f * f.dx);
+  S.hfdy = (float)(0.5 * f.f * f.dy);
+  S.fdx = (float)(f.f * f.dx);
+  S.fdy = (float)(f.f * f.dy);
+  S.theta = (float)f.theta;
+  S.dt = (float)(f.dt / f.n_sub);
+  S.idx = (float)(1.0 / f.dx);
+  S.idy = (float)(1.0 / f.dy);
+  c->cc.nx = f.nx;
+  c->cc.ny = f.ny;
+  c->cc.c = c->c;
+  c->cc.nrx = c->nrx;
+  c->cc.nry = c->nry;
+  c->cc.gb_x = (float)(f.g * f.H / (2.0 * f.f * f.dx));
+  c->cc.gb_y = (float)(f.g * f.H / (2.0 * f.f * f.dy));
+  // pull windows and S
+  const int r = 7 * c->c, W = 2 * r + 1;
+  c->rx = W > f.nx ? -1 : r;
+  c->ry = W > f.ny ? -1 : r;
+  c->wx = W > f.nx ? f.nx : W;
+  c->wy = W > f.ny ? f.ny : W;
+  std::vector<double> win((size_t)6 * c->wx * c->wy);
+  build_pull_windows(*c, win.data(), c->Mfine);
+  const double s2 = f.obs_sigma * f.obs_sigma;
+  double MR[4] = {c->Mfine[0] + s2, c->Mfine[1], c->Mfine[2], c->Mfine[3] + s2};
+  if (inverse_spd2(MR, c->S) != 0) {
+    free_ctx(c);
+    return fail(IEWPF_E_ARG, "H Q H^T + R is not positive definite");
+  }
+  if (build_local_block(*c, c->ahalf, c->Sc) != 0) {
+    free_ctx(c);
+    return fail(IEWPF_E_ARG, "coarse H Q H^T + R is not positive definite");
+  }
+  c->upd_strip_h = std::max(2, env_int("IEWPF_UPD_STRIP", 16));
+  c->n_upd_strips = ((f.nx + kGbOut - 1) / kGbOut) * ((f.ny + c->upd_strip_h - 1) / c->upd_strip_h);
+
+  int rc = 0;
+  const size_t nstate = 3 * c->ncell * (size_t)c->ne;
+  rc |= dev_alloc(&c->scratch, nstate);
+  rc |= dev_alloc(&c->xi, (size_t)c->ne * c->nr);
+  rc |= dev_alloc(&c->nu, (size_t)c->ne * c->nr);
+  rc |= dev_alloc(&c->coarse, (size_t)c->ne * c->nr);
+  rc |= dev_alloc(&c->coarse2, (size_t)c->ne * c->nr);
+  rc |= dev_alloc(&c->windows, win.size());
+  rc |= dev_alloc(&c->dmat, (size_t)kBlockN * kBlockN);
+  rc |= dev_alloc(&c->sd, (size_t)c->ne * c->max_obs * 2);
+  rc |= dev_alloc(&c->cval, c->ne);
+  rc |= dev_alloc(&c->dots, (size_t)3 * c->ne);
+  rc |= dev_alloc(&c->alpha, c->ne);
+  rc |= dev_alloc(&c->cstar, c->ne);
+  rc |= dev_alloc(&c->scal, 16);
+  rc |= dev_alloc(&c->obs_cells, (size_t)2 * c->max_obs);
+  rc |= dev_alloc(&c->obs_y, (size_t)2 * c->max_obs);
+  rc |= dev_alloc(&c->pt_off, (size_t)c->nr + 1);
+  rc |= dev_alloc(&c->pt_ent, (size_t)c->max_obs * kBlockN);
+  rc |= dev_alloc(&c->st_off, (size_t)c->n_upd_strips + 1);
+  rc |= dev_alloc(&c->st_ent, (size_t)c->n_upd_strips * c->max_obs);
+  rc |= dev_alloc(&c->dk1, (size_t)c->ne * c->max_obs * 2);
+  rc |= dev_alloc(&c->dpstar, (size_t)c->ne * c->max_obs * 2);
+  rc |= dev_alloc(&c->dobs, (size_t)c->max_obs * 2);
+  rc |= dev_alloc(&c->cflmax, 2);
+  rc |= dev_alloc(&c->dparents, (size_t)c->ne);
+  if (rc) {
+    free_ctx(c);
+    return IEWPF_E_HIP;
+  }
+  c->stage_bytes = stage_layout(*c).total;
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_stage), c->stage_bytes) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_small),
+                    sizeof(double) * std::max<size_t>(64, std::max<size_t>(2 * c->max_obs, 8 * (size_t)c->ne))) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming) != hipSuccess) {
+    free_ctx(c);
+    return fail(IEWPF_E_HIP, "pinned host allocation failed");
+  }
+  std::vector<float> winf(win.begin(), win.end());
+  std::vector<float> dm((size_t)kBlockN * kBlockN);
+  for (int i = 0; i < kBlockN; ++i)
+    for (int j = 0; j < kBlockN; ++j)
+      dm[i * kBlockN + j] = (float)(c->ahalf[i * kBlockN + j] - (i == j ? 1.0 : 0.0));
+  if (hipMemcpy(c->windows, winf.data(), sizeof(float) * winf.size(), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(c->dmat, dm.data(), sizeof(float) * dm.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    free_ctx(c);
+    return fail(IEWPF_E_HIP, "constant upload failed");
+  }
+  *out = c;
+  return 0;
+}
+
+void iewpf_destroy(iewpf_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  free_ctx(ctx);
+}
+
+int iewpf_window_size(iewpf_ctx* ctx, int32_t* wx, int32_t* wy) {
+  if (!ctx || !wx || !wy) return fail(IEWPF_E_ARG, "NULL argument");
+  *wx = ctx->wx;
+  *wy = ctx->wy;
+  return 0;
+}
+
+int iewpf_init_ensemble(iewpf_ctx* c, float* state, const float* base, uint64_t stream_index,
+                        void* stream) {
+  if (!c || !state) return fail(IEWPF_E_ARG, "NULL argument");
+  hipStream_t s = as_stream(stream);
+  if (!base) IEWPF_HIP_TRY(hipMemsetAsync(state, 0, sizeof(float) * 3 * c->ncell * c->ne, s));
+  launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, stream_index, kTagInit, c->cfg.ensemble_id, s);
+  launch_soar(c->cc, c->soar_init_f, c->ne, c->xi, c->coarse, s);
+  launch_gb_add(c->cc, c->ne, c->coarse, base, state, c->upd_strip_h, s);
+  IEWPF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int iewpf_step_ensemble(iewpf_ctx* c, float* state, int n_model_steps, uint64_t first_step,
+                        int noise_on_last, void* stream) {
+  if (!c || !state || n_model_steps < 0) return fail(IEWPF_E_ARG, "invalid argument");
+  return model_steps(c, state, n_model_steps, first_step, noise_on_last, as_stream(stream));
+}
+
+int iewpf_perturb(iewpf_ctx* c, float* state, uint64_t step_index, void* stream) {
+  if (!c || !state) return fail(IEWPF_E_ARG, "NULL argument");
+  hipStream_t s = as_stream(stream);
+  launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, step_index, kTagModelError, c->cfg.ensemble_id,
+                 s);
+  launch_soar(c->cc, c->soar_me_f, c->ne, c->xi, c->coarse, s);
+  launch_gb_add(c->cc, c->ne, c->coarse, nullptr, state, c->upd_strip_h, s);
+  IEWPF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int iewpf_assimilate(iewpf_ctx* c, float* state, const iewpf_obs* obs, int n_obs,
+                     uint64_t analysis_index, iewpf_stats* stats_out, void* stream) {
+  if (!c || !state || (n_obs > 0 && !obs) || n_obs < 0) return fail(IEWPF_E_ARG, "invalid argument");
+  if (n_obs > c->max_obs) return fail(IEWPF_E_CAPACITY, "more observations than max_obs");
+  hipStream_t s = as_stream(stream);
+  if (int rc = wait_stage(c)) return rc;
+  const StageLayout L = stage_layout(*c);
+  int32_t* cells = reinterpret_cast<int32_t*>(c->h_stage + L.cells);
+  double* y = reinterpret_cast<double*>(c->h_stage + L.y);
+  for (int o = 0; o < n_obs; ++o) {
+    cells[2 * o] = obs[o].j;
+    cells[2 * o + 1] = obs[o].k;
+    y[2 * o] = obs[o].y_hu;
+    y[2 * o + 1] = obs[o].y_hv;
+  }
+  if (int rc = check_cells(c, cells, n_obs)) return rc;
+  // coarse point -> (obs, block row) lists, ascending obs within each point
+  int32_t* pt_off = reinterpret_cast<int32_t*>(c->h_stage + L.pt_off);
+  int32_t* pt_ent = reinterpret_cast<int32_t*>(c->h_stage + L.pt_ent);
+  std::fill(pt_off, pt_off + c->nr + 1, 0);
+  for (int o = 0; o < n_obs; ++o) {
+    const int ao = cells[2 * o] / c->c, bo = cells[2 * o + 1] / c->c;
+    for (int q = 0; q < kBlockN; ++q) {
+      const int pa = ((ao + q % 7 - 3) % c->nrx + c->nrx) % c->nrx;
+      const int pb = ((bo + q / 7 - 3) % c->nry + c->nry) % c->nry;
+      pt_off[pb * c->nrx + pa + 1]++;
+    }
+  }
+  for (int p = 0; p < c->nr; ++p) pt_off[p + 1] += pt_off[p];
+  {
+    std::vector<int32_t> fillp(pt_off, pt_off + c->nr);
+    for (int o = 0; o < n_obs; ++o) {
+      const int ao = cells[2 * o] / c->c, bo = cells[2 * o + 1] / c->c;
+      for (int q = 0; q < kBlockN; ++q) {
+        const int pa = ((ao + q % 7 - 3) % c->nrx + c->nrx) % c->nrx;
+        const int pb = ((bo + q / 7 - 3) % c->nry + c->nry) % c->nry;
+        pt_ent[fillp[pb * c->nrx + pa]++] = (o << 8) | q;
+      }
+    }
+  }
+  // fine strip -> observations whose pull window reaches it
+  const int nsx = (c->nx + kGbOut - 1) / kGbOut;
+  const int nsy = (c->ny + c->upd_strip_h - 1) / c->upd_strip_h;
+  int32_t* st_off = reinterpret_cast<int32_t*>(c->h_stage + L.st_off);
+  int32_t* st_ent = reinterpret_cast<int32_t*>(c->h_stage + L.st_ent);
+  st_off[0] = 0;
+  int t = 0;
+  for (int sy = 0; sy < nsy; ++sy) {
+    const int k0 = sy * c->upd_strip_h;
+    const int lenk = std::min(c->upd_strip_h, c->ny - k0);
+    for (int sx = 0; sx < nsx; ++sx) {
+      const int j0 = sx * kGbOut;
+      const int lenj = std::min(kGbOut, c->nx - j0);
+      for (int o = 0; o < n_obs; ++o) {
+        const bool in_x = c->rx < 0 || circ_interval_dist(cells[2 * o], j0, lenj, c->nx) <= c->rx;
+        const bool in_y =
+            c->ry < 0 || circ_interval_dist(cells[2 * o + 1], k0, lenk, c->ny) <= c->ry;
+        if (in_x && in_y) st_ent[t++] = o;
+      }
+      st_off[sy * nsx + sx + 1] = t;
+    }
+  }
+  const size_t ne_cells = sizeof(int32_t) * 2 * (size_t)n_obs;
+  if (n_obs > 0) {
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->obs_cells, cells, ne_cells, hipMemcpyHostToDevice, s));
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->obs_y, y, sizeof(double) * 2 * n_obs, hipMemcpyHostToDevice, s));
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->pt_ent, pt_ent, sizeof(int32_t) * pt_off[c->nr],
+                                 hipMemcpyHostToDevice, s));
+  }
+  IEWPF_HIP_TRY(hipMemcpyAsync(c->pt_off, pt_off, sizeof(int32_t) * (c->nr + 1),
+                               hipMemcpyHostToDevice, s));
+  IEWPF_HIP_TRY(hipMemcpyAsync(c->st_off, st_off, sizeof(int32_t) * (c->n_upd_strips + 1),
+                               hipMemcpyHostToDevice, s));
+  if (t > 0)
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->st_ent, st_ent, sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
+  IEWPF_HIP_TRY(hipEventRecord(c->stage_ev, s));
+  c->stage_pending = true;
+  c->last_n_obs = n_obs;
+
+  // stages 1-2: innovations, S d, c_i
+  launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, c->S, state, c->obs_cells,
+                    c->obs_y, c->sd, c->cval, s);
+  // stage 3: xi, nu~ and their dot products
+  launch_rand_dots(c->ne, c->nr, c->cfg.seed, analysis_index, c->cfg.ensemble_id, c->xi, c->nu,
+                   c->dots, s);
+  // stages 4-5: cbar, beta, c*, alpha (the one ensemble-wide step)
+  launch_sync(c->ne, c->n_psi, (double)c->nr, c->cval, c->dots, c->alpha, c->cstar, c->scal, s);
+  // stage 6: r' on the coarse grid, SOAR, then one fused pass over the state
+  launch_posterior_coarse(c->cc, c->ne, c->xi, c->nu, c->dots, c->alpha, c->scal, c->dmat,
+                          c->pt_off, c->pt_ent, c->obs_cells, c->coarse2, s);
+  launch_soar(c->cc, c->soar_me_f, c->ne, c->coarse2, c->coarse, s);
+  PullConst P;
+  P.wx = c->wx;
+  P.wy = c->wy;
+  P.rx = c->rx;
+  P.ry = c->ry;
+  P.n_obs = n_obs;
+  P.strip_h = c->upd_strip_h;
+  P.n_strip_x = nsx;
+  P.n_strip_y = nsy;
+  launch_analysis_update(c->cc, P, c->ne, c->coarse, c->windows, c->sd, c->max_obs, c->obs_cells,
+                         c->st_off, c->st_ent, state, s);
+  IEWPF_HIP_TRY(hipGetLastError());
+  if (stats_out) {
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->h_small, c->scal, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
+    IEWPF_HIP_TRY(hipStreamSynchronize(s));
+    const double* v = c->h_small;
+    stats_out->cbar = v[0];
+    stats_out->beta = v[1];
+    stats_out->alpha_min = v[2];
+    stats_out->alpha_max = v[3];
+    stats_out->cstar_max = v[4];
+    stats_out->c_min = v[5];
+    stats_out->c_max = v[6];
+    stats_out->argmin_beta = (int32_t)v[7];
+    stats_out->n_obs = n_obs;
+    if (!(v[1] > 0.0)) return fail(IEWPF_E_BETA, "beta <= 0: ensemble violates N_psi >> N_y");
+  }
+  return 0;
+}
+
+int iewpf_particle_scalars(iewpf_ctx* c, double* out, void* stream) {
+  if (!c || !out) return fail(IEWPF_E_ARG, "NULL argument");
+  hipStream_t s = as_stream(stream);
+  std::vector<double> cv(c->ne), dt(3 * (size_t)c->ne), al(c->ne), cs(c->ne);
+  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  IEWPF_HIP_TRY(hipMemcpy(cv.data(), c->cval, sizeof(double) * c->ne, hipMemcpyDeviceToHost));
+  IEWPF_HIP_TRY(hipMemcpy(dt.data(), c->dots, sizeof(double) * 3 * c->ne, hipMemcpyDeviceToHost));
+  IEWPF_HIP_TRY(hipMemcpy(al.data(), c->alpha, sizeof(double) * c->ne, hipMemcpyDeviceToHost));
+  IEWPF_HIP_TRY(hipMemcpy(cs.data(), c->cstar, sizeof(double) * c->ne, hipMemcpyDeviceToHost));
+  const double scale = c->n_psi / (double)c->nr;
+  for (int i = 0; i < c->ne; ++i) {
+    double* o = out + 8 * (size_t)i;
+    o[0] = cv[i];
+    o[1] = dt[3 * i] * scale;
+    o[2] = dt[3 * i + 1] * scale;
+    o[3] = al[i];
+    o[4] = cs[i];
+    o[5] = dt[3 * i];
+    o[6] = dt[3 * i + 1];
+    o[7] = dt[3 * i + 2];
+  }
+  return 0;
+}
+
+int iewpf_observe_moorings(iewpf_ctx* c, const float* truth, const int32_t* cells_host, int n_obs,
+                           uint64_t analysis_index, iewpf_obs* obs_host, void* stream) {
+  if (!c || !truth || !cells_host || !obs_host || n_obs < 0) return fail(IEWPF_E_ARG, "NULL argument");
+  if (n_obs > c->max_obs) return fail(IEWPF_E_CAPACITY, "more observations than max_obs");
+  if (int rc = check_cells(c, cells_host, n_obs)) return rc;
+  if (n_obs == 0) return 0;
+  hipStream_t s = as_stream(stream);
+  if (int rc = wait_stage(c)) return rc;
+  const StageLayout L = stage_layout(*c);
+  int32_t* cells = reinterpret_cast<int32_t*>(c->h_stage + L.cells);
+  std::memcpy(cells, cells_host, sizeof(int32_t) * 2 * n_obs);
+  IEWPF_HIP_TRY(hipMemcpyAsync(c->obs_cells, cells, sizeof(int32_t) * 2 * n_obs,
+                               hipMemcpyHostToDevice, s));
+  launch_observe(n_obs, c->nx, c->ny, c->cfg.H, c->cfg.obs_sigma, c->cfg.seed, analysis_index,
+                 c->cfg.ensemble_id, truth, c->obs_cells, c->dobs, s);
+  IEWPF_HIP_TRY(hipGetLastError());
+  IEWPF_HIP_TRY(hipMemcpyAsync(c->h_small, c->dobs, sizeof(double) * 2 * n_obs,
+                               hipMemcpyDeviceToHost, s));
+  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  for (int o = 0; o < n_obs; ++o) {
+    obs_host[o].j = cells_host[2 * o];
+    obs_host[o].k = cells_host[2 * o + 1];
+    obs_host[o].y_hu = c->h_small[2 * o];
+    obs_host[o].y_hv = c->h_small[2 * o + 1];
+  }
+  return 0;
+}
+
+int iewpf_advect_drifters(iewpf_ctx* c, const float* psi_n, const float* psi_np1, double* pos,
+                          int n_drifters, void* stream) {
+  if (!c || !psi_n || !psi_np1 || !pos || n_drifters < 0) return fail(IEWPF_E_ARG, "NULL argument");
+  if (n_drifters > c->max_obs) return fail(IEWPF_E_CAPACITY, "more drifters than max_obs");
+  if (n_drifters == 0) return 0;
+  hipStream_t s = as_stream(stream);
+  const auto& f = c->cfg;
+  launch_drift_k1(c->ne, n_drifters, c->nx, c->ny, f.dx, f.dy, f.H, f.dt, psi_n, pos, c->dk1,
+                  c->dpstar, s);
+  launch_drift_k2(c->ne, n_drifters, c->nx, c->ny, f.dx, f.dy, f.H, f.dt, psi_np1, pos, c->dk1,
+                  c->dpstar, nullptr, s);
+  IEWPF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int iewpf_forecast_drifters(iewpf_ctx* c, float* state, double* pos, int n_drifters,
+                            int n_model_steps, uint64_t first_step, double* traj, void* stream) {
+  if (!c || !state || !pos || n_drifters < 0 || n_model_steps < 0)
+    return fail(IEWPF_E_ARG, "invalid argument");
+  if (n_drifters > c->max_obs) return fail(IEWPF_E_CAPACITY, "more drifters than max_obs");
+  hipStream_t s = as_stream(stream);
+  const auto& f = c->cfg;
+  const size_t per = (size_t)c->ne * n_drifters * 2;
+  if (traj && per)
+    IEWPF_HIP_TRY(hipMemcpyAsync(traj, pos, sizeof(double) * per, hipMemcpyDeviceToDevice, s));
+  for (int st = 0; st < n_model_steps; ++st) {
+    if (n_drifters)
+      launch_drift_k1(c->ne, n_drifters, c->nx, c->ny, f.dx, f.dy, f.H, f.dt, state, pos, c->dk1,
+                      c->dpstar, s);
+    if (int rc = model_steps(c, state, 1, first_step + st, 1, s)) return rc;
+    if (n_drifters)
+      launch_drift_k2(c->ne, n_drifters, c->nx, c->ny, f.dx, f.dy, f.H, f.dt, state, pos, c->dk1,
+                      c->dpstar, traj ? traj + (size_t)(st + 1) * per : nullptr, s);
+  }
+  IEWPF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int iewpf_resample(iewpf_ctx* c, float* state, const double* logw, uint64_t analysis_index,
+                   int32_t* parents, void* stream) {
+  if (!c || !state || !logw || !parents) return fail(IEWPF_E_ARG, "NULL argument");
+  hipStream_t s = as_stream(stream);
+  launch_resample(c->ne, c->cfg.seed, analysis_index, c->cfg.ensemble_id, logw, parents,
+                  c->dparents, s);
+  const size_t per = 3 * c->ncell;
+  if (per % 4 == 0) {
+    launch_gather_particles(c->ne, per, parents, state, c->scratch, s);
+  } else {
+    return fail(IEWPF_E_SHAPE, "3 nx ny must be a multiple of 4 for the particle gather");
+  }
+  IEWPF_HIP_TRY(hipMemcpyAsync(state, c->scratch, sizeof(float) * per * c->ne,
+                               hipMemcpyDeviceToDevice, s));
+  IEWPF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int iewpf_check_cfl(iewpf_ctx* c, const float* state, double* dt_out, void* stream) {
+  if (!c || !state || !dt_out) return fail(IEWPF_E_ARG, "NULL argument");
+  hipStream_t s = as_stream(stream);
+  IEWPF_HIP_TRY(hipMemsetAsync(c->cflmax, 0, 2 * sizeof(unsigned), s));
+  launch_cfl(c->ne, c->nx, c->ny, (float)c->cfg.H, (float)c->cfg.g, state, c->cflmax, s);
+  IEWPF_HIP_TRY(hipGetLastError());
+  unsigned w[2];
+  IEWPF_HIP_TRY(hipMemcpyAsync(c->h_small, c->cflmax, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  std::memcpy(w, c->h_small, sizeof(w));
+  float sx, sy;
+  std::memcpy(&sx, &w[0], 4);
+  std::memcpy(&sy, &w[1], 4);
+  const double dtc = 0.8 * 0.25 * std::min(c->cfg.dx / (double)sx, c->cfg.dy / (double)sy);
+  *dt_out = dtc;
+  if (!std::isfinite(dtc)) return fail(IEWPF_E_NONFINITE, "non-finite wave speed");
+  if (c->cfg.dt / c->cfg.n_sub > dtc) return fail(IEWPF_E_CFL, "scheme step exceeds the CFL limit");
+  return 0;
+}
+
+int iewpf_read_buffer(iewpf_ctx* c, int which, void* host_out, size_t bytes, void* stream) {
+  if (!c || !host_out) return fail(IEWPF_E_ARG, "NULL argument");
+  hipStream_t s = as_stream(stream);
+  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  const size_t nrf = sizeof(float) * (size_t)c->ne * c->nr;
+  auto need = [&](size_t n) { return bytes == n; };
+  switch (which) {
+    case 0:
+      if (!need(nrf)) break;
+      IEWPF_HIP_TRY(hipMemcpy(host_out, c->xi, nrf, hipMemcpyDeviceToHost));
+      return 0;
+    case 1:
+      if (!need(nrf)) break;
+      IEWPF_HIP_TRY(hipMemcpy(host_out, c->nu, nrf, hipMemcpyDeviceToHost));
+      return 0;
+    case 2:
+      if (!need(nrf)) break;
+      IEWPF_HIP_TRY(hipMemcpy(host_out, c->coarse2, nrf, hipMemcpyDeviceToHost));
+      return 0;
+    case 3:
+      if (!need(4 * sizeof(double))) break;
+      std::memcpy(host_out, c->S, bytes);
+      return 0;
+    case 4:
+      if (!need(4 * sizeof(double))) break;
+      std::memcpy(host_out, c->Sc, bytes);
+      return 0;
+    case 5:
+      if (!need(sizeof(double) * kBlockN * kBlockN)) break;
+      std::memcpy(host_out, c->ahalf, bytes);
+      return 0;
+    case 6:
+      if (!need(sizeof(float) * 6 * (size_t)c->wx * c->wy)) break;
+      IEWPF_HIP_TRY(hipMemcpy(host_out, c->windows, bytes, hipMemcpyDeviceToHost));
+      return 0;
+    case 7: {
+      if (!need(sizeof(double) * (size_t)c->ne * c->last_n_obs * 2)) break;
+      double* o = static_cast<double*>(host_out);
+      for (int i = 0; i < c->ne; ++i)
+        if (c->last_n_obs)
+          IEWPF_HIP_TRY(hipMemcpy(o + (size_t)i * c->last_n_obs * 2, c->sd + (size_t)i * c->max_obs * 2,
+                                  sizeof(double) * c->last_n_obs * 2, hipMemcpyDeviceToHost));
+      return 0;
+    }
+    case 8:
+      if (!need(25 * sizeof(double))) break;
+      std::memcpy(host_out, c->soar_me, bytes);
+      return 0;
+    default:
+      return fail(IEWPF_E_ARG, "unknown buffer id");
+  }
+  return fail(IEWPF_E_ARG, "byte count does not match the buffer");
+}
+
+}  // extern "C"

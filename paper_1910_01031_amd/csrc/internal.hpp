@@ -1,0 +1,167 @@
+// Internal declarations of the IEWPF HIP library: context layout, kernel constants and
+// launchers.  Everything here is private to libiewpf.so; the public ABI is iewpf.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "iewpf.h"
+
+namespace iewpf {
+
+// ---- error reporting -------------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define IEWPF_HIP_TRY(expr)                                                             \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return ::iewpf::fail(IEWPF_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---- constants passed by value to kernels ----------------------------------------------
+
+// Shallow-water scheme constants (float32, as used by the stencil).
+struct SweConst {
+  int nx, ny;
+  int strip_h;         // rows per wave strip
+  int n_strip_x, n_strip_y;
+  float H, g, inv2g, f;
+  float hfdx, hfdy;    // f dx / 2, f dy / 2 (Coriolis potential increments)
+  float fdx, fdy;      // f dx, f dy
+  float theta;
+  float dt, idx, idy;  // scheme step, 1/dx, 1/dy
+};
+
+// Coarse random grid and covariance stencils.
+struct CoarseConst {
+  int nx, ny;          // fine grid
+  int c;               // coarsening
+  int nrx, nry;        // coarse grid
+  float gb_x, gb_y;    // g H / (2 f dx), g H / (2 f dy)
+};
+
+// Observation / pull-window geometry for the analysis update.
+struct PullConst {
+  int wx, wy;          // stored window extents
+  int rx, ry;          // window radii (-1: folded onto the whole period)
+  int n_obs;
+  int strip_h, n_strip_x, n_strip_y;
+};
+
+constexpr int kWave = 64;
+constexpr int kSweHalo = 4;                   // lanes lost per side by the fused RK stages
+constexpr int kSweOut = kWave - 2 * kSweHalo;  // 56 output columns per wave
+constexpr int kGbHalo = 1;                    // lanes lost per side by the geostrophic stencil
+constexpr int kGbOut = kWave - 2 * kGbHalo;    // 62 output columns per wave
+constexpr int kBlockN = 49;                   // 7x7 local block of the posterior operator
+
+}  // namespace iewpf
+
+// ---- the context ------------------------------------------------------------------------
+struct iewpf_ctx {
+  iewpf_config cfg;
+  int nx, ny, c, nrx, nry, nr, ne, max_obs;
+  size_t ncell;            // nx * ny
+  double n_psi;            // 3 nx ny
+  // host-side precompute (float64)
+  double q0_me, q0_init;
+  double soar_me[25], soar_init[25];
+  double S[4], Sc[4], Mfine[4];
+  double ahalf[iewpf::kBlockN * iewpf::kBlockN];
+  int wx, wy, rx, ry;      // pull window geometry
+  iewpf::SweConst swe;
+  iewpf::CoarseConst cc;
+  float soar_me_f[25], soar_init_f[25];
+  // device workspaces
+  float* scratch = nullptr;    // one state-sized buffer [ne][3][ny][nx]
+  float* xi = nullptr;         // [ne][nr]
+  float* nu = nullptr;         // [ne][nr]
+  float* coarse = nullptr;     // [ne][nr] SOAR output / r'
+  float* coarse2 = nullptr;    // [ne][nr]
+  float* windows = nullptr;    // [6][wy][wx]: (s_u, s_v) x (eta, hu, hv)
+  float* dmat = nullptr;       // A^{1/2} - I, float32 [49][49]
+  double* sd = nullptr;        // [ne][max_obs][2]
+  double* cval = nullptr;      // [ne]
+  double* dots = nullptr;      // [ne][3]
+  double* alpha = nullptr;     // [ne]
+  double* cstar = nullptr;     // [ne]
+  double* scal = nullptr;      // [16] analysis scalars
+  int32_t* obs_cells = nullptr;  // [max_obs][2]
+  double* obs_y = nullptr;       // [max_obs][2]
+  int32_t* pt_off = nullptr;     // coarse-point CSR offsets [nr + 1]
+  int32_t* pt_ent = nullptr;     // entries (obs << 8 | block index) [max_obs * 49]
+  int32_t* st_off = nullptr;     // strip CSR offsets [n_strips + 1]
+  int32_t* st_ent = nullptr;     // obs ids per strip [n_strips * max_obs]
+  int n_upd_strips = 0;
+  int upd_strip_h = 16;
+  double* dk1 = nullptr;         // drifter k1 [ne][max_obs][2]
+  double* dpstar = nullptr;      // drifter p*  [ne][max_obs][2]
+  double* dobs = nullptr;        // observation synthesis output [max_obs][2]
+  unsigned* cflmax = nullptr;    // 2 words
+  int32_t* dparents = nullptr;   // resampling scratch [ne]
+  // pinned host staging
+  unsigned char* h_stage = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_ev = nullptr;
+  bool stage_pending = false;
+  double* h_small = nullptr;     // small pinned readback buffer
+  int last_n_obs = 0;
+};
+
+// ---- host precompute (host_precompute.cpp) ----------------------------------------------
+namespace iewpf {
+double soar_q0(double std_, double L0, double dxc, double dyc);
+void soar_stencil(double q0, double L0, double dxc, double dyc, double out[25]);
+// Pull windows for s = e_1 and s = e_2; out[6][wy][wx], plus the 2x2 H Q H^T at the centre.
+int build_pull_windows(const iewpf_ctx& ctx, double* out, double M[4]);
+// Local posterior block: A^{1/2} [49x49] and S_c.
+int build_local_block(const iewpf_ctx& ctx, double ahalf[49 * 49], double Sc[4]);
+int inverse_spd2(const double A[4], double out[4]);
+}  // namespace iewpf
+
+// ---- launchers (kernels in *.hip) ---------------------------------------------------------
+namespace iewpf {
+void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, hipStream_t s);
+void launch_normals(float* out, int n, int ne, uint64_t seed, uint64_t step, uint32_t tag,
+                    uint32_t ens, hipStream_t s);
+void launch_soar(const CoarseConst& C, const float* w25, int ne, const float* in, float* out,
+                 hipStream_t s);
+// psi (+)= Q_GB I_Omega z  [+ pull];  base != nullptr: psi = base + ...
+void launch_gb_add(const CoarseConst& C, int ne, const float* z, const float* base, float* psi,
+                   int strip_h, hipStream_t s);
+void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, const float* z,
+                            const float* windows, const double* sd, int max_obs,
+                            const int32_t* obs_cells, const int32_t* st_off,
+                            const int32_t* st_ent, float* psi, hipStream_t s);
+void launch_innovation(int ne, int n_obs, int max_obs, int nx, int ny, double H, const double S[4],
+                       const float* psi, const int32_t* cells, const double* y, double* sd,
+                       double* cval, hipStream_t s);
+void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens, float* xi,
+                      float* nu, double* dots, hipStream_t s);
+void launch_sync(int ne, double n_psi, double n_r, const double* cval, const double* dots,
+                 double* alpha, double* cstar, double* scal, hipStream_t s);
+void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,
+                             const double* dots, const double* alpha, const double* scal,
+                             const float* dmat, const int32_t* pt_off, const int32_t* pt_ent,
+                             const int32_t* cells, float* rout, hipStream_t s);
+void launch_observe(int n_obs, int nx, int ny, double H, double sigma, uint64_t seed,
+                    uint64_t step, uint32_t ens, const float* truth, const int32_t* cells,
+                    double* y, hipStream_t s);
+void launch_cfl(int ne, int nx, int ny, float H, float g, const float* psi, unsigned* out,
+                hipStream_t s);
+void launch_drift_k1(int ne, int nd, int nx, int ny, double dx, double dy, double H, double dt,
+                     const float* psi, const double* pos, double* k1, double* pstar,
+                     hipStream_t s);
+void launch_drift_k2(int ne, int nd, int nx, int ny, double dx, double dy, double H, double dt,
+                     const float* psi, double* pos, const double* k1, const double* pstar,
+                     double* traj, hipStream_t s);
+void launch_resample(int ne, uint64_t seed, uint64_t step, uint32_t ens, const double* logw,
+                     int32_t* parents, int32_t* counts, hipStream_t s);
+void launch_gather_particles(int ne, size_t per_particle, const int32_t* parents, const float* in,
+                             float* out, hipStream_t s);
+}  // namespace iewpf

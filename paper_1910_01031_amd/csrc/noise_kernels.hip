@@ -1,0 +1,228 @@
+// Covariance-operator kernels: normals on the coarse random grid, the SOAR stencil, and the
+// fine-grid pass Q_GB^{1/2} I_Omega (bicubic + geostrophic balance) that adds a coarse field
+// into the state, optionally together with the optimal-proposal pull windows.
+//
+// Paper: Section "Small scale model errors" (eq. soar_function, eq. local_soar_on_eta,
+// eq. geostrophic_balance_disc), Section "Efficient generation of model errors" (one
+// output element per work-item, perturbation never stored), Section "Optimal proposal
+// particles" (pull chain, eq. detailedOPDUpdate) and "Posterior particle states"
+// (eq. optUpdateEquationTwoStage).
+#include "internal.hpp"
+#include "philox_dev.hpp"
+
+namespace iewpf {
+namespace {
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+__device__ __forceinline__ int floordiv(int a, int b) {  // b > 0
+  const int q = a / b;
+  return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+// Catmull-Rom weights (taps -1, 0, 1, 2) at phase t.
+__device__ __forceinline__ void cr4(float t, float w[4]) {
+  const float t2 = t * t, t3 = t2 * t;
+  w[0] = 0.5f * (-t3 + 2.0f * t2 - t);
+  w[1] = 0.5f * (3.0f * t3 - 5.0f * t2 + 2.0f);
+  w[2] = 0.5f * (-3.0f * t3 + 4.0f * t2 + t);
+  w[3] = 0.5f * (t3 - t2);
+}
+
+struct Stencil25 {
+  float w[25];
+};
+
+__global__ __launch_bounds__(256) void normals_kernel(float* __restrict__ out, int n, uint64_t seed,
+                                                      uint64_t step, uint32_t tag, uint32_t ens) {
+  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
+  const int particle = blockIdx.y;
+  if (4 * blk >= n) return;
+  double z[4];
+  normals4(blk, step, tag, ens, particle, seed, z);
+  float* o = out + (size_t)particle * n;
+#pragma unroll
+  for (int l = 0; l < 4; ++l)
+    if (4 * blk + l < n) o[4 * blk + l] = static_cast<float>(z[l]);
+}
+
+__global__ __launch_bounds__(256) void soar_kernel(const float* __restrict__ in,
+                                                   float* __restrict__ out, int nrx, int nry,
+                                                   Stencil25 W) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nr = nrx * nry;
+  if (p >= nr) return;
+  const int particle = blockIdx.y;
+  const int b = p / nrx, a = p - b * nrx;
+  const float* src = in + (size_t)particle * nr;
+  float acc = 0.0f;
+#pragma unroll
+  for (int q = -2; q <= 2; ++q) {
+    const float* row = src + (size_t)wrapi(b + q, nry) * nrx;
+#pragma unroll
+    for (int pp = -2; pp <= 2; ++pp) acc += W.w[(q + 2) * 5 + (pp + 2)] * row[wrapi(a + pp, nrx)];
+  }
+  out[(size_t)particle * nr + p] = acc;
+}
+
+// Bicubic value of the coarse field z (one particle) at fine cell (j, k) given the lane's
+// x taps.
+__device__ __forceinline__ float bicubic_at(const float* __restrict__ z, const CoarseConst& C,
+                                            const int cx[4], const float wx[4], int k) {
+  const int num = 2 * k + 1 - C.c;
+  const int by = floordiv(num, 2 * C.c);
+  float wy[4];
+  cr4(static_cast<float>(num - 2 * C.c * by) / static_cast<float>(2 * C.c), wy);
+  float acc = 0.0f;
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    const float* row = z + (size_t)wrapi(by + n - 1, C.nry) * C.nrx;
+    const float rv = wx[0] * row[cx[0]] + wx[1] * row[cx[1]] + wx[2] * row[cx[2]] + wx[3] * row[cx[3]];
+    acc += wy[n] * rv;
+  }
+  return acc;
+}
+
+// Fine pass over wave strips of 62 output columns (lanes 1..62) marching down rows:
+//   psi(k) = (base or psi)(k) + (d_eta, -gH/(2 f dy) (d_eta(k+1) - d_eta(k-1)),
+//                                 gH/(2 f dx) (d_eta(j+1) - d_eta(j-1)))  [+ pull windows]
+// with d_eta = I_Omega z.
+template <bool PULL>
+__global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, PullConst P, int strip_h,
+                                                     int n_strip_x, int n_strip_y, int total_waves,
+                                                     const float* __restrict__ zall,
+                                                     const float* __restrict__ base,
+                                                     float* __restrict__ psi,
+                                                     const float* __restrict__ windows,
+                                                     const double* __restrict__ sd, int max_obs,
+                                                     const int32_t* __restrict__ cells,
+                                                     const int32_t* __restrict__ st_off,
+                                                     const int32_t* __restrict__ st_ent) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  if (wave >= total_waves) return;
+  const int per_particle = n_strip_x * n_strip_y;
+  const int particle = wave / per_particle;
+  const int strip = wave - particle * per_particle;
+  const int sy = strip / n_strip_x;
+  const int sx = strip - sy * n_strip_x;
+  const int nx = C.nx, ny = C.ny;
+  const size_t ncell = (size_t)nx * ny;
+  const float* z = zall + (size_t)particle * C.nrx * C.nry;
+  float* E = psi + (size_t)particle * 3 * ncell;
+  const float* B = base ? base : E;  // base: one shared state [3][ny][nx]
+
+  const int j = sx * kGbOut + lane - kGbHalo;
+  const int jw = wrapi(j, nx);
+  const bool writer = lane >= kGbHalo && lane < kWave - kGbHalo && j < nx;
+  // x taps of this lane (unshifted coarse grid: coarse point a at (a + 1/2) c dx)
+  int cx[4];
+  float wx[4];
+  {
+    const int num = 2 * jw + 1 - C.c;
+    const int bx = floordiv(num, 2 * C.c);
+    cr4(static_cast<float>(num - 2 * C.c * bx) / static_cast<float>(2 * C.c), wx);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) cx[m] = wrapi(bx + m - 1, C.nrx);
+  }
+  const int k0 = sy * strip_h;
+  const int k_end = min(k0 + strip_h, ny);
+  float dm2 = 0.0f, dm1 = 0.0f;  // d_eta rows m-2, m-1
+  int o_beg = 0, o_end = 0;
+  if (PULL) {
+    o_beg = st_off[strip];
+    o_end = st_off[strip + 1];
+  }
+  for (int m = k0 - 1; m <= k_end; ++m) {
+    const float d0 = bicubic_at(z, C, cx, wx, wrapi(m, ny));
+    if (m >= k0 + 1) {
+      const int k = m - 1;
+      const float de = dm1;
+      const float dhu = -C.gb_y * (d0 - dm2);
+      const float dhv = C.gb_x * (__shfl_down(dm1, 1, kWave) - __shfl_up(dm1, 1, kWave));
+      if (writer) {
+        float pe = 0.0f, pu = 0.0f, pv = 0.0f;
+        if (PULL) {
+          for (int t = o_beg; t < o_end; ++t) {
+            const int o = st_ent[t];
+            const int jo = cells[2 * o], ko = cells[2 * o + 1];
+            int ix, iy;
+            if (P.rx >= 0) {
+              int dj = j - jo;
+              dj = dj > nx / 2 ? dj - nx : (dj < -(nx / 2) ? dj + nx : dj);
+              if (dj < -P.rx || dj > P.rx) continue;
+              ix = dj + P.rx;
+            } else {
+              ix = wrapi(j - jo, nx);
+            }
+            if (P.ry >= 0) {
+              int dk = k - ko;
+              dk = dk > ny / 2 ? dk - ny : (dk < -(ny / 2) ? dk + ny : dk);
+              if (dk < -P.ry || dk > P.ry) continue;
+              iy = dk + P.ry;
+            } else {
+              iy = wrapi(k - ko, ny);
+            }
+            const size_t plane = (size_t)P.wx * P.wy;
+            const size_t idx = (size_t)iy * P.wx + ix;
+            const double* s = sd + ((size_t)particle * max_obs + o) * 2;
+            const float su = static_cast<float>(s[0]), sv = static_cast<float>(s[1]);
+            pe += su * windows[idx] + sv * windows[3 * plane + idx];
+            pu += su * windows[plane + idx] + sv * windows[4 * plane + idx];
+            pv += su * windows[2 * plane + idx] + sv * windows[5 * plane + idx];
+          }
+        }
+        const size_t o = (size_t)k * nx + j;
+        const size_t ob = o;  // base has the same [3][ny][nx] layout for one state
+        E[o] = B[ob] + (de + pe);
+        E[ncell + o] = B[ncell + ob] + (dhu + pu);
+        E[2 * ncell + o] = B[2 * ncell + ob] + (dhv + pv);
+      }
+    }
+    dm2 = dm1;
+    dm1 = d0;
+  }
+}
+
+}  // namespace
+
+void launch_normals(float* out, int n, int ne, uint64_t seed, uint64_t step, uint32_t tag,
+                    uint32_t ens, hipStream_t s) {
+  const int nblk = (n + 3) / 4;
+  hipLaunchKernelGGL(normals_kernel, dim3((nblk + 255) / 256, ne), dim3(256), 0, s, out, n, seed,
+                     step, tag, ens);
+}
+
+void launch_soar(const CoarseConst& C, const float* w25, int ne, const float* in, float* out,
+                 hipStream_t s) {
+  Stencil25 W;
+  for (int i = 0; i < 25; ++i) W.w[i] = w25[i];
+  const int nr = C.nrx * C.nry;
+  hipLaunchKernelGGL(soar_kernel, dim3((nr + 255) / 256, ne), dim3(256), 0, s, in, out, C.nrx,
+                     C.nry, W);
+}
+
+void launch_gb_add(const CoarseConst& C, int ne, const float* z, const float* base, float* psi,
+                   int strip_h, hipStream_t s) {
+  const int nsx = (C.nx + kGbOut - 1) / kGbOut;
+  const int nsy = (C.ny + strip_h - 1) / strip_h;
+  const int total = ne * nsx * nsy;
+  PullConst P{};
+  hipLaunchKernelGGL(gb_add_kernel<false>, dim3((total + 3) / 4), dim3(256), 0, s, C, P, strip_h,
+                     nsx, nsy, total, z, base, psi, nullptr, nullptr, 0, nullptr, nullptr,
+                     nullptr);
+}
+
+void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, const float* z,
+                            const float* windows, const double* sd, int max_obs,
+                            const int32_t* obs_cells, const int32_t* st_off,
+                            const int32_t* st_ent, float* psi, hipStream_t s) {
+  const int total = ne * P.n_strip_x * P.n_strip_y;
+  hipLaunchKernelGGL(gb_add_kernel<true>, dim3((total + 3) / 4), dim3(256), 0, s, C, P, P.strip_h,
+                     P.n_strip_x, P.n_strip_y, total, z, nullptr, psi, windows, sd, max_obs,
+                     obs_cells, st_off, st_ent);
+}
+
+}  // namespace iewpf

@@ -1,0 +1,180 @@
+"""GPU parity of the forecast path (scheme step, model error, initial ensemble) against the
+FP64 oracle, through the C ABI.  Tolerance (the benchmark spec): per field,
+max |gpu - oracle| / max |oracle| <= 1e-5 after one model step from the same
+FP32-representable input."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ensemble as oens
+from oracle import model_error as ome
+from oracle import swe as oswe
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1910_01031_amd import load
+    load()
+    return torch, torch.device("cuda:0")
+
+
+def _rel(got, ref):
+    return [float(np.abs(got[..., f, :, :] - ref[..., f, :, :]).max() / np.abs(ref[..., f, :, :]).max())
+            for f in range(3)]
+
+
+def _run_steps(torch, dev, cfg, ens32, n_steps, first_step=0, noise_on_last=False, max_obs=8):
+    from paper_1910_01031_amd import Context
+    ctx = Context(cfg, max_obs=max_obs)
+    st = torch.from_numpy(np.ascontiguousarray(ens32)).to(dev)
+    ctx.step_ensemble(st, n_steps, first_step=first_step, noise_on_last=noise_on_last)
+    torch.cuda.synchronize()
+    out = st.cpu().numpy().astype(np.float64)
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("shape,c,nsub", [((32, 32), 4, 1), ((68, 44), 4, 2), ((120, 70), 5, 1),
+                                          ((57, 112), 1, 1)])
+def test_scheme_step_parity(torch_dev, shape, c, nsub):
+    torch, dev = torch_dev
+    nx, ny = shape
+    _say(f"scheme step parity {shape} c={c} n_sub={nsub}")
+    cfg = W.Config(nx=nx, ny=ny, dx=1e4, dy=1e4, c_omega=c, n_sub=nsub, n_particles=3)
+    rng = np.random.default_rng(nx * 1000 + ny)
+    ens = W.as_f32(np.stack([W.random_state(cfg, rng) for _ in range(3)]))
+    got = _run_steps(torch, dev, cfg, ens, 1)
+    p = oswe.SweParams.of(cfg)
+    ref = np.stack([oswe.model_step(ens[i].astype(np.float64), p, cfg.dt, nsub) for i in range(3)])
+    err = _rel(got, ref)
+    _say(f"  rel err {err}")
+    assert max(err) < TOL
+
+
+def test_scheme_balanced_jet_parity(torch_dev):
+    torch, dev = torch_dev
+    _say("scheme balanced jet parity")
+    cfg = W.paper_scale(2).replace(nx=100, ny=300)
+    jet = W.jet_state(cfg)
+    ens = W.as_f32(np.stack([jet, jet + 0.01 * W.random_state(cfg, np.random.default_rng(0))]))
+    # two model steps: the model error follows the first one, not the last
+    got = _run_steps(torch, dev, cfg, ens, 2)
+    ref = np.stack([oens.step_member(ens[i], cfg, i, 0, 2, noise_on_last=False) for i in range(2)])
+    # hv of the pure jet stays ~0: compare with the scale of hu for that field
+    for i in range(2):
+        scale = [np.abs(ref[i, 0]).max(), np.abs(ref[i, 1]).max(), np.abs(ref[i, 1]).max()]
+        for f in range(3):
+            e = np.abs(got[i, f] - ref[i, f]).max() / scale[f]
+            assert e < 2 * TOL, (i, f, e)
+
+
+def test_paper_scale_step_sampled(torch_dev):
+    # full 500x300 grid, 100 particles, the launch configuration of the benchmark; the
+    # oracle recomputes three sampled particles
+    torch, dev = torch_dev
+    _say("paper-scale step parity (sampled particles)")
+    cfg = W.paper_scale()
+    jet = W.jet_state(cfg)
+    rng = np.random.default_rng(7)
+    ens = np.empty((cfg.n_particles, 3, cfg.ny, cfg.nx), dtype=np.float32)
+    for i in range(cfg.n_particles):
+        ens[i] = jet + 0.05 * W.random_state(cfg, rng, n_modes=3)
+    got = _run_steps(torch, dev, cfg, ens, 1)
+    p = oswe.SweParams.of(cfg)
+    for i in (0, 41, 99):
+        ref = oswe.model_step(ens[i].astype(np.float64), p, cfg.dt, cfg.n_sub)
+        err = _rel(got[i], ref)
+        _say(f"  particle {i} rel err {err}")
+        assert max(err) < TOL
+
+
+def test_model_error_parity(torch_dev):
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Context
+    for cfg in (W.tiny(), W.Config(nx=60, ny=45, dx=5e3, dy=5e3, c_omega=3, n_particles=4),
+                W.Config(nx=120, ny=80, dx=5e3, dy=6e3, c_omega=4, n_particles=2)):
+        _say(f"model error parity {cfg.nx}x{cfg.ny} c={cfg.c_omega}")
+        ctx = Context(cfg, max_obs=8)
+        st = torch.zeros((cfg.n_particles, 3, cfg.ny, cfg.nx), dtype=torch.float32, device=dev)
+        ctx.perturb(st, step_index=5)
+        torch.cuda.synchronize()
+        got = st.cpu().numpy().astype(np.float64)
+        w = ome.model_error_stencil(cfg)
+        for i in range(cfg.n_particles):
+            ref = oens.perturbation(cfg, 5, i, w)
+            err = _rel(got[i], ref)
+            assert max(err) < TOL, (i, err)
+        ctx.close()
+
+
+def test_initial_ensemble_parity(torch_dev):
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Context
+    _say("initial ensemble parity")
+    cfg = W.paper_scale(4).replace(nx=200, ny=120)
+    base = W.as_f32(W.jet_state(cfg))
+    ctx = Context(cfg, max_obs=8)
+    st = torch.empty((4, 3, cfg.ny, cfg.nx), dtype=torch.float32, device=dev)
+    ctx.init_ensemble(st, torch.from_numpy(base).to(dev), stream_index=3)
+    torch.cuda.synchronize()
+    got = st.cpu().numpy().astype(np.float64)
+    for i in range(4):
+        ref = oens.init_member(cfg, base.astype(np.float64), 3, i)
+        pert_ref = ref - base
+        pert_got = got[i] - base
+        err = _rel(pert_got, pert_ref)
+        assert max(err) < TOL, (i, err)
+    ctx.close()
+
+
+def test_stochastic_steps_parity(torch_dev):
+    torch, dev = torch_dev
+    _say("stochastic steps parity (3 steps with model error)")
+    cfg = W.tiny().replace(n_particles=4, me_std=0.01)
+    rng = np.random.default_rng(3)
+    ens = W.as_f32(np.stack([W.random_state(cfg, rng) for _ in range(4)]))
+    got = _run_steps(torch, dev, cfg, ens, 3, first_step=10, noise_on_last=True)
+    for i in range(4):
+        ref = oens.step_member(ens[i], cfg, i, 10, 3, noise_on_last=True)
+        err = _rel(got[i], ref)
+        assert max(err) < 3 * TOL, (i, err)
+
+
+def test_deterministic_repeat(torch_dev):
+    torch, dev = torch_dev
+    cfg = W.tiny().replace(n_particles=3)
+    rng = np.random.default_rng(4)
+    ens = W.as_f32(np.stack([W.random_state(cfg, rng) for _ in range(3)]))
+    a = _run_steps(torch, dev, cfg, ens, 2, noise_on_last=True)
+    b = _run_steps(torch, dev, cfg, ens, 2, noise_on_last=True)
+    assert np.array_equal(a, b)
+
+
+def test_cfl_check(torch_dev):
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Context
+    cfg = W.tiny().replace(n_particles=2)
+    ens = W.as_f32(np.stack([W.random_state(cfg, np.random.default_rng(i)) for i in range(2)]))
+    ctx = Context(cfg, max_obs=4)
+    st = torch.from_numpy(ens).to(dev)
+    dt, ok = ctx.check_cfl(st)
+    ref = min(oswe.cfl_dt(ens[i].astype(np.float64), oswe.SweParams.of(cfg)) for i in range(2))
+    assert abs(dt - ref) < 1e-5 * ref and ok
+    # a state with a 400 m/s current violates the fixed scheme step
+    ens[1, 1, 5, 5] = 400.0 * (cfg.H + ens[1, 0, 5, 5])
+    st = torch.from_numpy(ens).to(dev)
+    dt2, ok2 = ctx.check_cfl(st)
+    assert not ok2 and dt2 < cfg.dt
+    ctx.close()
