@@ -1,0 +1,184 @@
+"""Benchmark: one IEWPF data-assimilation cycle per step on the paper-scale ensemble.
+
+Workload (synthetic, shaped like the paper's 500x300 identical-twin experiments): 500x300
+periodic grid, dx = dy = 5 km, H = 230 m, 100 particles (float32 state), model error on a
+125x75 coarse grid, 225 moored buoys (15x15) observing (hu, hv).  One step = one 5-minute
+cycle: 10 model steps of 30 s (2 scheme steps each, model error after each model step but
+the last) followed by one two-stage IEWPF analysis.  Truth run and its observations are
+synthesised before the timed region (inputs resident when timing starts).
+
+value = particle-cell-scheme-steps per second over the whole cycle (forecast + analysis):
+  n_particles * nx * ny * 20 * K / elapsed.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# Algorithmic work of one scheme step (both SSP-RK2 stages) per cell: read eta, hu, hv
+# once and write them once (float32).
+BYTES_PER_CELL_STEP = 24.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--particles", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 360 MB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, cells, n_particles=2):
+    """The FP64 oracle on a bounded sample of the workload: n_particles particles of the
+    same grid through one full cycle (10 model steps + analysis with the 225 buoys)."""
+    from oracle import ensemble as oens
+    from oracle import iewpf as oiewpf
+    from oracle import observe as oobs
+    from oracle import philox as ophil
+    sub = cfg.replace(n_particles=n_particles)
+    jet = W.jet_state(sub)
+    ens = np.stack([oens.init_member(sub, jet, 0, i) for i in range(n_particles)])
+    truth = oens.init_member(sub.replace(ensemble_id=0x7FFF), jet, 1, 0)
+    noise = ophil.normals(2 * len(cells), sub.seed, 0, ophil.TAG_OBS, 0x7FFF, 0).reshape(-1, 2)
+    y = oobs.mooring_obs(truth, cells, sub.H, sub.obs_sigma, noise)
+    consts = oiewpf.AnalysisConstants(sub)
+    t0 = time.perf_counter()
+    fc = np.stack([oens.step_member(ens[i], sub, i, 0, 10, noise_on_last=False)
+                   for i in range(n_particles)])
+    oiewpf.analysis(fc, cells, y, sub, 0, consts=consts)
+    dt = time.perf_counter() - t0
+    work = n_particles * sub.nx * sub.ny * sub.n_sub * 10
+    return {"value": work / dt, "unit": "particle-cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_particles} of {cfg.n_particles} particles, one 5-min cycle (10 model "
+                      f"steps x {sub.n_sub} scheme steps + IEWPF analysis, {len(cells)} buoys), "
+                      f"single process, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_1910_01031_amd import Context, abi
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    cfg = W.paper_scale(args.particles)
+    cells = W.buoy_cells(cfg.nx, cfg.ny, 15, 15)
+    n_cycles = args.warmup + args.steps
+    steps_per_cycle = 10
+
+    ctx = Context(cfg, max_obs=len(cells))
+    tcfg = cfg.replace(n_particles=1, ensemble_id=0x7FFF)
+    tctx = Context(tcfg, max_obs=len(cells))
+    base = torch.from_numpy(W.as_f32(W.jet_state(cfg))).to(dev)
+    truth = torch.empty((1, 3, cfg.ny, cfg.nx), dtype=torch.float32, device=dev)
+    ens = torch.empty((cfg.n_particles, 3, cfg.ny, cfg.nx), dtype=torch.float32, device=dev)
+    tctx.init_ensemble(truth, base, stream_index=1)
+    ctx.init_ensemble(ens, base, stream_index=0)
+    obs = []
+    for c in range(n_cycles):
+        tctx.step_ensemble(truth, steps_per_cycle, first_step=c * steps_per_cycle, noise_on_last=True)
+        y = tctx.observe_moorings(truth, cells, analysis_index=c)
+        obs.append(abi.obs_array(cells, y))
+    torch.cuda.synchronize()
+
+    def cycle(c, stats=False):
+        ctx.step_ensemble(ens, steps_per_cycle, first_step=c * steps_per_cycle, noise_on_last=False)
+        return ctx.assimilate(ens, cells, None, analysis_index=c, want_stats=stats, obs=obs[c])
+
+    for c in range(args.warmup):
+        cycle(c)
+    torch.cuda.synchronize()
+
+    # timed region: K whole cycles
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for c in range(args.warmup, n_cycles - 1):
+        cycle(c)
+    last = cycle(n_cycles - 1, stats=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    ms_per_step = ms_total / args.steps
+    work = cfg.n_particles * cfg.nx * cfg.ny * cfg.n_sub * steps_per_cycle
+    value = work * args.steps / (ms_total / 1e3)
+    finite = bool(torch.isfinite(ens).all().item())
+
+    # per-kernel durations: the same cycles again with an event pair around every launch
+    ctx.set_trace(True)
+    for c in range(args.warmup, n_cycles):
+        cycle(c)
+    torch.cuda.synchronize()
+    tr = ctx.trace_read()
+    ctx.set_trace(False)
+    sub_ms = tr["scheme_step"][0] + tr["scheme_step_noise"][0]
+    sub_n = tr["scheme_step"][1] + tr["scheme_step_noise"][1]
+    avg_sub_ms = sub_ms / max(sub_n, 1)
+    analysis_ms = sum(tr[k][0] for k in ("innovation", "rand_dots", "beta_alpha",
+                                         "posterior_coarse", "analysis_update")) / args.steps
+    analysis_ms += tr["soar"][0] / max(tr["soar"][1], 1)  # one of the SOAR launches per cycle
+    bytes_per_launch = BYTES_PER_CELL_STEP * cfg.n_particles * cfg.nx * cfg.ny
+    achieved = bytes_per_launch / (avg_sub_ms / 1e3) / 1e9
+
+    if args.copy_calibration:
+        a = torch.empty(90_000_000, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": "particle-cell-steps/s",
+        "value": value,
+        "unit": "particle-cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 state, f64 weights/alpha/Cholesky",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale IEWPF cycle: 500x300 grid, dx 5 km, 100 particles, "
+                               "225 moored buoys, 10 model steps x 2 scheme steps + 1 analysis",
+                   "nx": cfg.nx, "ny": cfg.ny, "particles": cfg.n_particles,
+                   "buoys": int(len(cells)), "scheme_steps_per_cycle": cfg.n_sub * steps_per_cycle},
+        "iewpf_ms_per_analysis": analysis_ms,
+        "analysis_stats_last": {"beta": last["beta"], "cbar": last["cbar"],
+                                "alpha_min": last["alpha_min"], "alpha_max": last["alpha_max"]},
+        "state_finite": finite,
+        "kernel_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in tr.items()},
+        "roofline": {"bound": "hbm", "kernel": "swe_substep_kernel", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "avg_launch_ms": avg_sub_ms,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, cells)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

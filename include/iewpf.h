@@ -174,6 +174,18 @@ int iewpf_read_buffer(iewpf_ctx* ctx, int which, void* host_out, size_t bytes, v
 /* Window extents (x, y) of the stored pull windows (2r+1 or the folded grid size). */
 int iewpf_window_size(iewpf_ctx* ctx, int32_t* wx, int32_t* wy);
 
+/* Per-kernel timing with HIP events recorded around every launch on the call's stream
+ * (for measurement; off by default).  iewpf_set_trace(ctx, 1) starts a fresh record;
+ * iewpf_trace_read waits for the recorded events and returns, per kernel kind, the total
+ * milliseconds and launch count since the last start.  Kinds: 0 scheme step (both RK
+ * stages), 1 model-error normals, 2 SOAR, 3 geostrophic add (model error / initial state),
+ * 4 innovations, 5 xi/nu draws + dot products, 6 beta/alpha, 7 coarse posterior field,
+ * 8 analysis update pass, 9 scheme step with the model error of its model step fused in.
+ * n_kinds <= 16.  At most 8192 launches are recorded; later
+ * launches are not timed. */
+int iewpf_set_trace(iewpf_ctx* ctx, int on);
+int iewpf_trace_read(iewpf_ctx* ctx, double* ms_out, int32_t* count_out, int n_kinds);
+
 const char* iewpf_last_error(void);
 
 #ifdef __cplusplus

@@ -29,7 +29,10 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_perturb", "iewpf_assimilate", "iewpf_particle_scalars",
             "iewpf_observe_moorings", "iewpf_forecast_drifters", "iewpf_advect_drifters",
             "iewpf_resample", "iewpf_check_cfl", "iewpf_read_buffer", "iewpf_window_size",
-            "iewpf_last_error")
+            "iewpf_set_trace", "iewpf_trace_read", "iewpf_last_error")
+
+TRACE_KINDS = ("scheme_step", "me_normals", "soar", "gb_add", "innovation", "rand_dots",
+               "beta_alpha", "posterior_coarse", "analysis_update", "scheme_step_noise")
 
 
 class IewpfConfig(ctypes.Structure):
@@ -90,6 +93,8 @@ def load(path: str = LIB_PATH):
     lib.iewpf_read_buffer.argtypes = [vp, i32, vp, ctypes.c_size_t, vp]
     lib.iewpf_window_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32)]
+    lib.iewpf_set_trace.argtypes = [vp, i32]
+    lib.iewpf_trace_read.argtypes = [vp, f64p, vp, i32]
     lib.iewpf_last_error.restype = ctypes.c_char_p
     lib.iewpf_last_error.argtypes = []
     for name in EXPORTED:
@@ -224,6 +229,17 @@ class Context:
         if rc not in (0, IEWPF_E_CFL):
             _check(rc)
         return dt.value, rc == 0
+
+    def set_trace(self, on: bool):
+        _check(load().iewpf_set_trace(self.h, int(on)))
+
+    def trace_read(self):
+        """{kind: (total_ms, launches)} since the last set_trace(True)."""
+        n = len(TRACE_KINDS)
+        ms = np.zeros(n)
+        cnt = np.zeros(n, dtype=np.int32)
+        _check(load().iewpf_trace_read(self.h, ms.ctypes.data, cnt.ctypes.data, n))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(TRACE_KINDS)}
 
     def window_size(self):
         wx, wy = ctypes.c_int32(), ctypes.c_int32()

@@ -269,20 +269,25 @@ __global__ __launch_bounds__(kThreads) void posterior_coarse_kernel(
     return sb * (nv - a * xv) + sa * xv;
   };
   double acc = r_at(p);
-  const int b = p / C.nrx, av = p - b * C.nrx;
-  (void)b;
-  (void)av;
   for (int t = pt_off[p]; t < pt_off[p + 1]; ++t) {
     const int e = pt_ent[t];
     const int o = e >> 8, row = e & 255;
     const int ao = cells[2 * o] / C.c, bo = cells[2 * o + 1] / C.c;
     const float* drow = dmat + row * kBlockN;
-    double s = 0.0;
-    for (int q = 0; q < kBlockN; ++q) {
-      const int dk = q / 7 - 3, dj = q % 7 - 3;
-      const int pq = wrapi(bo + dk, C.nry) * C.nrx + wrapi(ao + dj, C.nrx);
-      s += (double)drow[q] * r_at(pq);
+    int rb[7], ca[7];
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+      int y = bo + d - 3, x = ao + d - 3;  // in [-3, n + 3), n >= 7
+      y = y < 0 ? y + C.nry : (y >= C.nry ? y - C.nry : y);
+      x = x < 0 ? x + C.nrx : (x >= C.nrx ? x - C.nrx : x);
+      rb[d] = y * C.nrx;
+      ca[d] = x;
     }
+    double s = 0.0;
+#pragma unroll
+    for (int dk = 0; dk < 7; ++dk)
+#pragma unroll
+      for (int dj = 0; dj < 7; ++dj) s += (double)drow[dk * 7 + dj] * r_at(rb[dk] + ca[dj]);
     acc += s;
   }
   rout[(size_t)i * nr + p] = static_cast<float>(acc);

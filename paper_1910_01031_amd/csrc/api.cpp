@@ -27,6 +27,35 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+int trace_begin(iewpf_ctx* c, int kind, hipStream_t s) {
+  if (!c->trace || c->n_trace >= kTraceMax) return -1;
+  const int slot = c->n_trace++;
+  c->trace_kind[slot] = kind;
+  (void)hipEventRecord(c->trace_ev[2 * slot], s);
+  return slot;
+}
+
+void trace_end(iewpf_ctx* c, int slot, hipStream_t s) {
+  if (slot >= 0) (void)hipEventRecord(c->trace_ev[2 * slot + 1], s);
+}
+
+int choose_row_strips(int columns, int ny, int slots, int halo_rows, int min_rows) {
+  int best = 1;
+  double best_cost = 1e300;
+  const int max_strips = std::max(1, ny / std::max(1, min_rows));
+  for (int n = 1; n <= max_strips; ++n) {
+    const long long waves = (long long)columns * n;
+    const long long rounds = (waves + slots - 1) / slots;
+    const int rows = (ny + n - 1) / n + halo_rows;
+    const double cost = (double)rounds * rows;
+    if (cost < best_cost - 1e-9) {
+      best_cost = cost;
+      best = n;
+    }
+  }
+  return best;
+}
+
 namespace {
 
 constexpr uint32_t kTagModelError = 1;
@@ -59,6 +88,12 @@ void free_ctx(iewpf_ctx* c) {
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->h_small) (void)hipHostFree(c->h_small);
   if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
+  if (c->trace_ev) {
+    for (int i = 0; i < 2 * kTraceMax; ++i)
+      if (c->trace_ev[i]) (void)hipEventDestroy(c->trace_ev[i]);
+    delete[] c->trace_ev;
+  }
+  delete[] c->trace_kind;
   delete c;
 }
 
@@ -89,6 +124,14 @@ StageLayout stage_layout(const iewpf_ctx& c) {
   return L;
 }
 
+int device_slots(int waves_per_cu) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  return cus * waves_per_cu;
+}
+
 int wait_stage(iewpf_ctx* c) {
   if (c->stage_pending) {
     IEWPF_HIP_TRY(hipEventSynchronize(c->stage_ev));
@@ -106,21 +149,42 @@ int check_cells(const iewpf_ctx* c, const int32_t* cells, int n) {
   return 0;
 }
 
+// psi += Q^{1/2} xi for every particle, xi from stream (step, model-error tag).
+void add_noise(iewpf_ctx* c, float* psi, uint64_t step, hipStream_t s) {
+  {
+    TraceScope t(c, kTrNormals, s);
+    launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, step, kTagModelError, c->cfg.ensemble_id, s);
+  }
+  {
+    TraceScope t(c, kTrSoar, s);
+    launch_soar(c->cc, c->soar_me_f, c->ne, c->xi, c->coarse, s);
+  }
+  TraceScope t(c, kTrGbAdd, s);
+  launch_gb_add(c->cc, c->ne, c->coarse, nullptr, psi, c->upd_strip_h, s);
+}
+
 int model_steps(iewpf_ctx* c, float* state, int n_steps, uint64_t first_step, int noise_on_last,
                 hipStream_t s) {
   float* cur = state;
   float* other = c->scratch;
   for (int st = 0; st < n_steps; ++st) {
-    for (int sub = 0; sub < c->cfg.n_sub; ++sub) {
-      launch_swe_substep(c->swe, c->ne, cur, other, s);
-      std::swap(cur, other);
-    }
     const bool noise = (st < n_steps - 1) || noise_on_last;
-    if (noise) {
-      launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, first_step + st, kTagModelError,
-                     c->cfg.ensemble_id, s);
+    if (noise) {  // coarse field z = SOAR xi, added by the last scheme step of this model step
+      {
+        TraceScope t(c, kTrNormals, s);
+        launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, first_step + st, kTagModelError,
+                       c->cfg.ensemble_id, s);
+      }
+      TraceScope t(c, kTrSoar, s);
       launch_soar(c->cc, c->soar_me_f, c->ne, c->xi, c->coarse, s);
-      launch_gb_add(c->cc, c->ne, c->coarse, nullptr, cur, c->upd_strip_h, s);
+    }
+    for (int sub = 0; sub < c->cfg.n_sub; ++sub) {
+      const bool fuse = noise && sub == c->cfg.n_sub - 1;
+      {
+        TraceScope t(c, fuse ? kTrSubstepNoise : kTrSubstep, s);
+        launch_swe_substep(c->swe, c->ne, cur, other, fuse ? c->coarse : nullptr, s);
+      }
+      std::swap(cur, other);
     }
   }
   if (cur != state)
@@ -138,6 +202,39 @@ using namespace iewpf;
 extern "C" {
 
 const char* iewpf_last_error(void) { return g_last_error.c_str(); }
+
+int iewpf_set_trace(iewpf_ctx* c, int on) {
+  if (!c) return fail(IEWPF_E_ARG, "NULL argument");
+  if (on && !c->trace_ev) {
+    c->trace_ev = new hipEvent_t[2 * kTraceMax]();
+    c->trace_kind = new int[kTraceMax]();
+    for (int i = 0; i < 2 * kTraceMax; ++i)
+      IEWPF_HIP_TRY(hipEventCreate(&c->trace_ev[i]));
+  }
+  c->trace = on != 0;
+  c->n_trace = 0;
+  return 0;
+}
+
+int iewpf_trace_read(iewpf_ctx* c, double* ms_out, int32_t* count_out, int n_kinds) {
+  if (!c || !ms_out || !count_out || n_kinds < 0 || n_kinds > 16)
+    return fail(IEWPF_E_ARG, "invalid argument");
+  for (int k = 0; k < n_kinds; ++k) {
+    ms_out[k] = 0.0;
+    count_out[k] = 0;
+  }
+  for (int i = 0; i < c->n_trace; ++i) {
+    IEWPF_HIP_TRY(hipEventSynchronize(c->trace_ev[2 * i + 1]));
+    float ms = 0.0f;
+    IEWPF_HIP_TRY(hipEventElapsedTime(&ms, c->trace_ev[2 * i], c->trace_ev[2 * i + 1]));
+    const int k = c->trace_kind[i];
+    if (k < n_kinds) {
+      ms_out[k] += ms;
+      count_out[k] += 1;
+    }
+  }
+  return 0;
+}
 
 int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   if (!cfg || !out) return fail(IEWPF_E_ARG, "NULL argument");
@@ -179,9 +276,17 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   SweConst& S = c->swe;
   S.nx = f.nx;
   S.ny = f.ny;
-  S.strip_h = std::max(4, env_int("IEWPF_SWE_STRIP", 32));
   S.n_strip_x = (f.nx + kSweOut - 1) / kSweOut;
-  S.n_strip_y = (f.ny + S.strip_h - 1) / S.strip_h;
+  {
+    // rows per wave strip: fit the waves of all particles to the resident wave slots
+    // (each wave marches strip_h + 8 rows of stage 1 and strip_h + 4 of stage 2)
+    const int forced = env_int("IEWPF_SWE_STRIP", 0);
+    const int n_ys = forced > 0 ? (f.ny + forced - 1) / forced
+                                : choose_row_strips(S.n_strip_x * f.n_particles, f.ny,
+                                                    device_slots(swe_waves_per_cu()), 6, 8);
+    S.strip_h = (f.ny + n_ys - 1) / n_ys;
+    S.n_strip_y = (f.ny + S.strip_h - 1) / S.strip_h;
+  }
   S.H = (float)f.H;
   S.g = (float)f.g;
   S.inv2g = (float)(1.0 / (2.0 * f.g));
@@ -194,6 +299,11 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   S.dt = (float)(f.dt / f.n_sub);
   S.idx = (float)(1.0 / f.dx);
   S.idy = (float)(1.0 / f.dy);
+  S.c = c->c;
+  S.nrx = c->nrx;
+  S.nry = c->nry;
+  S.gb_x = (float)(f.g * f.H / (2.0 * f.f * f.dx));
+  S.gb_y = (float)(f.g * f.H / (2.0 * f.f * f.dy));
   c->cc.nx = f.nx;
   c->cc.ny = f.ny;
   c->cc.c = c->c;
@@ -219,7 +329,15 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
     free_ctx(c);
     return fail(IEWPF_E_ARG, "coarse H Q H^T + R is not positive definite");
   }
-  c->upd_strip_h = std::max(2, env_int("IEWPF_UPD_STRIP", 16));
+  {
+    const int forced = env_int("IEWPF_UPD_STRIP", 0);
+    const int groups = (c->ne + update_particle_group() - 1) / update_particle_group();
+    const int nsx = (f.nx + kGbOut - 1) / kGbOut;
+    const int n_ys = forced > 0 ? (f.ny + forced - 1) / forced
+                                : choose_row_strips(nsx * groups, f.ny,
+                                                    device_slots(update_waves_per_cu()), 2, 4);
+    c->upd_strip_h = (f.ny + n_ys - 1) / n_ys;
+  }
   c->n_upd_strips = ((f.nx + kGbOut - 1) / kGbOut) * ((f.ny + c->upd_strip_h - 1) / c->upd_strip_h);
 
   int rc = 0;
@@ -310,10 +428,7 @@ int iewpf_step_ensemble(iewpf_ctx* c, float* state, int n_model_steps, uint64_t 
 int iewpf_perturb(iewpf_ctx* c, float* state, uint64_t step_index, void* stream) {
   if (!c || !state) return fail(IEWPF_E_ARG, "NULL argument");
   hipStream_t s = as_stream(stream);
-  launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, step_index, kTagModelError, c->cfg.ensemble_id,
-                 s);
-  launch_soar(c->cc, c->soar_me_f, c->ne, c->xi, c->coarse, s);
-  launch_gb_add(c->cc, c->ne, c->coarse, nullptr, state, c->upd_strip_h, s);
+  add_noise(c, state, step_index, s);
   IEWPF_HIP_TRY(hipGetLastError());
   return 0;
 }
@@ -398,17 +513,32 @@ int iewpf_assimilate(iewpf_ctx* c, float* state, const iewpf_obs* obs, int n_obs
   c->last_n_obs = n_obs;
 
   // stages 1-2: innovations, S d, c_i
-  launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, c->S, state, c->obs_cells,
-                    c->obs_y, c->sd, c->cval, s);
+  {
+    TraceScope tr(c, kTrInnov, s);
+    launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, c->S, state,
+                      c->obs_cells, c->obs_y, c->sd, c->cval, s);
+  }
   // stage 3: xi, nu~ and their dot products
-  launch_rand_dots(c->ne, c->nr, c->cfg.seed, analysis_index, c->cfg.ensemble_id, c->xi, c->nu,
-                   c->dots, s);
+  {
+    TraceScope tr(c, kTrRandDots, s);
+    launch_rand_dots(c->ne, c->nr, c->cfg.seed, analysis_index, c->cfg.ensemble_id, c->xi, c->nu,
+                     c->dots, s);
+  }
   // stages 4-5: cbar, beta, c*, alpha (the one ensemble-wide step)
-  launch_sync(c->ne, c->n_psi, (double)c->nr, c->cval, c->dots, c->alpha, c->cstar, c->scal, s);
+  {
+    TraceScope tr(c, kTrSync, s);
+    launch_sync(c->ne, c->n_psi, (double)c->nr, c->cval, c->dots, c->alpha, c->cstar, c->scal, s);
+  }
   // stage 6: r' on the coarse grid, SOAR, then one fused pass over the state
-  launch_posterior_coarse(c->cc, c->ne, c->xi, c->nu, c->dots, c->alpha, c->scal, c->dmat,
-                          c->pt_off, c->pt_ent, c->obs_cells, c->coarse2, s);
-  launch_soar(c->cc, c->soar_me_f, c->ne, c->coarse2, c->coarse, s);
+  {
+    TraceScope tr(c, kTrPosterior, s);
+    launch_posterior_coarse(c->cc, c->ne, c->xi, c->nu, c->dots, c->alpha, c->scal, c->dmat,
+                            c->pt_off, c->pt_ent, c->obs_cells, c->coarse2, s);
+  }
+  {
+    TraceScope tr(c, kTrSoar, s);
+    launch_soar(c->cc, c->soar_me_f, c->ne, c->coarse2, c->coarse, s);
+  }
   PullConst P;
   P.wx = c->wx;
   P.wy = c->wy;
@@ -418,8 +548,11 @@ int iewpf_assimilate(iewpf_ctx* c, float* state, const iewpf_obs* obs, int n_obs
   P.strip_h = c->upd_strip_h;
   P.n_strip_x = nsx;
   P.n_strip_y = nsy;
-  launch_analysis_update(c->cc, P, c->ne, c->coarse, c->windows, c->sd, c->max_obs, c->obs_cells,
+  {
+    TraceScope tr(c, kTrUpdate, s);
+    launch_analysis_update(c->cc, P, c->ne, c->coarse, c->windows, c->sd, c->max_obs, c->obs_cells,
                          c->st_off, c->st_ent, state, s);
+  }
   IEWPF_HIP_TRY(hipGetLastError());
   if (stats_out) {
     IEWPF_HIP_TRY(hipMemcpyAsync(c->h_small, c->scal, sizeof(double) * 8, hipMemcpyDeviceToHost, s));

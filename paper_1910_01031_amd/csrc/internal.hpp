@@ -35,6 +35,9 @@ struct SweConst {
   float fdx, fdy;      // f dx, f dy
   float theta;
   float dt, idx, idy;  // scheme step, 1/dx, 1/dy
+  // fused model error (last scheme step of a model step)
+  int c, nrx, nry;     // coarsening and coarse grid
+  float gb_x, gb_y;    // g H / (2 f dx), g H / (2 f dy)
 };
 
 // Coarse random grid and covariance stencils.
@@ -111,7 +114,30 @@ struct iewpf_ctx {
   bool stage_pending = false;
   double* h_small = nullptr;     // small pinned readback buffer
   int last_n_obs = 0;
+  // optional per-launch event trace
+  bool trace = false;
+  int n_trace = 0;
+  hipEvent_t* trace_ev = nullptr;   // [2 * kTraceMax]
+  int* trace_kind = nullptr;        // [kTraceMax]
 };
+
+namespace iewpf {
+constexpr int kTraceMax = 8192;
+enum TraceKind {
+  kTrSubstep = 0, kTrNormals, kTrSoar, kTrGbAdd, kTrInnov, kTrRandDots, kTrSync,
+  kTrPosterior, kTrUpdate, kTrSubstepNoise, kTrKinds
+};
+// Records a start event (returns the slot or -1) and the matching stop event.
+int trace_begin(iewpf_ctx* c, int kind, hipStream_t s);
+void trace_end(iewpf_ctx* c, int slot, hipStream_t s);
+struct TraceScope {
+  iewpf_ctx* c;
+  int slot;
+  hipStream_t s;
+  TraceScope(iewpf_ctx* c_, int kind, hipStream_t s_) : c(c_), slot(trace_begin(c_, kind, s_)), s(s_) {}
+  ~TraceScope() { trace_end(c, slot, s); }
+};
+}  // namespace iewpf
 
 // ---- host precompute (host_precompute.cpp) ----------------------------------------------
 namespace iewpf {
@@ -126,7 +152,17 @@ int inverse_spd2(const double A[4], double out[4]);
 
 // ---- launchers (kernels in *.hip) ---------------------------------------------------------
 namespace iewpf {
-void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, hipStream_t s);
+// resident waves per compute unit of the stencil / analysis-update kernels (occupancy)
+int swe_waves_per_cu();
+int update_waves_per_cu();
+int update_particle_group();
+// Number of row strips for a wave-per-strip kernel: minimises (launch rounds) x (rows a
+// wave marches), rounds = ceil(columns * n_strips / slots), rows = ceil(ny / n_strips) +
+// halo_rows.  columns = strips per row of strips (all particles).
+int choose_row_strips(int columns, int ny, int slots, int halo_rows, int min_rows);
+// z != nullptr: also add the model error Q_GB I_Omega z (z: [ne][nry][nrx] SOAR field)
+void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, const float* z,
+                        hipStream_t s);
 void launch_normals(float* out, int n, int ne, uint64_t seed, uint64_t step, uint32_t tag,
                     uint32_t ens, hipStream_t s);
 void launch_soar(const CoarseConst& C, const float* w25, int ne, const float* in, float* out,

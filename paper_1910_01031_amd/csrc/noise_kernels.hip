@@ -17,6 +17,8 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;
 }
+// i in [-n, 2n)
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 __device__ __forceinline__ int floordiv(int a, int b) {  // b > 0
   const int q = a / b;
   return (a % b != 0 && a < 0) ? q - 1 : q;
@@ -60,9 +62,9 @@ __global__ __launch_bounds__(256) void soar_kernel(const float* __restrict__ in,
   float acc = 0.0f;
 #pragma unroll
   for (int q = -2; q <= 2; ++q) {
-    const float* row = src + (size_t)wrapi(b + q, nry) * nrx;
+    const float* row = src + (size_t)wrap1(b + q, nry) * nrx;
 #pragma unroll
-    for (int pp = -2; pp <= 2; ++pp) acc += W.w[(q + 2) * 5 + (pp + 2)] * row[wrapi(a + pp, nrx)];
+    for (int pp = -2; pp <= 2; ++pp) acc += W.w[(q + 2) * 5 + (pp + 2)] * row[wrap1(a + pp, nrx)];
   }
   out[(size_t)particle * nr + p] = acc;
 }
@@ -78,7 +80,7 @@ __device__ __forceinline__ float bicubic_at(const float* __restrict__ z, const C
   float acc = 0.0f;
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
-    const float* row = z + (size_t)wrapi(by + n - 1, C.nry) * C.nrx;
+    const float* row = z + (size_t)wrap1(by + n - 1, C.nry) * C.nrx;
     const float rv = wx[0] * row[cx[0]] + wx[1] * row[cx[1]] + wx[2] * row[cx[2]] + wx[3] * row[cx[3]];
     acc += wy[n] * rv;
   }
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, PullConst P,
     const int bx = floordiv(num, 2 * C.c);
     cr4(static_cast<float>(num - 2 * C.c * bx) / static_cast<float>(2 * C.c), wx);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) cx[m] = wrapi(bx + m - 1, C.nrx);
+    for (int m = 0; m < 4; ++m) cx[m] = wrap1(bx + m - 1, C.nrx);
   }
   const int k0 = sy * strip_h;
   const int k_end = min(k0 + strip_h, ny);
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, PullConst P,
     o_end = st_off[strip + 1];
   }
   for (int m = k0 - 1; m <= k_end; ++m) {
-    const float d0 = bicubic_at(z, C, cx, wx, wrapi(m, ny));
+    const float d0 = bicubic_at(z, C, cx, wx, wrap1(m, ny));
     if (m >= k0 + 1) {
       const int k = m - 1;
       const float de = dm1;
@@ -186,6 +188,129 @@ __global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, PullConst P,
   }
 }
 
+// Analysis update, one fused pass over the state (eq. optUpdateEquationTwoStage with the
+// pull of eq. detailedOPDUpdate): psi += sum_o (s_u,o W_u + s_v,o W_v)(x - x_o) + Q_GB I_Omega z
+// for kPB particles per wave, so every window value fetched from cache serves kPB
+// particles.  W_u, W_v: precomputed responses to the unit vectors (stored windows); the
+// observation list of the strip comes from the host; the row window test is wave-uniform.
+constexpr int kPB = 4;
+
+__global__ __launch_bounds__(256) void analysis_update_kernel(
+    CoarseConst C, PullConst P, int ne, int total_waves, const float* __restrict__ zall,
+    float* __restrict__ psi, const float* __restrict__ windows, const double* __restrict__ sd,
+    int max_obs, const int32_t* __restrict__ cells, const int32_t* __restrict__ st_off,
+    const int32_t* __restrict__ st_ent) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  if (wave >= total_waves) return;
+  const int per_group = P.n_strip_x * P.n_strip_y;
+  const int group = wave / per_group;
+  const int strip = wave - group * per_group;
+  const int sy = strip / P.n_strip_x;
+  const int sx = strip - sy * P.n_strip_x;
+  const int p0 = group * kPB;
+  const int np = min(kPB, ne - p0);
+  const int nx = C.nx, ny = C.ny;
+  const size_t ncell = (size_t)nx * ny;
+  const size_t plane = (size_t)P.wx * P.wy;
+
+  const int j = sx * kGbOut + lane - kGbHalo;
+  const int jw = wrapi(j, nx);
+  const bool writer = lane >= kGbHalo && lane < kWave - kGbHalo && j < nx;
+  int cx[4];
+  float wx[4];
+  {
+    const int num = 2 * jw + 1 - C.c;
+    const int bx = floordiv(num, 2 * C.c);
+    cr4(static_cast<float>(num - 2 * C.c * bx) / static_cast<float>(2 * C.c), wx);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) cx[m] = wrap1(bx + m - 1, C.nrx);
+  }
+  const int k0 = sy * P.strip_h;
+  const int k_end = min(k0 + P.strip_h, ny);
+  const int o_beg = st_off[strip], o_end = st_off[strip + 1];
+  float dm2[kPB], dm1[kPB];
+#pragma unroll
+  for (int p = 0; p < kPB; ++p) dm2[p] = dm1[p] = 0.0f;
+  for (int m = k0 - 1; m <= k_end; ++m) {
+    float d0[kPB];
+#pragma unroll
+    for (int p = 0; p < kPB; ++p)
+      d0[p] = p < np ? bicubic_at(zall + (size_t)(p0 + p) * C.nrx * C.nry, C, cx, wx, wrap1(m, ny))
+                     : 0.0f;
+    if (m >= k0 + 1) {
+      const int k = m - 1;
+      float ae[kPB], au[kPB], av[kPB];
+#pragma unroll
+      for (int p = 0; p < kPB; ++p) {
+        ae[p] = dm1[p];
+        au[p] = -C.gb_y * (d0[p] - dm2[p]);
+        av[p] = C.gb_x * (__shfl_down(dm1[p], 1, kWave) - __shfl_up(dm1[p], 1, kWave));
+      }
+      for (int t = o_beg; t < o_end; ++t) {
+        const int o = st_ent[t];
+        const int jo = cells[2 * o], ko = cells[2 * o + 1];
+        int iy;
+        if (P.ry >= 0) {
+          int dk = k - ko;
+          dk = dk > ny / 2 ? dk - ny : (dk < -(ny / 2) ? dk + ny : dk);
+          if (dk < -P.ry || dk > P.ry) continue;  // the same for the whole wave
+          iy = dk + P.ry;
+        } else {
+          iy = wrapi(k - ko, ny);
+        }
+        int ix;
+        bool in = true;
+        if (P.rx >= 0) {
+          int dj = j - jo;
+          dj = dj > nx / 2 ? dj - nx : (dj < -(nx / 2) ? dj + nx : dj);
+          in = dj >= -P.rx && dj <= P.rx;
+          ix = in ? dj + P.rx : 0;
+        } else {
+          ix = wrapi(j - jo, nx);
+        }
+        const size_t idx = (size_t)iy * P.wx + ix;
+        float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, w4 = 0.f, w5 = 0.f;
+        if (in) {
+          w0 = windows[idx];
+          w1 = windows[plane + idx];
+          w2 = windows[2 * plane + idx];
+          w3 = windows[3 * plane + idx];
+          w4 = windows[4 * plane + idx];
+          w5 = windows[5 * plane + idx];
+        }
+#pragma unroll
+        for (int p = 0; p < kPB; ++p) {
+          if (p < np) {
+            const double* s2 = sd + ((size_t)(p0 + p) * max_obs + o) * 2;
+            const float su = static_cast<float>(s2[0]), sv = static_cast<float>(s2[1]);
+            ae[p] += su * w0 + sv * w3;
+            au[p] += su * w1 + sv * w4;
+            av[p] += su * w2 + sv * w5;
+          }
+        }
+      }
+      if (writer) {
+#pragma unroll
+        for (int p = 0; p < kPB; ++p) {
+          if (p < np) {
+            float* E = psi + (size_t)(p0 + p) * 3 * ncell;
+            const size_t off = (size_t)k * nx + j;
+            E[off] += ae[p];
+            E[ncell + off] += au[p];
+            E[2 * ncell + off] += av[p];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < kPB; ++p) {
+      dm2[p] = dm1[p];
+      dm1[p] = d0[p];
+    }
+  }
+}
+
 }  // namespace
 
 void launch_normals(float* out, int n, int ne, uint64_t seed, uint64_t step, uint32_t tag,
@@ -215,14 +340,23 @@ void launch_gb_add(const CoarseConst& C, int ne, const float* z, const float* ba
                      nullptr);
 }
 
+int update_waves_per_cu() {
+  int a = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, analysis_update_kernel, 256, 0) != hipSuccess)
+    return 16;
+  return 4 * (a > 0 ? a : 1);
+}
+
+int update_particle_group() { return kPB; }
+
 void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, const float* z,
                             const float* windows, const double* sd, int max_obs,
                             const int32_t* obs_cells, const int32_t* st_off,
                             const int32_t* st_ent, float* psi, hipStream_t s) {
-  const int total = ne * P.n_strip_x * P.n_strip_y;
-  hipLaunchKernelGGL(gb_add_kernel<true>, dim3((total + 3) / 4), dim3(256), 0, s, C, P, P.strip_h,
-                     P.n_strip_x, P.n_strip_y, total, z, nullptr, psi, windows, sd, max_obs,
-                     obs_cells, st_off, st_ent);
+  const int groups = (ne + kPB - 1) / kPB;
+  const int total = groups * P.n_strip_x * P.n_strip_y;
+  hipLaunchKernelGGL(analysis_update_kernel, dim3((total + 3) / 4), dim3(256), 0, s, C, P, ne, total,
+                     z, psi, windows, sd, max_obs, obs_cells, st_off, st_ent);
 }
 
 }  // namespace iewpf

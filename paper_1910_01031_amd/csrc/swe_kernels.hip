@@ -16,26 +16,38 @@
 // wave; the intermediate psi* never leaves registers.  Each stage consumes two lanes per
 // side, leaving 56 output columns per wave.  HBM traffic per scheme step: one read and
 // one write of the state (24 B per cell) plus the strip halo rows.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace iewpf {
 namespace {
 
+// Cross-lane moves by one lane inside the wave64; lanes at the wave ends are never written
+// back.  ds_bpermute is the default: the DPP wave shifts measured slower on gfx950.
+#ifdef IEWPF_XLANE_DPP
 __device__ __forceinline__ float lane_prev(float x) {  // value held by lane - 1
-  return __shfl_up(x, 1, kWave);
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x138 /* wave_shr:1 */, 0xF,
+                                                 0xF, true));
 }
 __device__ __forceinline__ float lane_next(float x) {  // value held by lane + 1
-  return __shfl_down(x, 1, kWave);
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x130 /* wave_shl:1 */, 0xF,
+                                                 0xF, true));
 }
+#else
+__device__ __forceinline__ float lane_prev(float x) { return __shfl_up(x, 1, kWave); }
+__device__ __forceinline__ float lane_next(float x) { return __shfl_down(x, 1, kWave); }
+#endif
 
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float sqrtf_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Generalized minmod of three slopes.
+// (min if all three are positive, max if all are negative, else 0) = max(lo, 0) + min(hi, 0)
 __device__ __forceinline__ float minmod3(float a, float b, float c) {
   const float lo = fminf(a, fminf(b, c));
   const float hi = fmaxf(a, fmaxf(b, c));
-  return lo > 0.0f ? lo : (hi < 0.0f ? hi : 0.0f);
+  return fmaxf(lo, 0.0f) + fminf(hi, 0.0f);
 }
 
 __device__ __forceinline__ float limited(float qm, float q0, float qp, float theta) {
@@ -145,10 +157,70 @@ __device__ __forceinline__ int wrap(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;
 }
+// i in [-n, 2n)
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-__global__ __launch_bounds__(256) void swe_substep_kernel(const float* __restrict__ in,
-                                                          float* __restrict__ out, SweConst C,
-                                                          int total_waves) {
+__device__ __forceinline__ void cr_weights(float t, float w[4]) {
+  const float t2 = t * t, t3 = t2 * t;
+  w[0] = 0.5f * (-t3 + 2.0f * t2 - t);
+  w[1] = 0.5f * (3.0f * t3 - 5.0f * t2 + 2.0f);
+  w[2] = 0.5f * (-3.0f * t3 + 4.0f * t2 + t);
+  w[3] = 0.5f * (t3 - t2);
+}
+
+// Model-error interpolation I_Omega of the coarse field z down the rows of a strip.  Each
+// lane keeps the x-interpolated values of the four coarse rows around the current fine
+// row; the window advances by one coarse row every c fine rows (the only loads), and a
+// fine row costs one 4-tap interpolation in y.  Coarse point b sits at (b + 1/2) c dy.
+struct CoarseRows {
+  int cx[4];
+  float wx[4];
+  float xr[4];   // x-interpolated coarse rows by-1 .. by+2
+  int by;        // base coarse row of the current window
+
+  __device__ __forceinline__ float xrow(const float* __restrict__ z, const SweConst& C, int b) const {
+    const float* row = z + (size_t)wrap1(b, C.nry) * C.nrx;
+    return wx[0] * row[cx[0]] + wx[1] * row[cx[1]] + wx[2] * row[cx[2]] + wx[3] * row[cx[3]];
+  }
+  __device__ __forceinline__ void init(const float* __restrict__ z, const SweConst& C, int jw,
+                                       int s) {
+    const int num = 2 * jw + 1 - C.c;
+    const int bx = (num >= 0 ? num : num - 2 * C.c + 1) / (2 * C.c);
+    cr_weights(static_cast<float>(num - 2 * C.c * bx) / static_cast<float>(2 * C.c), wx);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) cx[m] = wrap1(bx + m - 1, C.nrx);
+    const int ns = 2 * s + 1 - C.c;
+    by = (ns >= 0 ? ns : ns - 2 * C.c + 1) / (2 * C.c);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) xr[n] = xrow(z, C, by + n - 1);
+  }
+  // value at fine row s (unwrapped, non-decreasing between calls, s - previous s <= c)
+  __device__ __forceinline__ float at(const float* __restrict__ z, const SweConst& C, int s) {
+    const int ns = 2 * s + 1 - C.c;
+    const int b = (ns >= 0 ? ns : ns - 2 * C.c + 1) / (2 * C.c);
+    if (b != by) {  // wave-uniform: advance the window by one coarse row
+      xr[0] = xr[1];
+      xr[1] = xr[2];
+      xr[2] = xr[3];
+      xr[3] = xrow(z, C, b + 2);
+      by = b;
+    }
+    float wy[4];
+    cr_weights(static_cast<float>(ns - 2 * C.c * b) / static_cast<float>(2 * C.c), wy);
+    return wy[0] * xr[0] + wy[1] * xr[1] + wy[2] * xr[2] + wy[3] * xr[3];
+  }
+};
+
+// One scheme step of every particle.  NOISE: also add the model error Q_GB I_Omega z to the
+// output (z = SOAR xi on the coarse grid, one [nry][nrx] field per particle).
+#ifndef IEWPF_SWE_MIN_BLOCKS
+#define IEWPF_SWE_MIN_BLOCKS 1
+#endif
+template <bool NOISE>
+__global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_substep_kernel(const float* __restrict__ in,
+                                                          float* __restrict__ out,
+                                                          const float* __restrict__ zall,
+                                                          SweConst C, int total_waves) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
   if (wave >= total_waves) return;  // whole wave exits together
@@ -171,50 +243,88 @@ __global__ __launch_bounds__(256) void swe_substep_kernel(const float* __restric
   const bool writer = lane >= kSweHalo && lane < kWave - kSweHalo && j < nx;
   const int k0 = sy * C.strip_h;
   const int k_end = min(k0 + C.strip_h, ny);  // exclusive
-  const int m_first = k0 - 4, m_last = k_end + 3;
+
+  const float* z = nullptr;
+  CoarseRows cr;
+  if (NOISE) {
+    z = zall + (size_t)particle * C.nrx * C.nry;
+    cr.init(z, C, jw, k0 - 1);  // first model-error row needed: k0 - 1
+  }
 
   StagePipe s1 = {}, s2 = {};
-  // psi^n ring for the stage-2 combination: rows m-4 .. m-1 after a push of row m
+  // psi^n rows m-4 .. m-1 (before the push of row m) for the stage-2 combination
   float pe4 = 0, pq4 = 0, pr4 = 0, pe3 = 0, pq3 = 0, pr3 = 0, pe2 = 0, pq2 = 0, pr2 = 0;
   float pe1 = 0, pq1 = 0, pr1 = 0;
+  float dA = 0.0f, dB = 0.0f;  // model-error d_eta rows m-5, m-4
 
-  size_t off = (size_t)wrap(m_first, ny) * nx + jw;
+  size_t off = (size_t)wrap(k0 - 4, ny) * nx + jw;
   float ne_ = Ein[off], nq_ = Qin[off], nr_ = Rin[off];
-  for (int m = m_first; m <= m_last; ++m) {
+
+  // phase 1 (m = k0-4 .. k0-1): stage 1 only; phase 2 (k0 .. k0+3): both stages, no
+  // output yet; phase 3 (k0+4 .. k_end+3): both stages and row m-4 written.
+  auto step = [&](int m, bool stage2, bool emit) {
     const float e = ne_, q = nq_, r = nr_;
-    if (m < m_last) {  // prefetch the next row
-      const size_t o2 = (size_t)wrap(m + 1, ny) * nx + jw;
-      ne_ = Ein[o2];
-      nq_ = Qin[o2];
-      nr_ = Rin[o2];
-    }
+    const size_t o2 = (size_t)wrap1(m + 1, ny) * nx + jw;  // prefetch the next row
+    ne_ = Ein[o2];
+    nq_ = Qin[o2];
+    nr_ = Rin[o2];
     float se, sq, sr;
-    s1.push(e, q, r, C, se, sq, sr);  // psi* of row m - 2 (valid for m >= k0)
-    // psi^n ring: before the shift p*4 holds row m-4, the row stage 2 emits below
+    s1.push(e, q, r, C, se, sq, sr);  // psi* of row m - 2
     const float qe4 = pe4, qq4 = pq4, qr4 = pr4;
     pe4 = pe3; pq4 = pq3; pr4 = pr3;
     pe3 = pe2; pq3 = pq2; pr3 = pr2;
     pe2 = pe1; pq2 = pq1; pr2 = pr1;
     pe1 = e; pq1 = q; pr1 = r;
-    if (m >= k0) {
+    float dC = 0.0f;
+    if (NOISE && stage2 && m >= k0 + 2) dC = cr.at(z, C, m - 3);  // d_eta row m-3 (>= k0-1)
+    if (stage2) {
       float te, tq, tr;
       s2.push(se, sq, sr, C, te, tq, tr);  // psi* + dt L(psi*) of row m - 4
-      if (m >= k0 + 4 && writer) {
-        const size_t o = (size_t)(m - 4) * nx + j;
-        Eout[o] = 0.5f * (qe4 + te);
-        Qout[o] = 0.5f * (qq4 + tq);
-        Rout[o] = 0.5f * (qr4 + tr);
+      if (emit) {
+        float oe = 0.5f * (qe4 + te), oq = 0.5f * (qq4 + tq), orr = 0.5f * (qr4 + tr);
+        if (NOISE) {
+          oe += dB;
+          oq += -C.gb_y * (dC - dA);
+          orr += C.gb_x * (lane_next(dB) - lane_prev(dB));
+        }
+        if (writer) {
+          const size_t o = (size_t)(m - 4) * nx + j;
+          Eout[o] = oe;
+          Qout[o] = oq;
+          Rout[o] = orr;
+        }
       }
     }
-  }
+    if (NOISE) {
+      dA = dB;
+      dB = dC;
+    }
+  };
+  for (int m = k0 - 4; m < k0; ++m) step(m, false, false);
+  for (int m = k0; m < k0 + 4; ++m) step(m, true, false);
+#pragma unroll 4
+  for (int m = k0 + 4; m <= k_end + 3; ++m) step(m, true, true);
 }
 
 }  // namespace
 
-void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, hipStream_t s) {
+int swe_waves_per_cu() {
+  int a = 0, b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, swe_substep_kernel<true>, 256, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, swe_substep_kernel<false>, 256, 0) != hipSuccess)
+    return 16;
+  return 4 * std::max(1, std::min(a, b));
+}
+
+void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, const float* z,
+                        hipStream_t s) {
   const int total = ne * C.n_strip_x * C.n_strip_y;
   const int blocks = (total + 3) / 4;
-  hipLaunchKernelGGL(swe_substep_kernel, dim3(blocks), dim3(256), 0, s, in, out, C, total);
+  if (z)
+    hipLaunchKernelGGL(swe_substep_kernel<true>, dim3(blocks), dim3(256), 0, s, in, out, z, C, total);
+  else
+    hipLaunchKernelGGL(swe_substep_kernel<false>, dim3(blocks), dim3(256), 0, s, in, out, z, C,
+                       total);
 }
 
 }  // namespace iewpf
