@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--particles", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 360 MB device copy (counter calibration)")
     return ap.parse_args()
@@ -70,6 +71,75 @@ def cpu_baseline(cfg, cells, n_particles=2):
             "sample": f"{n_particles} of {cfg.n_particles} particles, one 5-min cycle (10 model "
                       f"steps x {sub.n_sub} scheme steps + IEWPF analysis, {len(cells)} buoys), "
                       f"single process, {dt:.1f} s"}
+
+
+def batched_leg(torch, dev, steps: int):
+    """Eight ensembles of uneven grids and sizes (500x300 x2, 400x400, ... 128x512; 50-200
+    particles; 30-225 buoys), strips autotuned per ensemble, one cycle = one hipGraph replay
+    (10 model steps + one analysis per ensemble)."""
+    from paper_1910_01031_amd import Batch, Context
+    ctxs, states, cells, ys, strips, work = [], [], [], [], [], 0
+    for cfg, (nbx, nby) in W.batched():
+        cl = W.buoy_cells(cfg.nx, cfg.ny, nbx, nby)
+        ctx = Context(cfg, max_obs=len(cl))
+        base = torch.from_numpy(W.as_f32(W.jet_state(cfg))).to(dev)
+        st = torch.empty((cfg.n_particles, 3, cfg.ny, cfg.nx), dtype=torch.float32, device=dev)
+        ctx.init_ensemble(st, base, stream_index=0)
+        tctx = Context(cfg.replace(n_particles=1, ensemble_id=0x7000 + cfg.ensemble_id),
+                       max_obs=len(cl))
+        truth = torch.empty((1, 3, cfg.ny, cfg.nx), dtype=torch.float32, device=dev)
+        tctx.init_ensemble(truth, base, stream_index=1)
+        ys.append(tctx.observe_moorings(truth, cl, analysis_index=0))
+        tctx.close()
+        strips.append(ctx.autotune(st))
+        ctxs.append(ctx)
+        states.append(st)
+        cells.append(cl)
+        work += cfg.n_particles * cfg.nx * cfg.ny * cfg.n_sub * 10
+    b = Batch(ctxs, states)
+    for e, cl in enumerate(cells):
+        b.set_cells(e, cl)
+    b.cycle(10, 0, 0, ys, use_graph=True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for c in range(1, steps + 1):
+        b.cycle(10, 10 * c, c, ys, use_graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    finite = all(bool(torch.isfinite(st).all().item()) for st in states)
+    out = {"workload": "8 uneven ensembles (850 particles, 945 buoys), one graph per cycle",
+           "ms_per_cycle": ms, "value": work / (ms / 1e3), "unit": "particle-cell-steps/s",
+           "autotuned_strip_rows": strips,
+           "state_finite": finite}
+    b.close()
+    for c in ctxs:
+        c.close()
+    return out
+
+
+def side_legs(torch, dev, ctx, ens, cfg):
+    """Drifter forecast (64 drifters per particle, 10 model steps) and SIR residual
+    resampling on the paper-scale ensemble."""
+    pos0 = np.stack([W.drifter_lattice(cfg, 8, 8) for _ in range(cfg.n_particles)])
+    pos = torch.from_numpy(pos0).to(dev)
+    traj = torch.zeros((11,) + pos.shape, dtype=torch.float64, device=dev)
+    logw = torch.from_numpy(np.random.default_rng(0).normal(size=cfg.n_particles)).to(dev)
+    par = torch.zeros(cfg.n_particles, dtype=torch.int32, device=dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e2 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.forecast_drifters(ens, pos, 10, first_step=100000, traj=traj)
+    e1.record()
+    ctx.resample(ens, logw, analysis_index=100000, parents=par)
+    e2.record()
+    torch.cuda.synchronize()
+    return {"drifter_forecast_ms_per_model_step": e0.elapsed_time(e1) / 10,
+            "drifters": int(pos.shape[0] * pos.shape[1]),
+            "resample_ms": e1.elapsed_time(e2)}
 
 
 def main():
@@ -175,6 +245,9 @@ def main():
                      "traffic": None, "avg_launch_ms": avg_sub_ms,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
+    out["side"] = side_legs(torch, dev, ctx, ens, cfg)
+    if not args.no_batched:
+        out["batched"] = batched_leg(torch, dev, 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, cells)
     print(json.dumps(out), flush=True)

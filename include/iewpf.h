@@ -174,6 +174,80 @@ int iewpf_read_buffer(iewpf_ctx* ctx, int which, void* host_out, size_t bytes, v
 /* Window extents (x, y) of the stored pull windows (2r+1 or the folded grid size). */
 int iewpf_window_size(iewpf_ctx* ctx, int32_t* wx, int32_t* wy);
 
+/* Picks the stencil's rows-per-wave strip by timing candidate heights (16..96) on `state`
+ * (read only; results go to the context's scratch buffer).  Waits for the stream; writes
+ * the chosen height to *strip_out.  Later calls on ctx use it. */
+int iewpf_autotune(iewpf_ctx* ctx, const float* state, int32_t* strip_out, void* stream);
+
+/* ---- several ensembles of uneven grid and size, one launch per scheme step ------------
+ * A batch groups n contexts (same dt and n_sub) and their state buffers.  Every scheme
+ * step of all ensembles is one kernel launch over a device table of (grid, buffers, wave
+ * range) jobs; model error and analysis run per ensemble.  Contexts and states are owned
+ * by the caller and must outlive the batch.  n <= 16. */
+typedef struct iewpf_batch iewpf_batch;
+int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewpf_batch** out);
+void iewpf_batch_destroy(iewpf_batch* b);
+
+/* Fixed observation cells of ensemble e (moorings; host [2*n_obs] of (j, k)): builds and
+ * uploads its index lists once.  Waits for the stream. */
+int iewpf_batch_set_cells(iewpf_batch* b, int e, const int32_t* cells_host, int n_obs,
+                          void* stream);
+
+/* One data-assimilation cycle of every ensemble: n_model_steps model steps (model error
+ * after every step but the last, streams first_step + s), then one IEWPF analysis per
+ * ensemble (stream analysis_index) with observation values y_host[e] (host float64
+ * [n_obs_e][2] for the cells set above).  use_graph != 0: the first call captures the whole
+ * cycle into one hipGraph (on an internal stream ordered after `stream`) and later calls
+ * replay it; the step and analysis indices are then read from device memory and y is
+ * copied in before each replay.  A different n_model_steps recaptures. */
+int iewpf_batch_cycle(iewpf_batch* b, int n_model_steps, uint64_t first_step,
+                      uint64_t analysis_index, const double* const* y_host, int use_graph,
+                      void* stream);
+
+/* ---- learned surrogate forecast ----------------------------------------------------------
+ * A 6-layer convolutional network (3x3 kernels, periodic padding, 3 -> 48 -> 48 -> 48 -> 48
+ * -> 48 -> 3, ReLU after the first five) that maps an ensemble state to the state one
+ * forecast window (10 model steps) later: psi' = psi + s * net((psi - mu) / sigma), per
+ * channel mu, sigma, s.  It runs in BF16 on the matrix cores with FP32 accumulation;
+ * parameters are FP32 master weights trained with Adam by the library's own forward and
+ * backward kernels.  The plain solver is its fallback: particles whose relative mass
+ * drift exceeds a tolerance are re-stepped.  Parameter vector layout: for each layer
+ * L = 0..5, weights [C_out][C_in][3][3] then biases [C_out] (float32). */
+typedef struct iewpf_net iewpf_net;
+/* Network with workspaces for up to max_cells = batch * ny * nx cells. */
+int iewpf_net_create(int max_cells, iewpf_net** out);
+void iewpf_net_destroy(iewpf_net* net);
+size_t iewpf_net_num_params(const iewpf_net* net);
+/* Copy host parameters in (resets the Adam state) / out; wait for the stream. */
+int iewpf_net_set_params(iewpf_net* net, const float* host, size_t count, void* stream);
+int iewpf_net_get_params(iewpf_net* net, float* host, size_t count, void* stream);
+/* Per-channel normalisation mu, sigma (inputs) and output scale s (3 floats each, host). */
+int iewpf_net_set_norm(iewpf_net* net, const float* mu, const float* sigma, const float* scale);
+/* state_out = state_in + s * net((state_in - mu) / sigma); device [B][3][H][W] float32 each
+ * (state_out may equal state_in). */
+int iewpf_net_forward(iewpf_net* net, const float* state_in, float* state_out, int B, int H,
+                      int W, void* stream);
+/* One Adam step (learning rate lr) on the MSE of net((x - mu)/sigma) against
+ * (target - x)/s over all cells and channels; x, target device [B][3][H][W].  loss_out:
+ * host pointer or NULL (when set the call waits and returns the loss before the update). */
+int iewpf_net_train_step(iewpf_net* net, const float* x, const float* target, int B, int H, int W,
+                         float lr, float* loss_out, void* stream);
+/* Loss gradient with respect to every parameter (host float [num_params]), without an
+ * update; also the loss and the raw network output y (host float [B*H*W][3], NHWC, or
+ * NULL).  Waits for the stream. */
+int iewpf_net_gradients(iewpf_net* net, const float* x, const float* target, int B, int H, int W,
+                        float* grads_host, float* loss_out, float* y_host, void* stream);
+/* One surrogate forecast window of the ensemble in place: the network replaces
+ * n_model_steps deterministic model steps; every particle whose relative mass drift
+ * |sum(H + eta') - sum(H + eta)| / sum(H + eta) exceeds drift_tol is re-stepped by the
+ * plain solver from its saved state; then one model-error draw (stream first_step +
+ * n_model_steps - 1) scaled by noise_scale is added to all particles.  n_fallback_out: host,
+ * particles re-stepped; drift_out: host double [n_particles] or NULL.  Waits for the stream.
+ * The first call allocates one state-sized buffer in the context. */
+int iewpf_surrogate_window(iewpf_ctx* ctx, iewpf_net* net, float* state, int n_model_steps,
+                           uint64_t first_step, double drift_tol, double noise_scale,
+                           int32_t* n_fallback_out, double* drift_out, void* stream);
+
 /* Per-kernel timing with HIP events recorded around every launch on the call's stream
  * (for measurement; off by default).  iewpf_set_trace(ctx, 1) starts a fresh record;
  * iewpf_trace_read waits for the recorded events and returns, per kernel kind, the total

@@ -4,6 +4,6 @@ The compute path is libiewpf.so (HIP kernels for gfx950, C ABI in include/iewpf.
 this package is its ctypes binding (`abi`) and the in-tree build step (`build`).
 """
 from . import abi
-from .abi import Context, IewpfError, load
+from .abi import Batch, Context, IewpfError, Net, load, surrogate_window
 
-__all__ = ["abi", "Context", "IewpfError", "load"]
+__all__ = ["abi", "Batch", "Context", "IewpfError", "Net", "load", "surrogate_window"]

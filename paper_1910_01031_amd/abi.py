@@ -29,7 +29,12 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_perturb", "iewpf_assimilate", "iewpf_particle_scalars",
             "iewpf_observe_moorings", "iewpf_forecast_drifters", "iewpf_advect_drifters",
             "iewpf_resample", "iewpf_check_cfl", "iewpf_read_buffer", "iewpf_window_size",
-            "iewpf_set_trace", "iewpf_trace_read", "iewpf_last_error")
+            "iewpf_set_trace", "iewpf_trace_read", "iewpf_autotune", "iewpf_batch_create",
+            "iewpf_batch_destroy", "iewpf_batch_set_cells", "iewpf_batch_cycle",
+            "iewpf_net_create", "iewpf_net_destroy", "iewpf_net_num_params",
+            "iewpf_net_set_params", "iewpf_net_get_params", "iewpf_net_set_norm",
+            "iewpf_net_forward", "iewpf_net_train_step", "iewpf_net_gradients",
+            "iewpf_surrogate_window", "iewpf_last_error")
 
 TRACE_KINDS = ("scheme_step", "me_normals", "soar", "gb_add", "innovation", "rand_dots",
                "beta_alpha", "posterior_coarse", "analysis_update", "scheme_step_noise")
@@ -93,12 +98,36 @@ def load(path: str = LIB_PATH):
     lib.iewpf_read_buffer.argtypes = [vp, i32, vp, ctypes.c_size_t, vp]
     lib.iewpf_window_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32)]
+    lib.iewpf_autotune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.iewpf_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), i32,
+                                       ctypes.POINTER(vp)]
+    lib.iewpf_batch_destroy.argtypes = [vp]
+    lib.iewpf_batch_destroy.restype = None
+    lib.iewpf_batch_set_cells.argtypes = [vp, i32, vp, i32, vp]
+    lib.iewpf_batch_cycle.argtypes = [vp, i32, u64, u64, ctypes.POINTER(vp), i32, vp]
+    lib.iewpf_net_create.argtypes = [i32, ctypes.POINTER(vp)]
+    lib.iewpf_net_destroy.argtypes = [vp]
+    lib.iewpf_net_destroy.restype = None
+    lib.iewpf_net_num_params.argtypes = [vp]
+    lib.iewpf_net_set_params.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.iewpf_net_get_params.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.iewpf_net_set_norm.argtypes = [vp, vp, vp, vp]
+    lib.iewpf_net_forward.argtypes = [vp, vp, vp, i32, i32, i32, vp]
+    lib.iewpf_net_train_step.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float,
+                                         ctypes.POINTER(ctypes.c_float), vp]
+    lib.iewpf_net_gradients.argtypes = [vp, vp, vp, i32, i32, i32, vp,
+                                        ctypes.POINTER(ctypes.c_float), vp, vp]
+    lib.iewpf_surrogate_window.argtypes = [vp, vp, vp, i32, u64, ctypes.c_double,
+                                           ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                                           vp, vp]
     lib.iewpf_set_trace.argtypes = [vp, i32]
     lib.iewpf_trace_read.argtypes = [vp, f64p, vp, i32]
+    lib.iewpf_net_num_params.restype = ctypes.c_size_t
     lib.iewpf_last_error.restype = ctypes.c_char_p
     lib.iewpf_last_error.argtypes = []
     for name in EXPORTED:
-        if name not in ("iewpf_destroy", "iewpf_last_error"):
+        if name not in ("iewpf_destroy", "iewpf_last_error", "iewpf_batch_destroy",
+                        "iewpf_net_destroy", "iewpf_net_num_params"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -230,6 +259,11 @@ class Context:
             _check(rc)
         return dt.value, rc == 0
 
+    def autotune(self, state, stream=None) -> int:
+        out = ctypes.c_int32()
+        _check(load().iewpf_autotune(self.h, _ptr(state), ctypes.byref(out), _stream(stream)))
+        return out.value
+
     def set_trace(self, on: bool):
         _check(load().iewpf_set_trace(self.h, int(on)))
 
@@ -251,3 +285,113 @@ class Context:
         _check(load().iewpf_read_buffer(self.h, which, out.ctypes.data, out.nbytes,
                                         _stream(stream)))
         return out
+
+
+class Batch:
+    """Several contexts stepped by one launch per scheme step (iewpf_batch_*)."""
+
+    def __init__(self, contexts, states):
+        lib = load()
+        n = len(contexts)
+        self.contexts = list(contexts)
+        self.states = list(states)
+        hs = (ctypes.c_void_p * n)(*[c.h.value for c in contexts])
+        ps = (ctypes.c_void_p * n)(*[t.data_ptr() for t in states])
+        h = ctypes.c_void_p()
+        _check(lib.iewpf_batch_create(hs, ps, n, ctypes.byref(h)))
+        self.h = h
+        self.n_obs = [0] * n
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().iewpf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_cells(self, e: int, cells: np.ndarray, stream=None):
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        _check(load().iewpf_batch_set_cells(self.h, e, cells.ctypes.data, len(cells), _stream(stream)))
+        self.n_obs[e] = len(cells)
+
+    def cycle(self, n_model_steps: int, first_step: int, analysis_index: int, y_list,
+              use_graph: bool = False, stream=None):
+        ys = [np.ascontiguousarray(y, dtype=np.float64) for y in y_list]
+        self._keep = ys
+        arr = (ctypes.c_void_p * len(ys))(*[y.ctypes.data for y in ys])
+        _check(load().iewpf_batch_cycle(self.h, n_model_steps, first_step, analysis_index, arr,
+                                        int(use_graph), _stream(stream)))
+
+
+class Net:
+    """The learned surrogate network (iewpf_net_*)."""
+
+    def __init__(self, max_cells: int):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.iewpf_net_create(int(max_cells), ctypes.byref(h)))
+        self.h = h
+        self.num_params = int(lib.iewpf_net_num_params(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().iewpf_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat: np.ndarray, stream=None):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(load().iewpf_net_set_params(self.h, flat.ctypes.data, flat.size, _stream(stream)))
+
+    def get_params(self, stream=None) -> np.ndarray:
+        out = np.zeros(self.num_params, dtype=np.float32)
+        _check(load().iewpf_net_get_params(self.h, out.ctypes.data, out.size, _stream(stream)))
+        return out
+
+    def set_norm(self, mu, sigma, scale):
+        arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (mu, sigma, scale)]
+        self._norm = arrs
+        _check(load().iewpf_net_set_norm(self.h, *[a.ctypes.data for a in arrs]))
+
+    def forward(self, state_in, state_out, stream=None):
+        B, _, H, W = state_in.shape
+        _check(load().iewpf_net_forward(self.h, _ptr(state_in), _ptr(state_out), B, H, W,
+                                        _stream(stream)))
+
+    def train_step(self, x, target, lr: float, want_loss: bool = False, stream=None):
+        B, _, H, W = x.shape
+        loss = ctypes.c_float()
+        _check(load().iewpf_net_train_step(self.h, _ptr(x), _ptr(target), B, H, W, lr,
+                                           ctypes.byref(loss) if want_loss else None,
+                                           _stream(stream)))
+        return loss.value if want_loss else None
+
+    def gradients(self, x, target, stream=None):
+        """(grads float32 [num_params], loss, y float32 [B*H*W, 3])."""
+        B, _, H, W = x.shape
+        g = np.zeros(self.num_params, dtype=np.float32)
+        y = np.zeros((B * H * W, 3), dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(load().iewpf_net_gradients(self.h, _ptr(x), _ptr(target), B, H, W, g.ctypes.data,
+                                          ctypes.byref(loss), y.ctypes.data, _stream(stream)))
+        return g, loss.value, y
+
+
+def surrogate_window(ctx, net, state, n_model_steps: int, first_step: int, drift_tol: float,
+                     noise_scale: float, stream=None):
+    """Returns (n_fallback, per-particle mass drift)."""
+    nf = ctypes.c_int32()
+    drift = np.zeros(ctx.cfg.n_particles)
+    _check(load().iewpf_surrogate_window(ctx.h, net.h, _ptr(state), n_model_steps, first_step,
+                                         drift_tol, noise_scale, ctypes.byref(nf),
+                                         drift.ctypes.data, _stream(stream)))
+    return nf.value, drift

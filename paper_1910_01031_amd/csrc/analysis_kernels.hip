@@ -67,17 +67,25 @@ __global__ __launch_bounds__(kThreads) void innovation_kernel(
   if (threadIdx.x == 0) cval[i] = phi;
 }
 
+// grid (kDotParts, ne): part q of particle i handles Philox blocks q*kThreads + t + k*stride;
+// partial sums go to part_dots[i][q][3] and are added in the fixed order q = 0.. by
+// reduce_dots_kernel.
+constexpr int kDotParts = 8;
+
 __global__ __launch_bounds__(kThreads) void rand_dots_kernel(int nr, uint64_t seed, uint64_t step,
                                                              uint32_t ens, float* __restrict__ xi,
                                                              float* __restrict__ nu,
-                                                             double* __restrict__ dots) {
+                                                             double* __restrict__ part_dots,
+                                                             const uint64_t* __restrict__ dyn) {
   __shared__ double sh[kThreads];
-  const int i = blockIdx.x;
+  if (dyn) step += dyn[1];  // analysis index from device memory (captured graphs)
+  const int i = blockIdx.y;
+  const int q = blockIdx.x;
   float* X = xi + (size_t)i * nr;
   float* N = nu + (size_t)i * nr;
   double xx = 0.0, nn = 0.0, nxv = 0.0;
   const int nblk = (nr + 3) / 4;
-  for (int b = threadIdx.x; b < nblk; b += kThreads) {
+  for (int b = q * kThreads + threadIdx.x; b < nblk; b += kThreads * kDotParts) {
     double zx[4], zn[4];
     normals4(b, step, 2u, ens, i, seed, zx);
     normals4(b, step, 3u, ens, i, seed, zn);
@@ -98,10 +106,27 @@ __global__ __launch_bounds__(kThreads) void rand_dots_kernel(int nr, uint64_t se
   nn = block_sum(nn, sh);
   nxv = block_sum(nxv, sh);
   if (threadIdx.x == 0) {
-    dots[3 * i] = xx;
-    dots[3 * i + 1] = nn;
-    dots[3 * i + 2] = nxv;
+    double* o = part_dots + ((size_t)i * kDotParts + q) * 3;
+    o[0] = xx;
+    o[1] = nn;
+    o[2] = nxv;
   }
+}
+
+__global__ void reduce_dots_kernel(int ne, const double* __restrict__ part_dots,
+                                   double* __restrict__ dots) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ne) return;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int q = 0; q < kDotParts; ++q) {
+    const double* o = part_dots + ((size_t)i * kDotParts + q) * 3;
+    a += o[0];
+    b += o[1];
+    c += o[2];
+  }
+  dots[3 * i] = a;
+  dots[3 * i + 1] = b;
+  dots[3 * i + 2] = c;
 }
 
 // (x - 1) - ln x for x = 1 + e, accurate for small e.
@@ -463,10 +488,13 @@ void launch_innovation(int ne, int n_obs, int max_obs, int nx, int ny, double H,
                      M, psi, cells, y, sd, cval);
 }
 
+int rand_dots_parts() { return kDotParts; }
+
 void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens, float* xi,
-                      float* nu, double* dots, hipStream_t s) {
-  hipLaunchKernelGGL(rand_dots_kernel, dim3(ne), dim3(kThreads), 0, s, nr, seed, step, ens, xi, nu,
-                     dots);
+                      float* nu, double* part_dots, double* dots, hipStream_t s, const uint64_t* dyn) {
+  hipLaunchKernelGGL(rand_dots_kernel, dim3(kDotParts, ne), dim3(kThreads), 0, s, nr, seed, step, ens,
+                     xi, nu, part_dots, dyn);
+  hipLaunchKernelGGL(reduce_dots_kernel, dim3((ne + 127) / 128), dim3(128), 0, s, ne, part_dots, dots);
 }
 
 void launch_sync(int ne, double n_psi, double n_r, const double* cval, const double* dots,

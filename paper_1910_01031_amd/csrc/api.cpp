@@ -15,6 +15,29 @@
 
 #include "internal.hpp"
 
+struct iewpf_batch {
+  int n = 0;
+  std::vector<iewpf_ctx*> ctx;
+  std::vector<float*> state;
+  std::vector<int> n_obs;
+  std::vector<size_t> y_off;     // offsets into the pinned y buffer
+  iewpf::SweJobTable* tab_plain = nullptr;  // device tables
+  iewpf::SweJobTable* tab_noise = nullptr;
+  int total_waves = 0;
+  int n_sub = 1;
+  uint64_t* d_dyn = nullptr;      // device counters: first step, analysis index
+  uint64_t* h_dyn = nullptr;      // pinned
+  double* h_y = nullptr;          // pinned observation values
+  size_t h_y_len = 0;
+  hipEvent_t copy_ev = nullptr;
+  bool copy_pending = false;
+  hipStream_t gs = nullptr;       // capture / replay stream
+  hipEvent_t in_ev = nullptr, out_ev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_steps = -1;
+};
+
 namespace iewpf {
 
 namespace {
@@ -79,7 +102,8 @@ int env_int(const char* name, int def) {
 
 void free_ctx(iewpf_ctx* c) {
   if (!c) return;
-  void* bufs[] = {c->scratch, c->xi,     c->nu,     c->coarse, c->coarse2, c->windows,
+  void* bufs[] = {c->saved, c->sdrift, c->sflags, c->scratch, c->part_dots, c->xi, c->nu,
+                  c->coarse, c->coarse2, c->windows,
                   c->dmat,    c->sd,     c->cval,   c->dots,   c->alpha,   c->cstar,
                   c->scal,    c->obs_cells, c->obs_y, c->pt_off, c->pt_ent, c->st_off,
                   c->st_ent,  c->dk1,    c->dpstar, c->dobs,   c->cflmax,  c->dparents};
@@ -163,6 +187,121 @@ void add_noise(iewpf_ctx* c, float* psi, uint64_t step, hipStream_t s) {
   launch_gb_add(c->cc, c->ne, c->coarse, nullptr, psi, c->upd_strip_h, s);
 }
 
+// Builds the per-call observation index lists from the cells in the pinned staging area
+// and uploads cells (and y when with_y) and the lists on the stream.
+//   coarse point -> (observation, 7x7 block row) pairs, ascending observations per point
+//   fine update strip -> observations whose pull window reaches it
+int upload_observations(iewpf_ctx* c, int n_obs, bool with_y, hipStream_t s) {
+  const StageLayout L = stage_layout(*c);
+  int32_t* cells = reinterpret_cast<int32_t*>(c->h_stage + L.cells);
+  double* y = reinterpret_cast<double*>(c->h_stage + L.y);
+  int32_t* pt_off = reinterpret_cast<int32_t*>(c->h_stage + L.pt_off);
+  int32_t* pt_ent = reinterpret_cast<int32_t*>(c->h_stage + L.pt_ent);
+  std::fill(pt_off, pt_off + c->nr + 1, 0);
+  auto block_point = [&](int o, int q) {
+    const int ao = cells[2 * o] / c->c, bo = cells[2 * o + 1] / c->c;
+    const int pa = ((ao + q % 7 - 3) % c->nrx + c->nrx) % c->nrx;
+    const int pb = ((bo + q / 7 - 3) % c->nry + c->nry) % c->nry;
+    return pb * c->nrx + pa;
+  };
+  for (int o = 0; o < n_obs; ++o)
+    for (int q = 0; q < kBlockN; ++q) pt_off[block_point(o, q) + 1]++;
+  for (int p = 0; p < c->nr; ++p) pt_off[p + 1] += pt_off[p];
+  {
+    std::vector<int32_t> fillp(pt_off, pt_off + c->nr);
+    for (int o = 0; o < n_obs; ++o)
+      for (int q = 0; q < kBlockN; ++q) pt_ent[fillp[block_point(o, q)]++] = (o << 8) | q;
+  }
+  const int nsx = (c->nx + kGbOut - 1) / kGbOut;
+  const int nsy = (c->ny + c->upd_strip_h - 1) / c->upd_strip_h;
+  int32_t* st_off = reinterpret_cast<int32_t*>(c->h_stage + L.st_off);
+  int32_t* st_ent = reinterpret_cast<int32_t*>(c->h_stage + L.st_ent);
+  st_off[0] = 0;
+  int t = 0;
+  for (int sy = 0; sy < nsy; ++sy) {
+    const int k0 = sy * c->upd_strip_h;
+    const int lenk = std::min(c->upd_strip_h, c->ny - k0);
+    for (int sx = 0; sx < nsx; ++sx) {
+      const int j0 = sx * kGbOut;
+      const int lenj = std::min(kGbOut, c->nx - j0);
+      for (int o = 0; o < n_obs; ++o) {
+        const bool in_x = c->rx < 0 || circ_interval_dist(cells[2 * o], j0, lenj, c->nx) <= c->rx;
+        const bool in_y =
+            c->ry < 0 || circ_interval_dist(cells[2 * o + 1], k0, lenk, c->ny) <= c->ry;
+        if (in_x && in_y) st_ent[t++] = o;
+      }
+      st_off[sy * nsx + sx + 1] = t;
+    }
+  }
+  if (n_obs > 0) {
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->obs_cells, cells, sizeof(int32_t) * 2 * n_obs,
+                                 hipMemcpyHostToDevice, s));
+    if (with_y)
+      IEWPF_HIP_TRY(hipMemcpyAsync(c->obs_y, y, sizeof(double) * 2 * n_obs, hipMemcpyHostToDevice, s));
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->pt_ent, pt_ent, sizeof(int32_t) * pt_off[c->nr],
+                                 hipMemcpyHostToDevice, s));
+  }
+  IEWPF_HIP_TRY(hipMemcpyAsync(c->pt_off, pt_off, sizeof(int32_t) * (c->nr + 1),
+                               hipMemcpyHostToDevice, s));
+  IEWPF_HIP_TRY(hipMemcpyAsync(c->st_off, st_off, sizeof(int32_t) * (c->n_upd_strips + 1),
+                               hipMemcpyHostToDevice, s));
+  if (t > 0)
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->st_ent, st_ent, sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
+  IEWPF_HIP_TRY(hipEventRecord(c->stage_ev, s));
+  c->stage_pending = true;
+  c->last_n_obs = n_obs;
+  return 0;
+}
+
+// The analysis kernels of one ensemble on the observations already on the device.
+// dyn: device counters (dyn[1] = analysis index added to analysis_index) or nullptr.
+int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_index,
+                    const uint64_t* dyn, hipStream_t s) {
+  // stages 1-2: innovations, S d, c_i
+  {
+    TraceScope tr(c, kTrInnov, s);
+    launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, c->S, state,
+                      c->obs_cells, c->obs_y, c->sd, c->cval, s);
+  }
+  // stage 3: xi, nu~ and their dot products
+  {
+    TraceScope tr(c, kTrRandDots, s);
+    launch_rand_dots(c->ne, c->nr, c->cfg.seed, analysis_index, c->cfg.ensemble_id, c->xi, c->nu,
+                     c->part_dots, c->dots, s, dyn);
+  }
+  // stages 4-5: cbar, beta, c*, alpha (the one ensemble-wide step)
+  {
+    TraceScope tr(c, kTrSync, s);
+    launch_sync(c->ne, c->n_psi, (double)c->nr, c->cval, c->dots, c->alpha, c->cstar, c->scal, s);
+  }
+  // stage 6: r' on the coarse grid, SOAR, then one fused pass over the state
+  {
+    TraceScope tr(c, kTrPosterior, s);
+    launch_posterior_coarse(c->cc, c->ne, c->xi, c->nu, c->dots, c->alpha, c->scal, c->dmat,
+                            c->pt_off, c->pt_ent, c->obs_cells, c->coarse2, s);
+  }
+  {
+    TraceScope tr(c, kTrSoar, s);
+    launch_soar(c->cc, c->soar_me_f, c->ne, c->coarse2, c->coarse, s);
+  }
+  PullConst P;
+  P.wx = c->wx;
+  P.wy = c->wy;
+  P.rx = c->rx;
+  P.ry = c->ry;
+  P.n_obs = n_obs;
+  P.strip_h = c->upd_strip_h;
+  P.n_strip_x = (c->nx + kGbOut - 1) / kGbOut;
+  P.n_strip_y = (c->ny + c->upd_strip_h - 1) / c->upd_strip_h;
+  {
+    TraceScope tr(c, kTrUpdate, s);
+    launch_analysis_update(c->cc, P, c->ne, c->coarse, c->windows, c->sd, c->max_obs, c->obs_cells,
+                           c->st_off, c->st_ent, state, s);
+  }
+  IEWPF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 int model_steps(iewpf_ctx* c, float* state, int n_steps, uint64_t first_step, int noise_on_last,
                 hipStream_t s) {
   float* cur = state;
@@ -192,6 +331,61 @@ int model_steps(iewpf_ctx* c, float* state, int n_steps, uint64_t first_step, in
                                  hipMemcpyDeviceToDevice, s));
   IEWPF_HIP_TRY(hipGetLastError());
   return 0;
+}
+
+// Model steps of every ensemble of a batch; dyn != nullptr reads the first step index
+// from dyn[0] (the kernels then see step offsets only).
+int batch_model_steps(iewpf_batch* b, int n_steps, uint64_t first_step, const uint64_t* dyn,
+                      hipStream_t s) {
+  int parity = 0;
+  for (int st = 0; st < n_steps; ++st) {
+    const bool noise = st < n_steps - 1;
+    if (noise) {
+      for (int e = 0; e < b->n; ++e) {
+        iewpf_ctx* c = b->ctx[e];
+        launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, (dyn ? 0 : first_step) + st,
+                       kTagModelError, c->cfg.ensemble_id, s, dyn);
+        launch_soar(c->cc, c->soar_me_f, c->ne, c->xi, c->coarse, s);
+      }
+    }
+    for (int sub = 0; sub < b->n_sub; ++sub) {
+      const bool fuse = noise && sub == b->n_sub - 1;
+      launch_swe_batch(fuse ? b->tab_noise : b->tab_plain, b->total_waves, parity, fuse, s);
+      parity ^= 1;
+    }
+  }
+  if (parity)
+    for (int e = 0; e < b->n; ++e)
+      IEWPF_HIP_TRY(hipMemcpyAsync(b->state[e], b->ctx[e]->scratch,
+                                   sizeof(float) * 3 * b->ctx[e]->ncell * b->ctx[e]->ne,
+                                   hipMemcpyDeviceToDevice, s));
+  IEWPF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int batch_cycle_body(iewpf_batch* b, int n_steps, uint64_t first_step, uint64_t analysis_index,
+                     const uint64_t* dyn, hipStream_t s) {
+  if (int rc = batch_model_steps(b, n_steps, first_step, dyn, s)) return rc;
+  for (int e = 0; e < b->n; ++e)
+    if (int rc = launch_analysis(b->ctx[e], b->state[e], b->n_obs[e], dyn ? 0 : analysis_index, dyn, s))
+      return rc;
+  return 0;
+}
+
+void free_batch(iewpf_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->tab_plain) (void)hipFree(b->tab_plain);
+  if (b->tab_noise) (void)hipFree(b->tab_noise);
+  if (b->d_dyn) (void)hipFree(b->d_dyn);
+  if (b->h_dyn) (void)hipHostFree(b->h_dyn);
+  if (b->h_y) (void)hipHostFree(b->h_y);
+  if (b->copy_ev) (void)hipEventDestroy(b->copy_ev);
+  if (b->in_ev) (void)hipEventDestroy(b->in_ev);
+  if (b->out_ev) (void)hipEventDestroy(b->out_ev);
+  if (b->gs) (void)hipStreamDestroy(b->gs);
+  delete b;
 }
 
 }  // namespace
@@ -280,10 +474,13 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   {
     // rows per wave strip: fit the waves of all particles to the resident wave slots
     // (each wave marches strip_h + 8 rows of stage 1 and strip_h + 4 of stage 2)
-    const int forced = env_int("IEWPF_SWE_STRIP", 0);
-    const int n_ys = forced > 0 ? (f.ny + forced - 1) / forced
-                                : choose_row_strips(S.n_strip_x * f.n_particles, f.ny,
-                                                    device_slots(swe_waves_per_cu()), 6, 8);
+    // 32 rows measured best on gfx950 at 500x300x100 (16..100 all within 10%); the
+    // occupancy model only takes over when that would leave the GPU under-filled
+    const int forced = env_int("IEWPF_SWE_STRIP", 32);
+    const int slots = device_slots(swe_waves_per_cu());
+    int n_ys = (f.ny + forced - 1) / forced;
+    if ((long long)S.n_strip_x * f.n_particles * n_ys < slots)
+      n_ys = choose_row_strips(S.n_strip_x * f.n_particles, f.ny, slots, 6, 8);
     S.strip_h = (f.ny + n_ys - 1) / n_ys;
     S.n_strip_y = (f.ny + S.strip_h - 1) / S.strip_h;
   }
@@ -352,6 +549,7 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   rc |= dev_alloc(&c->sd, (size_t)c->ne * c->max_obs * 2);
   rc |= dev_alloc(&c->cval, c->ne);
   rc |= dev_alloc(&c->dots, (size_t)3 * c->ne);
+  rc |= dev_alloc(&c->part_dots, (size_t)3 * c->ne * rand_dots_parts());
   rc |= dev_alloc(&c->alpha, c->ne);
   rc |= dev_alloc(&c->cstar, c->ne);
   rc |= dev_alloc(&c->scal, 16);
@@ -449,111 +647,8 @@ int iewpf_assimilate(iewpf_ctx* c, float* state, const iewpf_obs* obs, int n_obs
     y[2 * o + 1] = obs[o].y_hv;
   }
   if (int rc = check_cells(c, cells, n_obs)) return rc;
-  // coarse point -> (obs, block row) lists, ascending obs within each point
-  int32_t* pt_off = reinterpret_cast<int32_t*>(c->h_stage + L.pt_off);
-  int32_t* pt_ent = reinterpret_cast<int32_t*>(c->h_stage + L.pt_ent);
-  std::fill(pt_off, pt_off + c->nr + 1, 0);
-  for (int o = 0; o < n_obs; ++o) {
-    const int ao = cells[2 * o] / c->c, bo = cells[2 * o + 1] / c->c;
-    for (int q = 0; q < kBlockN; ++q) {
-      const int pa = ((ao + q % 7 - 3) % c->nrx + c->nrx) % c->nrx;
-      const int pb = ((bo + q / 7 - 3) % c->nry + c->nry) % c->nry;
-      pt_off[pb * c->nrx + pa + 1]++;
-    }
-  }
-  for (int p = 0; p < c->nr; ++p) pt_off[p + 1] += pt_off[p];
-  {
-    std::vector<int32_t> fillp(pt_off, pt_off + c->nr);
-    for (int o = 0; o < n_obs; ++o) {
-      const int ao = cells[2 * o] / c->c, bo = cells[2 * o + 1] / c->c;
-      for (int q = 0; q < kBlockN; ++q) {
-        const int pa = ((ao + q % 7 - 3) % c->nrx + c->nrx) % c->nrx;
-        const int pb = ((bo + q / 7 - 3) % c->nry + c->nry) % c->nry;
-        pt_ent[fillp[pb * c->nrx + pa]++] = (o << 8) | q;
-      }
-    }
-  }
-  // fine strip -> observations whose pull window reaches it
-  const int nsx = (c->nx + kGbOut - 1) / kGbOut;
-  const int nsy = (c->ny + c->upd_strip_h - 1) / c->upd_strip_h;
-  int32_t* st_off = reinterpret_cast<int32_t*>(c->h_stage + L.st_off);
-  int32_t* st_ent = reinterpret_cast<int32_t*>(c->h_stage + L.st_ent);
-  st_off[0] = 0;
-  int t = 0;
-  for (int sy = 0; sy < nsy; ++sy) {
-    const int k0 = sy * c->upd_strip_h;
-    const int lenk = std::min(c->upd_strip_h, c->ny - k0);
-    for (int sx = 0; sx < nsx; ++sx) {
-      const int j0 = sx * kGbOut;
-      const int lenj = std::min(kGbOut, c->nx - j0);
-      for (int o = 0; o < n_obs; ++o) {
-        const bool in_x = c->rx < 0 || circ_interval_dist(cells[2 * o], j0, lenj, c->nx) <= c->rx;
-        const bool in_y =
-            c->ry < 0 || circ_interval_dist(cells[2 * o + 1], k0, lenk, c->ny) <= c->ry;
-        if (in_x && in_y) st_ent[t++] = o;
-      }
-      st_off[sy * nsx + sx + 1] = t;
-    }
-  }
-  const size_t ne_cells = sizeof(int32_t) * 2 * (size_t)n_obs;
-  if (n_obs > 0) {
-    IEWPF_HIP_TRY(hipMemcpyAsync(c->obs_cells, cells, ne_cells, hipMemcpyHostToDevice, s));
-    IEWPF_HIP_TRY(hipMemcpyAsync(c->obs_y, y, sizeof(double) * 2 * n_obs, hipMemcpyHostToDevice, s));
-    IEWPF_HIP_TRY(hipMemcpyAsync(c->pt_ent, pt_ent, sizeof(int32_t) * pt_off[c->nr],
-                                 hipMemcpyHostToDevice, s));
-  }
-  IEWPF_HIP_TRY(hipMemcpyAsync(c->pt_off, pt_off, sizeof(int32_t) * (c->nr + 1),
-                               hipMemcpyHostToDevice, s));
-  IEWPF_HIP_TRY(hipMemcpyAsync(c->st_off, st_off, sizeof(int32_t) * (c->n_upd_strips + 1),
-                               hipMemcpyHostToDevice, s));
-  if (t > 0)
-    IEWPF_HIP_TRY(hipMemcpyAsync(c->st_ent, st_ent, sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
-  IEWPF_HIP_TRY(hipEventRecord(c->stage_ev, s));
-  c->stage_pending = true;
-  c->last_n_obs = n_obs;
-
-  // stages 1-2: innovations, S d, c_i
-  {
-    TraceScope tr(c, kTrInnov, s);
-    launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, c->S, state,
-                      c->obs_cells, c->obs_y, c->sd, c->cval, s);
-  }
-  // stage 3: xi, nu~ and their dot products
-  {
-    TraceScope tr(c, kTrRandDots, s);
-    launch_rand_dots(c->ne, c->nr, c->cfg.seed, analysis_index, c->cfg.ensemble_id, c->xi, c->nu,
-                     c->dots, s);
-  }
-  // stages 4-5: cbar, beta, c*, alpha (the one ensemble-wide step)
-  {
-    TraceScope tr(c, kTrSync, s);
-    launch_sync(c->ne, c->n_psi, (double)c->nr, c->cval, c->dots, c->alpha, c->cstar, c->scal, s);
-  }
-  // stage 6: r' on the coarse grid, SOAR, then one fused pass over the state
-  {
-    TraceScope tr(c, kTrPosterior, s);
-    launch_posterior_coarse(c->cc, c->ne, c->xi, c->nu, c->dots, c->alpha, c->scal, c->dmat,
-                            c->pt_off, c->pt_ent, c->obs_cells, c->coarse2, s);
-  }
-  {
-    TraceScope tr(c, kTrSoar, s);
-    launch_soar(c->cc, c->soar_me_f, c->ne, c->coarse2, c->coarse, s);
-  }
-  PullConst P;
-  P.wx = c->wx;
-  P.wy = c->wy;
-  P.rx = c->rx;
-  P.ry = c->ry;
-  P.n_obs = n_obs;
-  P.strip_h = c->upd_strip_h;
-  P.n_strip_x = nsx;
-  P.n_strip_y = nsy;
-  {
-    TraceScope tr(c, kTrUpdate, s);
-    launch_analysis_update(c->cc, P, c->ne, c->coarse, c->windows, c->sd, c->max_obs, c->obs_cells,
-                         c->st_off, c->st_ent, state, s);
-  }
-  IEWPF_HIP_TRY(hipGetLastError());
+  if (int rc = upload_observations(c, n_obs, true, s)) return rc;
+  if (int rc = launch_analysis(c, state, n_obs, analysis_index, nullptr, s)) return rc;
   if (stats_out) {
     IEWPF_HIP_TRY(hipMemcpyAsync(c->h_small, c->scal, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
     IEWPF_HIP_TRY(hipStreamSynchronize(s));
@@ -677,6 +772,239 @@ int iewpf_resample(iewpf_ctx* c, float* state, const double* logw, uint64_t anal
   IEWPF_HIP_TRY(hipMemcpyAsync(state, c->scratch, sizeof(float) * per * c->ne,
                                hipMemcpyDeviceToDevice, s));
   IEWPF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int iewpf_autotune(iewpf_ctx* c, const float* state, int32_t* strip_out, void* stream) {
+  if (!c || !state || !strip_out) return fail(IEWPF_E_ARG, "NULL argument");
+  hipStream_t s = as_stream(stream);
+  const int cands[] = {16, 24, 32, 40, 48, 64, 96};
+  hipEvent_t e0, e1;
+  IEWPF_HIP_TRY(hipEventCreate(&e0));
+  IEWPF_HIP_TRY(hipEventCreate(&e1));
+  SweConst best = c->swe;
+  float best_ms = 1e30f;
+  for (int h : cands) {
+    if (h > c->ny && h != cands[0]) break;
+    SweConst C = c->swe;
+    C.strip_h = std::min(h, c->ny);
+    C.n_strip_y = (c->ny + C.strip_h - 1) / C.strip_h;
+    launch_swe_substep(C, c->ne, state, c->scratch, nullptr, s);  // warm
+    IEWPF_HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < 4; ++r) launch_swe_substep(C, c->ne, state, c->scratch, nullptr, s);
+    IEWPF_HIP_TRY(hipEventRecord(e1, s));
+    IEWPF_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    IEWPF_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = C;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->swe = best;
+  *strip_out = best.strip_h;
+  return 0;
+}
+
+int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewpf_batch** out) {
+  if (!ctxs || !states || !out || n <= 0 || n > kMaxBatch) return fail(IEWPF_E_ARG, "invalid argument");
+  *out = nullptr;
+  for (int e = 0; e < n; ++e) {
+    if (!ctxs[e] || !states[e]) return fail(IEWPF_E_ARG, "NULL context or state");
+    if (ctxs[e]->cfg.n_sub != ctxs[0]->cfg.n_sub || ctxs[e]->cfg.dt != ctxs[0]->cfg.dt)
+      return fail(IEWPF_E_ARG, "batched ensembles need the same dt and n_sub");
+  }
+  iewpf_batch* b = new iewpf_batch();
+  b->n = n;
+  b->n_sub = ctxs[0]->cfg.n_sub;
+  SweJobTable plain{}, noise{};
+  plain.n = noise.n = n;
+  int w = 0;
+  size_t ylen = 0;
+  for (int e = 0; e < n; ++e) {
+    iewpf_ctx* c = ctxs[e];
+    b->ctx.push_back(c);
+    b->state.push_back(states[e]);
+    b->n_obs.push_back(0);
+    b->y_off.push_back(ylen);
+    ylen += 2 * (size_t)c->max_obs;
+    SweJob J{};
+    J.C = c->swe;
+    J.z = nullptr;
+    J.buf_a = states[e];
+    J.buf_b = c->scratch;
+    J.wave_begin = w;
+    plain.job[e] = J;
+    J.z = c->coarse;
+    noise.job[e] = J;
+    w += c->ne * c->swe.n_strip_x * c->swe.n_strip_y;
+  }
+  plain.total_waves = noise.total_waves = w;
+  b->total_waves = w;
+  b->h_y_len = ylen;
+  bool ok = hipMalloc(reinterpret_cast<void**>(&b->tab_plain), sizeof(SweJobTable)) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&b->tab_noise), sizeof(SweJobTable)) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&b->d_dyn), 2 * sizeof(uint64_t)) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&b->h_dyn), 2 * sizeof(uint64_t)) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&b->h_y), sizeof(double) * std::max<size_t>(ylen, 1)) ==
+                hipSuccess &&
+            hipEventCreateWithFlags(&b->copy_ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&b->in_ev, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&b->out_ev, hipEventDisableTiming) == hipSuccess &&
+            hipStreamCreateWithFlags(&b->gs, hipStreamNonBlocking) == hipSuccess &&
+            hipMemcpy(b->tab_plain, &plain, sizeof(SweJobTable), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(b->tab_noise, &noise, sizeof(SweJobTable), hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    free_batch(b);
+    return fail(IEWPF_E_HIP, "batch allocation failed");
+  }
+  *out = b;
+  return 0;
+}
+
+void iewpf_batch_destroy(iewpf_batch* b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  free_batch(b);
+}
+
+int iewpf_batch_set_cells(iewpf_batch* b, int e, const int32_t* cells_host, int n_obs, void* stream) {
+  if (!b || e < 0 || e >= b->n || (n_obs > 0 && !cells_host) || n_obs < 0)
+    return fail(IEWPF_E_ARG, "invalid argument");
+  iewpf_ctx* c = b->ctx[e];
+  if (n_obs > c->max_obs) return fail(IEWPF_E_CAPACITY, "more observations than max_obs");
+  if (int rc = check_cells(c, cells_host, n_obs)) return rc;
+  hipStream_t s = as_stream(stream);
+  if (int rc = wait_stage(c)) return rc;
+  const StageLayout L = stage_layout(*c);
+  std::memcpy(c->h_stage + L.cells, cells_host, sizeof(int32_t) * 2 * n_obs);
+  if (int rc = upload_observations(c, n_obs, false, s)) return rc;
+  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  c->stage_pending = false;
+  b->n_obs[e] = n_obs;
+  if (b->exec) {  // observation lists changed: capture again
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_steps = -1;
+  }
+  return 0;
+}
+
+int iewpf_batch_cycle(iewpf_batch* b, int n_model_steps, uint64_t first_step,
+                      uint64_t analysis_index, const double* const* y_host, int use_graph,
+                      void* stream) {
+  if (!b || n_model_steps < 1 || !y_host) return fail(IEWPF_E_ARG, "invalid argument");
+  hipStream_t s = as_stream(stream);
+  hipStream_t run = use_graph ? b->gs : s;
+  if (use_graph) {  // order the internal stream after the caller's work
+    IEWPF_HIP_TRY(hipEventRecord(b->in_ev, s));
+    IEWPF_HIP_TRY(hipStreamWaitEvent(run, b->in_ev, 0));
+  }
+  // observation values and counters: pinned host -> device, ahead of the cycle
+  if (b->copy_pending) {
+    IEWPF_HIP_TRY(hipEventSynchronize(b->copy_ev));
+    b->copy_pending = false;
+  }
+  for (int e = 0; e < b->n; ++e) {
+    if (b->n_obs[e] > 0 && !y_host[e]) return fail(IEWPF_E_ARG, "missing observation values");
+    std::memcpy(b->h_y + b->y_off[e], y_host[e], sizeof(double) * 2 * b->n_obs[e]);
+    if (b->n_obs[e] > 0)
+      IEWPF_HIP_TRY(hipMemcpyAsync(b->ctx[e]->obs_y, b->h_y + b->y_off[e],
+                                   sizeof(double) * 2 * b->n_obs[e], hipMemcpyHostToDevice, run));
+  }
+  if (use_graph) {
+    b->h_dyn[0] = first_step;
+    b->h_dyn[1] = analysis_index;
+    IEWPF_HIP_TRY(hipMemcpyAsync(b->d_dyn, b->h_dyn, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, run));
+  }
+  IEWPF_HIP_TRY(hipEventRecord(b->copy_ev, run));
+  b->copy_pending = true;
+  if (!use_graph) return batch_cycle_body(b, n_model_steps, first_step, analysis_index, nullptr, s);
+
+  if (!b->exec || b->graph_steps != n_model_steps) {
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);
+      (void)hipGraphDestroy(b->graph);
+      b->exec = nullptr;
+      b->graph = nullptr;
+    }
+    std::vector<bool> tr(b->n);
+    for (int e = 0; e < b->n; ++e) {
+      tr[e] = b->ctx[e]->trace;
+      b->ctx[e]->trace = false;  // no event records inside a capture
+    }
+    IEWPF_HIP_TRY(hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal));
+    const int rc = batch_cycle_body(b, n_model_steps, 0, 0, b->d_dyn, run);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(run, &g);
+    for (int e = 0; e < b->n; ++e) b->ctx[e]->trace = tr[e];
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ec != hipSuccess) return fail(IEWPF_E_HIP, std::string("graph capture: ") + hipGetErrorString(ec));
+    b->graph = g;
+    IEWPF_HIP_TRY(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    b->graph_steps = n_model_steps;
+  }
+  IEWPF_HIP_TRY(hipGraphLaunch(b->exec, run));
+  IEWPF_HIP_TRY(hipEventRecord(b->out_ev, run));
+  IEWPF_HIP_TRY(hipStreamWaitEvent(s, b->out_ev, 0));
+  return 0;
+}
+
+int iewpf_surrogate_window(iewpf_ctx* c, iewpf_net* net, float* state, int n_model_steps,
+                           uint64_t first_step, double drift_tol, double noise_scale,
+                           int32_t* n_fallback_out, double* drift_out, void* stream) {
+  if (!c || !net || !state || !n_fallback_out || n_model_steps < 1 || !(drift_tol >= 0))
+    return fail(IEWPF_E_ARG, "invalid argument");
+  hipStream_t s = as_stream(stream);
+  const size_t per = 3 * c->ncell;
+  if (!c->saved) {
+    IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->saved), sizeof(float) * per * c->ne));
+    IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->sdrift), sizeof(double) * c->ne));
+    IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->sflags), sizeof(int32_t) * c->ne));
+  }
+  IEWPF_HIP_TRY(hipMemcpyAsync(c->saved, state, sizeof(float) * per * c->ne, hipMemcpyDeviceToDevice, s));
+  if (int rc = iewpf_net_forward(net, c->saved, state, c->ne, c->ny, c->nx, stream)) return rc;
+  launch_mass_drift(c->saved, state, c->ne, (int)c->ncell, c->cfg.H, drift_tol, c->sdrift, c->sflags, s);
+  IEWPF_HIP_TRY(hipGetLastError());
+  std::vector<int32_t> flags(c->ne);
+  std::vector<double> drift(c->ne);
+  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  IEWPF_HIP_TRY(hipMemcpy(flags.data(), c->sflags, sizeof(int32_t) * c->ne, hipMemcpyDeviceToHost));
+  IEWPF_HIP_TRY(hipMemcpy(drift.data(), c->sdrift, sizeof(double) * c->ne, hipMemcpyDeviceToHost));
+  int nf = 0;
+  for (int i = 0; i < c->ne; ++i) {
+    if (!flags[i]) continue;
+    ++nf;  // plain deterministic model steps of particle i from its saved state
+    float* cur = state + per * i;
+    float* other = c->scratch + per * i;
+    IEWPF_HIP_TRY(hipMemcpyAsync(cur, c->saved + per * i, sizeof(float) * per, hipMemcpyDeviceToDevice, s));
+    for (int st = 0; st < n_model_steps; ++st)
+      for (int sub = 0; sub < c->cfg.n_sub; ++sub) {
+        launch_swe_substep(c->swe, 1, cur, other, nullptr, s);
+        std::swap(cur, other);
+      }
+    if (cur != state + per * i)
+      IEWPF_HIP_TRY(hipMemcpyAsync(state + per * i, cur, sizeof(float) * per, hipMemcpyDeviceToDevice, s));
+  }
+  if (noise_scale > 0.0) {  // one model-error draw for the window, scaled
+    float w[25];
+    for (int q = 0; q < 25; ++q) w[q] = (float)(noise_scale * c->soar_me[q]);
+    launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, first_step + n_model_steps - 1, kTagModelError,
+                   c->cfg.ensemble_id, s);
+    launch_soar(c->cc, w, c->ne, c->xi, c->coarse, s);
+    launch_gb_add(c->cc, c->ne, c->coarse, nullptr, state, c->upd_strip_h, s);
+  }
+  IEWPF_HIP_TRY(hipGetLastError());
+  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  *n_fallback_out = nf;
+  if (drift_out) std::memcpy(drift_out, drift.data(), sizeof(double) * c->ne);
   return 0;
 }
 

@@ -40,6 +40,21 @@ struct SweConst {
   float gb_x, gb_y;    // g H / (2 f dx), g H / (2 f dy)
 };
 
+// One ensemble of a batched stencil launch (device-resident table).
+struct SweJob {
+  SweConst C;
+  const float* z;   // fused model-error field of this launch or nullptr
+  float* buf_a;     // the caller's state
+  float* buf_b;     // the context's scratch state
+  int wave_begin;
+};
+constexpr int kMaxBatch = 16;
+struct SweJobTable {
+  int n;
+  int total_waves;
+  SweJob job[kMaxBatch];
+};
+
 // Coarse random grid and covariance stencils.
 struct CoarseConst {
   int nx, ny;          // fine grid
@@ -91,6 +106,7 @@ struct iewpf_ctx {
   double* sd = nullptr;        // [ne][max_obs][2]
   double* cval = nullptr;      // [ne]
   double* dots = nullptr;      // [ne][3]
+  double* part_dots = nullptr; // [ne][parts][3] partial dot products
   double* alpha = nullptr;     // [ne]
   double* cstar = nullptr;     // [ne]
   double* scal = nullptr;      // [16] analysis scalars
@@ -119,6 +135,10 @@ struct iewpf_ctx {
   int n_trace = 0;
   hipEvent_t* trace_ev = nullptr;   // [2 * kTraceMax]
   int* trace_kind = nullptr;        // [kTraceMax]
+  // surrogate window: saved input states and per-particle drift / flags
+  float* saved = nullptr;
+  double* sdrift = nullptr;
+  int32_t* sflags = nullptr;
 };
 
 namespace iewpf {
@@ -150,6 +170,39 @@ int build_local_block(const iewpf_ctx& ctx, double ahalf[49 * 49], double Sc[4])
 int inverse_spd2(const double A[4], double out[4]);
 }  // namespace iewpf
 
+// ---- surrogate network (surrogate_kernels.hip, surrogate_api.cpp) ----------------------------
+namespace iewpf {
+enum ConvIn { kInStateNorm = 0, kInNhwcVec = 1, kInNhwcSmall = 2 };
+enum ConvOut { kOutReluBf16 = 0, kOutResidState = 1, kOutF32 = 2, kOutMaskBf16 = 3 };
+struct ConvArgs {
+  int B, H, W;             // images and grid
+  int cin, cout;           // channels
+  int K, Kpad, Npad;       // K = 9 cin, padded to 32; output channels padded to 16
+  const void* in;          // kInStateNorm: float [B][3][H][W]; else bf16 [B][H][W][cin]
+  const uint16_t* wt;      // bf16 [Npad][Kpad]
+  const float* bias;       // [cout] or nullptr
+  void* out;               // by output mode
+  const float* state_in;   // kOutResidState: psi, float [B][3][H][W]
+  const uint16_t* mask;    // kOutMaskBf16: activation whose sign masks the output
+  float mu[3], isig[3], s[3];
+};
+void launch_conv(const ConvArgs& A, int in_mode, int out_mode, hipStream_t s);
+void launch_wgrad(const ConvArgs& A, int in_mode, const uint16_t* g, int gch, int cells_per_chunk,
+                  float* part, hipStream_t s);
+void launch_bgrad(const uint16_t* g, int gch, int ncells, int cells_per_chunk, float* part,
+                  hipStream_t s);
+void launch_reduce_grads(const float* wpart, const float* bpart, int nchunks, int cin, int cout,
+                         int Kpad, int Npad, float* gw, float* gb, hipStream_t s);
+void launch_mse(const float* y, const float* st_in, const float* st_tgt, int B, int H, int W,
+                const float sc[3], uint16_t* g, float* lpart, int nblocks, hipStream_t s);
+void launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
+                 float eps, float c1, float c2, hipStream_t s);
+void launch_prep_weights(const float* w, int cin, int cout, int Kf, int Npf, int Kd, int Npd,
+                         uint16_t* wf, uint16_t* wd, hipStream_t s);
+void launch_mass_drift(const float* before, const float* after, int ne, int ncell, double H,
+                       double tol, double* drift, int32_t* flags, hipStream_t s);
+}  // namespace iewpf
+
 // ---- launchers (kernels in *.hip) ---------------------------------------------------------
 namespace iewpf {
 // resident waves per compute unit of the stencil / analysis-update kernels (occupancy)
@@ -160,11 +213,13 @@ int update_particle_group();
 // wave marches), rounds = ceil(columns * n_strips / slots), rows = ceil(ny / n_strips) +
 // halo_rows.  columns = strips per row of strips (all particles).
 int choose_row_strips(int columns, int ny, int slots, int halo_rows, int min_rows);
+void launch_swe_batch(const SweJobTable* tab, int total_waves, int parity, bool noise,
+                      hipStream_t s);
 // z != nullptr: also add the model error Q_GB I_Omega z (z: [ne][nry][nrx] SOAR field)
 void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, const float* z,
                         hipStream_t s);
 void launch_normals(float* out, int n, int ne, uint64_t seed, uint64_t step, uint32_t tag,
-                    uint32_t ens, hipStream_t s);
+                    uint32_t ens, hipStream_t s, const uint64_t* dyn = nullptr);
 void launch_soar(const CoarseConst& C, const float* w25, int ne, const float* in, float* out,
                  hipStream_t s);
 // psi (+)= Q_GB I_Omega z  [+ pull];  base != nullptr: psi = base + ...
@@ -177,8 +232,10 @@ void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, co
 void launch_innovation(int ne, int n_obs, int max_obs, int nx, int ny, double H, const double S[4],
                        const float* psi, const int32_t* cells, const double* y, double* sd,
                        double* cval, hipStream_t s);
+int rand_dots_parts();
 void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens, float* xi,
-                      float* nu, double* dots, hipStream_t s);
+                      float* nu, double* part_dots, double* dots, hipStream_t s,
+                      const uint64_t* dyn = nullptr);
 void launch_sync(int ne, double n_psi, double n_r, const double* cval, const double* dots,
                  double* alpha, double* cstar, double* scal, hipStream_t s);
 void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,

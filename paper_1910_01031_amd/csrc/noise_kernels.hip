@@ -33,17 +33,54 @@ __device__ __forceinline__ void cr4(float t, float w[4]) {
   w[3] = 0.5f * (t3 - t2);
 }
 
+// x-interpolated coarse rows around the current fine row (see swe_kernels.hip for the
+// same scheme): the window advances one coarse row every c fine rows.
+struct CoarseWin {
+  float xr[4];
+  int by;
+  __device__ __forceinline__ float xrow(const float* __restrict__ z, const CoarseConst& C,
+                                        const int cx[4], const float wx[4], int b) const {
+    const float* row = z + (size_t)wrap1(b, C.nry) * C.nrx;
+    return wx[0] * row[cx[0]] + wx[1] * row[cx[1]] + wx[2] * row[cx[2]] + wx[3] * row[cx[3]];
+  }
+  __device__ __forceinline__ void init(const float* __restrict__ z, const CoarseConst& C,
+                                       const int cx[4], const float wx[4], int s) {
+    by = floordiv(2 * s + 1 - C.c, 2 * C.c);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) xr[n] = xrow(z, C, cx, wx, by + n - 1);
+  }
+  // fine row s (unwrapped), called with s increasing by one
+  __device__ __forceinline__ float at(const float* __restrict__ z, const CoarseConst& C,
+                                      const int cx[4], const float wx[4], int s) {
+    const int num = 2 * s + 1 - C.c;
+    const int b = floordiv(num, 2 * C.c);
+    if (b != by) {
+      xr[0] = xr[1];
+      xr[1] = xr[2];
+      xr[2] = xr[3];
+      xr[3] = xrow(z, C, cx, wx, b + 2);
+      by = b;
+    }
+    float wy[4];
+    cr4(static_cast<float>(num - 2 * C.c * b) / static_cast<float>(2 * C.c), wy);
+    return wy[0] * xr[0] + wy[1] * xr[1] + wy[2] * xr[2] + wy[3] * xr[3];
+  }
+};
+
 struct Stencil25 {
   float w[25];
 };
 
+// step index = step + dyn[0] when dyn is set (counters read from device memory so that a
+// captured graph advances its streams between replays)
 __global__ __launch_bounds__(256) void normals_kernel(float* __restrict__ out, int n, uint64_t seed,
-                                                      uint64_t step, uint32_t tag, uint32_t ens) {
+                                                      uint64_t step, uint32_t tag, uint32_t ens,
+                                                      const uint64_t* __restrict__ dyn) {
   const int blk = blockIdx.x * blockDim.x + threadIdx.x;
   const int particle = blockIdx.y;
   if (4 * blk >= n) return;
   double z[4];
-  normals4(blk, step, tag, ens, particle, seed, z);
+  normals4(blk, step + (dyn ? dyn[0] : 0), tag, ens, particle, seed, z);
   float* o = out + (size_t)particle * n;
 #pragma unroll
   for (int l = 0; l < 4; ++l)
@@ -132,13 +169,15 @@ __global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, PullConst P,
   const int k0 = sy * strip_h;
   const int k_end = min(k0 + strip_h, ny);
   float dm2 = 0.0f, dm1 = 0.0f;  // d_eta rows m-2, m-1
+  CoarseWin win;
+  win.init(z, C, cx, wx, k0 - 1);
   int o_beg = 0, o_end = 0;
   if (PULL) {
     o_beg = st_off[strip];
     o_end = st_off[strip + 1];
   }
   for (int m = k0 - 1; m <= k_end; ++m) {
-    const float d0 = bicubic_at(z, C, cx, wx, wrap1(m, ny));
+    const float d0 = win.at(z, C, cx, wx, m);
     if (m >= k0 + 1) {
       const int k = m - 1;
       const float de = dm1;
@@ -230,14 +269,17 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
   const int k_end = min(k0 + P.strip_h, ny);
   const int o_beg = st_off[strip], o_end = st_off[strip + 1];
   float dm2[kPB], dm1[kPB];
+  CoarseWin win[kPB];
 #pragma unroll
-  for (int p = 0; p < kPB; ++p) dm2[p] = dm1[p] = 0.0f;
+  for (int p = 0; p < kPB; ++p) {
+    dm2[p] = dm1[p] = 0.0f;
+    win[p].init(zall + (size_t)min(p0 + p, ne - 1) * C.nrx * C.nry, C, cx, wx, k0 - 1);
+  }
   for (int m = k0 - 1; m <= k_end; ++m) {
     float d0[kPB];
 #pragma unroll
     for (int p = 0; p < kPB; ++p)
-      d0[p] = p < np ? bicubic_at(zall + (size_t)(p0 + p) * C.nrx * C.nry, C, cx, wx, wrap1(m, ny))
-                     : 0.0f;
+      d0[p] = win[p].at(zall + (size_t)min(p0 + p, ne - 1) * C.nrx * C.nry, C, cx, wx, m);
     if (m >= k0 + 1) {
       const int k = m - 1;
       float ae[kPB], au[kPB], av[kPB];
@@ -314,10 +356,10 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
 }  // namespace
 
 void launch_normals(float* out, int n, int ne, uint64_t seed, uint64_t step, uint32_t tag,
-                    uint32_t ens, hipStream_t s) {
+                    uint32_t ens, hipStream_t s, const uint64_t* dyn) {
   const int nblk = (n + 3) / 4;
   hipLaunchKernelGGL(normals_kernel, dim3((nblk + 255) / 256, ne), dim3(256), 0, s, out, n, seed,
-                     step, tag, ens);
+                     step, tag, ens, dyn);
 }
 
 void launch_soar(const CoarseConst& C, const float* w25, int ne, const float* in, float* out,

@@ -1,0 +1,426 @@
+// Learned surrogate forecast: six 3x3 periodic convolutions (3 -> 48 x5 -> 3) in BF16 on
+// the matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation), its backward pass,
+// MSE loss, Adam and the mass-drift guard.
+//
+// Convolution as an implicit GEMM: M = output cells (16 consecutive cells of one row per
+// MFMA tile), N = output channels (tiles of 16), K = 9 taps x input channels (ordered
+// k = tap * C_in + c, tap = 3 ky + kx, padded to a multiple of 32).  Fragment layout of
+// v_mfma_f32_16x16x32_bf16: lane l holds row (l % 16) of A and column (l % 16) of B with
+// K elements 8 (l / 16) .. 8 (l / 16) + 7, and D rows 4 (l / 16) .. +3 of column l % 16.
+// Weights are stored transposed, Wt[n][k] (bf16), so a lane reads its 8 K values as one
+// 16-byte load; activations are NHWC bf16 so 8 consecutive channels of one tap are one
+// 16-byte load (C_in multiple of 8) or gathered element by element (C_in = 3).
+#include "internal.hpp"
+
+namespace iewpf {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// float -> bf16 bits, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+}  // namespace
+
+namespace {
+
+constexpr int kMT = 2;  // 16-cell M tiles per wave
+
+template <int IN>
+__device__ __forceinline__ bf16x8 load_a(const ConvArgs& A, int b, int y, int x, int k0) {
+  bf16x8 v;
+  if (IN == kInNhwcVec) {
+    if (k0 >= A.K) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = (__bf16)0.0f;
+      return v;
+    }
+    const int tap = k0 / A.cin, c0 = k0 - tap * A.cin;
+    const int ys = wrapc(y + tap / 3 - 1, A.H), xs = wrapc(x + tap % 3 - 1, A.W);
+    const uint16_t* p = static_cast<const uint16_t*>(A.in) +
+                        (((size_t)b * A.H + ys) * A.W + xs) * A.cin + c0;
+    const uint4 raw = *reinterpret_cast<const uint4*>(p);
+    v = __builtin_bit_cast(bf16x8, raw);
+    return v;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = k0 + i;
+      float f = 0.0f;
+      if (k < A.K) {
+        const int tap = k / A.cin, c = k - tap * A.cin;
+        const int ys = wrapc(y + tap / 3 - 1, A.H), xs = wrapc(x + tap % 3 - 1, A.W);
+        if (IN == kInStateNorm) {
+          const float* st = static_cast<const float*>(A.in);
+          const float val = st[(((size_t)b * 3 + c) * A.H + ys) * A.W + xs];
+          f = bf2f(f2bf((val - A.mu[c]) * A.isig[c]));
+        } else {
+          const uint16_t* q = static_cast<const uint16_t*>(A.in);
+          f = bf2f(q[(((size_t)b * A.H + ys) * A.W + xs) * A.cin + c]);
+        }
+      }
+      v[i] = (__bf16)f;
+    }
+    return v;
+  }
+}
+
+template <int IN, int OUT, int NT>
+__global__ __launch_bounds__(256) void conv3x3_mfma_kernel(ConvArgs A, int total_waves) {
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wave >= total_waves) return;
+  const int xt = (A.W + 16 * kMT - 1) / (16 * kMT);
+  const int b = wave / (A.H * xt);
+  const int r = wave - b * A.H * xt;
+  const int y = r / xt;
+  const int x0 = (r - y * xt) * 16 * kMT;
+  const int row = lane & 15, kq = lane >> 4;
+  f32x4 acc[kMT][NT];
+#pragma unroll
+  for (int m = 0; m < kMT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  const int nchunks = A.Kpad / 32;
+  for (int kc = 0; kc < nchunks; ++kc) {
+    const int k0 = kc * 32 + kq * 8;
+    bf16x8 bfr[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const uint16_t* p = A.wt + (size_t)(t * 16 + row) * A.Kpad + k0;
+      bfr[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+    }
+#pragma unroll
+    for (int m = 0; m < kMT; ++m) {
+      const int x = wrapc(x0 + m * 16 + row, A.W);
+      const bf16x8 afr = load_a<IN>(A, b, y, x, k0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[t], acc[m][t], 0, 0, 0);
+    }
+  }
+  // epilogue: lane holds cells 4 kq .. 4 kq + 3 of column n = 16 t + row
+#pragma unroll
+  for (int m = 0; m < kMT; ++m) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int n = t * 16 + row;
+      if (n >= A.cout) continue;
+      const float bn = A.bias ? A.bias[n] : 0.0f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int x = x0 + m * 16 + kq * 4 + q;
+        if (x >= A.W) continue;
+        const size_t cell = ((size_t)b * A.H + y) * A.W + x;
+        const float v = acc[m][t][q] + bn;
+        if (OUT == kOutReluBf16) {
+          static_cast<uint16_t*>(A.out)[cell * A.cout + n] = f2bf(fmaxf(v, 0.0f));
+        } else if (OUT == kOutF32) {
+          static_cast<float*>(A.out)[cell * A.cout + n] = v;
+        } else if (OUT == kOutMaskBf16) {
+          const bool on = bf2f(A.mask[cell * A.cout + n]) > 0.0f;
+          static_cast<uint16_t*>(A.out)[cell * A.cout + n] = f2bf(on ? v : 0.0f);
+        } else {  // residual into the state: psi' = psi + s (net)
+          const size_t o = (((size_t)b * 3 + n) * A.H + y) * A.W + x;
+          static_cast<float*>(A.out)[o] = A.state_in[o] + A.s[n] * v;
+        }
+      }
+    }
+  }
+}
+
+// Weight gradient of one layer over a chunk of cells: dW[n][k] = sum_cells g[cell][n] *
+// a(cell shifted by tap(k))[c(k)], as MFMA with M = n (16-tiles), N = k (16-tiles),
+// K = cells (32 per step).  Partial sums per chunk go to part[chunk][Npad][Kpad].
+template <int IN>
+__global__ __launch_bounds__(256) void wgrad_mfma_kernel(ConvArgs A, const uint16_t* __restrict__ g,
+                                                         int gch, int cells_per_chunk,
+                                                         float* __restrict__ part, int total_waves) {
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wave >= total_waves) return;
+  const int ktiles = A.Kpad / 16;
+  const int chunk = wave / ktiles;
+  const int ktile = wave - chunk * ktiles;
+  const int row = lane & 15, kq = lane >> 4;
+  const int ncells = A.B * A.H * A.W;
+  const int c_begin = chunk * cells_per_chunk;
+  const int c_end = min(c_begin + cells_per_chunk, ncells);
+  const int mtiles = A.Npad / 16;
+  f32x4 acc[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  const int k = ktile * 16 + row;  // B column of this lane
+  int tap = 0, c = 0;
+  if (k < A.K) {
+    tap = k / A.cin;
+    c = k - tap * A.cin;
+  }
+  for (int p0 = c_begin; p0 < c_end; p0 += 32) {
+    bf16x8 bfr;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int p = p0 + kq * 8 + i;
+      float f = 0.0f;
+      if (p < c_end && k < A.K) {
+        const int b = p / (A.H * A.W);
+        const int rr = p - b * A.H * A.W;
+        const int yy = rr / A.W, xx = rr - yy * A.W;
+        const int ys = wrapc(yy + tap / 3 - 1, A.H), xs = wrapc(xx + tap % 3 - 1, A.W);
+        if (IN == kInStateNorm) {
+          const float* st = static_cast<const float*>(A.in);
+          f = bf2f(f2bf((st[(((size_t)b * 3 + c) * A.H + ys) * A.W + xs] - A.mu[c]) * A.isig[c]));
+        } else {
+          const uint16_t* q = static_cast<const uint16_t*>(A.in);
+          f = bf2f(q[(((size_t)b * A.H + ys) * A.W + xs) * A.cin + c]);
+        }
+      }
+      bfr[i] = (__bf16)f;
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (t >= mtiles) break;
+      bf16x8 afr;
+      const int n = t * 16 + row;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int p = p0 + kq * 8 + i;
+        afr[i] = (__bf16)((p < c_end && n < gch) ? bf2f(g[(size_t)p * gch + n]) : 0.0f);
+      }
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr, acc[t], 0, 0, 0);
+    }
+  }
+  // D: rows n = 16 t + 4 kq + q, column k
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (t >= mtiles) break;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = t * 16 + kq * 4 + q;
+      part[((size_t)chunk * A.Npad + n) * A.Kpad + k] = acc[t][q];
+    }
+  }
+}
+
+// bias gradient partials: part[chunk][n] = sum over the chunk's cells of g[cell][n]
+__global__ void bgrad_kernel(const uint16_t* __restrict__ g, int gch, int ncells, int cells_per_chunk,
+                             float* __restrict__ part) {
+  const int chunk = blockIdx.x;
+  const int n = threadIdx.x;
+  if (n >= gch) return;
+  const int c0 = chunk * cells_per_chunk, c1 = min(c0 + cells_per_chunk, ncells);
+  float s = 0.0f;
+  for (int p = c0; p < c1; ++p) s += bf2f(g[(size_t)p * gch + n]);
+  part[(size_t)chunk * gch + n] = s;
+}
+
+// Sum partials over chunks in fixed order into the FP32 gradient of one layer
+// ([cout][cin][3][3] then [cout]).
+__global__ void reduce_grads_kernel(const float* __restrict__ wpart, const float* __restrict__ bpart,
+                                    int nchunks, int cin, int cout, int Kpad, int Npad,
+                                    float* __restrict__ gw, float* __restrict__ gb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nw = cout * cin * 9;
+  if (i < nw) {
+    const int n = i / (cin * 9);
+    const int rem = i - n * cin * 9;
+    const int c = rem / 9, tap = rem - c * 9;
+    const int k = tap * cin + c;
+    float s = 0.0f;
+    for (int q = 0; q < nchunks; ++q) s += wpart[((size_t)q * Npad + n) * Kpad + k];
+    gw[i] = s;
+  } else if (i < nw + cout) {
+    const int n = i - nw;
+    float s = 0.0f;
+    for (int q = 0; q < nchunks; ++q) s += bpart[(size_t)q * cout + n];
+    gb[n] = s;
+  }
+}
+
+// MSE of the network output y (float [cells][3]) against the normalised increment
+// (target - state)/s: per-block partial losses and g = bf16(2 (y - t) / n).
+__global__ void mse_kernel(const float* __restrict__ y, const float* __restrict__ st_in,
+                           const float* __restrict__ st_tgt, int B, int H, int W, float s0, float s1,
+                           float s2, uint16_t* __restrict__ g, float* __restrict__ lpart) {
+  __shared__ float sh[256];
+  const int ncells = B * H * W;
+  const float inv_n = 1.0f / (3.0f * ncells);
+  const float s[3] = {s0, s1, s2};
+  float acc = 0.0f;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < ncells; p += gridDim.x * blockDim.x) {
+    const int b = p / (H * W), rr = p - b * H * W;
+    for (int ch = 0; ch < 3; ++ch) {
+      const size_t o = ((size_t)b * 3 + ch) * H * W + rr;
+      const float t = (st_tgt[o] - st_in[o]) / s[ch];
+      const float d = y[(size_t)p * 3 + ch] - t;
+      acc += d * d;
+      g[(size_t)p * 3 + ch] = f2bf(2.0f * d * inv_n);
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) lpart[blockIdx.x] = sh[0] * inv_n;
+}
+
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int n, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Forward and transposed (input-gradient) bf16 layouts of one layer from its FP32 master
+// weights w[cout][cin][3][3]: wf[n][tap cin + c] = w[n][c][tap];
+// wd[c][tap' cout + n] = w[n][c][8 - tap'] (spatially flipped, channels swapped).
+__global__ void prep_weights_kernel(const float* __restrict__ w, int cin, int cout, int Kf, int Npf,
+                                    int Kd, int Npd, uint16_t* __restrict__ wf,
+                                    uint16_t* __restrict__ wd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nf = Npf * Kf, nd = wd ? Npd * Kd : 0;
+  if (i < nf) {
+    const int n = i / Kf, k = i - n * Kf;
+    float v = 0.0f;
+    if (n < cout && k < 9 * cin) {
+      const int tap = k / cin, c = k - tap * cin;
+      v = w[((size_t)n * cin + c) * 9 + tap];
+    }
+    wf[i] = f2bf(v);
+  } else if (i < nf + nd) {
+    const int j = i - nf;
+    const int c = j / Kd, k = j - c * Kd;
+    float v = 0.0f;
+    if (c < cin && k < 9 * cout) {
+      const int tap = k / cout, n = k - tap * cout;
+      v = w[((size_t)n * cin + c) * 9 + (8 - tap)];
+    }
+    wd[j] = f2bf(v);
+  }
+}
+
+// Per-particle relative mass drift |sum(H + eta') - sum(H + eta)| / sum(H + eta) in FP64;
+// flags[i] = drift > tol.
+__global__ void mass_drift_kernel(const float* __restrict__ before, const float* __restrict__ after,
+                                  int ncell, double H, double tol, double* __restrict__ drift,
+                                  int32_t* __restrict__ flags) {
+  __shared__ double sa[256], sb[256];
+  const int i = blockIdx.x;
+  const float* e0 = before + (size_t)i * 3 * ncell;
+  const float* e1 = after + (size_t)i * 3 * ncell;
+  double a = 0.0, b = 0.0;
+  for (int c = threadIdx.x; c < ncell; c += 256) {
+    a += (double)e0[c];
+    b += (double)e1[c];
+  }
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sa[threadIdx.x] += sa[threadIdx.x + w];
+      sb[threadIdx.x] += sb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double m0 = H * ncell + sa[0], m1 = H * ncell + sb[0];
+    const double d = fabs(m1 - m0) / m0;
+    drift[i] = d;
+    flags[i] = (d > tol || !isfinite(d)) ? 1 : 0;
+  }
+}
+
+template <int IN, int OUT, int NT>
+void launch_conv_t(const ConvArgs& A, hipStream_t s) {
+  const int xt = (A.W + 16 * kMT - 1) / (16 * kMT);
+  const int waves = A.B * A.H * xt;
+  hipLaunchKernelGGL((conv3x3_mfma_kernel<IN, OUT, NT>), dim3((waves + 3) / 4), dim3(256), 0, s, A,
+                     waves);
+}
+
+}  // namespace
+
+void launch_conv(const ConvArgs& A, int in_mode, int out_mode, hipStream_t s) {
+  const int nt = A.Npad / 16;
+#define IEWPF_CONV_CASE(I, O, T) \
+  if (in_mode == I && out_mode == O && nt == T) return launch_conv_t<I, O, T>(A, s);
+  IEWPF_CONV_CASE(kInStateNorm, kOutReluBf16, 3)
+  IEWPF_CONV_CASE(kInNhwcVec, kOutReluBf16, 3)
+  IEWPF_CONV_CASE(kInNhwcVec, kOutResidState, 1)
+  IEWPF_CONV_CASE(kInNhwcVec, kOutF32, 1)
+  IEWPF_CONV_CASE(kInNhwcVec, kOutMaskBf16, 3)
+  IEWPF_CONV_CASE(kInNhwcSmall, kOutMaskBf16, 3)
+#undef IEWPF_CONV_CASE
+}
+
+void launch_wgrad(const ConvArgs& A, int in_mode, const uint16_t* g, int gch, int cells_per_chunk,
+                  float* part, hipStream_t s) {
+  const int ncells = A.B * A.H * A.W;
+  const int nchunks = (ncells + cells_per_chunk - 1) / cells_per_chunk;
+  const int waves = nchunks * (A.Kpad / 16);
+  if (in_mode == kInStateNorm)
+    hipLaunchKernelGGL(wgrad_mfma_kernel<kInStateNorm>, dim3((waves + 3) / 4), dim3(256), 0, s, A, g,
+                       gch, cells_per_chunk, part, waves);
+  else
+    hipLaunchKernelGGL(wgrad_mfma_kernel<kInNhwcVec>, dim3((waves + 3) / 4), dim3(256), 0, s, A, g,
+                       gch, cells_per_chunk, part, waves);
+}
+
+void launch_bgrad(const uint16_t* g, int gch, int ncells, int cells_per_chunk, float* part,
+                  hipStream_t s) {
+  const int nchunks = (ncells + cells_per_chunk - 1) / cells_per_chunk;
+  hipLaunchKernelGGL(bgrad_kernel, dim3(nchunks), dim3(64), 0, s, g, gch, ncells, cells_per_chunk,
+                     part);
+}
+
+void launch_reduce_grads(const float* wpart, const float* bpart, int nchunks, int cin, int cout,
+                         int Kpad, int Npad, float* gw, float* gb, hipStream_t s) {
+  const int n = cout * cin * 9 + cout;
+  hipLaunchKernelGGL(reduce_grads_kernel, dim3((n + 255) / 256), dim3(256), 0, s, wpart, bpart,
+                     nchunks, cin, cout, Kpad, Npad, gw, gb);
+}
+
+void launch_mse(const float* y, const float* st_in, const float* st_tgt, int B, int H, int W,
+                const float sc[3], uint16_t* g, float* lpart, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(mse_kernel, dim3(nblocks), dim3(256), 0, s, y, st_in, st_tgt, B, H, W, sc[0],
+                     sc[1], sc[2], g, lpart);
+}
+
+void launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2,
+                 float eps, float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2,
+                     eps, c1, c2);
+}
+
+void launch_prep_weights(const float* w, int cin, int cout, int Kf, int Npf, int Kd, int Npd,
+                         uint16_t* wf, uint16_t* wd, hipStream_t s) {
+  const int n = Npf * Kf + (wd ? Npd * Kd : 0);
+  hipLaunchKernelGGL(prep_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w, cin, cout, Kf,
+                     Npf, Kd, Npd, wf, wd);
+}
+
+void launch_mass_drift(const float* before, const float* after, int ne, int ncell, double H,
+                       double tol, double* drift, int32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(mass_drift_kernel, dim3(ne), dim3(256), 0, s, before, after, ncell, H, tol,
+                     drift, flags);
+}
+
+}  // namespace iewpf

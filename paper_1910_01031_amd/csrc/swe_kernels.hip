@@ -217,13 +217,10 @@ struct CoarseRows {
 #define IEWPF_SWE_MIN_BLOCKS 1
 #endif
 template <bool NOISE>
-__global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_substep_kernel(const float* __restrict__ in,
-                                                          float* __restrict__ out,
-                                                          const float* __restrict__ zall,
-                                                          SweConst C, int total_waves) {
+__device__ __forceinline__ void substep_wave(const float* __restrict__ in, float* __restrict__ out,
+                                             const float* __restrict__ zall, const SweConst& C,
+                                             int wave) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  if (wave >= total_waves) return;  // whole wave exits together
   const int per_particle = C.n_strip_x * C.n_strip_y;
   const int particle = wave / per_particle;
   const int rem = wave - particle * per_particle;
@@ -302,8 +299,35 @@ __global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_substep_kernel(
   };
   for (int m = k0 - 4; m < k0; ++m) step(m, false, false);
   for (int m = k0; m < k0 + 4; ++m) step(m, true, false);
-#pragma unroll 4
   for (int m = k0 + 4; m <= k_end + 3; ++m) step(m, true, true);
+}
+
+template <bool NOISE>
+__global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_substep_kernel(
+    const float* __restrict__ in, float* __restrict__ out, const float* __restrict__ zall,
+    SweConst C, int total_waves) {
+  const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  if (wave >= total_waves) return;  // whole wave exits together
+  substep_wave<NOISE>(in, out, zall, C, wave);
+}
+
+// Several ensembles of different grids in one launch: the waves of ensemble e are
+// [job[e].wave_begin, job[e+1].wave_begin); parity selects which of the two buffers of
+// every ensemble is the input.  NOISE applies to the ensembles whose z is set.
+template <bool NOISE>
+__global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_batch_kernel(
+    const SweJobTable* __restrict__ tab, int parity) {
+  const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  if (wave >= tab->total_waves) return;
+  int e = 0;
+  while (e + 1 < tab->n && wave >= tab->job[e + 1].wave_begin) ++e;
+  const SweJob& J = tab->job[e];
+  const float* in = parity ? J.buf_b : J.buf_a;
+  float* out = parity ? J.buf_a : J.buf_b;
+  if (NOISE && J.z != nullptr)
+    substep_wave<true>(in, out, J.z, J.C, wave - J.wave_begin);
+  else
+    substep_wave<false>(in, out, nullptr, J.C, wave - J.wave_begin);
 }
 
 }  // namespace
@@ -314,6 +338,15 @@ int swe_waves_per_cu() {
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, swe_substep_kernel<false>, 256, 0) != hipSuccess)
     return 16;
   return 4 * std::max(1, std::min(a, b));
+}
+
+void launch_swe_batch(const SweJobTable* tab, int total_waves, int parity, bool noise,
+                      hipStream_t s) {
+  const int blocks = (total_waves + 3) / 4;
+  if (noise)
+    hipLaunchKernelGGL(swe_batch_kernel<true>, dim3(blocks), dim3(256), 0, s, tab, parity);
+  else
+    hipLaunchKernelGGL(swe_batch_kernel<false>, dim3(blocks), dim3(256), 0, s, tab, parity);
 }
 
 void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, const float* z,

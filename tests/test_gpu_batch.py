@@ -1,0 +1,142 @@
+"""GPU tests of the batched path (several ensembles of uneven grids in one launch per scheme
+step) and of its hipGraph capture: bit-equality with the single-ensemble path, every
+graph replay equal to the eager cycle (with eager work and synchronisations between
+replays), and parity of one batched cycle with the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ensemble as oens
+from oracle import iewpf as oiewpf
+from oracle import observe as oobs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1910_01031_amd import load
+    load()
+    return torch, torch.device("cuda:0")
+
+
+SPECS = [((64, 48), 4, 5, (3, 2)), ((40, 56), 4, 3, (2, 3)), ((45, 35), 5, 4, (3, 2))]
+
+
+def _make(torch, dev, spread=0.004):
+    from paper_1910_01031_amd import Context
+    cfgs, ctxs, ens, cells, ys = [], [], [], [], []
+    for e, ((nx, ny), c, ne, lat) in enumerate(SPECS):
+        cfg = W.Config(nx=nx, ny=ny, dx=5e3, dy=5e3, c_omega=c, n_sub=2, n_particles=ne,
+                       ensemble_id=e, me_std=2e-3)
+        base = oens.init_member(cfg, None, 0, 999)
+        small = cfg.replace(init_std=spread)
+        x = W.as_f32(np.stack([oens.init_member(small, base, 1, i) for i in range(ne)]))
+        truth = oens.init_member(small.replace(ensemble_id=77 + e), base, 1, 0)
+        cl = W.buoy_cells(nx, ny, *lat)
+        y = oobs.mooring_obs(truth, cl, cfg.H, cfg.obs_sigma, np.zeros((len(cl), 2)))
+        cfgs.append(cfg)
+        ctxs.append(Context(cfg, max_obs=16))
+        ens.append(x)
+        cells.append(cl)
+        ys.append(y)
+    return cfgs, ctxs, ens, cells, ys
+
+
+def test_batched_cycle_equals_single_ensemble_path(torch_dev):
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Batch
+    _say("batched cycle vs single-ensemble cycles")
+    cfgs, ctxs, ens, cells, ys = _make(torch, dev)
+    single = [torch.from_numpy(x.copy()).to(dev) for x in ens]
+    for e in range(len(cfgs)):
+        ctxs[e].step_ensemble(single[e], 3, first_step=10, noise_on_last=False)
+        ctxs[e].assimilate(single[e], cells[e], ys[e], analysis_index=4, want_stats=False)
+    batched = [torch.from_numpy(x.copy()).to(dev) for x in ens]
+    b = Batch(ctxs, batched)
+    for e in range(len(cfgs)):
+        b.set_cells(e, cells[e])
+    b.cycle(3, 10, 4, ys, use_graph=False)
+    torch.cuda.synchronize()
+    for e in range(len(cfgs)):
+        assert torch.equal(single[e], batched[e]), e
+    b.close()
+
+
+def test_graph_replays_equal_eager(torch_dev):
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Batch
+    _say("graph replays vs eager cycles")
+    cfgs, ctxs, ens, cells, ys = _make(torch, dev)
+    eager = [torch.from_numpy(x.copy()).to(dev) for x in ens]
+    graph = [torch.from_numpy(x.copy()).to(dev) for x in ens]
+    # two batches over the same contexts would share workspaces: use separate contexts
+    from paper_1910_01031_amd import Context
+    ctxs2 = [Context(cfg, max_obs=16) for cfg in cfgs]
+    be = Batch(ctxs, eager)
+    bg = Batch(ctxs2, graph)
+    for e in range(len(cfgs)):
+        be.set_cells(e, cells[e])
+        bg.set_cells(e, cells[e])
+    for cyc in range(4):
+        yc = [y + 0.1 * cyc for y in ys]
+        be.cycle(3, 3 * cyc, cyc, yc, use_graph=False)
+        torch.cuda.synchronize()
+        bg.cycle(3, 3 * cyc, cyc, yc, use_graph=True)
+        torch.cuda.synchronize()
+        _ = sum(float(g.abs().sum()) for g in graph)  # eager torch work between replays
+        for e in range(len(cfgs)):
+            assert torch.equal(eager[e], graph[e]), (cyc, e)
+    be.close()
+    bg.close()
+
+
+def test_batched_cycle_oracle_parity(torch_dev):
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Batch
+    _say("batched cycle vs oracle")
+    cfgs, ctxs, ens, cells, ys = _make(torch, dev)
+    st = [torch.from_numpy(x.copy()).to(dev) for x in ens]
+    b = Batch(ctxs, st)
+    for e in range(len(cfgs)):
+        b.set_cells(e, cells[e])
+    b.cycle(2, 6, 2, ys, use_graph=True)
+    torch.cuda.synchronize()
+    for e, cfg in enumerate(cfgs):
+        got = st[e].cpu().numpy().astype(np.float64)
+        fc = np.stack([oens.step_member(ens[e][i], cfg, i, 6, 2, noise_on_last=False)
+                       for i in range(cfg.n_particles)])
+        ref, info = oiewpf.analysis(W.as_f32(fc).astype(np.float64), cells[e], ys[e], cfg, 2)
+        for f in range(3):
+            err = np.abs(got[:, f] - ref[:, f]).max() / np.abs(ref[:, f]).max()
+            _say(f"  ensemble {e} field {f} rel err {err}")
+            assert err < 2e-5
+    b.close()
+
+
+def test_autotune_keeps_results(torch_dev):
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Context
+    cfg = W.Config(nx=120, ny=90, dx=5e3, dy=5e3, n_sub=2, n_particles=4)
+    rng = np.random.default_rng(1)
+    ens = W.as_f32(np.stack([W.random_state(cfg, rng) for _ in range(4)]))
+    a = Context(cfg, max_obs=4)
+    t = torch.from_numpy(ens.copy()).to(dev)
+    h = a.autotune(t)
+    assert 16 <= h <= 96
+    assert torch.equal(t, torch.from_numpy(ens).to(dev))  # state untouched
+    b = Context(cfg, max_obs=4)
+    ta, tb = t.clone(), t.clone()
+    a.step_ensemble(ta, 2, 0, True)
+    b.step_ensemble(tb, 2, 0, True)
+    torch.cuda.synchronize()
+    assert torch.equal(ta, tb)  # the strip height does not change results
