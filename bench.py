@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--particles", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-train-steps", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 360 MB device copy (counter calibration)")
     return ap.parse_args()
@@ -140,6 +142,90 @@ def side_legs(torch, dev, ctx, ens, cfg):
     return {"drifter_forecast_ms_per_model_step": e0.elapsed_time(e1) / 10,
             "drifters": int(pos.shape[0] * pos.shape[1]),
             "resample_ms": e1.elapsed_time(e2)}
+
+
+def surrogate_leg(torch, dev, ctx, ens, cfg, train_steps: int):
+    """Learned surrogate of the 5-minute window on the paper-scale ensemble.  Training pairs
+    (psi, ten deterministic model steps of psi) come from the same workload's own forecast:
+    four windows of a 100-particle ensemble drawn around the jet with its own random
+    streams (400 states of 500x300, 60 M cells); held-out pairs from one window of another
+    ensemble.  Reports the training time, held-out RMSE against the plain forecast (and
+    persistence for scale), the time of the network forward alone and of the guarded window
+    against ten plain model steps, and the fallbacks."""
+    from paper_1910_01031_amd import Net, surrogate_window
+    from paper_1910_01031_amd import surrogate as sur
+    base = W.jet_state(cfg)
+    t0 = time.perf_counter()
+    pairs = sur.make_pairs(torch, cfg, 400, base, group=cfg.n_particles, spinup_steps=10,
+                           windows_per_group=4, stream_base=100)
+    held = sur.make_pairs(torch, cfg, 100, base, group=cfg.n_particles, spinup_steps=30,
+                          windows_per_group=1, stream_base=900)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    net = Net(cfg.n_particles * cfg.n_cells)
+    net.set_params(sur.init_params(0))
+    t0 = time.perf_counter()
+    hist = sur.train(net, pairs, train_steps, batch=1, log_every=max(1, train_steps // 5))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    held.mu, held.sigma, held.scale = pairs.mu, pairs.sigma, pairs.scale
+    rmse, persist = sur.evaluate(torch, net, held, batch=25)
+    del pairs, held
+
+    start = ens.clone()
+    out = torch.empty_like(ens)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    reps = 3
+    net.forward(start, out)
+    e[0].record()
+    for r in range(reps):
+        net.forward(start, out)
+    e[1].record()
+    plain = ens.clone()
+    e[2].record()
+    for r in range(reps):
+        ctx.step_ensemble(plain, 10, first_step=500_000 + 10 * r, noise_on_last=True)
+    e[3].record()
+    sst = start.clone()
+    nfs = []
+    e[4].record()
+    for r in range(reps):
+        nf, _ = surrogate_window(ctx, net, sst, 10, 500_000 + 10 * r, drift_tol=1e-4,
+                                 noise_scale=3.0)
+        nfs.append(nf)
+    e[5].record()
+    torch.cuda.synchronize()
+    fwd_ms = e[0].elapsed_time(e[1]) / reps
+    plain_ms = e[2].elapsed_time(e[3]) / reps
+    sur_ms = e[4].elapsed_time(e[5]) / reps
+    # accuracy on the benchmark ensemble: one deterministic window from the same states
+    pdet = start.clone()
+    for k in range(10):
+        ctx.step_ensemble(pdet, 1, first_step=600_000 + k, noise_on_last=False)
+    sdet = start.clone()
+    nf_det, drift = surrogate_window(ctx, net, sdet, 10, 600_000, drift_tol=1e-4, noise_scale=0.0)
+    net.forward(start, out)
+    torch.cuda.synchronize()
+    d = (out - pdet).double()
+    inc = (pdet - start).double()
+    rm = [float(d[:, c].pow(2).mean().sqrt()) for c in range(3)]
+    ri = [float(inc[:, c].pow(2).mean().sqrt()) for c in range(3)]
+    eta_drift = float(((out[:, 0] - start[:, 0]).double().mean(dim=(1, 2)).abs()).max() / cfg.H)
+    ens.copy_(start)
+    net.close()
+    flop = 171_072 * cfg.n_particles * cfg.n_cells
+    return {"train_states": 400, "train_cells": 400 * cfg.n_cells, "train_steps": train_steps,
+            "batch_states": 1, "pair_generation_s": gen_s, "train_s": train_s,
+            "loss_history": hist,
+            "heldout_rmse_eta_hu_hv": rmse.tolist(),
+            "heldout_persistence_rmse": persist.tolist(),
+            "forward_ms": fwd_ms, "forward_tflops": flop / (fwd_ms / 1e3) / 1e12,
+            "window_ms_plain": plain_ms, "window_ms_surrogate": sur_ms,
+            "speedup": plain_ms / sur_ms, "fallbacks_per_window": nfs,
+            "rmse_vs_plain_eta_hu_hv": rm,
+            "window_increment_rms_eta_hu_hv": ri,
+            "fallbacks_deterministic": nf_det,
+            "max_mass_drift": float(np.max(drift)), "max_mean_eta_drift_over_H": eta_drift}
 
 
 def main():
@@ -248,6 +334,8 @@ def main():
     out["side"] = side_legs(torch, dev, ctx, ens, cfg)
     if not args.no_batched:
         out["batched"] = batched_leg(torch, dev, 3)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(torch, dev, ctx, ens, cfg, args.surrogate_train_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, cells)
     print(json.dumps(out), flush=True)

@@ -232,6 +232,12 @@ int iewpf_net_forward(iewpf_net* net, const float* state_in, float* state_out, i
  * host pointer or NULL (when set the call waits and returns the loss before the update). */
 int iewpf_net_train_step(iewpf_net* net, const float* x, const float* target, int B, int H, int W,
                          float lr, float* loss_out, void* stream);
+/* Input of hidden layer `layer` (1..5) from the last forward or training call: BF16 bits
+ * (round to nearest even of the ReLU output of layer `layer`-1), NHWC [cells][48], copied to
+ * host uint16 [count]; count must equal 48 * cells of that call.  Waits for the stream.
+ * For inspection and testing of the mixed-precision forward pass. */
+int iewpf_net_read_activation(iewpf_net* net, int layer, uint16_t* host, size_t count,
+                              void* stream);
 /* Loss gradient with respect to every parameter (host float [num_params]), without an
  * update; also the loss and the raw network output y (host float [B*H*W][3], NHWC, or
  * NULL).  Waits for the stream. */

@@ -33,7 +33,8 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_batch_destroy", "iewpf_batch_set_cells", "iewpf_batch_cycle",
             "iewpf_net_create", "iewpf_net_destroy", "iewpf_net_num_params",
             "iewpf_net_set_params", "iewpf_net_get_params", "iewpf_net_set_norm",
-            "iewpf_net_forward", "iewpf_net_train_step", "iewpf_net_gradients",
+            "iewpf_net_forward", "iewpf_net_train_step", "iewpf_net_read_activation",
+            "iewpf_net_gradients",
             "iewpf_surrogate_window", "iewpf_last_error")
 
 TRACE_KINDS = ("scheme_step", "me_normals", "soar", "gb_add", "innovation", "rand_dots",
@@ -115,6 +116,7 @@ def load(path: str = LIB_PATH):
     lib.iewpf_net_forward.argtypes = [vp, vp, vp, i32, i32, i32, vp]
     lib.iewpf_net_train_step.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float,
                                          ctypes.POINTER(ctypes.c_float), vp]
+    lib.iewpf_net_read_activation.argtypes = [vp, i32, vp, ctypes.c_size_t, vp]
     lib.iewpf_net_gradients.argtypes = [vp, vp, vp, i32, i32, i32, vp,
                                         ctypes.POINTER(ctypes.c_float), vp, vp]
     lib.iewpf_surrogate_window.argtypes = [vp, vp, vp, i32, u64, ctypes.c_double,
@@ -374,6 +376,13 @@ class Net:
                                            ctypes.byref(loss) if want_loss else None,
                                            _stream(stream)))
         return loss.value if want_loss else None
+
+    def read_activation(self, layer: int, cells: int, stream=None) -> np.ndarray:
+        """BF16 bits (uint16 [cells][48]) of the input of hidden layer `layer` (1..5)."""
+        out = np.zeros((cells, 48), dtype=np.uint16)
+        _check(load().iewpf_net_read_activation(self.h, layer, out.ctypes.data, out.size,
+                                                _stream(stream)))
+        return out
 
     def gradients(self, x, target, stream=None):
         """(grads float32 [num_params], loss, y float32 [B*H*W, 3])."""

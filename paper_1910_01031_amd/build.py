@@ -21,7 +21,11 @@ SOURCES = ["api.cpp", "host_precompute.cpp", "surrogate_api.cpp", "swe_kernels.h
 ARCH = os.environ.get("IEWPF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+# -ffp-contract=on: a*b+c is fused only inside one source expression, so every inlined copy
+# of a formula (halo rows and interior rows of a strip, single and batched launches) rounds
+# identically and results do not depend on the strip height or the launch form.
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
+          "-ffp-contract=on",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

@@ -978,20 +978,27 @@ int iewpf_surrogate_window(iewpf_ctx* c, iewpf_net* net, float* state, int n_mod
   IEWPF_HIP_TRY(hipStreamSynchronize(s));
   IEWPF_HIP_TRY(hipMemcpy(flags.data(), c->sflags, sizeof(int32_t) * c->ne, hipMemcpyDeviceToHost));
   IEWPF_HIP_TRY(hipMemcpy(drift.data(), c->sdrift, sizeof(double) * c->ne, hipMemcpyDeviceToHost));
-  int nf = 0;
-  for (int i = 0; i < c->ne; ++i) {
-    if (!flags[i]) continue;
-    ++nf;  // plain deterministic model steps of particle i from its saved state
-    float* cur = state + per * i;
-    float* other = c->scratch + per * i;
-    IEWPF_HIP_TRY(hipMemcpyAsync(cur, c->saved + per * i, sizeof(float) * per, hipMemcpyDeviceToDevice, s));
+  // Flagged particles: their saved inputs are packed into the scratch buffer and stepped
+  // together by the plain scheme (deterministic model steps); the saved buffer, no longer
+  // needed once packed, is the ping-pong partner.  Results are scattered back into state.
+  std::vector<int> fl;
+  for (int i = 0; i < c->ne; ++i)
+    if (flags[i]) fl.push_back(i);
+  const int nf = static_cast<int>(fl.size());
+  if (nf > 0) {
+    for (int k = 0; k < nf; ++k)
+      IEWPF_HIP_TRY(hipMemcpyAsync(c->scratch + per * k, c->saved + per * fl[k], sizeof(float) * per,
+                                   hipMemcpyDeviceToDevice, s));
+    float* cur = c->scratch;
+    float* other = c->saved;
     for (int st = 0; st < n_model_steps; ++st)
       for (int sub = 0; sub < c->cfg.n_sub; ++sub) {
-        launch_swe_substep(c->swe, 1, cur, other, nullptr, s);
+        launch_swe_substep(c->swe, nf, cur, other, nullptr, s);
         std::swap(cur, other);
       }
-    if (cur != state + per * i)
-      IEWPF_HIP_TRY(hipMemcpyAsync(state + per * i, cur, sizeof(float) * per, hipMemcpyDeviceToDevice, s));
+    for (int k = 0; k < nf; ++k)
+      IEWPF_HIP_TRY(hipMemcpyAsync(state + per * fl[k], cur + per * k, sizeof(float) * per,
+                                   hipMemcpyDeviceToDevice, s));
   }
   if (noise_scale > 0.0) {  // one model-error draw for the window, scaled
     float w[25];

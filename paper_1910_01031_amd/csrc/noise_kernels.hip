@@ -283,6 +283,18 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
     if (m >= k0 + 1) {
       const int k = m - 1;
       float ae[kPB], au[kPB], av[kPB];
+      float se[kPB], su_[kPB], sv_[kPB];  // state values, loaded before the observation loop
+      const size_t off = (size_t)k * nx + j;
+#pragma unroll
+      for (int p = 0; p < kPB; ++p) {
+        se[p] = su_[p] = sv_[p] = 0.0f;
+        if (writer && p < np) {
+          const float* E = psi + (size_t)(p0 + p) * 3 * ncell;
+          se[p] = E[off];
+          su_[p] = E[ncell + off];
+          sv_[p] = E[2 * ncell + off];
+        }
+      }
 #pragma unroll
       for (int p = 0; p < kPB; ++p) {
         ae[p] = dm1[p];
@@ -337,10 +349,9 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
         for (int p = 0; p < kPB; ++p) {
           if (p < np) {
             float* E = psi + (size_t)(p0 + p) * 3 * ncell;
-            const size_t off = (size_t)k * nx + j;
-            E[off] += ae[p];
-            E[ncell + off] += au[p];
-            E[2 * ncell + off] += av[p];
+            E[off] = se[p] + ae[p];
+            E[ncell + off] = su_[p] + au[p];
+            E[2 * ncell + off] = sv_[p] + av[p];
           }
         }
       }

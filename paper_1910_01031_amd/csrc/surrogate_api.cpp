@@ -21,6 +21,7 @@ int pad_to(int x, int m) { return (x + m - 1) / m * m; }
 
 struct iewpf_net {
   int max_cells = 0;
+  long long last_cells = 0;  // cells of the last forward / training call
   size_t np = 0;
   size_t woff[kLayers], boff[kLayers];
   int Kf[kLayers], Npf[kLayers], Kd[kLayers], Npd[kLayers];
@@ -84,6 +85,7 @@ ConvArgs conv_args(const iewpf_net* n, int layer, int B, int H, int W) {
 // Layers 0..4 of the forward pass (activations kept for the backward pass); layer 5 by the
 // caller (residual into a state, or raw output for training).
 void forward_hidden(iewpf_net* n, const float* state, int B, int H, int W, hipStream_t s) {
+  n->last_cells = (long long)B * H * W;
   for (int L = 0; L < 5; ++L) {
     ConvArgs A = conv_args(n, L, B, H, W);
     A.in = L == 0 ? static_cast<const void*>(state) : static_cast<const void*>(n->act[L]);
@@ -274,6 +276,15 @@ int iewpf_net_train_step(iewpf_net* n, const float* x, const float* target, int 
     for (int i = 0; i < n->loss_blocks; ++i) acc += n->h_loss[i];
     *loss_out = (float)acc;
   }
+  return 0;
+}
+
+int iewpf_net_read_activation(iewpf_net* n, int layer, uint16_t* host, size_t count, void* stream) {
+  if (!n || !host || layer < 1 || layer > 5) return fail(IEWPF_E_ARG, "invalid argument");
+  if (count != (size_t)48 * n->last_cells || n->last_cells == 0)
+    return fail(IEWPF_E_ARG, "count must be 48 x the cells of the last call");
+  IEWPF_HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  IEWPF_HIP_TRY(hipMemcpy(host, n->act[layer], count * 2, hipMemcpyDeviceToHost));
   return 0;
 }
 

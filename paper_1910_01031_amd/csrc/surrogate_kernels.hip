@@ -85,6 +85,9 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_kernel(ConvArgs A, int total
   const int y = r / xt;
   const int x0 = (r - y * xt) * 16 * kMT;
   const int row = lane & 15, kq = lane >> 4;
+  int xa[kMT];  // A-operand cell of this lane per M tile (cells past the row end wrap; unused)
+#pragma unroll
+  for (int m = 0; m < kMT; ++m) xa[m] = (x0 + m * 16 + row) % A.W;
   f32x4 acc[kMT][NT];
 #pragma unroll
   for (int m = 0; m < kMT; ++m)
@@ -101,8 +104,7 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_kernel(ConvArgs A, int total
     }
 #pragma unroll
     for (int m = 0; m < kMT; ++m) {
-      const int x = wrapc(x0 + m * 16 + row, A.W);
-      const bf16x8 afr = load_a<IN>(A, b, y, x, k0);
+      const bf16x8 afr = load_a<IN>(A, b, y, xa[m], k0);
 #pragma unroll
       for (int t = 0; t < NT; ++t)
         acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[t], acc[m][t], 0, 0, 0);

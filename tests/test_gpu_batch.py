@@ -126,7 +126,7 @@ def test_batched_cycle_oracle_parity(torch_dev):
 def test_autotune_keeps_results(torch_dev):
     torch, dev = torch_dev
     from paper_1910_01031_amd import Context
-    cfg = W.Config(nx=120, ny=90, dx=5e3, dy=5e3, n_sub=2, n_particles=4)
+    cfg = W.Config(nx=120, ny=92, dx=5e3, dy=5e3, n_sub=2, n_particles=4)
     rng = np.random.default_rng(1)
     ens = W.as_f32(np.stack([W.random_state(cfg, rng) for _ in range(4)]))
     a = Context(cfg, max_obs=4)
@@ -134,7 +134,17 @@ def test_autotune_keeps_results(torch_dev):
     h = a.autotune(t)
     assert 16 <= h <= 96
     assert torch.equal(t, torch.from_numpy(ens).to(dev))  # state untouched
-    b = Context(cfg, max_obs=4)
+    import os
+    other = 16 if h != 16 else 48  # a second context with a different strip height
+    old = os.environ.get("IEWPF_SWE_STRIP")
+    os.environ["IEWPF_SWE_STRIP"] = str(other)
+    try:
+        b = Context(cfg, max_obs=4)
+    finally:
+        if old is None:
+            del os.environ["IEWPF_SWE_STRIP"]
+        else:
+            os.environ["IEWPF_SWE_STRIP"] = old
     ta, tb = t.clone(), t.clone()
     a.step_ensemble(ta, 2, 0, True)
     b.step_ensemble(tb, 2, 0, True)

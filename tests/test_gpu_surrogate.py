@@ -1,0 +1,362 @@
+"""GPU parity of the learned surrogate (BF16 MFMA convolutions, backward pass, Adam, mass-drift
+guard with plain-solver fallback) against the FP64 oracle on BF16-rounded operands.
+
+Forward pass, layer by layer (the exact check).  Both sides round the same operands to
+BF16; they differ only in how the K = 9 C_in products of a pre-activation are summed (FP32 on
+the matrix cores, FP64 in the oracle).  Fed the GPU's own BF16 input of a layer, the oracle's
+FP64 pre-activation z and the GPU's FP32 one differ by at most (K + 2) 2^-24 (sum |w a| + |b|)
+(the standard bound for a K-term floating-point sum).  Rounding to BF16 is monotone, so the
+GPU's BF16 output must lie between bf16(relu(z - delta)) and bf16(relu(z + delta)): equal to
+the oracle's rounding except where z sits within delta of a rounding boundary, and one of the
+two neighbours there.  The rounding of the layer-0 input is replayed in FP32 as the kernel
+computes it, so it is compared bit for bit.
+
+Forward pass, end to end.  A boundary case that rounds the other way moves one layer input by
+one BF16 ulp (2^-8 relative) and the later layers carry that on; the end-to-end outputs are
+therefore compared statistically (99.9 % of them within 2^-6 of the output RMS, all within
+2^-4, mean deviation below 2^-11 of it; observed: 99.9 % within 2^-7.8, all within 2^-6.6).
+
+Gradients are compared per tensor in relative Frobenius norm (1e-2): the loss gradient and
+every pre-activation gradient are rounded to BF16 on both sides, so the same boundary cases
+are the only source of difference.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import surrogate as osur
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _flat(params):
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params])
+
+
+def _unflat(flat):
+    out, off = [], 0
+    for i in range(6):
+        cin, cout = osur.CHANNELS[i], osur.CHANNELS[i + 1]
+        w = flat[off:off + cout * cin * 9].reshape(cout, cin, 3, 3).astype(np.float64)
+        off += cout * cin * 9
+        b = flat[off:off + cout].astype(np.float64)
+        off += cout
+        out.append((w, b))
+    return out
+
+
+def _params(seed, last_scale=1.0, bias_std=0.05):
+    rng = np.random.default_rng(seed)
+    p = osur.init_params(rng, last_scale=last_scale)
+    p = [(w, (rng.normal(size=b.shape) * bias_std).astype(np.float32).astype(np.float64))
+         for w, b in p]
+    return p
+
+
+def _states(B, H, W, seed):
+    cfg = wl.tiny().replace(nx=W, ny=H)
+    rng = np.random.default_rng(seed)
+    return np.stack([wl.random_state(cfg, rng) for _ in range(B)]).astype(np.float32)
+
+
+NORM = (np.array([0.0, 0.0, 0.0], np.float32), np.array([0.4, 50.0, 50.0], np.float32),
+        np.array([0.01, 1.0, 1.0], np.float32))
+
+
+def _x_norm(psi):
+    mu, sig, _ = NORM
+    return (psi.astype(np.float64) - mu[:, None, None]) / sig[:, None, None]
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (3, 20, 37), (1, 5, 7), (2, 9, 50)])
+def test_forward_matches_oracle(B, H, W):
+    _need_gpu()
+    from paper_1910_01031_amd import Net
+    params = _params(11 + H)
+    psi = _states(B, H, W, 5 + W)
+    net = Net(B * H * W)
+    net.set_params(_flat(params).astype(np.float32))
+    net.set_norm(*NORM)
+    d_in = torch.from_numpy(psi).cuda()
+    d_out = torch.empty_like(d_in)
+    net.forward(d_in, d_out)
+    torch.cuda.synchronize()
+    got = d_out.cpu().numpy().astype(np.float64)
+    s = NORM[2].astype(np.float64)
+    for b in range(B):
+        y, _ = osur.forward(params, _x_norm(psi[b]))
+        want = psi[b].astype(np.float64) + s[:, None, None] * y
+        y_gpu = (got[b] - psi[b].astype(np.float64)) / s[:, None, None]
+        # the FP32 residual add rounds psi + s y once: compare net outputs through it
+        f32_slack = np.abs(want) * 2.0 ** -23 / s[:, None, None]
+        rms = np.sqrt(np.mean(y * y))
+        err = np.maximum(np.abs(y_gpu - y) - f32_slack, 0.0)
+        assert np.quantile(err, 0.999) <= 2.0 ** -6 * rms, (b, np.quantile(err, 0.999), rms)
+        assert err.max() <= 2.0 ** -4 * rms, (b, err.max(), rms)
+        assert np.mean(err) <= 2.0 ** -11 * rms
+    net.close()
+
+
+def _bf16_bits_to_f64(u16):
+    return (u16.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (3, 20, 37), (1, 5, 7), (2, 9, 50)])
+def test_forward_layerwise_exact(B, H, W):
+    """Every layer's BF16 output equals the oracle's rounding of its FP64 pre-activation
+    (computed from the GPU's own BF16 input), up to the rounding-boundary cases bounded by
+    the FP32 summation error; the last layer's FP32 output within that error."""
+    _need_gpu()
+    from paper_1910_01031_amd import Net
+    params = _params(11 + H)
+    psi = _states(B, H, W, 5 + W)
+    net = Net(B * H * W)
+    net.set_params(_flat(params).astype(np.float32))
+    net.set_norm(*NORM)
+    d_in = torch.from_numpy(psi).cuda()
+    d_out = torch.empty_like(d_in)
+    net.forward(d_in, d_out)
+    torch.cuda.synchronize()
+    out = d_out.cpu().numpy().astype(np.float64)
+    cells = B * H * W
+    acts = [None] + [_bf16_bits_to_f64(net.read_activation(L, cells)).reshape(B, H, W, 48)
+                     .transpose(0, 3, 1, 2) for L in range(1, 6)]
+    mu, sig, sc = NORM
+    isig = np.float32(1.0) / sig
+    x32 = (psi - mu[None, :, None, None]) * isig[None, :, None, None]  # FP32, as the kernel
+    a0 = osur.bf16_round(x32)
+    n_boundary = 0
+    for b in range(B):
+        a = a0[b]
+        for i, (w, bias) in enumerate(params):
+            wq = osur.bf16_round(w)
+            z = osur.conv3x3(a, wq, bias)
+            K = 9 * a.shape[0]
+            delta = (K + 2) * 2.0 ** -24 * osur.conv3x3(np.abs(a), np.abs(wq), np.abs(bias))
+            if i < 5:
+                lo = osur.bf16_round(np.maximum(z - delta, 0.0))
+                hi = osur.bf16_round(np.maximum(z + delta, 0.0))
+                got = acts[i + 1][b]
+                assert np.all((got >= lo) & (got <= hi)), (b, i)
+                n_boundary += int(np.sum(got != osur.bf16_round(np.maximum(z, 0.0))))
+                a = got
+            else:
+                s = sc.astype(np.float64)[:, None, None]
+                want = psi[b].astype(np.float64) + s * z
+                tol = s * delta + (np.abs(want) + s * np.abs(z)) * 2.0 ** -23
+                assert np.all(np.abs(out[b] - want) <= tol), (b, np.max(np.abs(out[b] - want) - tol))
+    # boundary cases are rare: a few per million outputs
+    assert n_boundary <= max(4, 1e-4 * 5 * 48 * cells), n_boundary
+    net.close()
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 16, 16), (1, 12, 40)])
+def test_gradients_match_oracle(B, H, W):
+    _need_gpu()
+    from paper_1910_01031_amd import Net
+    params = _params(3 + W, last_scale=0.5)
+    psi = _states(B, H, W, 21)
+    tgt = psi + _states(B, H, W, 22) * np.array([0.01, 0.5, 0.5], np.float32)[None, :, None, None]
+    net = Net(B * H * W)
+    net.set_params(_flat(params).astype(np.float32))
+    net.set_norm(*NORM)
+    g, loss, y = net.gradients(torch.from_numpy(psi).cuda(), torch.from_numpy(tgt).cuda())
+    s = NORM[2].astype(np.float64)
+    # oracle over the batch: the loss is the mean over all cells and channels of the batch
+    ys, caches = [], []
+    for b in range(B):
+        yb, cb = osur.forward(params, _x_norm(psi[b]))
+        ys.append(yb)
+        caches.append(cb)
+    yo = np.stack(ys)
+    t = (tgt.astype(np.float64) - psi.astype(np.float64)) / s[None, :, None, None]
+    loss_o, gout = osur.mse_loss_and_grad(yo, t)
+    gsum = None
+    for b in range(B):
+        gb = osur.backward(params, caches[b], gout[b], round_grads=True)
+        fb = np.concatenate([np.concatenate([w.ravel(), bb.ravel()]) for w, bb in gb])
+        gsum = fb if gsum is None else gsum + fb
+    # network output (cells x channels, NHWC on the GPU)
+    y_gpu = y.reshape(B, H, W, 3).transpose(0, 3, 1, 2)
+    assert np.max(np.abs(y_gpu - yo)) <= 2.0 ** -7 * np.sqrt(np.mean(yo * yo))
+    assert abs(loss - loss_o) <= 1e-3 * loss_o
+    off = 0
+    for i in range(6):
+        cin, cout = osur.CHANNELS[i], osur.CHANNELS[i + 1]
+        for n in (cout * cin * 9, cout):
+            a, o = g[off:off + n].astype(np.float64), gsum[off:off + n]
+            rel = np.linalg.norm(a - o) / max(np.linalg.norm(o), 1e-30)
+            assert rel <= 1e-2, (i, n, rel)
+            off += n
+    net.close()
+
+
+def test_adam_step_matches_oracle():
+    _need_gpu()
+    from paper_1910_01031_amd import Net
+    B, H, W = 2, 16, 16
+    params = _params(9, last_scale=0.5)
+    p0 = _flat(params).astype(np.float32)
+    psi = _states(B, H, W, 31)
+    tgt = psi + _states(B, H, W, 32) * np.array([0.01, 0.5, 0.5], np.float32)[None, :, None, None]
+    net = Net(B * H * W)
+    net.set_params(p0)
+    net.set_norm(*NORM)
+    dx, dt = torch.from_numpy(psi).cuda(), torch.from_numpy(tgt).cuda()
+    g, _, _ = net.gradients(dx, dt)
+    lr = 1e-3
+    net.train_step(dx, dt, lr)          # first Adam step from the same gradients
+    g2, _, _ = net.gradients(dx, dt)     # parameters moved: gradients differ
+    net.train_step(dx, dt, lr)
+    p2 = net.get_params()
+    opt = osur.Adam([(p0.astype(np.float64), np.zeros(1))], lr=lr)
+    p1o = opt.step([(p0.astype(np.float64), np.zeros(1))], [(g.astype(np.float64), np.zeros(1))])
+    p2o = opt.step(p1o, [(g2.astype(np.float64), np.zeros(1))])[0][0]
+    # FP32 Adam vs FP64: |p| ~ 0.1, lr = 1e-3; differences are FP32 roundoff except where a
+    # gradient is near zero (m / sqrt(v) then depends on the last bits of g)
+    big = (np.abs(g) > 1e-3 * np.abs(g).max()) & (np.abs(g2) > 1e-3 * np.abs(g2).max())
+    assert np.max(np.abs(p2 - p2o)[big]) <= 1e-6
+    assert np.max(np.abs(p2 - p2o)) <= 2.0 * lr + 1e-6
+    net.close()
+
+
+def test_training_reduces_loss():
+    _need_gpu()
+    from paper_1910_01031_amd import Context, Net
+    cfg = wl.tiny().replace(dx=5e3, dy=5e3, n_sub=2, n_particles=16, init_std=0.3)
+    ctx = Context(cfg)
+    base = torch.from_numpy(wl.jet_state(cfg).astype(np.float32)).cuda()
+    x = torch.empty((cfg.n_particles, 3, cfg.ny, cfg.nx), device="cuda")
+    ctx.init_ensemble(x, base, stream_index=7)
+    t = x.clone()
+    for k in range(10):  # ten deterministic model steps (the 5-minute window)
+        ctx.step_ensemble(t, 1, first_step=k, noise_on_last=False)
+    torch.cuda.synchronize()
+    net = Net(cfg.n_particles * cfg.n_cells)
+    net.set_params(_flat(_params(1, last_scale=0.1, bias_std=0.0)).astype(np.float32))
+    xs = x.cpu().numpy()
+    inc = t.cpu().numpy() - xs
+    mu = xs.mean(axis=(0, 2, 3))
+    sig = xs.std(axis=(0, 2, 3)) + 1e-6
+    sc = inc.std(axis=(0, 2, 3)) + 1e-9
+    net.set_norm(mu, sig, sc)
+    losses = [net.train_step(x, t, 1e-3, want_loss=True) for _ in range(150)]
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.5 * losses[0], (losses[0], losses[-1])
+    net.close()
+    ctx.close()
+
+
+def _window_setup(n_particles=6):
+    from paper_1910_01031_amd import Context, Net
+    cfg = wl.tiny().replace(dx=5e3, dy=5e3, n_sub=2, n_particles=n_particles, init_std=0.3)
+    ctx = Context(cfg)
+    base = torch.from_numpy(wl.jet_state(cfg).astype(np.float32)).cuda()
+    x = torch.empty((cfg.n_particles, 3, cfg.ny, cfg.nx), device="cuda")
+    ctx.init_ensemble(x, base, stream_index=3)
+    net = Net(cfg.n_particles * cfg.n_cells)
+    params = _params(4, last_scale=0.2)
+    return cfg, ctx, net, params, x
+
+
+def test_window_without_fallback_is_the_network():
+    _need_gpu()
+    from paper_1910_01031_amd import surrogate_window
+    cfg, ctx, net, params, x = _window_setup()
+    net.set_params(_flat(params).astype(np.float32))
+    net.set_norm(*NORM)
+    ref = torch.empty_like(x)
+    net.forward(x, ref)
+    st = x.clone()
+    nf, drift = surrogate_window(ctx, net, st, 10, 0, drift_tol=1e30, noise_scale=0.0)
+    torch.cuda.synchronize()
+    assert nf == 0
+    assert torch.equal(st, ref)
+    xin, out = x.cpu().numpy().astype(np.float64), st.cpu().numpy().astype(np.float64)
+    for i in range(cfg.n_particles):
+        assert abs(drift[i] - osur.mass_drift(xin[i], out[i], cfg.H)) <= 1e-12
+    net.close()
+    ctx.close()
+
+
+def test_forced_drift_falls_back_to_the_plain_solver():
+    """A large bias on the eta output channel forces mass drift; every particle above the
+    threshold is re-stepped by the plain solver, the others keep the network output."""
+    _need_gpu()
+    from paper_1910_01031_amd import surrogate_window
+    cfg, ctx, net, params, x = _window_setup()
+    plain = x.clone()
+    ctx.step_ensemble(plain, 1, first_step=0, noise_on_last=False)
+    netout = torch.empty_like(x)
+    # all particles drift: bias 1e3 on the eta increment (scale 0.01 -> +10 m of eta)
+    w5, b5 = params[5]
+    forced = params[:5] + [(w5, b5 + np.array([1e3, 0.0, 0.0]))]
+    net.set_params(_flat(forced).astype(np.float32))
+    net.set_norm(*NORM)
+    st = x.clone()
+    nf, drift = surrogate_window(ctx, net, st, 1, 0, drift_tol=1e-4, noise_scale=0.0)
+    torch.cuda.synchronize()
+    assert nf == cfg.n_particles and np.all(drift > 1e-4)
+    assert torch.equal(st, plain)
+    # mixed: threshold between the particles' drifts under the unforced network
+    net.set_params(_flat(params).astype(np.float32))
+    net.forward(x, netout)
+    st = x.clone()
+    _, d0 = surrogate_window(ctx, net, st, 1, 0, drift_tol=1e30, noise_scale=0.0)
+    tol = float(np.median(d0))
+    st = x.clone()
+    nf, drift = surrogate_window(ctx, net, st, 1, 0, drift_tol=tol, noise_scale=0.0)
+    torch.cuda.synchronize()
+    flagged = drift > tol
+    assert nf == int(flagged.sum()) and 0 < nf < cfg.n_particles
+    for i in range(cfg.n_particles):
+        assert torch.equal(st[i], plain[i] if flagged[i] else netout[i]), i
+    net.close()
+    ctx.close()
+
+
+def test_window_noise_is_one_scaled_model_error_draw():
+    _need_gpu()
+    from paper_1910_01031_amd import surrogate_window
+    cfg, ctx, net, params, x = _window_setup()
+    net.set_params(_flat(params).astype(np.float32))
+    net.set_norm(*NORM)
+    det = x.clone()
+    surrogate_window(ctx, net, det, 10, 20, drift_tol=1e30, noise_scale=0.0)
+    ref = det.clone()
+    ctx.perturb(ref, 29)
+    st = x.clone()
+    surrogate_window(ctx, net, st, 10, 20, drift_tol=1e30, noise_scale=1.0)
+    torch.cuda.synchronize()
+    assert torch.equal(st, ref)
+    st3 = x.clone()
+    surrogate_window(ctx, net, st3, 10, 20, drift_tol=1e30, noise_scale=3.0)
+    torch.cuda.synchronize()
+    p1 = (ref - det).double()
+    p3 = (st3 - det).double()
+    scale = p1.abs().max().item()
+    assert scale > 0
+    assert (p3 - 3.0 * p1).abs().max().item() <= 1e-3 * scale + 1e-6 * det.abs().max().item()
+    net.close()
+    ctx.close()
+
+
+def test_rejects_oversized_and_invalid_calls():
+    _need_gpu()
+    from paper_1910_01031_amd import IewpfError, Net
+    net = Net(100)
+    x = torch.zeros((1, 3, 10, 11), device="cuda")
+    with pytest.raises(IewpfError):
+        net.forward(x, torch.empty_like(x))
+    with pytest.raises(IewpfError):
+        net.set_params(np.zeros(net.num_params - 1, np.float32))
+    with pytest.raises(IewpfError):
+        net.set_norm([0, 0, 0], [1, 0, 1], [1, 1, 1])
+    net.close()
