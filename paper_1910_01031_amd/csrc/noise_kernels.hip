@@ -268,6 +268,29 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
   const int k0 = sy * P.strip_h;
   const int k_end = min(k0 + P.strip_h, ny);
   const int o_beg = st_off[strip], o_end = st_off[strip + 1];
+  // The strip's observation list, one entry per lane (first 64 entries): cell and S d of
+  // each particle of the group, so the row loop reads them with lane broadcasts instead of
+  // dependent global loads.
+  int l_jo = 0, l_ko = 0;
+  float l_su[kPB], l_sv[kPB];
+  {
+    const int t = o_beg + lane;
+    const int o = t < o_end ? st_ent[t] : -1;
+#pragma unroll
+    for (int p = 0; p < kPB; ++p) l_su[p] = l_sv[p] = 0.0f;
+    if (o >= 0) {
+      l_jo = cells[2 * o];
+      l_ko = cells[2 * o + 1];
+#pragma unroll
+      for (int p = 0; p < kPB; ++p) {
+        if (p < np) {
+          const double* s2 = sd + ((size_t)(p0 + p) * max_obs + o) * 2;
+          l_su[p] = static_cast<float>(s2[0]);
+          l_sv[p] = static_cast<float>(s2[1]);
+        }
+      }
+    }
+  }
   float dm2[kPB], dm1[kPB];
   CoarseWin win[kPB];
 #pragma unroll
@@ -302,8 +325,16 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
         av[p] = C.gb_x * (__shfl_down(dm1[p], 1, kWave) - __shfl_up(dm1[p], 1, kWave));
       }
       for (int t = o_beg; t < o_end; ++t) {
-        const int o = st_ent[t];
-        const int jo = cells[2 * o], ko = cells[2 * o + 1];
+        const int q = t - o_beg;  // wave-uniform
+        int o = 0, jo, ko;
+        if (q < kWave) {
+          jo = __builtin_amdgcn_readlane(l_jo, q);
+          ko = __builtin_amdgcn_readlane(l_ko, q);
+        } else {
+          o = st_ent[t];
+          jo = cells[2 * o];
+          ko = cells[2 * o + 1];
+        }
         int iy;
         if (P.ry >= 0) {
           int dk = k - ko;
@@ -336,8 +367,15 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
 #pragma unroll
         for (int p = 0; p < kPB; ++p) {
           if (p < np) {
-            const double* s2 = sd + ((size_t)(p0 + p) * max_obs + o) * 2;
-            const float su = static_cast<float>(s2[0]), sv = static_cast<float>(s2[1]);
+            float su, sv;
+            if (q < kWave) {
+              su = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l_su[p]), q));
+              sv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l_sv[p]), q));
+            } else {
+              const double* s2 = sd + ((size_t)(p0 + p) * max_obs + o) * 2;
+              su = static_cast<float>(s2[0]);
+              sv = static_cast<float>(s2[1]);
+            }
             ae[p] += su * w0 + sv * w3;
             au[p] += su * w1 + sv * w4;
             av[p] += su * w2 + sv * w5;

@@ -10,6 +10,8 @@
 // Weights are stored transposed, Wt[n][k] (bf16), so a lane reads its 8 K values as one
 // 16-byte load; activations are NHWC bf16 so 8 consecutive channels of one tap are one
 // 16-byte load (C_in multiple of 8) or gathered element by element (C_in = 3).
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace iewpf {
@@ -17,6 +19,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -137,6 +140,222 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_kernel(ConvArgs A, int total
         }
       }
     }
+  }
+}
+
+// Convolutions of the network as a persistent, LDS-tiled implicit GEMM (every forward layer
+// and the 48 -> 48 input gradients of the backward pass).  A workgroup of eight waves owns a
+// tile of 8 output rows x 64 columns of one image.  The (8 + 2) x (64 + 2) input pixels
+// (periodic wrap) sit in LDS, as do the layer's weights (loaded once per workgroup); every
+// wave computes one output row as 4 pixel tiles x NT channel tiles of
+// v_mfma_f32_16x16x32_bf16.  The operands are swapped with respect to the generic kernel
+// (A = weights, rows = output channels; B = pixels), so a lane ends with 4 consecutive
+// channels of one pixel.  While a tile is computed, the next tile's input is already being
+// fetched into registers; it is written to LDS between two barriers.
+//   CIN = 48: hidden-layer input, bf16 NHWC, K = 9 x 48 (14 chunks of 32), k = 48 tap + c.
+//   CIN = 8:  the normalised state (3 channels zero-padded to 8), K = 9 x 8 (3 chunks),
+//             k = 8 tap + c; the weights are re-laid from their k = 3 tap + c form.
+// LDS row strides are padded (pixel: 56 channels; weight row: K + 8) so that the 16 lanes
+// of a fragment read hit distinct banks.
+template <int CIN>
+struct TileGeom {
+  static constexpr int CP = CIN == 48 ? 56 : 8;      // LDS pixel stride (bf16)
+  static constexpr int CHUNKS = CIN == 48 ? 14 : 3;  // K chunks of 32
+  static constexpr int KP = CHUNKS * 32;             // padded K
+  static constexpr int WS = KP + 8;                  // LDS weight row stride (bf16)
+  static constexpr int VPP = CIN / 8;                // 16-byte vectors per pixel (NHWC input)
+};
+constexpr int kTW = 64;  // output columns per tile
+constexpr int kTH = 8;   // output rows per tile (one per wave)
+constexpr int kTThreads = 64 * kTH;
+
+__device__ __forceinline__ int wrapm(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+__device__ __forceinline__ void tile_origin(int t, int xt, int yt, int& b, int& y0, int& x0) {
+  b = t / (yt * xt);
+  const int r = t - b * yt * xt;
+  y0 = (r / xt) * kTH;
+  x0 = (r - (r / xt) * xt) * kTW;
+}
+
+template <int CIN, int NT>
+constexpr int tile_lds_bytes() {
+  return 2 * ((kTH + 2) * (kTW + 2) * TileGeom<CIN>::CP + NT * 16 * TileGeom<CIN>::WS);
+}
+
+template <int CIN, int NT, int IN, int OUT>
+__global__ __launch_bounds__(kTThreads) void conv_tile_kernel(ConvArgs A, int ntiles) {
+  using G = TileGeom<CIN>;
+  constexpr int kPix = (kTH + 2) * (kTW + 2);
+  constexpr int kTileElems = kPix * G::CP;
+  extern __shared__ __align__(16) uint16_t lds[];
+  uint16_t* tile = lds;
+  uint16_t* wl = lds + kTileElems;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, kq = lane >> 4;
+
+  // weights -> LDS, [NT * 16][WS]
+  for (int i = threadIdx.x; i < NT * 16 * (G::KP / 8); i += kTThreads) {
+    const int n = i / (G::KP / 8), kv = i - n * (G::KP / 8);
+    uint4 v;
+    if (CIN == 48) {
+      v = *reinterpret_cast<const uint4*>(A.wt + (size_t)n * A.Kpad + kv * 8);
+    } else {  // kv = tap; stored layout k = 3 tap + c
+      uint32_t e0 = 0, e1 = 0;
+      if (kv < 9) {
+        const uint16_t* src = A.wt + (size_t)n * A.Kpad + kv * 3;
+        e0 = (uint32_t)src[0] | ((uint32_t)src[1] << 16);
+        e1 = (uint32_t)src[2];
+      }
+      v = make_uint4(e0, e1, 0u, 0u);
+    }
+    *reinterpret_cast<uint4*>(wl + n * G::WS + kv * 8) = v;
+  }
+
+  const int xt = (A.W + kTW - 1) / kTW, yt = (A.H + kTH - 1) / kTH;
+
+  // registers holding the next tile's input
+  constexpr int kVecs = IN == kInStateNorm ? kPix : kPix * G::VPP;
+  constexpr int kPer = (kVecs + kTThreads - 1) / kTThreads;
+  u32x4 pre[IN == kInStateNorm ? 1 : kPer];
+  float pf[IN == kInStateNorm ? kPer : 1][3];
+
+  // Iteration t: write tile t (fetched in the previous iteration) to LDS, start fetching
+  // tile t + gridDim.x, compute tile t.  The first iteration only fetches.
+  for (int t = (int)blockIdx.x - (int)gridDim.x; t < ntiles; t += gridDim.x) {
+    const int tn = t + (int)gridDim.x;
+    if (t >= 0) {  // uniform across the workgroup
+      __syncthreads();  // weights written / the previous tile's LDS reads are done
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const int v = threadIdx.x + i * kTThreads;
+        if (v < kVecs) {
+          if (IN == kInStateNorm) {
+            uint32_t h[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) h[c] = f2bf((pf[i][c] - A.mu[c]) * A.isig[c]);
+            *reinterpret_cast<uint4*>(tile + v * G::CP) = make_uint4(h[0] | (h[1] << 16), h[2], 0u, 0u);
+          } else {
+            const int pix = v / G::VPP, cv = v - pix * G::VPP;
+            *reinterpret_cast<u32x4*>(tile + pix * G::CP + cv * 8) = pre[i];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (tn < ntiles) {  // in flight during the MFMAs below
+      int b, y0, x0;
+      tile_origin(tn, xt, yt, b, y0, x0);
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const int v = threadIdx.x + i * kTThreads;
+        if (v < kVecs) {
+          if (IN == kInStateNorm) {
+            const int rr = v / (kTW + 2), cc = v - rr * (kTW + 2);
+            const int ys = wrapm(y0 - 1 + rr, A.H), xs = wrapm(x0 - 1 + cc, A.W);
+            const size_t plane = (size_t)A.H * A.W;
+            const float* st = static_cast<const float*>(A.in) + (size_t)b * 3 * plane + (size_t)ys * A.W + xs;
+            pf[i][0] = st[0];
+            pf[i][1] = st[plane];
+            pf[i][2] = st[2 * plane];
+          } else {
+            const int pix = v / G::VPP, cv = v - pix * G::VPP;
+            const int rr = pix / (kTW + 2), cc = pix - rr * (kTW + 2);
+            const int ys = wrapm(y0 - 1 + rr, A.H), xs = wrapm(x0 - 1 + cc, A.W);
+            pre[i] = *reinterpret_cast<const u32x4*>(static_cast<const uint16_t*>(A.in) +
+                                                     (((size_t)b * A.H + ys) * A.W + xs) * CIN + cv * 8);
+          }
+        }
+      }
+    }
+    if (t < 0) continue;
+    int b, y0, x0;
+    tile_origin(t, xt, yt, b, y0, x0);
+    const int y = y0 + wave;
+    if (y < A.H) {  // wave-uniform
+    f32x4 acc[NT][4];
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[q][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kc = 0; kc < G::CHUNKS; ++kc) {
+      const int k = kc * 32 + kq * 8;
+      int tap, c0;
+      if (CIN == 48) {
+        tap = k / 48;
+        c0 = k - tap * 48;
+        if (k >= 9 * 48) {  // padding: zero weights times valid (finite) activations
+          tap = 8;
+          c0 = 0;
+        }
+      } else {
+        tap = k / 8;
+        c0 = 0;
+        if (tap > 8) tap = 8;  // padding taps: zero weights
+      }
+      const int dy = tap / 3, dx = tap - dy * 3;
+      const uint16_t* base = tile + ((wave + dy) * (kTW + 2) + dx + row) * G::CP + c0;
+      bf16x8 afr[NT];
+#pragma unroll
+      for (int q = 0; q < NT; ++q)
+        afr[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wl + (q * 16 + row) * G::WS + k));
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const bf16x8 bfr =
+            __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(base + m * 16 * G::CP));
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+          acc[q][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[q], bfr, acc[q][m], 0, 0, 0);
+      }
+    }
+    // lane: pixel x0 + 16 m + row, channels 16 q + 4 kq .. + 3
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int x = x0 + m * 16 + row;
+      if (x >= A.W) continue;
+      const size_t cell = ((size_t)b * A.H + y) * A.W + x;
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int n0 = q * 16 + kq * 4;
+        if (OUT == kOutReluBf16 || OUT == kOutMaskBf16) {
+          float4 bn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          if (A.bias) bn = *reinterpret_cast<const float4*>(A.bias + n0);
+          const float bias[4] = {bn.x, bn.y, bn.z, bn.w};
+          uint2 mk = make_uint2(0, 0);
+          if (OUT == kOutMaskBf16) mk = *reinterpret_cast<const uint2*>(A.mask + cell * A.cout + n0);
+          uint32_t h[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float v = acc[q][m][e] + bias[e];
+            if (OUT == kOutReluBf16) {
+              h[e] = f2bf(fmaxf(v, 0.0f));
+            } else {
+              const uint32_t word = e < 2 ? mk.x : mk.y;
+              const uint16_t me = (uint16_t)(e & 1 ? word >> 16 : word & 0xFFFFu);
+              h[e] = f2bf(bf2f(me) > 0.0f ? v : 0.0f);
+            }
+          }
+          *reinterpret_cast<uint2*>(static_cast<uint16_t*>(A.out) + cell * A.cout + n0) =
+              make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+        } else if (kq == 0) {  // NT == 1: channels 0..2 of the state
+#pragma unroll
+          for (int e = 0; e < 3; ++e) {
+            const float v = acc[q][m][e] + (A.bias ? A.bias[e] : 0.0f);
+            if (OUT == kOutF32) {
+              static_cast<float*>(A.out)[cell * 3 + e] = v;
+            } else {  // residual into the state: psi' = psi + s (net)
+              const size_t o = (((size_t)b * 3 + e) * A.H + y) * A.W + x;
+              static_cast<float*>(A.out)[o] = A.state_in[o] + A.s[e] * v;
+            }
+          }
+        }
+      }
+    }
+    }  // y < H
   }
 }
 
@@ -360,7 +579,47 @@ void launch_conv_t(const ConvArgs& A, hipStream_t s) {
 
 }  // namespace
 
+static int cu_count() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
+template <int CIN, int NT, int IN, int OUT>
+void launch_tile(const ConvArgs& A, hipStream_t s) {
+  constexpr int bytes = tile_lds_bytes<CIN, NT>();
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(conv_tile_kernel<CIN, NT, IN, OUT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    attr = true;
+  }
+  const int ntiles = A.B * ((A.H + kTH - 1) / kTH) * ((A.W + kTW - 1) / kTW);
+  const int per_cu = bytes > 80 * 1024 ? 1 : 2;
+  const int nb = ntiles < per_cu * cu_count() ? ntiles : per_cu * cu_count();
+  hipLaunchKernelGGL((conv_tile_kernel<CIN, NT, IN, OUT>), dim3(nb), dim3(kTThreads), bytes, s, A,
+                     ntiles);
+}
+
 void launch_conv(const ConvArgs& A, int in_mode, int out_mode, hipStream_t s) {
+  if (in_mode == kInNhwcVec && A.cin == 48 && A.Kpad == TileGeom<48>::KP) {
+    if (A.cout == 48 && A.Npad == 48 && out_mode == kOutReluBf16)
+      return launch_tile<48, 3, kInNhwcVec, kOutReluBf16>(A, s);
+    if (A.cout == 48 && A.Npad == 48 && out_mode == kOutMaskBf16)
+      return launch_tile<48, 3, kInNhwcVec, kOutMaskBf16>(A, s);
+    if (A.cout == 3 && A.Npad == 16 && out_mode == kOutResidState)
+      return launch_tile<48, 1, kInNhwcVec, kOutResidState>(A, s);
+    if (A.cout == 3 && A.Npad == 16 && out_mode == kOutF32)
+      return launch_tile<48, 1, kInNhwcVec, kOutF32>(A, s);
+  }
+  if (in_mode == kInStateNorm && A.cin == 3 && A.cout == 48 && A.Npad == 48 && A.Kpad == 32 &&
+      out_mode == kOutReluBf16)
+    return launch_tile<8, 3, kInStateNorm, kOutReluBf16>(A, s);
   const int nt = A.Npad / 16;
 #define IEWPF_CONV_CASE(I, O, T) \
   if (in_mode == I && out_mode == O && nt == T) return launch_conv_t<I, O, T>(A, s);
