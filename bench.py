@@ -29,9 +29,32 @@ import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 # Algorithmic work of one scheme step (both SSP-RK2 stages) per cell: read eta, hu, hv
-# once and write them once (float32).
+# once and write them once (float32) ...
 BYTES_PER_CELL_STEP = 24.0
+# ... and the scheme's arithmetic, counted from its definition (each +, -, x, /, sqrt, min,
+# max one flop): per stage 3 (primitives) + 2 x 54 (x and y reconstructions) + 2 x 55 (one
+# x and one y face flux) + 25 (update) = 246; two stages and the RK2 average: 498.
+FLOPS_PER_CELL_STEP = 498.0
+# Network forward: 2 x (27 x 48 + 4 x 432 x 48 + 432 x 3) multiply-adds per pixel.
+SURROGATE_FLOPS_PER_PIXEL = 171_072
+# HBM bytes per launch of the plain scheme step on this workload, from rocprofv3 counters
+# (FETCH_SIZE x 2 + WRITE_SIZE x 1, the scale factors a plain device copy of known size
+# reads), with the SHA-256 of the kernel source they were taken on: reported only while
+# the source is unchanged.
+MEASURED_TRAFFIC = {"bytes": 2 * 140305.5 * 1024 + 180202.0 * 1024,
+                    "source_sha256": "ce3fda7d2e1325e3ccb6e68adcaa16818f3498cea0b3fa9280cb790669f866f2"}
+
+
+def _kernel_source_hash():
+    """SHA-256 over the scheme kernel's source, its header and the build flags."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in (("csrc", "swe_kernels.hip"), ("csrc", "internal.hpp"), ("build.py",)):
+        with open(os.path.join(ROOT, "paper_1910_01031_amd", *rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -144,6 +167,54 @@ def side_legs(torch, dev, ctx, ens, cfg):
             "resample_ms": e1.elapsed_time(e2)}
 
 
+def drifter_comparison(torch, dev, ctx, net, start, cfg, windows: int = 12):
+    """One hour (12 windows of 10 model steps) of drifter forecast, 64 drifters per particle
+    on an 8x8 lattice, from the same ensemble: plain model (two runs with different
+    model-error streams) and surrogate (plain re-step above a mass drift of 1e-4, one
+    model-error draw scaled by 3 per window).  Position RMSE between paired drifters
+    (minimum-image distances): surrogate vs plain, and plain vs plain (what the model error
+    alone makes two forecasts differ by); the ensemble spread of the plain forecast."""
+    from paper_1910_01031_amd import forecast_drifters_surrogate
+    lx, ly = cfg.nx * cfg.dx, cfg.ny * cfg.dy
+    pos0 = torch.from_numpy(np.stack([W.drifter_lattice(cfg, 8, 8)
+                                      for _ in range(cfg.n_particles)])).to(dev)
+    n_steps = 10 * windows
+    runs = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    for k, (name, first) in enumerate((("plain_a", 700_000), ("plain_b", 800_000),
+                                       ("surrogate", 700_000))):
+        st = start.clone()
+        pos = pos0.clone()
+        ev[2 * k].record()
+        if name == "surrogate":
+            nf = forecast_drifters_surrogate(ctx, net, st, pos, windows, 10, first, 1e-4, 3.0)
+        else:
+            ctx.forecast_drifters(st, pos, n_steps, first_step=first)
+            nf = None
+        ev[2 * k + 1].record()
+        runs[name] = (pos, nf)
+    torch.cuda.synchronize()
+    ms = {name: ev[2 * k].elapsed_time(ev[2 * k + 1]) for k, name in
+          enumerate(("plain_a", "plain_b", "surrogate"))}
+
+    def min_image(d):
+        L = torch.tensor([lx, ly], dtype=torch.float64, device=dev)
+        return torch.remainder(d + 0.5 * L, L) - 0.5 * L
+
+    def rmse(a, b):
+        return float(min_image(a - b).pow(2).sum(dim=-1).mean().sqrt())
+
+    pa = runs["plain_a"][0]
+    centre = pa[0:1] + min_image(pa - pa[0:1]).mean(dim=0, keepdim=True)
+    spread = float(min_image(pa - centre).pow(2).sum(dim=-1).mean().sqrt())
+    return {"drifters": int(pos0.shape[0] * pos0.shape[1]), "hours": windows / 12.0,
+            "ms_plain": ms["plain_a"], "ms_surrogate": ms["surrogate"],
+            "speedup": ms["plain_a"] / ms["surrogate"],
+            "rmse_surrogate_vs_plain_m": rmse(runs["surrogate"][0], pa),
+            "rmse_plain_vs_plain_m": rmse(runs["plain_b"][0], pa),
+            "spread_plain_m": spread, "surrogate_fallbacks": runs["surrogate"][1]}
+
+
 def surrogate_leg(torch, dev, ctx, ens, cfg, train_steps: int):
     """Learned surrogate of the 5-minute window on the paper-scale ensemble.  Training pairs
     (psi, ten deterministic model steps of psi) come from the same workload's own forecast:
@@ -203,7 +274,8 @@ def surrogate_leg(torch, dev, ctx, ens, cfg, train_steps: int):
     for k in range(10):
         ctx.step_ensemble(pdet, 1, first_step=600_000 + k, noise_on_last=False)
     sdet = start.clone()
-    nf_det, drift = surrogate_window(ctx, net, sdet, 10, 600_000, drift_tol=1e-4, noise_scale=0.0)
+    nf_det, drift_w = surrogate_window(ctx, net, sdet, 10, 600_000, drift_tol=1e-4,
+                                       noise_scale=0.0)
     net.forward(start, out)
     torch.cuda.synchronize()
     d = (out - pdet).double()
@@ -211,21 +283,24 @@ def surrogate_leg(torch, dev, ctx, ens, cfg, train_steps: int):
     rm = [float(d[:, c].pow(2).mean().sqrt()) for c in range(3)]
     ri = [float(inc[:, c].pow(2).mean().sqrt()) for c in range(3)]
     eta_drift = float(((out[:, 0] - start[:, 0]).double().mean(dim=(1, 2)).abs()).max() / cfg.H)
+    drift = drifter_comparison(torch, dev, ctx, net, start, cfg)
     ens.copy_(start)
     net.close()
-    flop = 171_072 * cfg.n_particles * cfg.n_cells
+    flop = SURROGATE_FLOPS_PER_PIXEL * cfg.n_particles * cfg.n_cells
     return {"train_states": 400, "train_cells": 400 * cfg.n_cells, "train_steps": train_steps,
             "batch_states": 1, "pair_generation_s": gen_s, "train_s": train_s,
             "loss_history": hist,
             "heldout_rmse_eta_hu_hv": rmse.tolist(),
             "heldout_persistence_rmse": persist.tolist(),
             "forward_ms": fwd_ms, "forward_tflops": flop / (fwd_ms / 1e3) / 1e12,
+            "forward_mfma_frac": flop / (fwd_ms / 1e3) / 1e12 / BF16_MFMA_PEAK_TFLOPS,
             "window_ms_plain": plain_ms, "window_ms_surrogate": sur_ms,
             "speedup": plain_ms / sur_ms, "fallbacks_per_window": nfs,
             "rmse_vs_plain_eta_hu_hv": rm,
             "window_increment_rms_eta_hu_hv": ri,
             "fallbacks_deterministic": nf_det,
-            "max_mass_drift": float(np.max(drift)), "max_mean_eta_drift_over_H": eta_drift}
+            "max_mass_drift": float(np.max(drift_w)), "max_mean_eta_drift_over_H": eta_drift,
+            "drifters_1h": drift}
 
 
 def main():
@@ -289,14 +364,17 @@ def main():
     torch.cuda.synchronize()
     tr = ctx.trace_read()
     ctx.set_trace(False)
-    sub_ms = tr["scheme_step"][0] + tr["scheme_step_noise"][0]
-    sub_n = tr["scheme_step"][1] + tr["scheme_step_noise"][1]
-    avg_sub_ms = sub_ms / max(sub_n, 1)
     analysis_ms = sum(tr[k][0] for k in ("innovation", "rand_dots", "beta_alpha",
                                          "posterior_coarse", "analysis_update")) / args.steps
     analysis_ms += tr["soar"][0] / max(tr["soar"][1], 1)  # one of the SOAR launches per cycle
-    bytes_per_launch = BYTES_PER_CELL_STEP * cfg.n_particles * cfg.nx * cfg.ny
-    achieved = bytes_per_launch / (avg_sub_ms / 1e3) / 1e9
+    plain_ms = tr["scheme_step"][0] / max(tr["scheme_step"][1], 1)
+    launch_cells = cfg.n_particles * cfg.nx * cfg.ny
+    bytes_per_launch = BYTES_PER_CELL_STEP * launch_cells
+    flops_per_launch = FLOPS_PER_CELL_STEP * launch_cells
+    achieved_tflops = flops_per_launch / (plain_ms / 1e3) / 1e12
+    achieved_gbs = bytes_per_launch / (plain_ms / 1e3) / 1e9
+    traffic = (MEASURED_TRAFFIC["bytes"]
+               if MEASURED_TRAFFIC["source_sha256"] == _kernel_source_hash() else None)
 
     if args.copy_calibration:
         a = torch.empty(90_000_000, dtype=torch.float32, device=dev)
@@ -326,10 +404,16 @@ def main():
                                 "alpha_min": last["alpha_min"], "alpha_max": last["alpha_max"]},
         "state_finite": finite,
         "kernel_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in tr.items()},
-        "roofline": {"bound": "hbm", "kernel": "swe_substep_kernel", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "avg_launch_ms": avg_sub_ms,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "roofline": {"bound": "alu", "kernel": "swe_substep_kernel<false> (scheme step)",
+                     "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic, "avg_launch_ms": plain_ms,
+                     "algorithmic_flops_per_launch": flops_per_launch,
+                     "hbm": {"achieved_gbs": achieved_gbs, "peak_gbs": HBM_PEAK_GBS,
+                             "frac": achieved_gbs / HBM_PEAK_GBS,
+                             "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "avg_launch_ms_with_model_error": (tr["scheme_step_noise"][0] /
+                                                        max(tr["scheme_step_noise"][1], 1))},
     }
     out["side"] = side_legs(torch, dev, ctx, ens, cfg)
     if not args.no_batched:

@@ -254,6 +254,20 @@ int iewpf_surrogate_window(iewpf_ctx* ctx, iewpf_net* net, float* state, int n_m
                            uint64_t first_step, double drift_tol, double noise_scale,
                            int32_t* n_fallback_out, double* drift_out, void* stream);
 
+/* Drifter forecast with the surrogate standing in for the model: n_windows windows of
+ * steps_per_window model steps, each one iewpf_surrogate_window (plain re-step of the
+ * particles whose mass drift exceeds drift_tol) followed by one model-error draw scaled by
+ * noise_scale (stream first_step + (w + 1) steps_per_window - 1, tag 1).  Within a window the
+ * drifters take steps_per_window Heun steps of dt in the states interpolated linearly in time
+ * between the window's start and its (deterministic) end.  pos, traj as in
+ * iewpf_forecast_drifters (traj: [n_windows steps_per_window + 1][...] or NULL);
+ * n_fallback_out: host, re-stepped particles summed over the windows (or NULL).  Waits for
+ * the stream.  Allocates one state-sized buffer in the context on its first call. */
+int iewpf_forecast_drifters_surrogate(iewpf_ctx* ctx, iewpf_net* net, float* state, double* pos,
+                                      int n_drifters, int n_windows, int steps_per_window,
+                                      uint64_t first_step, double drift_tol, double noise_scale,
+                                      double* traj, int32_t* n_fallback_out, void* stream);
+
 /* Per-kernel timing with HIP events recorded around every launch on the call's stream
  * (for measurement; off by default).  iewpf_set_trace(ctx, 1) starts a fresh record;
  * iewpf_trace_read waits for the recorded events and returns, per kernel kind, the total

@@ -4,6 +4,8 @@ The compute path is libiewpf.so (HIP kernels for gfx950, C ABI in include/iewpf.
 this package is its ctypes binding (`abi`) and the in-tree build step (`build`).
 """
 from . import abi
-from .abi import Batch, Context, IewpfError, Net, load, surrogate_window
+from .abi import (Batch, Context, IewpfError, Net, forecast_drifters_surrogate, load,
+                  surrogate_window)
 
-__all__ = ["abi", "Batch", "Context", "IewpfError", "Net", "load", "surrogate_window"]
+__all__ = ["abi", "Batch", "Context", "IewpfError", "Net", "forecast_drifters_surrogate", "load",
+           "surrogate_window"]

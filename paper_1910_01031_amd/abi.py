@@ -35,7 +35,7 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_net_set_params", "iewpf_net_get_params", "iewpf_net_set_norm",
             "iewpf_net_forward", "iewpf_net_train_step", "iewpf_net_read_activation",
             "iewpf_net_gradients",
-            "iewpf_surrogate_window", "iewpf_last_error")
+            "iewpf_surrogate_window", "iewpf_forecast_drifters_surrogate", "iewpf_last_error")
 
 TRACE_KINDS = ("scheme_step", "me_normals", "soar", "gb_add", "innovation", "rand_dots",
                "beta_alpha", "posterior_coarse", "analysis_update", "scheme_step_noise")
@@ -122,6 +122,9 @@ def load(path: str = LIB_PATH):
     lib.iewpf_surrogate_window.argtypes = [vp, vp, vp, i32, u64, ctypes.c_double,
                                            ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
                                            vp, vp]
+    lib.iewpf_forecast_drifters_surrogate.argtypes = [vp, vp, vp, vp, i32, i32, i32, u64,
+                                                      ctypes.c_double, ctypes.c_double, vp,
+                                                      ctypes.POINTER(ctypes.c_int32), vp]
     lib.iewpf_set_trace.argtypes = [vp, i32]
     lib.iewpf_trace_read.argtypes = [vp, f64p, vp, i32]
     lib.iewpf_net_num_params.restype = ctypes.c_size_t
@@ -404,3 +407,14 @@ def surrogate_window(ctx, net, state, n_model_steps: int, first_step: int, drift
                                          drift_tol, noise_scale, ctypes.byref(nf),
                                          drift.ctypes.data, _stream(stream)))
     return nf.value, drift
+
+
+def forecast_drifters_surrogate(ctx, net, state, pos, n_windows: int, steps_per_window: int,
+                                first_step: int, drift_tol: float, noise_scale: float, traj=None,
+                                stream=None) -> int:
+    """Surrogate drifter forecast; returns the number of plain re-steps over all windows."""
+    nf = ctypes.c_int32()
+    _check(load().iewpf_forecast_drifters_surrogate(
+        ctx.h, net.h, _ptr(state), _ptr(pos), int(pos.shape[1]), n_windows, steps_per_window,
+        first_step, drift_tol, noise_scale, _ptr(traj), ctypes.byref(nf), _stream(stream)))
+    return nf.value

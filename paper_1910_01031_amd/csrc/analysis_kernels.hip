@@ -359,8 +359,10 @@ __global__ __launch_bounds__(256) void cfl_kernel(size_t n_cells_total, size_t n
 }
 
 // Bilinear velocity of one particle's state at position (px, py) (metres, unwrapped).
-__device__ void velocity_at(const float* __restrict__ E, int nx, int ny, double dx, double dy,
-                            double H, double px, double py, double& u, double& v) {
+// Velocity of the state Ea + w (Eb - Ea) (Eb = Ea, w = 0: the state Ea itself).
+__device__ void velocity_at(const float* __restrict__ Ea, const float* __restrict__ Eb, double w,
+                            int nx, int ny, double dx, double dy, double H, double px, double py,
+                            double& u, double& v) {
   const size_t ncell = (size_t)nx * ny;
   const double fx = px / dx - 0.5, fy = py / dy - 0.5;
   const double fj = floor(fx), fk = floor(fy);
@@ -378,23 +380,31 @@ __device__ void velocity_at(const float* __restrict__ E, int nx, int ny, double 
   for (int b = 0; b < 2; ++b)
     for (int a = 0; a < 2; ++a) {
       const size_t c = (size_t)ks[b] * nx + js[a];
-      const double h = H + (double)E[c];
-      const double w = wxs[a] * wys[b];
-      u += w * ((double)E[ncell + c] / h);
-      v += w * ((double)E[2 * ncell + c] / h);
+      double f[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double ea = Ea[q * ncell + c];
+        f[q] = ea + w * ((double)Eb[q * ncell + c] - ea);
+      }
+      const double h = H + f[0];
+      const double wt = wxs[a] * wys[b];
+      u += wt * (f[1] / h);
+      v += wt * (f[2] / h);
     }
 }
 
 __global__ void drift_k1_kernel(int ne, int nd, int nx, int ny, double dx, double dy, double H,
                                 double dt, const float* __restrict__ psi,
+                                const float* __restrict__ psi_b, double w,
                                 const double* __restrict__ pos, double* __restrict__ k1,
                                 double* __restrict__ pstar) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ne * nd) return;
   const int i = t / nd;
   const float* E = psi + (size_t)i * 3 * nx * ny;
+  const float* Eb = psi_b + (size_t)i * 3 * nx * ny;
   double u, v;
-  velocity_at(E, nx, ny, dx, dy, H, pos[2 * t], pos[2 * t + 1], u, v);
+  velocity_at(E, Eb, w, nx, ny, dx, dy, H, pos[2 * t], pos[2 * t + 1], u, v);
   k1[2 * t] = u;
   k1[2 * t + 1] = v;
   pstar[2 * t] = pos[2 * t] + dt * u;
@@ -402,15 +412,17 @@ __global__ void drift_k1_kernel(int ne, int nd, int nx, int ny, double dx, doubl
 }
 
 __global__ void drift_k2_kernel(int ne, int nd, int nx, int ny, double dx, double dy, double H,
-                                double dt, const float* __restrict__ psi, double* __restrict__ pos,
+                                double dt, const float* __restrict__ psi,
+                                const float* __restrict__ psi_b, double w, double* __restrict__ pos,
                                 const double* __restrict__ k1, const double* __restrict__ pstar,
                                 double* __restrict__ traj) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ne * nd) return;
   const int i = t / nd;
   const float* E = psi + (size_t)i * 3 * nx * ny;
+  const float* Eb = psi_b + (size_t)i * 3 * nx * ny;
   double u, v;
-  velocity_at(E, nx, ny, dx, dy, H, pstar[2 * t], pstar[2 * t + 1], u, v);
+  velocity_at(E, Eb, w, nx, ny, dx, dy, H, pstar[2 * t], pstar[2 * t + 1], u, v);
   const double px = pos[2 * t] + 0.5 * dt * (k1[2 * t] + u);
   const double py = pos[2 * t + 1] + 0.5 * dt * (k1[2 * t + 1] + v);
   pos[2 * t] = px;
@@ -531,18 +543,18 @@ void launch_cfl(int ne, int nx, int ny, float H, float g, const float* psi, unsi
 
 void launch_drift_k1(int ne, int nd, int nx, int ny, double dx, double dy, double H, double dt,
                      const float* psi, const double* pos, double* k1, double* pstar,
-                     hipStream_t s) {
+                     hipStream_t s, const float* psi_b, double w) {
   const int n = ne * nd;
   hipLaunchKernelGGL(drift_k1_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ne, nd, nx, ny, dx, dy,
-                     H, dt, psi, pos, k1, pstar);
+                     H, dt, psi, psi_b ? psi_b : psi, psi_b ? w : 0.0, pos, k1, pstar);
 }
 
 void launch_drift_k2(int ne, int nd, int nx, int ny, double dx, double dy, double H, double dt,
                      const float* psi, double* pos, const double* k1, const double* pstar,
-                     double* traj, hipStream_t s) {
+                     double* traj, hipStream_t s, const float* psi_b, double w) {
   const int n = ne * nd;
   hipLaunchKernelGGL(drift_k2_kernel, dim3((n + 255) / 256), dim3(256), 0, s, ne, nd, nx, ny, dx, dy,
-                     H, dt, psi, pos, k1, pstar, traj);
+                     H, dt, psi, psi_b ? psi_b : psi, psi_b ? w : 0.0, pos, k1, pstar, traj);
 }
 
 void launch_resample(int ne, uint64_t seed, uint64_t step, uint32_t ens, const double* logw,

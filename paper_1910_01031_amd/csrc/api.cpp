@@ -102,7 +102,7 @@ int env_int(const char* name, int def) {
 
 void free_ctx(iewpf_ctx* c) {
   if (!c) return;
-  void* bufs[] = {c->saved, c->sdrift, c->sflags, c->scratch, c->part_dots, c->xi, c->nu,
+  void* bufs[] = {c->wstart, c->saved, c->sdrift, c->sflags, c->scratch, c->part_dots, c->xi, c->nu,
                   c->coarse, c->coarse2, c->windows,
                   c->dmat,    c->sd,     c->cval,   c->dots,   c->alpha,   c->cstar,
                   c->scal,    c->obs_cells, c->obs_y, c->pt_off, c->pt_ent, c->st_off,
@@ -184,6 +184,15 @@ void add_noise(iewpf_ctx* c, float* psi, uint64_t step, hipStream_t s) {
     launch_soar(c->cc, c->soar_me_f, c->ne, c->xi, c->coarse, s);
   }
   TraceScope t(c, kTrGbAdd, s);
+  launch_gb_add(c->cc, c->ne, c->coarse, nullptr, psi, c->upd_strip_h, s);
+}
+
+// One model-error draw (stream `step`, tag 1) with the SOAR weights scaled by `scale`.
+void add_scaled_noise(iewpf_ctx* c, float* psi, uint64_t step, double scale, hipStream_t s) {
+  float w[25];
+  for (int q = 0; q < 25; ++q) w[q] = (float)(scale * c->soar_me[q]);
+  launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, step, kTagModelError, c->cfg.ensemble_id, s);
+  launch_soar(c->cc, w, c->ne, c->xi, c->coarse, s);
   launch_gb_add(c->cc, c->ne, c->coarse, nullptr, psi, c->upd_strip_h, s);
 }
 
@@ -1000,18 +1009,51 @@ int iewpf_surrogate_window(iewpf_ctx* c, iewpf_net* net, float* state, int n_mod
       IEWPF_HIP_TRY(hipMemcpyAsync(state + per * fl[k], cur + per * k, sizeof(float) * per,
                                    hipMemcpyDeviceToDevice, s));
   }
-  if (noise_scale > 0.0) {  // one model-error draw for the window, scaled
-    float w[25];
-    for (int q = 0; q < 25; ++q) w[q] = (float)(noise_scale * c->soar_me[q]);
-    launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, first_step + n_model_steps - 1, kTagModelError,
-                   c->cfg.ensemble_id, s);
-    launch_soar(c->cc, w, c->ne, c->xi, c->coarse, s);
-    launch_gb_add(c->cc, c->ne, c->coarse, nullptr, state, c->upd_strip_h, s);
-  }
+  if (noise_scale > 0.0) add_scaled_noise(c, state, first_step + n_model_steps - 1, noise_scale, s);
   IEWPF_HIP_TRY(hipGetLastError());
   IEWPF_HIP_TRY(hipStreamSynchronize(s));
   *n_fallback_out = nf;
   if (drift_out) std::memcpy(drift_out, drift.data(), sizeof(double) * c->ne);
+  return 0;
+}
+
+int iewpf_forecast_drifters_surrogate(iewpf_ctx* c, iewpf_net* net, float* state, double* pos,
+                                      int n_drifters, int n_windows, int steps_per_window,
+                                      uint64_t first_step, double drift_tol, double noise_scale,
+                                      double* traj, int32_t* n_fallback_out, void* stream) {
+  if (!c || !net || !state || !pos || n_drifters < 0 || n_windows < 0 || steps_per_window < 1)
+    return fail(IEWPF_E_ARG, "invalid argument");
+  if (n_drifters > c->max_obs) return fail(IEWPF_E_CAPACITY, "more drifters than max_obs");
+  hipStream_t s = as_stream(stream);
+  const auto& f = c->cfg;
+  const size_t per_state = 3 * c->ncell * (size_t)c->ne;
+  if (!c->wstart) IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->wstart), sizeof(float) * per_state));
+  const size_t per = (size_t)c->ne * n_drifters * 2;
+  if (traj && per)
+    IEWPF_HIP_TRY(hipMemcpyAsync(traj, pos, sizeof(double) * per, hipMemcpyDeviceToDevice, s));
+  int total_fallback = 0;
+  for (int w = 0; w < n_windows; ++w) {
+    const uint64_t step0 = first_step + (uint64_t)w * steps_per_window;
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->wstart, state, sizeof(float) * per_state, hipMemcpyDeviceToDevice, s));
+    int32_t nf = 0;
+    if (int rc = iewpf_surrogate_window(c, net, state, steps_per_window, step0, drift_tol, 0.0, &nf,
+                                        nullptr, stream))
+      return rc;
+    total_fallback += nf;
+    // drifters: Heun steps in the states interpolated linearly in time across the window
+    for (int st = 0; st < steps_per_window && n_drifters; ++st) {
+      const double wa = (double)st / steps_per_window, wb = (double)(st + 1) / steps_per_window;
+      launch_drift_k1(c->ne, n_drifters, c->nx, c->ny, f.dx, f.dy, f.H, f.dt, c->wstart, pos, c->dk1,
+                      c->dpstar, s, state, wa);
+      const size_t ti = (size_t)w * steps_per_window + st + 1;
+      launch_drift_k2(c->ne, n_drifters, c->nx, c->ny, f.dx, f.dy, f.H, f.dt, c->wstart, pos, c->dk1,
+                      c->dpstar, traj ? traj + ti * per : nullptr, s, state, wb);
+    }
+    if (noise_scale > 0.0) add_scaled_noise(c, state, step0 + steps_per_window - 1, noise_scale, s);
+  }
+  IEWPF_HIP_TRY(hipGetLastError());
+  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  if (n_fallback_out) *n_fallback_out = total_fallback;
   return 0;
 }
 

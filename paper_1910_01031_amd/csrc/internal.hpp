@@ -139,6 +139,7 @@ struct iewpf_ctx {
   float* saved = nullptr;
   double* sdrift = nullptr;
   int32_t* sflags = nullptr;
+  float* wstart = nullptr;  // surrogate drifter forecast: the state at the window start
 };
 
 namespace iewpf {
@@ -247,12 +248,13 @@ void launch_observe(int n_obs, int nx, int ny, double H, double sigma, uint64_t 
                     double* y, hipStream_t s);
 void launch_cfl(int ne, int nx, int ny, float H, float g, const float* psi, unsigned* out,
                 hipStream_t s);
+// psi_b, w: the velocity is taken from psi + w (psi_b - psi) (psi_b NULL: from psi)
 void launch_drift_k1(int ne, int nd, int nx, int ny, double dx, double dy, double H, double dt,
                      const float* psi, const double* pos, double* k1, double* pstar,
-                     hipStream_t s);
+                     hipStream_t s, const float* psi_b = nullptr, double w = 0.0);
 void launch_drift_k2(int ne, int nd, int nx, int ny, double dx, double dy, double H, double dt,
                      const float* psi, double* pos, const double* k1, const double* pstar,
-                     double* traj, hipStream_t s);
+                     double* traj, hipStream_t s, const float* psi_b = nullptr, double w = 0.0);
 void launch_resample(int ne, uint64_t seed, uint64_t step, uint32_t ens, const double* logw,
                      int32_t* parents, int32_t* counts, hipStream_t s);
 void launch_gather_particles(int ne, size_t per_particle, const int32_t* parents, const float* in,

@@ -155,14 +155,17 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_kernel(ConvArgs A, int total
 //   CIN = 48: hidden-layer input, bf16 NHWC, K = 9 x 48 (14 chunks of 32), k = 48 tap + c.
 //   CIN = 8:  the normalised state (3 channels zero-padded to 8), K = 9 x 8 (3 chunks),
 //             k = 8 tap + c; the weights are re-laid from their k = 3 tap + c form.
-// LDS row strides are padded (pixel: 56 channels; weight row: K + 8) so that the 16 lanes
-// of a fragment read hit distinct banks.
+// LDS strides.  A 16-byte LDS read (ds_read_b128) is served 32 lanes at a time, and
+// measured bank conflicts on gfx950 fit 128 banks of 4 bytes: the 32 lanes (16 rows x 2
+// K-quads 16 bytes apart) are conflict-free when the row stride in 4-byte words is 8 x odd
+// modulo 128.  Pixel stride: 48 channels = 24 words (conflict-free unpadded); weight rows:
+// 232 words for K = 448 and 56 words for K = 96.
 template <int CIN>
 struct TileGeom {
-  static constexpr int CP = CIN == 48 ? 56 : 8;      // LDS pixel stride (bf16)
+  static constexpr int CP = CIN;                     // LDS pixel stride (bf16)
   static constexpr int CHUNKS = CIN == 48 ? 14 : 3;  // K chunks of 32
   static constexpr int KP = CHUNKS * 32;             // padded K
-  static constexpr int WS = KP + 8;                  // LDS weight row stride (bf16)
+  static constexpr int WS = CIN == 48 ? 464 : 112;   // LDS weight row stride (bf16)
   static constexpr int VPP = CIN / 8;                // 16-byte vectors per pixel (NHWC input)
 };
 constexpr int kTW = 64;  // output columns per tile

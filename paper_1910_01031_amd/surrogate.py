@@ -1,13 +1,14 @@
 """Training and evaluation of the learned surrogate forecast on the GPU.
 
 The surrogate maps a state psi_t to psi_{t + 5 min} (ten deterministic model steps of the
-finite-volume scheme).  Training pairs come from small periodic ensembles at the target grid
-spacing and scheme step (a 3x3 convolutional network is translation invariant, so a network
-trained on 32x32 tiles applies to any grid of the same spacing): each ensemble is drawn around
-a balanced jet, spun up with stochastic model steps, and then paired window by window with its
-deterministic ten-step forecast.  Every arithmetic step runs in the library's kernels
-(ensemble generation, scheme, network forward/backward, Adam); this module only orders the
-calls and slices device buffers.
+finite-volume scheme).  Training pairs come from ensembles on a grid of the target spacing and
+scheme step (a 3x3 convolutional network is translation invariant, so it applies to any grid
+of that spacing; the states should resemble the ones it will see): each ensemble is drawn
+around a balanced base state, spun up with stochastic model steps, and then paired window by
+window with its deterministic ten-step forecast.  Every arithmetic step runs in the library's
+kernels (ensemble generation, scheme, network forward/backward, Adam); this module only orders
+the calls and slices device buffers.  `python -m paper_1910_01031_amd.surrogate` times the
+forward pass.
 """
 from __future__ import annotations
 
@@ -115,3 +116,47 @@ def evaluate(torch, net: abi.Net, pairs: PairSet, batch: int = 256):
         sp += ((pairs.x[lo:hi] - pairs.t[lo:hi]).double() ** 2).sum(dim=(0, 2, 3))
     cells = n * pairs.x.shape[2] * pairs.x.shape[3]
     return (torch.sqrt(se / cells).cpu().numpy(), torch.sqrt(sp / cells).cpu().numpy())
+
+
+def time_forward(torch, batch: int, ny: int, nx: int, reps: int = 5, seed: int = 0):
+    """Milliseconds per network forward on `batch` random states of ny x nx (He-initialised
+    weights), after two untimed calls."""
+    net = abi.Net(batch * ny * nx)
+    try:
+        net.set_params(init_params(seed))
+        net.set_norm(np.zeros(3, np.float32), np.array([0.4, 50.0, 50.0], np.float32),
+                     np.array([0.01, 1.0, 1.0], np.float32))
+        gen = torch.Generator(device="cuda").manual_seed(seed)
+        scale = torch.tensor([0.4, 50.0, 50.0], device="cuda")[None, :, None, None]
+        x = torch.randn((batch, 3, ny, nx), device="cuda", generator=gen) * scale
+        y = torch.empty_like(x)
+        for _ in range(2):
+            net.forward(x, y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            net.forward(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    finally:
+        net.close()
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+
+    import torch
+
+    ap = argparse.ArgumentParser(description="time the surrogate forward pass")
+    ap.add_argument("--batch", type=int, default=100)
+    ap.add_argument("--ny", type=int, default=300)
+    ap.add_argument("--nx", type=int, default=500)
+    ap.add_argument("--reps", type=int, default=5)
+    a = ap.parse_args()
+    ms = time_forward(torch, a.batch, a.ny, a.nx, a.reps)
+    flop = 171_072 * a.batch * a.ny * a.nx
+    print(json.dumps({"forward_ms": ms, "tflops": flop / (ms / 1e3) / 1e12,
+                      "shape": [a.batch, 3, a.ny, a.nx]}), flush=True)

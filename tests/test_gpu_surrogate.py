@@ -360,3 +360,45 @@ def test_rejects_oversized_and_invalid_calls():
     with pytest.raises(IewpfError):
         net.set_norm([0, 0, 0], [1, 0, 1], [1, 1, 1])
     net.close()
+
+
+def test_surrogate_drifter_forecast_matches_interpolated_heun():
+    """Drifters under the surrogate: every window's end state is the network output, and the
+    drifters take Heun steps in the states interpolated linearly in time across the window
+    (the oracle's Heun step on the same interpolated states)."""
+    _need_gpu()
+    from oracle import drifters as odr
+    from paper_1910_01031_amd import forecast_drifters_surrogate
+    cfg, ctx, net, params, x = _window_setup(n_particles=3)
+    net.set_params(_flat(params).astype(np.float32))
+    net.set_norm(*NORM)
+    rng = np.random.default_rng(8)
+    pos0 = np.stack([wl.drifter_lattice(cfg, 3, 3) + rng.normal(scale=2e3, size=(9, 2))
+                     for _ in range(3)])
+    p = torch.from_numpy(pos0.copy()).cuda()
+    traj = torch.zeros((21, 3, 9, 2), dtype=torch.float64, device="cuda")
+    st = x.clone()
+    nf = forecast_drifters_surrogate(ctx, net, st, p, 2, 10, 40, drift_tol=1e30,
+                                     noise_scale=0.0, traj=traj)
+    assert nf == 0
+    e1 = torch.empty_like(x)
+    net.forward(x, e1)
+    e2 = torch.empty_like(x)
+    net.forward(e1, e2)
+    torch.cuda.synchronize()
+    assert torch.equal(st, e2)
+    ends = [x.cpu().numpy().astype(np.float64), e1.cpu().numpy().astype(np.float64),
+            e2.cpu().numpy().astype(np.float64)]
+    got = traj.cpu().numpy()
+    for i in range(3):
+        pos = pos0[i].copy()
+        for w in range(2):
+            a, b = ends[w][i], ends[w + 1][i]
+            for s in range(10):
+                pa = a + (s / 10.0) * (b - a)
+                pb = a + ((s + 1) / 10.0) * (b - a)
+                pos = odr.heun_step(pos, pa, pb, cfg, cfg.dt)
+                assert np.abs(got[w * 10 + s + 1, i] - pos).max() < 1e-8, (i, w, s)
+    assert np.abs(p.cpu().numpy()[i] - pos).max() < 1e-8
+    net.close()
+    ctx.close()
