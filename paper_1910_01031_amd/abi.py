@@ -80,6 +80,12 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_1910_01031_amd/build.py "
                            "(the HIP library is required; there is no fallback)")
+    # torch ships its own HIP runtime: load it first so that the library binds to the same
+    # one (a second runtime loaded before torch's leaves torch without devices).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i32, u64, f64p = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p
     lib.iewpf_create.argtypes = [ctypes.POINTER(IewpfConfig), ctypes.POINTER(vp)]

@@ -144,10 +144,11 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_kernel(ConvArgs A, int total
 }
 
 // Convolutions of the network as a persistent, LDS-tiled implicit GEMM (every forward layer
-// and the 48 -> 48 input gradients of the backward pass).  A workgroup of eight waves owns a
-// tile of 8 output rows x 64 columns of one image.  The (8 + 2) x (64 + 2) input pixels
-// (periodic wrap) sit in LDS, as do the layer's weights (loaded once per workgroup); every
-// wave computes one output row as 4 pixel tiles x NT channel tiles of
+// and the 48 -> 48 input gradients of the backward pass).  A workgroup of kTH waves owns a
+// tile of kTH output rows x kTW columns of one image (8 x 32 by default, the fastest of the
+// shapes timed).  The (kTH + 2) x (kTW + 2) input pixels (periodic wrap) sit in LDS, as do the
+// layer's weights (loaded once per workgroup); every wave computes one output row as kTW / 16
+// pixel tiles x NT channel tiles of
 // v_mfma_f32_16x16x32_bf16.  The operands are swapped with respect to the generic kernel
 // (A = weights, rows = output channels; B = pixels), so a lane ends with 4 consecutive
 // channels of one pixel.  While a tile is computed, the next tile's input is already being
@@ -159,17 +160,26 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_kernel(ConvArgs A, int total
 // measured bank conflicts on gfx950 fit 128 banks of 4 bytes: the 32 lanes (16 rows x 2
 // K-quads 16 bytes apart) are conflict-free when the row stride in 4-byte words is 8 x odd
 // modulo 128.  Pixel stride: 48 channels = 24 words (conflict-free unpadded); weight rows:
-// 232 words for K = 448 and 56 words for K = 96.
+// the 432 stored K values = 216 words (lanes past K take zero fragments instead of reading),
+// and 56 words for the 96 (zero-padded) K values of the 8-channel input.
 template <int CIN>
 struct TileGeom {
   static constexpr int CP = CIN;                     // LDS pixel stride (bf16)
   static constexpr int CHUNKS = CIN == 48 ? 14 : 3;  // K chunks of 32
   static constexpr int KP = CHUNKS * 32;             // padded K
-  static constexpr int WS = CIN == 48 ? 464 : 112;   // LDS weight row stride (bf16)
+  static constexpr int KW = CIN == 48 ? 432 : 96;    // K values stored per weight row
+  static constexpr int WS = CIN == 48 ? 432 : 112;   // LDS weight row stride (bf16)
   static constexpr int VPP = CIN / 8;                // 16-byte vectors per pixel (NHWC input)
 };
-constexpr int kTW = 64;  // output columns per tile
-constexpr int kTH = 8;   // output rows per tile (one per wave)
+#ifndef IEWPF_CONV_TW
+#define IEWPF_CONV_TW 32
+#endif
+#ifndef IEWPF_CONV_TH
+#define IEWPF_CONV_TH 8
+#endif
+constexpr int kTW = IEWPF_CONV_TW;  // output columns per tile (multiple of 16)
+constexpr int kTH = IEWPF_CONV_TH;  // output rows per tile (one per wave)
+constexpr int kTM = kTW / 16;       // pixel tiles per wave
 constexpr int kTThreads = 64 * kTH;
 
 __device__ __forceinline__ int wrapm(int i, int n) {
@@ -201,8 +211,8 @@ __global__ __launch_bounds__(kTThreads) void conv_tile_kernel(ConvArgs A, int nt
   const int row = lane & 15, kq = lane >> 4;
 
   // weights -> LDS, [NT * 16][WS]
-  for (int i = threadIdx.x; i < NT * 16 * (G::KP / 8); i += kTThreads) {
-    const int n = i / (G::KP / 8), kv = i - n * (G::KP / 8);
+  for (int i = threadIdx.x; i < NT * 16 * (G::KW / 8); i += kTThreads) {
+    const int n = i / (G::KW / 8), kv = i - n * (G::KW / 8);
     uint4 v;
     if (CIN == 48) {
       v = *reinterpret_cast<const uint4*>(A.wt + (size_t)n * A.Kpad + kv * 8);
@@ -279,11 +289,11 @@ __global__ __launch_bounds__(kTThreads) void conv_tile_kernel(ConvArgs A, int nt
     tile_origin(t, xt, yt, b, y0, x0);
     const int y = y0 + wave;
     if (y < A.H) {  // wave-uniform
-    f32x4 acc[NT][4];
+    f32x4 acc[NT][kTM];
 #pragma unroll
     for (int q = 0; q < NT; ++q)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) acc[q][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int m = 0; m < kTM; ++m) acc[q][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int kc = 0; kc < G::CHUNKS; ++kc) {
       const int k = kc * 32 + kq * 8;
@@ -304,10 +314,14 @@ __global__ __launch_bounds__(kTThreads) void conv_tile_kernel(ConvArgs A, int nt
       const uint16_t* base = tile + ((wave + dy) * (kTW + 2) + dx + row) * G::CP + c0;
       bf16x8 afr[NT];
 #pragma unroll
-      for (int q = 0; q < NT; ++q)
-        afr[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(wl + (q * 16 + row) * G::WS + k));
+      for (int q = 0; q < NT; ++q) {
+        u32x4 w = u32x4{0u, 0u, 0u, 0u};
+        if (kc * 32 + 32 <= G::KW || k < G::KW)  // the first test is compile-time
+          w = *reinterpret_cast<const u32x4*>(wl + (q * 16 + row) * G::WS + k);
+        afr[q] = __builtin_bit_cast(bf16x8, w);
+      }
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
+      for (int m = 0; m < kTM; ++m) {
         const bf16x8 bfr =
             __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(base + m * 16 * G::CP));
 #pragma unroll
@@ -317,7 +331,7 @@ __global__ __launch_bounds__(kTThreads) void conv_tile_kernel(ConvArgs A, int nt
     }
     // lane: pixel x0 + 16 m + row, channels 16 q + 4 kq .. + 3
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < kTM; ++m) {
       const int x = x0 + m * 16 + row;
       if (x >= A.W) continue;
       const size_t cell = ((size_t)b * A.H + y) * A.W + x;
@@ -603,7 +617,15 @@ void launch_tile(const ConvArgs& A, hipStream_t s) {
     attr = true;
   }
   const int ntiles = A.B * ((A.H + kTH - 1) / kTH) * ((A.W + kTW - 1) / kTW);
-  const int per_cu = bytes > 80 * 1024 ? 1 : 2;
+  static int per_cu = 0;  // resident workgroups per CU (registers and LDS)
+  if (per_cu == 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(conv_tile_kernel<CIN, NT, IN, OUT>), kTThreads,
+            bytes) != hipSuccess || n < 1)
+      n = 1;
+    per_cu = n;
+  }
   const int nb = ntiles < per_cu * cu_count() ? ntiles : per_cu * cu_count();
   hipLaunchKernelGGL((conv_tile_kernel<CIN, NT, IN, OUT>), dim3(nb), dim3(kTThreads), bytes, s, A,
                      ntiles);
