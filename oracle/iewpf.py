@@ -6,7 +6,8 @@ Stage 1  innovations d_i (eq. etaCompensatedInnovation);
 Stage 2  pull psi^a = psi^f + Q H^T S d with the per-observation chain of eq.
          detailedOPDUpdate: S d -> H^T -> coarse grid shifted onto the observed cell ->
          Q_GB^{1/2,T} (eq. adjointGeoBalance) -> Q_SOAR -> Q_SOAR -> I_Omega -> Q_GB;
-         observations are treated independently with 2x2 blocks S, pulls summed;
+         observations are treated independently with 2x2 blocks S, pulls summed (or,
+         optionally, S is the inverse of the full H Q H^T + R over all observations);
          c_i = sum_o d^T S d (eq. ciMultiDrifter; the previous weights are equal after an
          IEWPF step, so their constant term is dropped).  All weights are in -2 log w units.
 Stage 3  xi, nu~ ~ N(0, I) on Omega^R, nu = nu~ made perpendicular to xi with preserved
@@ -92,6 +93,36 @@ def s_matrix(cfg, w: np.ndarray, jo: int = 0, ko: int = 0) -> np.ndarray:
     """S = (H Q~ H^T + R)^{-1}, R = sigma^2 I (eq. S_extended)."""
     M = hqht(cfg, w, jo, ko)
     return inverse_via_cholesky(M + cfg.obs_sigma ** 2 * np.eye(2))
+
+
+def hqht_full(cfg, w: np.ndarray, cells: np.ndarray) -> np.ndarray:
+    """H Q~ H^T over all observations together, [2 n_obs, 2 n_obs] with rows/columns ordered
+    (observation, component): column (o, b) pushes the unit vector e_b at observation o
+    through the pull chain and reads (hu, hv) at every observed cell.  Blocks between
+    observations further apart than the chain's reach are exactly zero; the 2x2 diagonal
+    blocks equal hqht().  (The paper treats observations independently, i.e. keeps only the
+    diagonal blocks; this is the exact operator it approximates.)"""
+    n = len(cells)
+    M = np.zeros((2 * n, 2 * n))
+    for o in range(n):
+        jo, ko = int(cells[o, 0]), int(cells[o, 1])
+        for b, (su, sv) in enumerate(((1.0, 0.0), (0.0, 1.0))):
+            p = pull_one(su, sv, jo, ko, cfg, w)
+            for o2 in range(n):
+                j2, k2 = int(cells[o2, 0]), int(cells[o2, 1])
+                M[2 * o2, 2 * o + b] = p[1, k2, j2]
+                M[2 * o2 + 1, 2 * o + b] = p[2, k2, j2]
+    return M
+
+
+def s_full(cfg, w: np.ndarray, cells: np.ndarray) -> np.ndarray:
+    """S = (H Q~ H^T + R)^{-1} over all observations (eq. S_extended without the
+    independence assumption), through a Cholesky factorisation of the symmetric part.  With
+    c_Omega = 1 the chain's matrix is symmetric (it is H Q H^T); with c_Omega > 1 each
+    observation's pull uses a coarse grid aligned on its own cell, so the cross blocks are
+    only nearly symmetric and their symmetric part is used."""
+    M = hqht_full(cfg, w, cells)
+    return inverse_via_cholesky(M + cfg.obs_sigma ** 2 * np.eye(M.shape[0]))
 
 
 # --------------------------------------------------------------------------------------
@@ -202,13 +233,16 @@ class AnalysisConstants:
 
 
 def analysis(ens_f: np.ndarray, cells: np.ndarray, y: np.ndarray, cfg, analysis_index: int,
-             consts: AnalysisConstants | None = None, particles=None):
+             consts: AnalysisConstants | None = None, particles=None,
+             full_innovation: bool = False):
     """Two-stage IEWPF analysis of a forecast ensemble [Ne, 3, ny, nx] (float64 result).
 
     `particles` optionally restricts stage 6 (the state update) to a subset of particle
     indices; stages 1-5 always use the whole ensemble (stage 4 couples all particles).
-    Returns (ens_out, info) where ens_out holds only the updated particles in `particles`
-    order."""
+    `full_innovation` replaces the paper's independent 2x2 blocks of S by the inverse of the
+    full H Q H^T + R over all observations (s_full) in the pull and in c_i; stage 6 keeps
+    the paper's local blocks.  Returns (ens_out, info) where ens_out holds only the updated
+    particles in `particles` order."""
     if consts is None:
         consts = AnalysisConstants(cfg)
     ne = ens_f.shape[0]
@@ -218,7 +252,11 @@ def analysis(ens_f: np.ndarray, cells: np.ndarray, y: np.ndarray, cfg, analysis_
 
     # Stage 1 + part of 2: innovations and c_i
     d_all = np.stack([ob.innovations(ens_f[i], cells, y, cfg.H) for i in range(ne)])
-    sd_all = d_all @ S.T                                    # S d_o per observation
+    if full_innovation and len(cells):
+        Sf = s_full(cfg, consts.w, cells)
+        sd_all = (d_all.reshape(ne, -1) @ Sf.T).reshape(d_all.shape)
+    else:
+        sd_all = d_all @ S.T                                # S d_o per observation
     c = np.einsum("iok,iok->i", d_all, sd_all)
 
     # Stage 3
