@@ -117,6 +117,19 @@ int iewpf_step_ensemble(iewpf_ctx* ctx, float* state, int n_model_steps, uint64_
 /* Add one model-error draw (stream step_index, tag 1) to every particle, in place. */
 int iewpf_perturb(iewpf_ctx* ctx, float* state, uint64_t step_index, void* stream);
 
+/* Full innovation covariance on (1) or off (0, the default).  The paper treats observations
+ * independently: S = (H Q H^T + R)^{-1} is the same 2x2 block for every observation (eq.
+ * S_extended and the assumption after it that observations are far apart).  When on,
+ * iewpf_assimilate uses S = (sym(H Q H^T) + R)^{-1} over all observations together
+ * ([2 n_obs]^2, float64 Cholesky on the device) in the pull and in c_i; the posterior
+ * perturbation keeps the paper's local blocks.  H Q H^T's entries are the pull windows read
+ * at the offsets between observed cells; with c_Omega > 1 each observation's chain uses a
+ * coarse grid aligned on its own cell, so its symmetric part is used.  S is rebuilt only
+ * when the observed cells change (that call waits for the stream).  Requires
+ * 2 max_obs <= 1024 (IEWPF_E_CAPACITY otherwise); allocates its buffers on the first call;
+ * not available to batched cycles. */
+int iewpf_set_full_innovation(iewpf_ctx* ctx, int on);
+
 /* Two-stage IEWPF analysis of the forecast ensemble in place (Section "Efficient
  * implementation of the IEWPF scheme"): innovations, pull, perpendicular xi/nu (streams
  * (analysis_index, tags 2 and 3)), beta, alpha (Lambert W_0), local P^{1/2} and the
@@ -168,7 +181,8 @@ int iewpf_check_cfl(iewpf_ctx* ctx, const float* state, double* dt_out, void* st
  * which: 0 xi [Ne][NR] f32, 1 nu~ [Ne][NR] f32, 2 r' [Ne][NR] f32, 3 S 2x2 f64,
  * 4 S_c 2x2 f64, 5 A^{1/2} 49x49 f64, 6 pull windows [2][3][W][W] f32 with W given by
  * iewpf_window_size, 7 S d of the last analysis [Ne][n_obs][2] f64, 8 model-error SOAR
- * stencil 5x5 f64.  bytes must equal the buffer size. */
+ * stencil 5x5 f64, 9 the full S [2 n_obs][2 n_obs] f64 of the last full-covariance analysis.
+ * bytes must equal the buffer size. */
 int iewpf_read_buffer(iewpf_ctx* ctx, int which, void* host_out, size_t bytes, void* stream);
 
 /* Window extents (x, y) of the stored pull windows (2r+1 or the folded grid size). */

@@ -272,6 +272,114 @@ __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, do
   }
 }
 
+// Full innovation covariance (all observations together instead of independent 2x2 blocks).
+// Entry ((o2, a), (o, b)) of the chain's H Q H^T is component a (hu, hv) of the pull window
+// of unit vector e_b, read at the offset of observation o2's cell from observation o's cell
+// (zero beyond the window's reach); the matrix is symmetrised and R = sigma^2 I added.
+__global__ void hqht_full_kernel(int n_obs, int nx, int ny, int rx, int ry, int wx, int wy,
+                                 const double* __restrict__ win, const int32_t* __restrict__ cells,
+                                 double sigma2, double* __restrict__ M) {
+  const int n = 2 * n_obs;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n) return;
+  const int r = t / n, col = t - r * n;
+  const size_t plane = (size_t)wx * wy;
+  auto entry = [&](int rr, int cc) -> double {
+    const int o2 = rr >> 1, a = rr & 1, o = cc >> 1, b = cc & 1;
+    int dj = cells[2 * o2] - cells[2 * o], dk = cells[2 * o2 + 1] - cells[2 * o + 1];
+    int ix, iy;
+    if (rx >= 0) {
+      dj = dj > nx / 2 ? dj - nx : (dj < -(nx / 2) ? dj + nx : dj);
+      if (dj < -rx || dj > rx) return 0.0;
+      ix = dj + rx;
+    } else {
+      ix = wrapi(dj, nx);
+    }
+    if (ry >= 0) {
+      dk = dk > ny / 2 ? dk - ny : (dk < -(ny / 2) ? dk + ny : dk);
+      if (dk < -ry || dk > ry) return 0.0;
+      iy = dk + ry;
+    } else {
+      iy = wrapi(dk, ny);
+    }
+    return win[(size_t)(b * 3 + 1 + a) * plane + (size_t)iy * wx + ix];
+  };
+  M[t] = 0.5 * (entry(r, col) + entry(col, r)) + (r == col ? sigma2 : 0.0);
+}
+
+// S = A^{-1} for a symmetric positive definite A [n][n] (n <= kCholThreads), one workgroup,
+// float64: Cholesky A = L L^T in place (right-looking, pivot column staged in LDS), X = L^{-1}
+// column by column (one thread per column), then S = X^T X written over A.  status[0] = 1
+// when a pivot is not positive.
+constexpr int kCholThreads = 1024;
+__global__ __launch_bounds__(kCholThreads) void chol_inverse_kernel(int n, double* __restrict__ A,
+                                                                    double* __restrict__ X,
+                                                                    int32_t* __restrict__ status) {
+  __shared__ double col[kCholThreads];
+  const int tid = threadIdx.x;
+  if (tid == 0) status[0] = 0;
+  for (int j = 0; j < n; ++j) {
+    __syncthreads();
+    if (tid == 0) {
+      const double d = A[(size_t)j * n + j];
+      if (!(d > 0.0)) status[0] = 1;
+      col[j] = sqrt(d > 0.0 ? d : 1.0);
+      A[(size_t)j * n + j] = col[j];
+    }
+    __syncthreads();
+    const double p = col[j];
+    for (int i = j + 1 + tid; i < n; i += kCholThreads) {
+      const double v = A[(size_t)i * n + j] / p;
+      A[(size_t)i * n + j] = v;
+      col[i] = v;
+    }
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int t = tid; t < m * m; t += kCholThreads) {
+      const int i = j + 1 + t / m, k = j + 1 + t % m;
+      if (k <= i) A[(size_t)i * n + k] -= col[i] * col[k];
+    }
+  }
+  __syncthreads();
+  if (tid < n) {  // column c of X = L^{-1}
+    const int c = tid;
+    for (int r = c; r < n; ++r) {
+      double s = r == c ? 1.0 : 0.0;
+      for (int j = c; j < r; ++j) s -= A[(size_t)r * n + j] * X[(size_t)j * n + c];
+      X[(size_t)r * n + c] = s / A[(size_t)r * n + r];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < n * n; t += kCholThreads) {  // S[i][j] = sum_{k >= max(i, j)} X[k][i] X[k][j]
+    const int i = t / n, j = t - i * n;
+    double s = 0.0;
+    for (int k = i > j ? i : j; k < n; ++k) s += X[(size_t)k * n + i] * X[(size_t)k * n + j];
+    A[t] = s;  // L is no longer read: this phase reads X only
+  }
+}
+
+// sd = S d and c_i = d^T S d for every particle, with the full S [2 n_obs][2 n_obs].
+__global__ __launch_bounds__(kThreads) void sd_full_kernel(int n_obs, int max_obs,
+                                                           const double* __restrict__ S,
+                                                           const double* __restrict__ d,
+                                                           double* __restrict__ sd,
+                                                           double* __restrict__ cval) {
+  __shared__ double sh[kThreads];
+  const int i = blockIdx.x;
+  const int n = 2 * n_obs;
+  const double* di = d + (size_t)i * max_obs * 2;
+  double phi = 0.0;
+  for (int r = threadIdx.x; r < n; r += kThreads) {
+    const double* row = S + (size_t)r * n;
+    double s = 0.0;
+    for (int c = 0; c < n; ++c) s += row[c] * di[c];
+    sd[(size_t)i * max_obs * 2 + r] = s;
+    phi += di[r] * s;
+  }
+  phi = block_sum(phi, sh);
+  if (threadIdx.x == 0) cval[i] = phi;
+}
+
 __global__ __launch_bounds__(kThreads) void posterior_coarse_kernel(
     CoarseConst C, const float* __restrict__ xi, const float* __restrict__ nu,
     const double* __restrict__ dots, const double* __restrict__ alpha,
@@ -523,6 +631,24 @@ void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, cons
   hipLaunchKernelGGL(posterior_coarse_kernel, dim3((nr + kThreads - 1) / kThreads, ne),
                      dim3(kThreads), 0, s, C, xi, nu, dots, alpha, scal, dmat, pt_off, pt_ent,
                      cells, rout);
+}
+
+void launch_hqht_full(int n_obs, int nx, int ny, int rx, int ry, int wx, int wy, const double* win,
+                      const int32_t* cells, double sigma2, double* M, hipStream_t s) {
+  const int n = 2 * n_obs;
+  hipLaunchKernelGGL(hqht_full_kernel, dim3((n * n + 255) / 256), dim3(256), 0, s, n_obs, nx, ny, rx,
+                     ry, wx, wy, win, cells, sigma2, M);
+}
+
+int chol_max_order() { return kCholThreads; }
+
+void launch_chol_inverse(int n, double* A, double* X, int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(chol_inverse_kernel, dim3(1), dim3(kCholThreads), 0, s, n, A, X, status);
+}
+
+void launch_sd_full(int ne, int n_obs, int max_obs, const double* S, const double* d, double* sd,
+                    double* cval, hipStream_t s) {
+  hipLaunchKernelGGL(sd_full_kernel, dim3(ne), dim3(kThreads), 0, s, n_obs, max_obs, S, d, sd, cval);
 }
 
 void launch_observe(int n_obs, int nx, int ny, double H, double sigma, uint64_t seed,

@@ -102,7 +102,8 @@ int env_int(const char* name, int def) {
 
 void free_ctx(iewpf_ctx* c) {
   if (!c) return;
-  void* bufs[] = {c->wstart, c->saved, c->sdrift, c->sflags, c->scratch, c->part_dots, c->xi, c->nu,
+  void* bufs[] = {c->windows64, c->fS, c->fX, c->dinn, c->fstatus,
+                  c->wstart, c->saved, c->sdrift, c->sflags, c->scratch, c->part_dots, c->xi, c->nu,
                   c->coarse, c->coarse2, c->windows,
                   c->dmat,    c->sd,     c->cval,   c->dots,   c->alpha,   c->cstar,
                   c->scal,    c->obs_cells, c->obs_y, c->pt_off, c->pt_ent, c->st_off,
@@ -262,6 +263,27 @@ int upload_observations(iewpf_ctx* c, int n_obs, bool with_y, hipStream_t s) {
   return 0;
 }
 
+// Full innovation covariance for the observed cells (already on the device): rebuilt and
+// inverted only when the cell set differs from the cached one; waits for the stream then.
+int prepare_full_s(iewpf_ctx* c, const int32_t* cells, int n_obs, hipStream_t s) {
+  if (n_obs == c->f_n && std::equal(cells, cells + 2 * n_obs, c->f_cells.begin())) return 0;
+  const double s2 = c->cfg.obs_sigma * c->cfg.obs_sigma;
+  launch_hqht_full(n_obs, c->nx, c->ny, c->rx, c->ry, c->wx, c->wy, c->windows64, c->obs_cells, s2,
+                   c->fS, s);
+  launch_chol_inverse(2 * n_obs, c->fS, c->fX, c->fstatus, s);
+  IEWPF_HIP_TRY(hipGetLastError());
+  int32_t st = 0;
+  IEWPF_HIP_TRY(hipMemcpyAsync(&st, c->fstatus, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  if (st != 0) {
+    c->f_n = -1;
+    return fail(IEWPF_E_ARG, "full H Q H^T + R is not positive definite");
+  }
+  c->f_cells.assign(cells, cells + 2 * n_obs);
+  c->f_n = n_obs;
+  return 0;
+}
+
 // The analysis kernels of one ensemble on the observations already on the device.
 // dyn: device counters (dyn[1] = analysis index added to analysis_index) or nullptr.
 int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_index,
@@ -269,8 +291,15 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
   // stages 1-2: innovations, S d, c_i
   {
     TraceScope tr(c, kTrInnov, s);
-    launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, c->S, state,
-                      c->obs_cells, c->obs_y, c->sd, c->cval, s);
+    if (c->full_innov && n_obs > 0) {  // raw d, then S d and c_i with the full S
+      const double I2[4] = {1.0, 0.0, 0.0, 1.0};
+      launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, I2, state, c->obs_cells,
+                        c->obs_y, c->dinn, c->cval, s);
+      launch_sd_full(c->ne, n_obs, c->max_obs, c->fS, c->dinn, c->sd, c->cval, s);
+    } else {
+      launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, c->S, state,
+                        c->obs_cells, c->obs_y, c->sd, c->cval, s);
+    }
   }
   // stage 3: xi, nu~ and their dot products
   {
@@ -586,6 +615,7 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
     free_ctx(c);
     return fail(IEWPF_E_HIP, "pinned host allocation failed");
   }
+  c->h_win64 = win;
   std::vector<float> winf(win.begin(), win.end());
   std::vector<float> dm((size_t)kBlockN * kBlockN);
   for (int i = 0; i < kBlockN; ++i)
@@ -640,6 +670,30 @@ int iewpf_perturb(iewpf_ctx* c, float* state, uint64_t step_index, void* stream)
   return 0;
 }
 
+int iewpf_set_full_innovation(iewpf_ctx* c, int on) {
+  if (!c) return fail(IEWPF_E_ARG, "NULL context");
+  if (!on) {
+    c->full_innov = false;
+    return 0;
+  }
+  const int n = 2 * c->max_obs;
+  if (n > chol_max_order()) return fail(IEWPF_E_CAPACITY, "2 max_obs exceeds the full-covariance limit");
+  if (!c->fS) {
+    int rc = 0;
+    rc |= dev_alloc(&c->windows64, c->h_win64.size());
+    rc |= dev_alloc(&c->fS, (size_t)n * n);
+    rc |= dev_alloc(&c->fX, (size_t)n * n);
+    rc |= dev_alloc(&c->dinn, (size_t)c->ne * c->max_obs * 2);
+    rc |= dev_alloc(&c->fstatus, 1);
+    if (rc) return IEWPF_E_HIP;
+    IEWPF_HIP_TRY(hipMemcpy(c->windows64, c->h_win64.data(), sizeof(double) * c->h_win64.size(),
+                            hipMemcpyHostToDevice));
+  }
+  c->full_innov = true;
+  c->f_n = -1;
+  return 0;
+}
+
 int iewpf_assimilate(iewpf_ctx* c, float* state, const iewpf_obs* obs, int n_obs,
                      uint64_t analysis_index, iewpf_stats* stats_out, void* stream) {
   if (!c || !state || (n_obs > 0 && !obs) || n_obs < 0) return fail(IEWPF_E_ARG, "invalid argument");
@@ -657,6 +711,9 @@ int iewpf_assimilate(iewpf_ctx* c, float* state, const iewpf_obs* obs, int n_obs
   }
   if (int rc = check_cells(c, cells, n_obs)) return rc;
   if (int rc = upload_observations(c, n_obs, true, s)) return rc;
+  if (c->full_innov && n_obs > 0) {
+    if (int rc = prepare_full_s(c, cells, n_obs, s)) return rc;
+  }
   if (int rc = launch_analysis(c, state, n_obs, analysis_index, nullptr, s)) return rc;
   if (stats_out) {
     IEWPF_HIP_TRY(hipMemcpyAsync(c->h_small, c->scal, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
@@ -824,6 +881,8 @@ int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewp
     if (!ctxs[e] || !states[e]) return fail(IEWPF_E_ARG, "NULL context or state");
     if (ctxs[e]->cfg.n_sub != ctxs[0]->cfg.n_sub || ctxs[e]->cfg.dt != ctxs[0]->cfg.dt)
       return fail(IEWPF_E_ARG, "batched ensembles need the same dt and n_sub");
+    if (ctxs[e]->full_innov)
+      return fail(IEWPF_E_ARG, "batched cycles use the independent-block innovation covariance");
   }
   iewpf_batch* b = new iewpf_batch();
   b->n = n;
@@ -1119,6 +1178,12 @@ int iewpf_read_buffer(iewpf_ctx* c, int which, void* host_out, size_t bytes, voi
         if (c->last_n_obs)
           IEWPF_HIP_TRY(hipMemcpy(o + (size_t)i * c->last_n_obs * 2, c->sd + (size_t)i * c->max_obs * 2,
                                   sizeof(double) * c->last_n_obs * 2, hipMemcpyDeviceToHost));
+      return 0;
+    }
+    case 9: {
+      const size_t n = 2 * (size_t)(c->f_n > 0 ? c->f_n : 0);
+      if (!c->fS || n == 0 || !need(sizeof(double) * n * n)) break;
+      IEWPF_HIP_TRY(hipMemcpy(host_out, c->fS, sizeof(double) * n * n, hipMemcpyDeviceToHost));
       return 0;
     }
     case 8:

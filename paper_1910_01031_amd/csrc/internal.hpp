@@ -10,6 +10,8 @@
 
 #include "iewpf.h"
 
+#include <vector>
+
 namespace iewpf {
 
 // ---- error reporting -------------------------------------------------------------------
@@ -140,6 +142,17 @@ struct iewpf_ctx {
   double* sdrift = nullptr;
   int32_t* sflags = nullptr;
   float* wstart = nullptr;  // surrogate drifter forecast: the state at the window start
+  // full innovation covariance (optional): float64 windows, S [2 n]^2 of the cached cell set,
+  // work matrix, raw innovations, status word
+  bool full_innov = false;
+  double* windows64 = nullptr;
+  double* fS = nullptr;
+  double* fX = nullptr;
+  double* dinn = nullptr;
+  int32_t* fstatus = nullptr;
+  std::vector<int32_t> f_cells;  // cells the cached S was built for
+  int f_n = -1;
+  std::vector<double> h_win64;  // float64 pull windows [2][3][wy][wx] (host copy)
 };
 
 namespace iewpf {
@@ -237,6 +250,14 @@ int rand_dots_parts();
 void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens, float* xi,
                       float* nu, double* part_dots, double* dots, hipStream_t s,
                       const uint64_t* dyn = nullptr);
+// Full innovation covariance: assemble sym(H Q H^T) + sigma^2 I [2 n_obs]^2 (float64) from the
+// float64 pull windows, invert it in one workgroup (n <= chol_max_order()), S d and c_i.
+void launch_hqht_full(int n_obs, int nx, int ny, int rx, int ry, int wx, int wy, const double* win,
+                      const int32_t* cells, double sigma2, double* M, hipStream_t s);
+int chol_max_order();
+void launch_chol_inverse(int n, double* A, double* X, int32_t* status, hipStream_t s);
+void launch_sd_full(int ne, int n_obs, int max_obs, const double* S, const double* d, double* sd,
+                    double* cval, hipStream_t s);
 void launch_sync(int ne, double n_psi, double n_r, const double* cval, const double* dots,
                  double* alpha, double* cstar, double* scal, hipStream_t s);
 void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,

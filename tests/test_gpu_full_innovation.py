@@ -1,0 +1,110 @@
+"""GPU parity of the full innovation covariance (S over all observations together instead of
+the paper's independent 2x2 blocks) against the oracle's s_full and analysis(full_innovation)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import iewpf as oiewpf
+from oracle import model_error as ome
+from oracle import observe as oobs
+from test_gpu_analysis import TOL, _check_scalars, _ensemble_near
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda:0")
+
+
+def _run(torch, dev, cfg, ens32, cells, y, aidx, max_obs, full=True):
+    from paper_1910_01031_amd import Context
+    ctx = Context(cfg, max_obs=max_obs)
+    ctx.set_full_innovation(full)
+    st = torch.from_numpy(np.ascontiguousarray(ens32)).to(dev)
+    stats = ctx.assimilate(st, cells, y, analysis_index=aidx)
+    torch.cuda.synchronize()
+    sc = ctx.particle_scalars()
+    n = 2 * len(cells)
+    S = ctx.read_buffer(9, (n, n), np.float64) if full else None
+    out = st.cpu().numpy().astype(np.float64)
+    ctx.close()
+    return out, stats, sc, S
+
+
+def test_full_s_matches_oracle_and_analysis_parity(torch_dev):
+    torch, dev = torch_dev
+    _say("full innovation covariance: S and analysis vs oracle (64x48, 6 overlapping obs)")
+    cfg = W.Config(nx=64, ny=48, dx=1e4, dy=1e4, c_omega=4, n_particles=6, me_std=2e-3)
+    ens, truth = _ensemble_near(cfg, 6, 0.003)
+    cells = np.array([[10, 10], [12, 11], [15, 13], [40, 30], [63, 47], [0, 0]], dtype=np.int32)
+    y = oobs.mooring_obs(truth, cells, cfg.H, cfg.obs_sigma, np.zeros((6, 2)))
+    got, stats, sc, S = _run(torch, dev, cfg, ens, cells, y, 2, 8)
+    w = ome.model_error_stencil(cfg)
+    Sref = oiewpf.s_full(cfg, w, cells)
+    assert np.abs(S - Sref).max() < 1e-9 * np.abs(Sref).max()
+    ref, info = oiewpf.analysis(ens.astype(np.float64), cells, y, cfg, 2, full_innovation=True)
+    _check_scalars(stats, sc, info, cfg.n_psi)
+    for f in range(3):
+        err = np.abs(got[:, f] - ref[:, f]).max() / np.abs(ref[:, f]).max()
+        _say(f"  field {f} rel err {err}")
+        assert err < TOL, (f, err)
+    # the paper's independent blocks give a different analysis for these observations
+    blk, _, _, _ = _run(torch, dev, cfg, ens, cells, y, 2, 8, full=False)
+    assert np.abs(blk - got).max() > 10 * TOL * np.abs(got).max()
+
+
+def test_separated_observations_full_equals_blocks(torch_dev):
+    torch, dev = torch_dev
+    cfg = W.tiny().replace(c_omega=1, n_particles=4)
+    ens, truth = _ensemble_near(cfg, 4, 0.003)
+    cells = np.array([[2, 2], [18, 18]], dtype=np.int32)
+    y = oobs.mooring_obs(truth, cells, cfg.H, cfg.obs_sigma, np.zeros((2, 2)))
+    full, sf, _, _ = _run(torch, dev, cfg, ens, cells, y, 1, 4)
+    blk, sb, _, _ = _run(torch, dev, cfg, ens, cells, y, 1, 4, full=False)
+    assert abs(sf["cbar"] - sb["cbar"]) < 1e-9 * abs(sb["cbar"])
+    assert np.abs(full - blk).max() < 1e-6 * np.abs(blk).max()
+
+
+def test_full_s_inverse_at_paper_scale(torch_dev):
+    """225 buoys on 500x300 (neighbours 20 rows apart overlap): the device S (450x450) times
+    the matrix assembled independently from the oracle's translation-invariant pull response
+    is the identity."""
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Context
+    _say("full S at paper scale (225 buoys)")
+    cfg = W.paper_scale(2)
+    cells = W.buoy_cells(cfg.nx, cfg.ny, 15, 15)
+    ctx = Context(cfg, max_obs=len(cells))
+    ctx.set_full_innovation(True)
+    st = torch.from_numpy(W.as_f32(np.stack([W.jet_state(cfg)] * 2))).to(dev)
+    ctx.assimilate(st, cells, np.zeros((len(cells), 2)), analysis_index=0)
+    torch.cuda.synchronize()
+    n = 2 * len(cells)
+    S = ctx.read_buffer(9, (n, n), np.float64)
+    ctx.close()
+    # M from the oracle chain: one pull per unit vector at an observed cell, read at offsets
+    w = ome.model_error_stencil(cfg)
+    j0, k0 = int(cells[0, 0]), int(cells[0, 1])
+    resp = [oiewpf.pull_one(1.0, 0.0, j0, k0, cfg, w), oiewpf.pull_one(0.0, 1.0, j0, k0, cfg, w)]
+    M = np.zeros((n, n))
+    for o in range(len(cells)):
+        dj = cells[:, 0] - cells[o, 0]
+        dk = cells[:, 1] - cells[o, 1]
+        jj = (j0 + dj) % cfg.nx
+        kk = (k0 + dk) % cfg.ny
+        for b in range(2):
+            M[0::2, 2 * o + b] = resp[b][1, kk, jj]
+            M[1::2, 2 * o + b] = resp[b][2, kk, jj]
+    A = 0.5 * (M + M.T) + cfg.obs_sigma ** 2 * np.eye(n)
+    assert np.abs(S @ A - np.eye(n)).max() < 1e-9
+    assert np.abs(S - S.T).max() < 1e-12 * np.abs(S).max()
