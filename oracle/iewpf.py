@@ -234,7 +234,7 @@ class AnalysisConstants:
 
 def analysis(ens_f: np.ndarray, cells: np.ndarray, y: np.ndarray, cfg, analysis_index: int,
              consts: AnalysisConstants | None = None, particles=None,
-             full_innovation: bool = False):
+             full_innovation: bool = False, one_stage: bool = False):
     """Two-stage IEWPF analysis of a forecast ensemble [Ne, 3, ny, nx] (float64 result).
 
     `particles` optionally restricts stage 6 (the state update) to a subset of particle
@@ -242,7 +242,12 @@ def analysis(ens_f: np.ndarray, cells: np.ndarray, y: np.ndarray, cfg, analysis_
     `full_innovation` replaces the paper's independent 2x2 blocks of S by the inverse of the
     full H Q H^T + R over all observations (s_full) in the pull and in c_i; stage 6 keeps
     the paper's local blocks.  Returns (ens_out, info) where ens_out holds only the updated
-    particles in `particles` order."""
+    particles in `particles` order.
+
+    `one_stage` runs the original one-stage IEWPF instead (Appendix A, eq.
+    iewpfUpdateAgain): no nu term (beta = 0), target weight w_target = max_i c_i (eq.
+    iewpf_targetWeight), c*_i = w_target - c_i (eq. iewpfCStar), alpha_i by the Lambert W
+    limit of eq. numericalEqForAlpha; info["cbar"] then holds w_target."""
     if consts is None:
         consts = AnalysisConstants(cfg)
     ne = ens_f.shape[0]
@@ -275,9 +280,14 @@ def analysis(ens_f: np.ndarray, cells: np.ndarray, y: np.ndarray, cfg, analysis_
     zeta = dots[:, 1] * n_psi / n_r
 
     # Stage 4-5
-    cbar, beta, cstar = beta_and_cstar(c, zeta)
-    if not beta > 0.0:
-        raise ValueError(f"beta = {beta} <= 0: the ensemble violates N_psi >> N_y")
+    if one_stage:
+        cbar = float(np.max(c)) if ne else 0.0       # w_target
+        beta = 0.0
+        cstar = np.maximum(0.0, cbar - c)
+    else:
+        cbar, beta, cstar = beta_and_cstar(c, zeta)
+        if not beta > 0.0:
+            raise ValueError(f"beta = {beta} <= 0: the ensemble violates N_psi >> N_y")
     alpha = np.array([iewpf_alpha(gamma[i], cstar[i], n_psi) for i in range(ne)])
 
     # Stage 6

@@ -99,3 +99,47 @@ def iewpf_alpha(gamma: float, cstar: float, n_psi: float) -> float:
         return 1.0
     w = w0_branch_form(x, cn)
     return -w / x
+
+
+def iewpf_alpha_incomplete_gamma(gamma: float, cstar: float, n: float) -> float:
+    """alpha from the exact equation of the one-stage scheme (eq. numericalEqForAlpha):
+        P(N/2, alpha gamma/2) = exp(-c*/2) P(N/2, gamma/2),
+    P the regularised lower incomplete gamma function, solved for alpha < 1 by Newton in
+    u = ln alpha on F(u) = ln P(s, x e^u) - ln P(s, x) + c*/2 (s = N/2, x = gamma/2).
+    F is increasing in u with F(0) = c*/2 >= 0, so the root is at u <= 0.  Feasible while
+    ln P(s, x) stays representable, i.e. for small N (for large N the Lambert W limit
+    iewpf_alpha applies, which this converges to as N grows)."""
+    from scipy.special import gammainc, gammaln
+    s, x = 0.5 * n, 0.5 * gamma
+    cs = max(cstar, 0.0)
+    if cs == 0.0:
+        return 1.0
+    lp_x = math.log(gammainc(s, x))
+
+    def F(u):  # -inf where P underflows (far left of the root)
+        p = gammainc(s, x * math.exp(u))
+        return math.log(p) - lp_x + 0.5 * cs if p > 0.0 else -math.inf
+
+    def dF(u):  # d/du ln P(s, x e^u) = (x e^u)^s e^{-x e^u} / (Gamma(s) P(s, x e^u))
+        xu = x * math.exp(u)
+        return math.exp(s * math.log(xu) - xu - gammaln(s) - math.log(gammainc(s, xu)))
+
+    # bracket F(lo) <= 0 <= F(0), starting from twice the large-N (Lambert W) estimate
+    lo = 2.0 * math.log(iewpf_alpha(gamma, cs, n)) - 1e-3
+    while F(lo) > 0.0:
+        lo *= 2.0
+    hi, u = 0.0, 0.5 * lo
+    for _ in range(200):
+        f = F(u)
+        if f > 0.0:
+            hi = u
+        else:
+            lo = u
+        un = u - f / dF(u) if math.isfinite(f) else 0.5 * (lo + hi)
+        if not (lo < un < hi):  # keep Newton inside the bracket, else bisect
+            un = 0.5 * (lo + hi)
+        if abs(un - u) <= 1e-15 * max(1.0, abs(u)):
+            u = un
+            break
+        u = un
+    return math.exp(u)
