@@ -117,6 +117,15 @@ int iewpf_step_ensemble(iewpf_ctx* ctx, float* state, int n_model_steps, uint64_
 /* Add one model-error draw (stream step_index, tag 1) to every particle, in place. */
 int iewpf_perturb(iewpf_ctx* ctx, float* state, uint64_t step_index, void* stream);
 
+/* Filter scheme of iewpf_assimilate: 0 (default) the two-stage IEWPF (target weight = mean
+ * c_i, beta from eq. betaTwoStage, update eq. optUpdateEquationTwoStage); 1 the original
+ * one-stage IEWPF of Appendix A (eq. iewpfUpdateAgain: no nu term; target weight
+ * max_i c_i, eq. iewpf_targetWeight; c*_i = target - c_i, eq. iewpfCStar; alpha_i by eq.
+ * iewpfAlphaSol).  With 1, stats_out->cbar is the target weight, beta is 0 and argmin_beta
+ * is the particle with the largest c_i.  A batch's graph keeps the scheme its contexts had
+ * at its first cycle. */
+int iewpf_set_scheme(iewpf_ctx* ctx, int scheme);
+
 /* Full innovation covariance on (1) or off (0, the default).  The paper treats observations
  * independently: S = (H Q H^T + R)^{-1} is the same 2x2 block for every observation (eq.
  * S_extended and the assumption after it that observations are far apart).  When on,

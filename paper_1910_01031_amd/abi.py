@@ -36,7 +36,7 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_net_forward", "iewpf_net_train_step", "iewpf_net_read_activation",
             "iewpf_net_gradients",
             "iewpf_surrogate_window", "iewpf_forecast_drifters_surrogate",
-            "iewpf_set_full_innovation", "iewpf_last_error")
+            "iewpf_set_full_innovation", "iewpf_set_scheme", "iewpf_last_error")
 
 TRACE_KINDS = ("scheme_step", "me_normals", "soar", "gb_add", "innovation", "rand_dots",
                "beta_alpha", "posterior_coarse", "analysis_update", "scheme_step_noise")
@@ -133,6 +133,7 @@ def load(path: str = LIB_PATH):
                                                       ctypes.c_double, ctypes.c_double, vp,
                                                       ctypes.POINTER(ctypes.c_int32), vp]
     lib.iewpf_set_full_innovation.argtypes = [vp, i32]
+    lib.iewpf_set_scheme.argtypes = [vp, i32]
     lib.iewpf_set_trace.argtypes = [vp, i32]
     lib.iewpf_trace_read.argtypes = [vp, f64p, vp, i32]
     lib.iewpf_net_num_params.restype = ctypes.c_size_t
@@ -236,6 +237,10 @@ class Context:
                                        ctypes.byref(st) if want_stats else None,
                                        _stream(stream)))
         return st.as_dict() if want_stats else None
+
+    def set_scheme(self, one_stage: bool):
+        """False: two-stage IEWPF (default); True: the one-stage scheme."""
+        _check(load().iewpf_set_scheme(self.h, 1 if one_stage else 0))
 
     def set_full_innovation(self, on: bool):
         _check(load().iewpf_set_full_innovation(self.h, 1 if on else 0))

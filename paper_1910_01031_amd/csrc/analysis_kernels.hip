@@ -192,7 +192,12 @@ __device__ double alpha_solve(double gamma, double cstar, double N) {
   return y / x;
 }
 
+// one_stage = 0: two-stage scheme (target = mean c, beta from eq. betaTwoStage, c* from eq.
+// cistarTwoStage).  one_stage = 1: the original scheme of Appendix A (target = max c, eq.
+// iewpf_targetWeight; no nu term, beta = 0; c* = target - c_i, eq. iewpfCStar); scal[0] then
+// holds the target and scal[7] the particle that sets it.
 __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, double n_r,
+                                                        int one_stage,
                                                         const double* __restrict__ cval,
                                                         const double* __restrict__ dots,
                                                         double* __restrict__ alpha,
@@ -203,14 +208,15 @@ __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, do
   __shared__ int shi[kThreads];
   double s = 0.0;
   for (int i = threadIdx.x; i < ne; i += kThreads) s += cval[i];
-  const double cbar = block_sum(s, sh) / ne;
+  const double cmean = block_sum(s, sh) / ne;
   const double scale = n_psi / n_r;
-  // beta = min_i ((cbar - c_i)/zeta_i + 1), argmin with the smallest index on ties
+  // two-stage: beta = min_i ((cbar - c_i)/zeta_i + 1); one-stage: the largest c_i (as the
+  // minimum of -c_i); argmin with the smallest index on ties
   double bmin = 1e300;
   int imin = 0x7fffffff;
   for (int i = threadIdx.x; i < ne; i += kThreads) {
     const double zeta = dots[3 * i + 1] * scale;
-    const double b = (cbar - cval[i]) / zeta + 1.0;
+    const double b = one_stage ? -cval[i] : (cmean - cval[i]) / zeta + 1.0;
     if (b < bmin || (b == bmin && i < imin)) {
       bmin = b;
       imin = i;
@@ -230,15 +236,16 @@ __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, do
     }
     __syncthreads();
   }
-  const double beta = shb[0];
+  const double beta = one_stage ? 0.0 : shb[0];
+  const double cbar = one_stage ? -shb[0] : cmean;  // the target weight
   const int argmin = shi[0];
   __syncthreads();
   double amin = 1e300, amax = -1e300, csmax = 0.0, cmin = 1e300, cmax = -1e300;
   for (int i = threadIdx.x; i < ne; i += kThreads) {
     const double gamma = dots[3 * i] * scale;
     const double zeta = dots[3 * i + 1] * scale;
-    const double cs = fmax(0.0, cbar - cval[i] - (beta - 1.0) * zeta);
-    const double a = beta > 0.0 ? alpha_solve(gamma, cs, n_psi) : 0.0;
+    const double cs = fmax(0.0, one_stage ? cbar - cval[i] : cbar - cval[i] - (beta - 1.0) * zeta);
+    const double a = (one_stage || beta > 0.0) ? alpha_solve(gamma, cs, n_psi) : 0.0;
     cstar[i] = cs;
     alpha[i] = a;
     amin = fmin(amin, a);
@@ -617,10 +624,10 @@ void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens
   hipLaunchKernelGGL(reduce_dots_kernel, dim3((ne + 127) / 128), dim3(128), 0, s, ne, part_dots, dots);
 }
 
-void launch_sync(int ne, double n_psi, double n_r, const double* cval, const double* dots,
-                 double* alpha, double* cstar, double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(sync_kernel, dim3(1), dim3(kThreads), 0, s, ne, n_psi, n_r, cval, dots, alpha,
-                     cstar, scal);
+void launch_sync(int ne, double n_psi, double n_r, int one_stage, const double* cval,
+                 const double* dots, double* alpha, double* cstar, double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(sync_kernel, dim3(1), dim3(kThreads), 0, s, ne, n_psi, n_r, one_stage, cval,
+                     dots, alpha, cstar, scal);
 }
 
 void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,

@@ -310,7 +310,8 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
   // stages 4-5: cbar, beta, c*, alpha (the one ensemble-wide step)
   {
     TraceScope tr(c, kTrSync, s);
-    launch_sync(c->ne, c->n_psi, (double)c->nr, c->cval, c->dots, c->alpha, c->cstar, c->scal, s);
+    launch_sync(c->ne, c->n_psi, (double)c->nr, c->one_stage, c->cval, c->dots, c->alpha, c->cstar,
+                c->scal, s);
   }
   // stage 6: r' on the coarse grid, SOAR, then one fused pass over the state
   {
@@ -670,6 +671,12 @@ int iewpf_perturb(iewpf_ctx* c, float* state, uint64_t step_index, void* stream)
   return 0;
 }
 
+int iewpf_set_scheme(iewpf_ctx* c, int scheme) {
+  if (!c || (scheme != 0 && scheme != 1)) return fail(IEWPF_E_ARG, "scheme must be 0 or 1");
+  c->one_stage = scheme;
+  return 0;
+}
+
 int iewpf_set_full_innovation(iewpf_ctx* c, int on) {
   if (!c) return fail(IEWPF_E_ARG, "NULL context");
   if (!on) {
@@ -728,7 +735,8 @@ int iewpf_assimilate(iewpf_ctx* c, float* state, const iewpf_obs* obs, int n_obs
     stats_out->c_max = v[6];
     stats_out->argmin_beta = (int32_t)v[7];
     stats_out->n_obs = n_obs;
-    if (!(v[1] > 0.0)) return fail(IEWPF_E_BETA, "beta <= 0: ensemble violates N_psi >> N_y");
+    if (!c->one_stage && !(v[1] > 0.0))
+      return fail(IEWPF_E_BETA, "beta <= 0: ensemble violates N_psi >> N_y");
   }
   return 0;
 }

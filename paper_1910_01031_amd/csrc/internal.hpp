@@ -145,6 +145,7 @@ struct iewpf_ctx {
   // full innovation covariance (optional): float64 windows, S [2 n]^2 of the cached cell set,
   // work matrix, raw innovations, status word
   bool full_innov = false;
+  int one_stage = 0;  // 1: the one-stage scheme (target max c, no nu term)
   double* windows64 = nullptr;
   double* fS = nullptr;
   double* fX = nullptr;
@@ -258,8 +259,8 @@ int chol_max_order();
 void launch_chol_inverse(int n, double* A, double* X, int32_t* status, hipStream_t s);
 void launch_sd_full(int ne, int n_obs, int max_obs, const double* S, const double* d, double* sd,
                     double* cval, hipStream_t s);
-void launch_sync(int ne, double n_psi, double n_r, const double* cval, const double* dots,
-                 double* alpha, double* cstar, double* scal, hipStream_t s);
+void launch_sync(int ne, double n_psi, double n_r, int one_stage, const double* cval,
+                 const double* dots, double* alpha, double* cstar, double* scal, hipStream_t s);
 void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,
                              const double* dots, const double* alpha, const double* scal,
                              const float* dmat, const int32_t* pt_off, const int32_t* pt_ent,

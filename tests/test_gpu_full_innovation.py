@@ -108,3 +108,38 @@ def test_full_s_inverse_at_paper_scale(torch_dev):
     A = 0.5 * (M + M.T) + cfg.obs_sigma ** 2 * np.eye(n)
     assert np.abs(S @ A - np.eye(n)).max() < 1e-9
     assert np.abs(S - S.T).max() < 1e-12 * np.abs(S).max()
+
+
+@pytest.mark.parametrize("full", [False, True])
+def test_one_stage_scheme_parity(torch_dev, full):
+    """The one-stage scheme (target weight max c, no nu term) against the oracle, with the
+    paper's 2x2 blocks and with the full innovation covariance."""
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Context
+    _say(f"one-stage scheme parity (full covariance {full})")
+    cfg = W.Config(nx=64, ny=48, dx=1e4, dy=1e4, c_omega=4, n_particles=6, me_std=2e-3)
+    ens, truth = _ensemble_near(cfg, 6, 0.003)
+    cells = np.array([[10, 10], [12, 11], [40, 30], [63, 47]], dtype=np.int32)
+    y = oobs.mooring_obs(truth, cells, cfg.H, cfg.obs_sigma, np.zeros((4, 2)))
+    ctx = Context(cfg, max_obs=8)
+    ctx.set_scheme(True)
+    ctx.set_full_innovation(full)
+    st = torch.from_numpy(np.ascontiguousarray(ens)).to(dev)
+    stats = ctx.assimilate(st, cells, y, analysis_index=4)
+    torch.cuda.synchronize()
+    sc = ctx.particle_scalars()
+    got = st.cpu().numpy().astype(np.float64)
+    ctx.close()
+    ref, info = oiewpf.analysis(ens.astype(np.float64), cells, y, cfg, 4, full_innovation=full,
+                                one_stage=True)
+    assert stats["beta"] == 0.0
+    assert abs(stats["cbar"] - info["cbar"]) < 1e-9 * abs(info["cbar"])
+    assert stats["argmin_beta"] == int(np.argmax(info["c"]))
+    assert np.abs(sc[:, 0] - info["c"]).max() < 1e-9 * np.abs(info["c"]).max()
+    assert np.abs(sc[:, 3] - info["alpha"]).max() < 1e-7
+    # every particle reaches the target weight (one-stage form, no nu term)
+    w = (sc[:, 3] - 1.0) * sc[:, 1] - cfg.n_psi * np.log(sc[:, 3]) + sc[:, 0]
+    assert np.abs(w - stats["cbar"]).max() < 1e-9 * cfg.n_psi
+    for f in range(3):
+        err = np.abs(got[:, f] - ref[:, f]).max() / np.abs(ref[:, f]).max()
+        assert err < TOL, (f, err)
