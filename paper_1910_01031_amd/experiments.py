@@ -1,0 +1,195 @@
+"""Statistical checks of the filter on the GPU (Section "Rank histograms for IEWPF" and Section
+"Collapse of the standard particle filter"), at reduced scale.
+
+rank_histograms: independent data-assimilation experiments, each with its own truth drawn
+  from the same prior as its ensemble.  Moorings in the western half of the domain are
+  assimilated every 5 minutes, then a 1-hour forecast follows.  For hu and hv at cells
+  (100, y), y = 0, 50, ..., 250, the rank of the observed truth (truth + observation error)
+  among the ensemble values (member + observation error) is recorded.  A correct filter
+  gives flat histograms.  Experiments run 16 at a time as one batch (one hipGraph replay
+  per cycle).
+
+sir_collapse: an ensemble assimilates drifters with the IEWPF, runs to the next
+  observation time, and the standard particle filter's normalised weights (depending on the
+  innovations and R only) are computed for random subsets of the drifters.  For each subset
+  size, the mean number of particles whose weight exceeds 1/N_e (those residual resampling
+  is guaranteed to keep) is reported, for R and for 10 R.
+
+Every model step and analysis runs in the library's kernels.  The ranks and weights are
+computed here from a handful of values read back.
+Run as `python -m paper_1910_01031_amd.experiments` from the repository root (it uses the
+seeded workload recipes in `workloads/`).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import abi
+
+
+def _workloads():
+    import workloads
+    return workloads
+
+
+def rank_histograms(torch, n_experiments: int = 128, n_particles: int = 40, da_hours: float = 6.0,
+                    forecast_hours: float = 1.0, spinup_hours: float = 1.0, batch: int = 16,
+                    seed: int = 0):
+    """Returns dict(hist=[2][6][N_e+1] int (hu, hv x cells), accumulated=[2][N_e+1],
+    chi2 / p-value of each accumulated histogram against the uniform one)."""
+    W = _workloads()
+    from scipy.stats import chi2 as chi2_dist
+    dev = torch.device("cuda")
+    cfg0 = W.paper_scale(n_particles)
+    cells = W.buoy_cells(cfg0.nx // 2, cfg0.ny, 8, 15)  # 120 moorings, western half
+    probe = [(100, y) for y in range(0, cfg0.ny, 50)]
+    base = torch.from_numpy(W.as_f32(W.jet_state(cfg0))).to(dev)
+    steps = 10                                          # model steps per 5-minute cycle
+    n_spin = int(round(spinup_hours * 12)) * steps
+    n_cyc = int(round(da_hours * 12))
+    n_fc = int(round(forecast_hours * 12)) * steps
+    rng = np.random.default_rng(seed)
+    sig = cfg0.obs_sigma
+    hist = np.zeros((2, len(probe), n_particles + 1), dtype=np.int64)
+    for b0 in range(0, n_experiments, batch):
+        ne_b = min(batch, n_experiments - b0)
+        ctxs, ens, tctxs, truths = [], [], [], []
+        for e in range(b0, b0 + ne_b):
+            c = abi.Context(cfg0.replace(ensemble_id=1000 + e, seed=cfg0.seed + seed),
+                            max_obs=len(cells))
+            st = torch.empty((n_particles, 3, cfg0.ny, cfg0.nx), device=dev)
+            c.init_ensemble(st, base, stream_index=e)
+            c.step_ensemble(st, n_spin, first_step=0, noise_on_last=True)
+            t = abi.Context(cfg0.replace(n_particles=1, ensemble_id=100000 + e,
+                                         seed=cfg0.seed + seed), max_obs=len(cells))
+            tr = torch.empty((1, 3, cfg0.ny, cfg0.nx), device=dev)
+            t.init_ensemble(tr, base, stream_index=e)   # same prior, own random stream
+            t.step_ensemble(tr, n_spin, first_step=0, noise_on_last=True)
+            ctxs.append(c)
+            ens.append(st)
+            tctxs.append(t)
+            truths.append(tr)
+        bt = abi.Batch(ctxs, ens)
+        for e in range(ne_b):
+            bt.set_cells(e, cells)
+        for cyc in range(n_cyc):
+            first = n_spin + cyc * steps
+            ys = []
+            for t, tr in zip(tctxs, truths):
+                t.step_ensemble(tr, steps, first_step=first, noise_on_last=True)
+                ys.append(t.observe_moorings(tr, cells, analysis_index=cyc))
+            bt.cycle(steps, first, cyc, ys, use_graph=True)
+        first = n_spin + n_cyc * steps
+        for e in range(ne_b):
+            ctxs[e].step_ensemble(ens[e], n_fc, first_step=first, noise_on_last=True)
+            tctxs[e].step_ensemble(truths[e], n_fc, first_step=first, noise_on_last=True)
+        torch.cuda.synchronize()
+        for e in range(ne_b):
+            for p, (j, k) in enumerate(probe):
+                vals = ens[e][:, 1:3, k, j].double().cpu().numpy()      # [N_e][hu, hv]
+                tv = truths[e][0, 1:3, k, j].double().cpu().numpy()
+                for v in range(2):
+                    member = vals[:, v] + sig * rng.standard_normal(n_particles)
+                    observed = tv[v] + sig * rng.standard_normal()
+                    hist[v, p, int(np.sum(member < observed))] += 1
+        bt.close()
+        for c in ctxs + tctxs:
+            c.close()
+    acc = hist.sum(axis=1)
+    out = {"n_experiments": n_experiments, "n_particles": n_particles, "da_hours": da_hours,
+           "forecast_hours": forecast_hours, "cells": probe, "hist": hist.tolist(),
+           "accumulated": acc.tolist()}
+    for v, name in enumerate(("hu", "hv")):
+        expect = acc[v].sum() / (n_particles + 1)
+        chi2 = float(((acc[v] - expect) ** 2 / expect).sum())
+        out[f"chi2_{name}"] = chi2
+        out[f"p_{name}"] = float(chi2_dist.sf(chi2, n_particles))
+    return out
+
+
+def sir_collapse(torch, n_particles: int = 100, da_hours: float = 6.0, n_drifters: int = 64,
+                 max_observed: int = 10, subsets: int = 50, seed: int = 0):
+    """Mean number of particles with standard-particle-filter weight > 1/N_e for 1..max_observed
+    observed drifters (random subsets), with R and with 10 R."""
+    W = _workloads()
+    dev = torch.device("cuda")
+    cfg = W.paper_scale(n_particles)
+    base = torch.from_numpy(W.as_f32(W.jet_state(cfg))).to(dev)
+    ctx = abi.Context(cfg, max_obs=n_drifters)
+    ens = torch.empty((n_particles, 3, cfg.ny, cfg.nx), device=dev)
+    ctx.init_ensemble(ens, base, stream_index=0)
+    tctx = abi.Context(cfg.replace(n_particles=1, ensemble_id=0x7FFF), max_obs=n_drifters)
+    truth = torch.empty((1, 3, cfg.ny, cfg.nx), device=dev)
+    tctx.init_ensemble(truth, base, stream_index=1)
+    side = int(round(math.sqrt(n_drifters)))
+    pos = torch.from_numpy(W.drifter_lattice(cfg, side, side)[None]).to(dev)
+    steps = 10
+
+    def drifter_cells():
+        p = pos[0].cpu().numpy()
+        j = np.floor(p[:, 0] / cfg.dx).astype(np.int64) % cfg.nx
+        k = np.floor(p[:, 1] / cfg.dy).astype(np.int64) % cfg.ny
+        return np.stack([j, k], axis=1).astype(np.int32)
+
+    n_cyc = int(round(da_hours * 12))
+    for cyc in range(n_cyc + 1):
+        tctx.forecast_drifters(truth, pos, steps, first_step=cyc * steps)  # truth and drifters
+        cells = drifter_cells()
+        y = tctx.observe_moorings(truth, cells, analysis_index=cyc)
+        ctx.step_ensemble(ens, steps, first_step=cyc * steps, noise_on_last=False)
+        if cyc < n_cyc:
+            ctx.assimilate(ens, cells, y, analysis_index=cyc, want_stats=False)
+    torch.cuda.synchronize()
+    # innovations of every particle at every drifter (eq. etaCompensatedInnovation)
+    jj, kk = cells[:, 0], cells[:, 1]
+    st = ens[:, :, kk, jj].double().cpu().numpy()                 # [N_e][3][n_drifters]
+    scale = (cfg.H + st[:, 0]) / cfg.H
+    d = np.stack([y[None, :, 0] * scale - st[:, 1], y[None, :, 1] * scale - st[:, 2]], axis=2)
+    rng = np.random.default_rng(seed)
+    out = {"n_particles": n_particles, "da_hours": da_hours, "n_drifters": n_drifters,
+           "observed": list(range(1, max_observed + 1))}
+    for label, r in (("R", cfg.obs_sigma ** 2), ("10R", 10 * cfg.obs_sigma ** 2)):
+        means = []
+        for m in range(1, max_observed + 1):
+            kept = []
+            for _ in range(subsets):
+                sub = rng.choice(n_drifters, size=m, replace=False)
+                logw = -0.5 * np.sum(d[:, sub, :] ** 2, axis=(1, 2)) / r
+                w = np.exp(logw - logw.max())
+                w /= w.sum()
+                kept.append(int(np.sum(w > 1.0 / n_particles)))
+            means.append(float(np.mean(kept)))
+        out[f"kept_{label}"] = means
+    ctx.close()
+    tctx.close()
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    import sys
+    import time
+
+    import torch
+
+    ap = argparse.ArgumentParser(description="rank histograms and SIR collapse (reduced scale)")
+    ap.add_argument("--experiments", type=int, default=128)
+    ap.add_argument("--da-hours", type=float, default=6.0)
+    ap.add_argument("--skip-rank", action="store_true")
+    ap.add_argument("--skip-sir", action="store_true")
+    a = ap.parse_args()
+    res = {}
+    if not a.skip_rank:
+        t0 = time.perf_counter()
+        res["rank_histograms"] = rank_histograms(torch, n_experiments=a.experiments,
+                                                 da_hours=a.da_hours)
+        res["rank_histograms"]["seconds"] = time.perf_counter() - t0
+        print("rank histograms done", file=sys.stderr, flush=True)
+    if not a.skip_sir:
+        t0 = time.perf_counter()
+        res["sir_collapse"] = sir_collapse(torch, da_hours=a.da_hours)
+        res["sir_collapse"]["seconds"] = time.perf_counter() - t0
+    print(json.dumps(res), flush=True)
