@@ -272,7 +272,9 @@ int iewpf_net_gradients(iewpf_net* net, const float* x, const float* target, int
  * plain solver from its saved state; then one model-error draw (stream first_step +
  * n_model_steps - 1) scaled by noise_scale is added to all particles.  n_fallback_out: host,
  * particles re-stepped; drift_out: host double [n_particles] or NULL.  Waits for the stream.
- * The first call allocates one state-sized buffer in the context. */
+ * The network runs on as many particles at a time as its max_cells holds (at least one
+ * particle's cells, else IEWPF_E_CAPACITY).  The first call allocates one state-sized
+ * buffer in the context. */
 int iewpf_surrogate_window(iewpf_ctx* ctx, iewpf_net* net, float* state, int n_model_steps,
                            uint64_t first_step, double drift_tol, double noise_scale,
                            int32_t* n_fallback_out, double* drift_out, void* stream);

@@ -202,6 +202,7 @@ struct ConvArgs {
   float mu[3], isig[3], s[3];
 };
 void launch_conv(const ConvArgs& A, int in_mode, int out_mode, hipStream_t s);
+int net_max_cells(const iewpf_net* n);
 void launch_wgrad(const ConvArgs& A, int in_mode, const uint16_t* g, int gch, int cells_per_chunk,
                   float* part, hipStream_t s);
 void launch_bgrad(const uint16_t* g, int gch, int ncells, int cells_per_chunk, float* part,

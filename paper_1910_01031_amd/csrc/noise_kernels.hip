@@ -232,7 +232,10 @@ __global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, PullConst P,
 // for kPB particles per wave, so every window value fetched from cache serves kPB
 // particles.  W_u, W_v: precomputed responses to the unit vectors (stored windows); the
 // observation list of the strip comes from the host; the row window test is wave-uniform.
-constexpr int kPB = 4;
+#ifndef IEWPF_UPD_PB
+#define IEWPF_UPD_PB 4
+#endif
+constexpr int kPB = IEWPF_UPD_PB;
 
 __global__ __launch_bounds__(256) void analysis_update_kernel(
     CoarseConst C, PullConst P, int ne, int total_waves, const float* __restrict__ zall,

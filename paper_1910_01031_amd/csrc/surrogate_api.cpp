@@ -145,6 +145,9 @@ void forward_backward(iewpf_net* n, const float* x, const float* tgt, int B, int
 }
 
 }  // namespace
+
+int net_max_cells(const iewpf_net* n) { return n ? n->max_cells : 0; }
+
 }  // namespace iewpf
 
 using namespace iewpf;

@@ -15,6 +15,10 @@ sir_collapse: an ensemble assimilates drifters with the IEWPF, runs to the next
   size, the mean number of particles whose weight exceeds 1/N_e (those residual resampling
   is guaranteed to keep) is reported, for R and for 10 R.
 
+drift_forecast: the large-ensemble drift forecast (1000 particles, 24 h of analyses on the
+  225 moorings, then 12 h of drifter forecast with the plain model and the surrogate side by
+  side): forecast error and spread per hour, throughput.
+
 Every model step and analysis runs in the library's kernels.  The ranks and weights are
 computed here from a handful of values read back.
 Run as `python -m paper_1910_01031_amd.experiments` from the repository root (it uses the
@@ -167,6 +171,103 @@ def sir_collapse(torch, n_particles: int = 100, da_hours: float = 6.0, n_drifter
     return out
 
 
+def _errors(torch, pos, truth_pos, lx, ly):
+    """E(t) (eq. errorNorm: RMS distance of every member's drifter from the true drifter)
+    and RMSE(t) (the same about the ensemble mean), minimum-image distances, metres."""
+    L = torch.tensor([lx, ly], dtype=torch.float64, device=pos.device)
+
+    def mi(d):
+        return torch.remainder(d + 0.5 * L, L) - 0.5 * L
+
+    err = float(mi(pos - truth_pos[None]).pow(2).sum(dim=-1).mean().sqrt())
+    centre = pos[0:1] + mi(pos - pos[0:1]).mean(dim=0, keepdim=True)
+    rmse = float(mi(pos - centre).pow(2).sum(dim=-1).mean().sqrt())
+    return err, rmse
+
+
+def drift_forecast(torch, n_particles: int = 1000, da_hours: float = 24.0,
+                   forecast_hours: float = 12.0, n_drifters: int = 64, train_steps: int = 1000,
+                   net_particles: int = 100):
+    """The large-ensemble drift forecast: n_particles through da_hours of two-stage IEWPF on
+    the 225 moorings, then a forecast of n_drifters drifters per particle (bilinear velocity,
+    Heun, dt = 30 s) with the plain model and with the surrogate (trained first on the
+    workload's own forecast windows, plain re-step above a mass drift of 1e-4, one
+    model-error draw scaled by 3 per window).  Reports, per forecast hour, the forecast error
+    E(t) against the true drifters and the spread RMSE(t) for both, and the throughput."""
+    import time
+    W = _workloads()
+    from . import surrogate as sur
+    dev = torch.device("cuda")
+    cfg = W.large_ensemble().replace(n_particles=n_particles)
+    cells = W.buoy_cells(cfg.nx, cfg.ny, 15, 15)
+    lx, ly = cfg.nx * cfg.dx, cfg.ny * cfg.dy
+    base = torch.from_numpy(W.as_f32(W.jet_state(cfg))).to(dev)
+    ctx = abi.Context(cfg, max_obs=len(cells))
+    ens = torch.empty((n_particles, 3, cfg.ny, cfg.nx), device=dev)
+    ctx.init_ensemble(ens, base, stream_index=0)
+    tctx = abi.Context(cfg.replace(n_particles=1, ensemble_id=0x7FFF), max_obs=len(cells))
+    truth = torch.empty((1, 3, cfg.ny, cfg.nx), device=dev)
+    tctx.init_ensemble(truth, base, stream_index=1)
+    steps = 10
+    n_cyc = int(round(da_hours * 12))
+    obs = []
+    for cyc in range(n_cyc):  # the truth run and its observations, before timing
+        tctx.step_ensemble(truth, steps, first_step=cyc * steps, noise_on_last=True)
+        obs.append(abi.obs_array(cells, tctx.observe_moorings(truth, cells, analysis_index=cyc)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for cyc in range(n_cyc):
+        ctx.step_ensemble(ens, steps, first_step=cyc * steps, noise_on_last=False)
+        ctx.assimilate(ens, cells, None, analysis_index=cyc, want_stats=False, obs=obs[cyc])
+    torch.cuda.synchronize()
+    da_s = time.perf_counter() - t0
+    # surrogate trained on the workload's own windows (a 100-particle ensemble of this grid)
+    pairs = sur.make_pairs(torch, cfg.replace(n_particles=net_particles), 4 * net_particles,
+                           W.jet_state(cfg), group=net_particles, spinup_steps=10,
+                           windows_per_group=4, stream_base=100)
+    net = abi.Net(net_particles * cfg.n_cells)
+    net.set_params(sur.init_params(0))
+    sur.train(net, pairs, train_steps, batch=1)
+    del pairs
+    side = int(round(math.sqrt(n_drifters)))
+    lattice = torch.from_numpy(W.drifter_lattice(cfg, side, side)).to(dev)
+    pos_t = lattice[None].clone()
+    runs = {"plain": [ens.clone(), lattice[None].repeat(n_particles, 1, 1).contiguous()],
+            "surrogate": [ens.clone(), lattice[None].repeat(n_particles, 1, 1).contiguous()]}
+    del ens
+    hours = int(round(forecast_hours))
+    first = n_cyc * steps
+    out = {"n_particles": n_particles, "da_hours": da_hours, "forecast_hours": hours,
+           "n_drifters": n_drifters, "da_seconds": da_s,
+           "da_particle_cell_steps_per_s": n_particles * cfg.n_cells * cfg.n_sub * steps * n_cyc / da_s,
+           "hour": list(range(1, hours + 1)), "plain": {"E": [], "RMSE": [], "seconds": 0.0},
+           "surrogate": {"E": [], "RMSE": [], "seconds": 0.0, "fallbacks": 0}}
+    for h in range(hours):
+        f0 = first + h * 12 * steps
+        tctx.forecast_drifters(truth, pos_t, 12 * steps, first_step=f0)
+        for name, (st, pos) in runs.items():
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if name == "plain":
+                ctx.forecast_drifters(st, pos, 12 * steps, first_step=f0)
+            else:
+                out[name]["fallbacks"] += abi.forecast_drifters_surrogate(
+                    ctx, net, st, pos, 12, steps, f0, 1e-4, 3.0)
+            torch.cuda.synchronize()
+            out[name]["seconds"] += time.perf_counter() - t1
+            e, r = _errors(torch, pos, pos_t[0], lx, ly)
+            out[name]["E"].append(e)
+            out[name]["RMSE"].append(r)
+    cells_steps = n_particles * cfg.n_cells * cfg.n_sub * steps * 12 * hours
+    for name in runs:
+        out[name]["particle_cell_steps_per_s"] = cells_steps / out[name]["seconds"]
+    out["speedup"] = out["plain"]["seconds"] / out["surrogate"]["seconds"]
+    net.close()
+    ctx.close()
+    tctx.close()
+    return out
+
+
 if __name__ == "__main__":
     import argparse
     import json
@@ -180,6 +281,8 @@ if __name__ == "__main__":
     ap.add_argument("--da-hours", type=float, default=6.0)
     ap.add_argument("--skip-rank", action="store_true")
     ap.add_argument("--skip-sir", action="store_true")
+    ap.add_argument("--drift", action="store_true", help="also the large-ensemble drift forecast")
+    ap.add_argument("--drift-particles", type=int, default=1000)
     a = ap.parse_args()
     res = {}
     if not a.skip_rank:
@@ -192,4 +295,8 @@ if __name__ == "__main__":
         t0 = time.perf_counter()
         res["sir_collapse"] = sir_collapse(torch, da_hours=a.da_hours)
         res["sir_collapse"]["seconds"] = time.perf_counter() - t0
+    if a.drift:
+        t0 = time.perf_counter()
+        res["drift_forecast"] = drift_forecast(torch, n_particles=a.drift_particles)
+        res["drift_forecast"]["seconds"] = time.perf_counter() - t0
     print(json.dumps(res), flush=True)
