@@ -74,10 +74,13 @@ _lib = None
 
 
 def load(path: str = LIB_PATH):
-    """Load the library (raises if it is missing)."""
+    """Load the library (raises if it is missing).  IEWPF_LIBRARY, when set, names another
+    build of it (a tuning variant) in place of the in-tree one."""
     global _lib
     if _lib is not None:
         return _lib
+    if path == LIB_PATH and os.environ.get("IEWPF_LIBRARY"):
+        path = os.environ["IEWPF_LIBRARY"]
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_1910_01031_amd/build.py "
                            "(the HIP library is required; there is no fallback)")

@@ -10,6 +10,7 @@
 // Weights are stored transposed, Wt[n][k] (bf16), so a lane reads its 8 K values as one
 // 16-byte load; activations are NHWC bf16 so 8 consecutive channels of one tap are one
 // 16-byte load (C_in multiple of 8) or gathered element by element (C_in = 3).
+#include <cstdlib>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -145,10 +146,9 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_kernel(ConvArgs A, int total
 
 // Convolutions of the network as a persistent, LDS-tiled implicit GEMM (every forward layer
 // and the 48 -> 48 input gradients of the backward pass).  A workgroup of kTH waves owns a
-// tile of kTH output rows x kTW columns of one image (8 x 32 by default, the fastest of the
-// shapes timed).  The (kTH + 2) x (kTW + 2) input pixels (periodic wrap) sit in LDS, as do the
-// layer's weights (loaded once per workgroup); every wave computes one output row as kTW / 16
-// pixel tiles x NT channel tiles of
+// tile of kTH output rows x kTW columns of one image.  The (kTH + 2) x (kTW + 2) input
+// pixels (periodic wrap) sit in LDS, as do the layer's weights (loaded once per workgroup);
+// every wave computes one output row as kTW / 16 pixel tiles x NT channel tiles of
 // v_mfma_f32_16x16x32_bf16.  The operands are swapped with respect to the generic kernel
 // (A = weights, rows = output channels; B = pixels), so a lane ends with 4 consecutive
 // channels of one pixel.  While a tile is computed, the next tile's input is already being
@@ -171,22 +171,12 @@ struct TileGeom {
   static constexpr int WS = CIN == 48 ? 432 : 112;   // LDS weight row stride (bf16)
   static constexpr int VPP = CIN / 8;                // 16-byte vectors per pixel (NHWC input)
 };
-#ifndef IEWPF_CONV_TW
-#define IEWPF_CONV_TW 32
-#endif
-#ifndef IEWPF_CONV_TH
-#define IEWPF_CONV_TH 8
-#endif
-constexpr int kTW = IEWPF_CONV_TW;  // output columns per tile (multiple of 16)
-constexpr int kTH = IEWPF_CONV_TH;  // output rows per tile (one per wave)
-constexpr int kTM = kTW / 16;       // pixel tiles per wave
-constexpr int kTThreads = 64 * kTH;
-
 __device__ __forceinline__ int wrapm(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;
 }
 
+template <int kTH, int kTW>
 __device__ __forceinline__ void tile_origin(int t, int xt, int yt, int& b, int& y0, int& x0) {
   b = t / (yt * xt);
   const int r = t - b * yt * xt;
@@ -194,13 +184,15 @@ __device__ __forceinline__ void tile_origin(int t, int xt, int yt, int& b, int& 
   x0 = (r - (r / xt) * xt) * kTW;
 }
 
-template <int CIN, int NT>
+template <int CIN, int NT, int kTH, int kTW>
 constexpr int tile_lds_bytes() {
   return 2 * ((kTH + 2) * (kTW + 2) * TileGeom<CIN>::CP + NT * 16 * TileGeom<CIN>::WS);
 }
 
-template <int CIN, int NT, int IN, int OUT>
-__global__ __launch_bounds__(kTThreads) void conv_tile_kernel(ConvArgs A, int ntiles) {
+template <int CIN, int NT, int IN, int OUT, int kTH, int kTW>
+__global__ __launch_bounds__(64 * kTH) void conv_tile_kernel(ConvArgs A, int ntiles) {
+  constexpr int kTM = kTW / 16;
+  constexpr int kTThreads = 64 * kTH;
   using G = TileGeom<CIN>;
   constexpr int kPix = (kTH + 2) * (kTW + 2);
   constexpr int kTileElems = kPix * G::CP;
@@ -261,7 +253,7 @@ __global__ __launch_bounds__(kTThreads) void conv_tile_kernel(ConvArgs A, int nt
     }
     if (tn < ntiles) {  // in flight during the MFMAs below
       int b, y0, x0;
-      tile_origin(tn, xt, yt, b, y0, x0);
+      tile_origin<kTH, kTW>(tn, xt, yt, b, y0, x0);
 #pragma unroll
       for (int i = 0; i < kPer; ++i) {
         const int v = threadIdx.x + i * kTThreads;
@@ -286,7 +278,7 @@ __global__ __launch_bounds__(kTThreads) void conv_tile_kernel(ConvArgs A, int nt
     }
     if (t < 0) continue;
     int b, y0, x0;
-    tile_origin(t, xt, yt, b, y0, x0);
+    tile_origin<kTH, kTW>(t, xt, yt, b, y0, x0);
     const int y = y0 + wave;
     if (y < A.H) {  // wave-uniform
     f32x4 acc[NT][kTM];
@@ -607,44 +599,62 @@ static int cu_count() {
   return cus;
 }
 
-template <int CIN, int NT, int IN, int OUT>
+template <int CIN, int NT, int IN, int OUT, int kTH, int kTW>
 void launch_tile(const ConvArgs& A, hipStream_t s) {
-  constexpr int bytes = tile_lds_bytes<CIN, NT>();
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(conv_tile_kernel<CIN, NT, IN, OUT>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    attr = true;
-  }
-  const int ntiles = A.B * ((A.H + kTH - 1) / kTH) * ((A.W + kTW - 1) / kTW);
+  constexpr int bytes = tile_lds_bytes<CIN, NT, kTH, kTW>();
+  constexpr int threads = 64 * kTH;
+  auto* kern = conv_tile_kernel<CIN, NT, IN, OUT, kTH, kTW>;
   static int per_cu = 0;  // resident workgroups per CU (registers and LDS)
   if (per_cu == 0) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &n, reinterpret_cast<const void*>(conv_tile_kernel<CIN, NT, IN, OUT>), kTThreads,
-            bytes) != hipSuccess || n < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(kern),
+                                                     threads, bytes) != hipSuccess || n < 1)
       n = 1;
     per_cu = n;
   }
+  const int ntiles = A.B * ((A.H + kTH - 1) / kTH) * ((A.W + kTW - 1) / kTW);
   const int nb = ntiles < per_cu * cu_count() ? ntiles : per_cu * cu_count();
-  hipLaunchKernelGGL((conv_tile_kernel<CIN, NT, IN, OUT>), dim3(nb), dim3(kTThreads), bytes, s, A,
-                     ntiles);
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(threads), bytes, s, A, ntiles);
+}
+
+// Tile shape per layer kind (rows x columns): 0 = 8 x 32, 1 = 8 x 64, 2 = 16 x 32,
+// 3 = 16 x 64.  The defaults are the fastest measured at 100 x 300 x 500 (outputs are
+// identical for every shape); IEWPF_CONV_SHAPE_<kind> selects another one for timing.
+int conv_shape(const char* name, int def) {
+  const char* v = std::getenv(name);
+  const int x = v ? std::atoi(v) : def;
+  return x >= 0 && x <= 3 ? x : def;
+}
+
+template <int CIN, int NT, int IN, int OUT>
+void launch_tile_shape(const ConvArgs& A, int shape, hipStream_t s) {
+  switch (shape) {
+    case 1: return launch_tile<CIN, NT, IN, OUT, 8, 64>(A, s);
+    case 2: return launch_tile<CIN, NT, IN, OUT, 16, 32>(A, s);
+    case 3: return launch_tile<CIN, NT, IN, OUT, 16, 64>(A, s);
+    default: return launch_tile<CIN, NT, IN, OUT, 8, 32>(A, s);
+  }
 }
 
 void launch_conv(const ConvArgs& A, int in_mode, int out_mode, hipStream_t s) {
+  static const int shape_hidden = conv_shape("IEWPF_CONV_SHAPE_HIDDEN", 2);
+  static const int shape_first = conv_shape("IEWPF_CONV_SHAPE_FIRST", 3);
+  static const int shape_last = conv_shape("IEWPF_CONV_SHAPE_LAST", 0);
   if (in_mode == kInNhwcVec && A.cin == 48 && A.Kpad == TileGeom<48>::KP) {
     if (A.cout == 48 && A.Npad == 48 && out_mode == kOutReluBf16)
-      return launch_tile<48, 3, kInNhwcVec, kOutReluBf16>(A, s);
+      return launch_tile_shape<48, 3, kInNhwcVec, kOutReluBf16>(A, shape_hidden, s);
     if (A.cout == 48 && A.Npad == 48 && out_mode == kOutMaskBf16)
-      return launch_tile<48, 3, kInNhwcVec, kOutMaskBf16>(A, s);
+      return launch_tile_shape<48, 3, kInNhwcVec, kOutMaskBf16>(A, shape_hidden, s);
     if (A.cout == 3 && A.Npad == 16 && out_mode == kOutResidState)
-      return launch_tile<48, 1, kInNhwcVec, kOutResidState>(A, s);
+      return launch_tile_shape<48, 1, kInNhwcVec, kOutResidState>(A, shape_last, s);
     if (A.cout == 3 && A.Npad == 16 && out_mode == kOutF32)
-      return launch_tile<48, 1, kInNhwcVec, kOutF32>(A, s);
+      return launch_tile_shape<48, 1, kInNhwcVec, kOutF32>(A, shape_last, s);
   }
   if (in_mode == kInStateNorm && A.cin == 3 && A.cout == 48 && A.Npad == 48 && A.Kpad == 32 &&
       out_mode == kOutReluBf16)
-    return launch_tile<8, 3, kInStateNorm, kOutReluBf16>(A, s);
+    return launch_tile_shape<8, 3, kInStateNorm, kOutReluBf16>(A, shape_first, s);
   const int nt = A.Npad / 16;
 #define IEWPF_CONV_CASE(I, O, T) \
   if (in_mode == I && out_mode == O && nt == T) return launch_conv_t<I, O, T>(A, s);

@@ -172,15 +172,28 @@ __device__ __forceinline__ void cr_weights(float t, float w[4]) {
 // lane keeps the x-interpolated values of the four coarse rows around the current fine
 // row; the window advances by one coarse row every c fine rows (the only loads), and a
 // fine row costs one 4-tap interpolation in y.  Coarse point b sits at (b + 1/2) c dy.
+// The four coarse values of the row that enters next are loaded one window step ahead, so
+// their latency is hidden behind c fine rows.
 struct CoarseRows {
   int cx[4];
   float wx[4];
   float xr[4];   // x-interpolated coarse rows by-1 .. by+2
+  float nr[4];   // raw values of coarse row by+3 (prefetched)
   int by;        // base coarse row of the current window
 
-  __device__ __forceinline__ float xrow(const float* __restrict__ z, const SweConst& C, int b) const {
+  __device__ __forceinline__ float combine(const float r[4]) const {
+    return wx[0] * r[0] + wx[1] * r[1] + wx[2] * r[2] + wx[3] * r[3];
+  }
+  __device__ __forceinline__ void fetch(const float* __restrict__ z, const SweConst& C, int b,
+                                        float r[4]) const {
     const float* row = z + (size_t)wrap1(b, C.nry) * C.nrx;
-    return wx[0] * row[cx[0]] + wx[1] * row[cx[1]] + wx[2] * row[cx[2]] + wx[3] * row[cx[3]];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) r[m] = row[cx[m]];
+  }
+  __device__ __forceinline__ float xrow(const float* __restrict__ z, const SweConst& C, int b) const {
+    float r[4];
+    fetch(z, C, b, r);
+    return combine(r);
   }
   __device__ __forceinline__ void init(const float* __restrict__ z, const SweConst& C, int jw,
                                        int s) {
@@ -193,6 +206,7 @@ struct CoarseRows {
     by = (ns >= 0 ? ns : ns - 2 * C.c + 1) / (2 * C.c);
 #pragma unroll
     for (int n = 0; n < 4; ++n) xr[n] = xrow(z, C, by + n - 1);
+    fetch(z, C, by + 3, nr);
   }
   // value at fine row s (unwrapped, non-decreasing between calls, s - previous s <= c)
   __device__ __forceinline__ float at(const float* __restrict__ z, const SweConst& C, int s) {
@@ -202,8 +216,9 @@ struct CoarseRows {
       xr[0] = xr[1];
       xr[1] = xr[2];
       xr[2] = xr[3];
-      xr[3] = xrow(z, C, b + 2);
+      xr[3] = combine(nr);  // row b + 2 = old by + 3
       by = b;
+      fetch(z, C, b + 3, nr);
     }
     float wy[4];
     cr_weights(static_cast<float>(ns - 2 * C.c * b) / static_cast<float>(2 * C.c), wy);
@@ -216,6 +231,7 @@ struct CoarseRows {
 #ifndef IEWPF_SWE_MIN_BLOCKS
 #define IEWPF_SWE_MIN_BLOCKS 1
 #endif
+
 template <bool NOISE>
 __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float* __restrict__ out,
                                              const float* __restrict__ zall, const SweConst& C,
