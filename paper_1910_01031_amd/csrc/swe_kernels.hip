@@ -42,16 +42,18 @@ __device__ __forceinline__ float lane_next(float x) { return __shfl_down(x, 1, k
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float sqrtf_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// Generalized minmod of three slopes.
-// (min if all three are positive, max if all are negative, else 0) = max(lo, 0) + min(hi, 0)
+// Generalized minmod of three slopes: the smallest if all three are positive, the largest if
+// all are negative, else 0 -- which is the median of (min, max, 0).
 __device__ __forceinline__ float minmod3(float a, float b, float c) {
   const float lo = fminf(a, fminf(b, c));
   const float hi = fmaxf(a, fmaxf(b, c));
-  return fmaxf(lo, 0.0f) + fminf(hi, 0.0f);
+  return __builtin_amdgcn_fmed3f(lo, hi, 0.0f);
 }
 
-__device__ __forceinline__ float limited(float qm, float q0, float qp, float theta) {
-  return minmod3(theta * (q0 - qm), 0.5f * (qp - qm), theta * (qp - q0));
+// Twice the limited slope, minmod(2 theta (q0 - qm), qp - qm, 2 theta (qp - q0)): the
+// factor 2 is exact, so the half-slope face offsets below round as with the slope itself.
+__device__ __forceinline__ float limited2(float qm, float q0, float qp, float theta2) {
+  return minmod3(theta2 * (q0 - qm), qp - qm, theta2 * (qp - q0));
 }
 
 // Central-upwind flux between a left (-) and right (+) face state (eta, normal velocity,
@@ -82,13 +84,14 @@ __device__ __forceinline__ void x_divergence(float e, float u, float v, const Sw
   const float Kc = C.g * e;
   const float Kp = C.g * eE_ - C.hfdx * (v + vE_);
   const float Km = C.g * eW_ + C.hfdx * (v + vW_);
-  const float sK = limited(Km, Kc, Kp, C.theta);
-  const float su = limited(uW_, u, uE_, C.theta);
-  const float sv = limited(vW_, v, vE_, C.theta);
-  const float off = (sK + C.fdx * v) * C.inv2g;
+  const float theta2 = 2.0f * C.theta;
+  const float sK = limited2(Km, Kc, Kp, theta2);  // all three slopes doubled
+  const float su = limited2(uW_, u, uE_, theta2);
+  const float sv = limited2(vW_, v, vE_, theta2);
+  const float off = (sK + (2.0f * C.fdx) * v) * (0.5f * C.inv2g);
   const float eEf = e + off, eWf = e - off;
-  const float uEf = u + 0.5f * su, uWf = u - 0.5f * su;
-  const float vEf = v + 0.5f * sv, vWf = v - 0.5f * sv;
+  const float uEf = u + 0.25f * su, uWf = u - 0.25f * su;
+  const float vEf = v + 0.25f * sv, vWf = v - 0.25f * sv;
   // face j+1/2: left = east face of this cell, right = west face of cell j+1
   float F0, F1, F2;
   cu_flux(eEf, uEf, vEf, lane_next(eWf), lane_next(uWf), lane_next(vWf), C, F0, F1, F2);
@@ -108,16 +111,17 @@ __device__ __forceinline__ void y_recon(float em, float um, float vm, float e, f
   const float Lc = C.g * e;
   const float Lp = C.g * ep + C.hfdy * (u + up);
   const float Lm = C.g * em - C.hfdy * (u + um);
-  const float sL = limited(Lm, Lc, Lp, C.theta);
-  const float su = limited(um, u, up, C.theta);
-  const float sv = limited(vm, v, vp, C.theta);
-  const float off = (sL - C.fdy * u) * C.inv2g;
+  const float theta2 = 2.0f * C.theta;
+  const float sL = limited2(Lm, Lc, Lp, theta2);  // all three slopes doubled
+  const float su = limited2(um, u, up, theta2);
+  const float sv = limited2(vm, v, vp, theta2);
+  const float off = (sL - (2.0f * C.fdy) * u) * (0.5f * C.inv2g);
   N.e = e + off;
   S.e = e - off;
-  N.n = v + 0.5f * sv;
-  S.n = v - 0.5f * sv;
-  N.t = u + 0.5f * su;
-  S.t = u - 0.5f * su;
+  N.n = v + 0.25f * sv;
+  S.n = v - 0.25f * sv;
+  N.t = u + 0.25f * su;
+  S.t = u - 0.25f * su;
 }
 
 // One RK stage as a row pipeline: push row m (eta, hu, hv), emit row m-2 of
@@ -315,35 +319,45 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
   };
   for (int m = k0 - 4; m < k0; ++m) step(m, false, false);
   for (int m = k0; m < k0 + 4; ++m) step(m, true, false);
-  for (int m = k0 + 4; m <= k_end + 3; ++m) step(m, true, true);
+  // four rows per trip (the period of the row rotation), so the pipeline registers are
+  // renamed instead of moved
+  int m = k0 + 4;
+  for (; m + 3 <= k_end + 3; m += 4) {
+    step(m, true, true);
+    step(m + 1, true, true);
+    step(m + 2, true, true);
+    step(m + 3, true, true);
+  }
+  for (; m <= k_end + 3; ++m) step(m, true, true);
 }
 
 template <bool NOISE>
 __global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_substep_kernel(
     const float* __restrict__ in, float* __restrict__ out, const float* __restrict__ zall,
     SweConst C, int total_waves) {
-  const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  // wave-uniform: held in scalar registers, so the strip and particle offsets are scalar
+  const int wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave));
   if (wave >= total_waves) return;  // whole wave exits together
   substep_wave<NOISE>(in, out, zall, C, wave);
 }
 
 // Several ensembles of different grids in one launch: the waves of ensemble e are
 // [job[e].wave_begin, job[e+1].wave_begin); parity selects which of the two buffers of
-// every ensemble is the input.  NOISE applies to the ensembles whose z is set.
+// every ensemble is the input.  With NOISE every job's z is set (the host builds the two
+// tables that way).
 template <bool NOISE>
 __global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_batch_kernel(
     const SweJobTable* __restrict__ tab, int parity) {
-  const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave));
   if (wave >= tab->total_waves) return;
   int e = 0;
   while (e + 1 < tab->n && wave >= tab->job[e + 1].wave_begin) ++e;
   const SweJob& J = tab->job[e];
   const float* in = parity ? J.buf_b : J.buf_a;
   float* out = parity ? J.buf_a : J.buf_b;
-  if (NOISE && J.z != nullptr)
-    substep_wave<true>(in, out, J.z, J.C, wave - J.wave_begin);
-  else
-    substep_wave<false>(in, out, nullptr, J.C, wave - J.wave_begin);
+  substep_wave<NOISE>(in, out, J.z, J.C, wave - J.wave_begin);
 }
 
 }  // namespace
