@@ -202,6 +202,11 @@ int iewpf_window_size(iewpf_ctx* ctx, int32_t* wx, int32_t* wy);
  * the chosen height to *strip_out.  Later calls on ctx use it. */
 int iewpf_autotune(iewpf_ctx* ctx, const float* state, int32_t* strip_out, void* stream);
 
+/* Sets the stencil's rows-per-wave strip height directly (1 <= rows; heights above ny mean
+ * one strip per column block).  Results do not depend on it.  Later calls on ctx use it;
+ * batches created before keep the height they were built with.  IEWPF_E_ARG for rows < 1. */
+int iewpf_set_strip_rows(iewpf_ctx* ctx, int rows);
+
 /* ---- several ensembles of uneven grid and size, one launch per scheme step ------------
  * A batch groups n contexts (same dt and n_sub) and their state buffers.  Every scheme
  * step of all ensembles is one kernel launch over a device table of (grid, buffers, wave

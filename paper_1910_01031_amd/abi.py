@@ -29,7 +29,8 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_perturb", "iewpf_assimilate", "iewpf_particle_scalars",
             "iewpf_observe_moorings", "iewpf_forecast_drifters", "iewpf_advect_drifters",
             "iewpf_resample", "iewpf_check_cfl", "iewpf_read_buffer", "iewpf_window_size",
-            "iewpf_set_trace", "iewpf_trace_read", "iewpf_autotune", "iewpf_batch_create",
+            "iewpf_set_trace", "iewpf_trace_read", "iewpf_autotune", "iewpf_set_strip_rows",
+            "iewpf_batch_create",
             "iewpf_batch_destroy", "iewpf_batch_set_cells", "iewpf_batch_cycle",
             "iewpf_net_create", "iewpf_net_destroy", "iewpf_net_num_params",
             "iewpf_net_set_params", "iewpf_net_get_params", "iewpf_net_set_norm",
@@ -110,6 +111,7 @@ def load(path: str = LIB_PATH):
     lib.iewpf_window_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_int32)]
     lib.iewpf_autotune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.iewpf_set_strip_rows.argtypes = [vp, i32]
     lib.iewpf_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), i32,
                                        ctypes.POINTER(vp)]
     lib.iewpf_batch_destroy.argtypes = [vp]
@@ -287,6 +289,9 @@ class Context:
         out = ctypes.c_int32()
         _check(load().iewpf_autotune(self.h, _ptr(state), ctypes.byref(out), _stream(stream)))
         return out.value
+
+    def set_strip_rows(self, rows: int):
+        _check(load().iewpf_set_strip_rows(self.h, int(rows)))
 
     def set_trace(self, on: bool):
         _check(load().iewpf_set_trace(self.h, int(on)))

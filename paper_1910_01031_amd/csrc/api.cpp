@@ -884,6 +884,13 @@ int iewpf_autotune(iewpf_ctx* c, const float* state, int32_t* strip_out, void* s
   return 0;
 }
 
+int iewpf_set_strip_rows(iewpf_ctx* c, int rows) {
+  if (!c || rows < 1) return fail(IEWPF_E_ARG, "strip rows must be >= 1");
+  c->swe.strip_h = std::min(rows, c->ny);
+  c->swe.n_strip_y = (c->ny + c->swe.strip_h - 1) / c->swe.strip_h;
+  return 0;
+}
+
 int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewpf_batch** out) {
   if (!ctxs || !states || !out || n <= 0 || n > kMaxBatch) return fail(IEWPF_E_ARG, "invalid argument");
   *out = nullptr;

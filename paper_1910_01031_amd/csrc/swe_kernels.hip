@@ -17,6 +17,7 @@
 // side, leaving 56 output columns per wave.  HBM traffic per scheme step: one read and
 // one write of the state (24 B per cell) plus the strip halo rows.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -66,13 +67,15 @@ __device__ __forceinline__ void cu_flux(float eL, float nL, float tL, float eR, 
   const float cL = sqrtf_fast(C.g * hL), cR = sqrtf_fast(C.g * hR);
   const float ap = fmaxf(fmaxf(nL + cL, nR + cR), 0.0f);
   const float am = fminf(fminf(nL - cL, nR - cR), 0.0f);
+  // F = wL F(-) - wR F(+) + apam (psi+ - psi-), wL = a+/(a+ - a-), wR = a-/(a+ - a-)
   const float inv = rcpf(ap - am);
-  const float apam = ap * am * inv;
+  const float wL = ap * inv, wR = am * inv;
+  const float apam = wL * am;
   const float ML = qL * nL + C.g * eL * (C.H + 0.5f * eL);
   const float MR = qR * nR + C.g * eR * (C.H + 0.5f * eR);
-  F0 = (ap * qL - am * qR) * inv + apam * (eR - eL);
-  F1 = (ap * ML - am * MR) * inv + apam * (qR - qL);
-  F2 = (ap * (qL * tL) - am * (qR * tR)) * inv + apam * (pR - pL);
+  F0 = wL * qL - wR * qR + apam * (eR - eL);
+  F1 = wL * ML - wR * MR + apam * (qR - qL);
+  F2 = wL * (qL * tL) - wR * (qR * tR) + apam * (pR - pL);
 }
 
 // x-direction flux divergence F_{j+1/2} - F_{j-1/2} of one row (mass, hu, hv).
@@ -125,7 +128,15 @@ __device__ __forceinline__ void y_recon(float em, float um, float vm, float e, f
 }
 
 // One RK stage as a row pipeline: push row m (eta, hu, hv), emit row m-2 of
-// psi + dt L(psi) (the forward-Euler part of the stage).
+// psi + dt L(psi) (the forward-Euler part of the stage).  The mode skips what the rows at
+// the ends of a strip do not need:
+//   kPushStore:  keep the row only (rows above the first one whose x divergence is used);
+//   kPushNoFlux: x divergence and y reconstruction, no y flux (the first such row; the
+//                face above it is never used); the emitted row is not defined;
+//   kPushFull:   everything;
+//   kPushNoX:    no x divergence (rows below the last emitted one feed only y faces).
+enum { kPushStore, kPushNoFlux, kPushFull, kPushNoX };
+
 struct StagePipe {
   // rows m-2 ("a") and m-1 ("b")
   float ea, qa, ra, ua, va, ea_x0, ea_x1, ea_x2;
@@ -133,20 +144,25 @@ struct StagePipe {
   YFace Na;          // north face state of row m-2
   float g0, g1, g2;  // y flux at face (m-2) - 1/2: mass, hv (normal), hu (tangential)
 
+  template <int MODE>
   __device__ __forceinline__ void push(float e, float q, float r, const SweConst& C, float& oe,
                                        float& oq, float& orr) {
     const float rh = rcpf(C.H + e);
     const float u = q * rh, v = r * rh;
-    float x0, x1, x2;
-    x_divergence(e, u, v, C, x0, x1, x2);
-    YFace Nb, Sb;
-    y_recon(ea, ua, va, eb, ub, vb, e, u, v, C, Nb, Sb);  // row m-1
-    float G0, G1, G2;                                     // face (m-2) + 1/2
-    cu_flux(Na.e, Na.n, Na.t, Sb.e, Sb.n, Sb.t, C, G0, G1, G2);
-    const float dt = C.dt;
-    oe = ea + dt * (-ea_x0 * C.idx - (G0 - g0) * C.idy);
-    oq = qa + dt * (-ea_x1 * C.idx - (G2 - g2) * C.idy + C.f * ra);
-    orr = ra + dt * (-ea_x2 * C.idx - (G1 - g1) * C.idy - C.f * qa);
+    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+    if (MODE == kPushNoFlux || MODE == kPushFull) x_divergence(e, u, v, C, x0, x1, x2);
+    YFace Nb = {}, Sb = {};
+    if (MODE != kPushStore) y_recon(ea, ua, va, eb, ub, vb, e, u, v, C, Nb, Sb);  // row m-1
+    float G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;                                     // face (m-2) + 1/2
+    if (MODE == kPushFull || MODE == kPushNoX) {
+      cu_flux(Na.e, Na.n, Na.t, Sb.e, Sb.n, Sb.t, C, G0, G1, G2);
+      const float dt = C.dt;
+      oe = ea + dt * (-ea_x0 * C.idx - (G0 - g0) * C.idy);
+      oq = qa + dt * (-ea_x1 * C.idx - (G2 - g2) * C.idy + C.f * ra);
+      orr = ra + dt * (-ea_x2 * C.idx - (G1 - g1) * C.idy - C.f * qa);
+    } else {
+      oe = oq = orr = 0.0f;
+    }
     // advance
     ea = eb; qa = qb; ra = rb; ua = ub; va = vb;
     ea_x0 = eb_x0; ea_x1 = eb_x1; ea_x2 = eb_x2;
@@ -156,6 +172,9 @@ struct StagePipe {
     g0 = G0; g1 = G1; g2 = G2;
   }
 };
+
+template <int V>
+using PushMode = std::integral_constant<int, V>;
 
 __device__ __forceinline__ int wrap(int i, int n) {
   i %= n;
@@ -277,16 +296,19 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
   size_t off = (size_t)wrap(k0 - 4, ny) * nx + jw;
   float ne_ = Ein[off], nq_ = Qin[off], nr_ = Rin[off];
 
-  // phase 1 (m = k0-4 .. k0-1): stage 1 only; phase 2 (k0 .. k0+3): both stages, no
-  // output yet; phase 3 (k0+4 .. k_end+3): both stages and row m-4 written.
-  auto step = [&](int m, bool stage2, bool emit) {
+  // Rows m = k0-4 .. k0-1: stage 1 only; k0 .. k0+3: both stages, no output yet;
+  // k0+4 .. k_end+3: both stages and row m-4 written.  Stage 1 must produce rows
+  // k0-2 .. k_end+1 and stage 2 rows k0 .. k_end-1; the push modes drop the rest.
+  auto step = [&](int m, auto mode1, auto mode2, bool emit) {
+    constexpr int M1 = decltype(mode1)::value, M2 = decltype(mode2)::value;
+    constexpr bool stage2 = M2 >= 0;
     const float e = ne_, q = nq_, r = nr_;
     const size_t o2 = (size_t)wrap1(m + 1, ny) * nx + jw;  // prefetch the next row
     ne_ = Ein[o2];
     nq_ = Qin[o2];
     nr_ = Rin[o2];
     float se, sq, sr;
-    s1.push(e, q, r, C, se, sq, sr);  // psi* of row m - 2
+    s1.template push<M1>(e, q, r, C, se, sq, sr);  // psi* of row m - 2
     const float qe4 = pe4, qq4 = pq4, qr4 = pr4;
     pe4 = pe3; pq4 = pq3; pr4 = pr3;
     pe3 = pe2; pq3 = pq2; pr3 = pr2;
@@ -296,7 +318,7 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
     if (NOISE && stage2 && m >= k0 + 2) dC = cr.at(z, C, m - 3);  // d_eta row m-3 (>= k0-1)
     if (stage2) {
       float te, tq, tr;
-      s2.push(se, sq, sr, C, te, tq, tr);  // psi* + dt L(psi*) of row m - 4
+      s2.template push<(M2 < 0 ? kPushStore : M2)>(se, sq, sr, C, te, tq, tr);  // row m - 4
       if (emit) {
         float oe = 0.5f * (qe4 + te), oq = 0.5f * (qq4 + tq), orr = 0.5f * (qr4 + tr);
         if (NOISE) {
@@ -317,18 +339,33 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
       dB = dC;
     }
   };
-  for (int m = k0 - 4; m < k0; ++m) step(m, false, false);
-  for (int m = k0; m < k0 + 4; ++m) step(m, true, false);
+  using Off = PushMode<-1>;
+  using Store = PushMode<kPushStore>;
+  using NoFlux = PushMode<kPushNoFlux>;
+  using Full = PushMode<kPushFull>;
+  using NoX = PushMode<kPushNoX>;
+  step(k0 - 4, Store{}, Off{}, false);
+  step(k0 - 3, Store{}, Off{}, false);
+  step(k0 - 2, NoFlux{}, Off{}, false);
+  step(k0 - 1, Full{}, Off{}, false);
+  step(k0, Full{}, Store{}, false);
+  step(k0 + 1, Full{}, Store{}, false);
+  step(k0 + 2, Full{}, NoFlux{}, false);
+  step(k0 + 3, Full{}, Full{}, false);
+  // rows from k_end+2 on are below the last stage-1 (k_end+1) and stage-2 (k_end-1)
+  // rows whose x divergence is used
+  const int m_tail = max(k_end + 2, k0 + 4);
   // four rows per trip (the period of the row rotation), so the pipeline registers are
   // renamed instead of moved
   int m = k0 + 4;
-  for (; m + 3 <= k_end + 3; m += 4) {
-    step(m, true, true);
-    step(m + 1, true, true);
-    step(m + 2, true, true);
-    step(m + 3, true, true);
+  for (; m + 3 < m_tail; m += 4) {
+    step(m, Full{}, Full{}, true);
+    step(m + 1, Full{}, Full{}, true);
+    step(m + 2, Full{}, Full{}, true);
+    step(m + 3, Full{}, Full{}, true);
   }
-  for (; m <= k_end + 3; ++m) step(m, true, true);
+  for (; m < m_tail; ++m) step(m, Full{}, Full{}, true);
+  for (; m <= k_end + 3; ++m) step(m, NoX{}, NoX{}, true);
 }
 
 template <bool NOISE>

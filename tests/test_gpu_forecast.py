@@ -152,6 +152,38 @@ def test_stochastic_steps_parity(torch_dev):
         assert max(err) < 3 * TOL, (i, err)
 
 
+def test_strip_heights_identical_and_match_oracle(torch_dev):
+    """Every rows-per-wave strip height gives the same bits (plain and model-error steps),
+    down to one row per wave and ragged last strips of 1..3 rows, and matches the oracle."""
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Context
+    cfg = W.Config(nx=60, ny=27, dx=5e3, dy=5e3, c_omega=3, n_sub=2, n_particles=3,
+                   me_std=0.01)
+    rng = np.random.default_rng(27)
+    ens = W.as_f32(np.stack([W.random_state(cfg, rng) for _ in range(3)]))
+    outs = {}
+    for rows in (1, 2, 4, 5, 13, 27, 64):
+        _say(f"strip height {rows} rows (ny 27)")
+        ctx = Context(cfg, max_obs=4)
+        ctx.set_strip_rows(rows)
+        st = torch.from_numpy(np.ascontiguousarray(ens)).to(dev)
+        ctx.step_ensemble(st, 2, first_step=4, noise_on_last=True)
+        torch.cuda.synchronize()
+        outs[rows] = st.cpu().numpy()
+        ctx.close()
+    for rows, o in outs.items():
+        assert np.array_equal(o, outs[27]), rows
+    for i in range(3):
+        ref = oens.step_member(ens[i], cfg, i, 4, 2, noise_on_last=True)
+        err = _rel(outs[27][i].astype(np.float64), ref)
+        assert max(err) < 2 * TOL, (i, err)
+    ctx = Context(cfg, max_obs=4)
+    from paper_1910_01031_amd import IewpfError
+    with pytest.raises(IewpfError):
+        ctx.set_strip_rows(0)
+    ctx.close()
+
+
 def test_deterministic_repeat(torch_dev):
     torch, dev = torch_dev
     cfg = W.tiny().replace(n_particles=3)
