@@ -255,6 +255,11 @@ struct CoarseRows {
 #define IEWPF_SWE_MIN_BLOCKS 1
 #endif
 
+#ifndef IEWPF_SWE_PREFETCH
+#define IEWPF_SWE_PREFETCH 3
+#endif
+static_assert(IEWPF_SWE_PREFETCH >= 1 && IEWPF_SWE_PREFETCH <= 8, "prefetch distance");
+
 template <bool NOISE>
 __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float* __restrict__ out,
                                              const float* __restrict__ zall, const SweConst& C,
@@ -293,8 +298,16 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
   float pe1 = 0, pq1 = 0, pr1 = 0;
   float dA = 0.0f, dB = 0.0f;  // model-error d_eta rows m-5, m-4
 
-  size_t off = (size_t)wrap(k0 - 4, ny) * nx + jw;
-  float ne_ = Ein[off], nq_ = Qin[off], nr_ = Rin[off];
+  // rows m .. m + kPf - 1 are loaded (in flight) before row m is pushed
+  constexpr int kPf = IEWPF_SWE_PREFETCH;
+  float ne_[kPf], nq_[kPf], nr_[kPf];
+#pragma unroll
+  for (int i = 0; i < kPf; ++i) {
+    const size_t off = (size_t)wrap(k0 - 4 + i, ny) * nx + jw;
+    ne_[i] = Ein[off];
+    nq_[i] = Qin[off];
+    nr_[i] = Rin[off];
+  }
 
   // Rows m = k0-4 .. k0-1: stage 1 only; k0 .. k0+3: both stages, no output yet;
   // k0+4 .. k_end+3: both stages and row m-4 written.  Stage 1 must produce rows
@@ -302,11 +315,18 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
   auto step = [&](int m, auto mode1, auto mode2, bool emit) {
     constexpr int M1 = decltype(mode1)::value, M2 = decltype(mode2)::value;
     constexpr bool stage2 = M2 >= 0;
-    const float e = ne_, q = nq_, r = nr_;
-    const size_t o2 = (size_t)wrap1(m + 1, ny) * nx + jw;  // prefetch the next row
-    ne_ = Ein[o2];
-    nq_ = Qin[o2];
-    nr_ = Rin[o2];
+    const float e = ne_[0], q = nq_[0], r = nr_[0];
+#pragma unroll
+    for (int i = 0; i + 1 < kPf; ++i) {
+      ne_[i] = ne_[i + 1];
+      nq_[i] = nq_[i + 1];
+      nr_[i] = nr_[i + 1];
+    }
+    // m + kPf < ny + 3 + kPf < 3 ny (ny >= 7): two conditional wraps suffice
+    const size_t o2 = (size_t)wrap1(wrap1(m + kPf, ny), ny) * nx + jw;
+    ne_[kPf - 1] = Ein[o2];
+    nq_[kPf - 1] = Qin[o2];
+    nr_[kPf - 1] = Rin[o2];
     float se, sq, sr;
     s1.template push<M1>(e, q, r, C, se, sq, sr);  // psi* of row m - 2
     const float qe4 = pe4, qq4 = pq4, qr4 = pr4;
