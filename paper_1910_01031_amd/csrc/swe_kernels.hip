@@ -71,11 +71,14 @@ __device__ __forceinline__ void cu_flux(float eL, float nL, float tL, float eR, 
   const float inv = rcpf(ap - am);
   const float wL = ap * inv, wR = am * inv;
   const float apam = wL * am;
-  const float ML = qL * nL + C.g * eL * (C.H + 0.5f * eL);
-  const float MR = qR * nR + C.g * eR * (C.H + 0.5f * eR);
-  F0 = wL * qL - wR * qR + apam * (eR - eL);
+  const float wqL = wL * qL, wqR = wR * qR;
+  // normal momentum flux q n + g eta (H + eta/2) = q n + eta (g H + (g/2) eta)
+  const float gH = C.g * C.H, hg = 0.5f * C.g;
+  const float ML = qL * nL + eL * (gH + hg * eL);
+  const float MR = qR * nR + eR * (gH + hg * eR);
+  F0 = (wqL - wqR) + apam * (eR - eL);
   F1 = wL * ML - wR * MR + apam * (qR - qL);
-  F2 = wL * (qL * tL) - wR * (qR * tR) + apam * (pR - pL);
+  F2 = (wqL * tL - wqR * tR) + apam * (pR - pL);
 }
 
 // x-direction flux divergence F_{j+1/2} - F_{j-1/2} of one row (mass, hu, hv).
@@ -103,21 +106,22 @@ __device__ __forceinline__ void x_divergence(float e, float u, float v, const Sw
   d2 = F2 - lane_prev(F2);  // x tangential momentum = hv
 }
 
-// y reconstruction of row k from rows k-1, k, k+1: north and south face states
-// (eta, v = normal, u = tangential).
+// y reconstruction of row k: north and south face states (eta, v = normal, u = tangential)
+// from the differences to row k-1 (dLm, dum, dvm) and to row k+1 (dLp, dup, dvp), with
+// L = g (eta + U) and U the Coriolis potential local to row k.  The difference between rows
+// k and k+1 is the same whichever of the two rows the potential is local to, so each one is
+// computed once and serves both rows.
 struct YFace {
   float e, n, t;
 };
-__device__ __forceinline__ void y_recon(float em, float um, float vm, float e, float u, float v,
-                                        float ep, float up, float vp, const SweConst& C,
+__device__ __forceinline__ void y_recon(float e, float u, float v, float dLm, float dum, float dvm,
+                                        float dLp, float dup, float dvp, const SweConst& C,
                                         YFace& N, YFace& S) {
-  const float Lc = C.g * e;
-  const float Lp = C.g * ep + C.hfdy * (u + up);
-  const float Lm = C.g * em - C.hfdy * (u + um);
   const float theta2 = 2.0f * C.theta;
-  const float sL = limited2(Lm, Lc, Lp, theta2);  // all three slopes doubled
-  const float su = limited2(um, u, up, theta2);
-  const float sv = limited2(vm, v, vp, theta2);
+  // doubled slopes minmod(2 theta a, a + b, 2 theta b)
+  const float sL = minmod3(theta2 * dLm, dLm + dLp, theta2 * dLp);
+  const float su = minmod3(theta2 * dum, dum + dup, theta2 * dup);
+  const float sv = minmod3(theta2 * dvm, dvm + dvp, theta2 * dvp);
   const float off = (sL - (2.0f * C.fdy) * u) * (0.5f * C.inv2g);
   N.e = e + off;
   S.e = e - off;
@@ -139,8 +143,9 @@ enum { kPushStore, kPushNoFlux, kPushFull, kPushNoX };
 
 struct StagePipe {
   // rows m-2 ("a") and m-1 ("b")
-  float ea, qa, ra, ua, va, ea_x0, ea_x1, ea_x2;
+  float ea, qa, ra, ea_x0, ea_x1, ea_x2;
   float eb, qb, rb, ub, vb, eb_x0, eb_x1, eb_x2;
+  float dL, du, dv;  // y differences between rows m-1 and m-2 (potential local to either)
   YFace Na;          // north face state of row m-2
   float g0, g1, g2;  // y flux at face (m-2) - 1/2: mass, hv (normal), hu (tangential)
 
@@ -149,10 +154,12 @@ struct StagePipe {
                                        float& oq, float& orr) {
     const float rh = rcpf(C.H + e);
     const float u = q * rh, v = r * rh;
+    const float dLn = C.g * (e - eb) + C.hfdy * (ub + u);  // rows m and m-1
+    const float dun = u - ub, dvn = v - vb;
     float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
     if (MODE == kPushNoFlux || MODE == kPushFull) x_divergence(e, u, v, C, x0, x1, x2);
     YFace Nb = {}, Sb = {};
-    if (MODE != kPushStore) y_recon(ea, ua, va, eb, ub, vb, e, u, v, C, Nb, Sb);  // row m-1
+    if (MODE != kPushStore) y_recon(eb, ub, vb, dL, du, dv, dLn, dun, dvn, C, Nb, Sb);  // row m-1
     float G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;                                     // face (m-2) + 1/2
     if (MODE == kPushFull || MODE == kPushNoX) {
       cu_flux(Na.e, Na.n, Na.t, Sb.e, Sb.n, Sb.t, C, G0, G1, G2);
@@ -164,9 +171,10 @@ struct StagePipe {
       oe = oq = orr = 0.0f;
     }
     // advance
-    ea = eb; qa = qb; ra = rb; ua = ub; va = vb;
+    ea = eb; qa = qb; ra = rb;
     ea_x0 = eb_x0; ea_x1 = eb_x1; ea_x2 = eb_x2;
     eb = e; qb = q; rb = r; ub = u; vb = v;
+    dL = dLn; du = dun; dv = dvn;
     eb_x0 = x0; eb_x1 = x1; eb_x2 = x2;
     Na = Nb;
     g0 = G0; g1 = G1; g2 = G2;
