@@ -132,19 +132,19 @@ __device__ __forceinline__ void y_recon(float e, float u, float v, float dLm, fl
 }
 
 // One RK stage as a row pipeline: push row m (eta, hu, hv), emit row m-2 of
-// psi + dt L(psi) (the forward-Euler part of the stage).  The mode skips what the rows at
-// the ends of a strip do not need:
-//   kPushStore:  keep the row only (rows above the first one whose x divergence is used);
-//   kPushNoFlux: x divergence and y reconstruction, no y flux (the first such row; the
-//                face above it is never used); the emitted row is not defined;
-//   kPushFull:   everything;
-//   kPushNoX:    no x divergence (rows below the last emitted one feed only y faces).
-enum { kPushStore, kPushNoFlux, kPushFull, kPushNoX };
+// psi + dt L(psi) (the forward-Euler part of the stage).  The x divergence of row m-2 is
+// computed when the row is emitted.  The mode skips what the rows at the top of a strip do
+// not need:
+//   kPushStore:    keep the row only;
+//   kPushNoFlux:   y reconstruction of row m-1 only (the face above it is never used);
+//   kPushFluxOnly: y reconstruction and y flux, nothing emitted (row m-2 is not needed);
+//   kPushFull:     everything.
+enum { kPushStore, kPushNoFlux, kPushFluxOnly, kPushFull };
 
 struct StagePipe {
   // rows m-2 ("a") and m-1 ("b")
-  float ea, qa, ra, ea_x0, ea_x1, ea_x2;
-  float eb, qb, rb, ub, vb, eb_x0, eb_x1, eb_x2;
+  float ea, qa, ra, ua, va;
+  float eb, qb, rb, ub, vb;
   float dL, du, dv;  // y differences between rows m-1 and m-2 (potential local to either)
   YFace Na;          // north face state of row m-2
   float g0, g1, g2;  // y flux at face (m-2) - 1/2: mass, hv (normal), hu (tangential)
@@ -156,26 +156,25 @@ struct StagePipe {
     const float u = q * rh, v = r * rh;
     const float dLn = C.g * (e - eb) + C.hfdy * (ub + u);  // rows m and m-1
     const float dun = u - ub, dvn = v - vb;
-    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
-    if (MODE == kPushNoFlux || MODE == kPushFull) x_divergence(e, u, v, C, x0, x1, x2);
     YFace Nb = {}, Sb = {};
     if (MODE != kPushStore) y_recon(eb, ub, vb, dL, du, dv, dLn, dun, dvn, C, Nb, Sb);  // row m-1
     float G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;                                     // face (m-2) + 1/2
-    if (MODE == kPushFull || MODE == kPushNoX) {
+    if (MODE == kPushFluxOnly || MODE == kPushFull)
       cu_flux(Na.e, Na.n, Na.t, Sb.e, Sb.n, Sb.t, C, G0, G1, G2);
+    if (MODE == kPushFull) {
+      float x0, x1, x2;
+      x_divergence(ea, ua, va, C, x0, x1, x2);  // row m-2
       const float dt = C.dt;
-      oe = ea + dt * (-ea_x0 * C.idx - (G0 - g0) * C.idy);
-      oq = qa + dt * (-ea_x1 * C.idx - (G2 - g2) * C.idy + C.f * ra);
-      orr = ra + dt * (-ea_x2 * C.idx - (G1 - g1) * C.idy - C.f * qa);
+      oe = ea + dt * (-x0 * C.idx - (G0 - g0) * C.idy);
+      oq = qa + dt * (-x1 * C.idx - (G2 - g2) * C.idy + C.f * ra);
+      orr = ra + dt * (-x2 * C.idx - (G1 - g1) * C.idy - C.f * qa);
     } else {
       oe = oq = orr = 0.0f;
     }
     // advance
-    ea = eb; qa = qb; ra = rb;
-    ea_x0 = eb_x0; ea_x1 = eb_x1; ea_x2 = eb_x2;
+    ea = eb; qa = qb; ra = rb; ua = ub; va = vb;
     eb = e; qb = q; rb = r; ub = u; vb = v;
     dL = dLn; du = dun; dv = dvn;
-    eb_x0 = x0; eb_x1 = x1; eb_x2 = x2;
     Na = Nb;
     g0 = G0; g1 = G1; g2 = G2;
   }
@@ -319,7 +318,7 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
 
   // Rows m = k0-4 .. k0-1: stage 1 only; k0 .. k0+3: both stages, no output yet;
   // k0+4 .. k_end+3: both stages and row m-4 written.  Stage 1 must produce rows
-  // k0-2 .. k_end+1 and stage 2 rows k0 .. k_end-1; the push modes drop the rest.
+  // k0-2 .. k_end+1 and stage 2 rows k0 .. k_end-1; the push modes drop the rows above.
   auto step = [&](int m, auto mode1, auto mode2, bool emit) {
     constexpr int M1 = decltype(mode1)::value, M2 = decltype(mode2)::value;
     constexpr bool stage2 = M2 >= 0;
@@ -370,30 +369,26 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
   using Off = PushMode<-1>;
   using Store = PushMode<kPushStore>;
   using NoFlux = PushMode<kPushNoFlux>;
+  using FluxOnly = PushMode<kPushFluxOnly>;
   using Full = PushMode<kPushFull>;
-  using NoX = PushMode<kPushNoX>;
   step(k0 - 4, Store{}, Off{}, false);
   step(k0 - 3, Store{}, Off{}, false);
   step(k0 - 2, NoFlux{}, Off{}, false);
-  step(k0 - 1, Full{}, Off{}, false);
+  step(k0 - 1, FluxOnly{}, Off{}, false);
   step(k0, Full{}, Store{}, false);
   step(k0 + 1, Full{}, Store{}, false);
   step(k0 + 2, Full{}, NoFlux{}, false);
-  step(k0 + 3, Full{}, Full{}, false);
-  // rows from k_end+2 on are below the last stage-1 (k_end+1) and stage-2 (k_end-1)
-  // rows whose x divergence is used
-  const int m_tail = max(k_end + 2, k0 + 4);
+  step(k0 + 3, Full{}, FluxOnly{}, false);
   // four rows per trip (the period of the row rotation), so the pipeline registers are
   // renamed instead of moved
   int m = k0 + 4;
-  for (; m + 3 < m_tail; m += 4) {
+  for (; m + 3 <= k_end + 3; m += 4) {
     step(m, Full{}, Full{}, true);
     step(m + 1, Full{}, Full{}, true);
     step(m + 2, Full{}, Full{}, true);
     step(m + 3, Full{}, Full{}, true);
   }
-  for (; m < m_tail; ++m) step(m, Full{}, Full{}, true);
-  for (; m <= k_end + 3; ++m) step(m, NoX{}, NoX{}, true);
+  for (; m <= k_end + 3; ++m) step(m, Full{}, Full{}, true);
 }
 
 template <bool NOISE>
