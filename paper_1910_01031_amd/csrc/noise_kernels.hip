@@ -236,6 +236,35 @@ __global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, PullConst P,
 #define IEWPF_UPD_PB 4
 #endif
 constexpr int kPB = IEWPF_UPD_PB;
+#ifndef IEWPF_UPD_OBS_BATCH
+#define IEWPF_UPD_OBS_BATCH 4
+#endif
+constexpr int kObsBatch = IEWPF_UPD_OBS_BATCH;
+
+// Offset (ix, iy) of cell (j, k) in the stored window of the observation at (jo, ko);
+// false when the cell is outside the window (radius -1: the window covers the period).
+__device__ __forceinline__ bool window_offset(const PullConst& P, int nx, int ny, int j, int k,
+                                              int jo, int ko, int& ix, int& iy) {
+  bool in = true;
+  if (P.ry >= 0) {
+    int dk = k - ko;
+    dk = dk > ny / 2 ? dk - ny : (dk < -(ny / 2) ? dk + ny : dk);
+    in = dk >= -P.ry && dk <= P.ry;
+    iy = in ? dk + P.ry : 0;
+  } else {
+    iy = wrapi(k - ko, ny);
+  }
+  if (P.rx >= 0) {
+    int dj = j - jo;
+    dj = dj > nx / 2 ? dj - nx : (dj < -(nx / 2) ? dj + nx : dj);
+    const bool inx = dj >= -P.rx && dj <= P.rx;
+    ix = inx ? dj + P.rx : 0;
+    in = in && inx;
+  } else {
+    ix = wrapi(j - jo, nx);
+  }
+  return in;
+}
 
 __global__ __launch_bounds__(256) void analysis_update_kernel(
     CoarseConst C, PullConst P, int ne, int total_waves, const float* __restrict__ zall,
@@ -243,7 +272,8 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
     int max_obs, const int32_t* __restrict__ cells, const int32_t* __restrict__ st_off,
     const int32_t* __restrict__ st_ent) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave));
   if (wave >= total_waves) return;
   const int per_group = P.n_strip_x * P.n_strip_y;
   const int group = wave / per_group;
@@ -327,61 +357,55 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
         au[p] = -C.gb_y * (d0[p] - dm2[p]);
         av[p] = C.gb_x * (__shfl_down(dm1[p], 1, kWave) - __shfl_up(dm1[p], 1, kWave));
       }
-      for (int t = o_beg; t < o_end; ++t) {
-        const int q = t - o_beg;  // wave-uniform
-        int o = 0, jo, ko;
-        if (q < kWave) {
-          jo = __builtin_amdgcn_readlane(l_jo, q);
-          ko = __builtin_amdgcn_readlane(l_ko, q);
-        } else {
-          o = st_ent[t];
-          jo = cells[2 * o];
-          ko = cells[2 * o + 1];
+      // observations held in lanes: kObsBatch at a time, all window loads of a batch issued
+      // before its multiply-adds
+      const int n_lane = min(o_end - o_beg, kWave);
+      for (int q0 = 0; q0 < n_lane; q0 += kObsBatch) {
+        float w[kObsBatch][6];
+        float su[kObsBatch][kPB], sv[kObsBatch][kPB];
+#pragma unroll
+        for (int u = 0; u < kObsBatch; ++u) {
+          const int q = q0 + u < n_lane ? q0 + u : n_lane - 1;  // wave-uniform
+          const int jo = __builtin_amdgcn_readlane(l_jo, q);
+          const int ko = __builtin_amdgcn_readlane(l_ko, q);
+          int ix, iy;
+          const bool in = q0 + u < n_lane && window_offset(P, nx, ny, j, k, jo, ko, ix, iy);
+          const size_t idx = (size_t)iy * P.wx + ix;
+#pragma unroll
+          for (int f = 0; f < 6; ++f) w[u][f] = in ? windows[f * plane + idx] : 0.0f;
+#pragma unroll
+          for (int p = 0; p < kPB; ++p) {
+            su[u][p] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l_su[p]), q));
+            sv[u][p] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l_sv[p]), q));
+          }
         }
-        int iy;
-        if (P.ry >= 0) {
-          int dk = k - ko;
-          dk = dk > ny / 2 ? dk - ny : (dk < -(ny / 2) ? dk + ny : dk);
-          if (dk < -P.ry || dk > P.ry) continue;  // the same for the whole wave
-          iy = dk + P.ry;
-        } else {
-          iy = wrapi(k - ko, ny);
+#pragma unroll
+        for (int u = 0; u < kObsBatch; ++u) {
+#pragma unroll
+          for (int p = 0; p < kPB; ++p) {
+            ae[p] += su[u][p] * w[u][0] + sv[u][p] * w[u][3];
+            au[p] += su[u][p] * w[u][1] + sv[u][p] * w[u][4];
+            av[p] += su[u][p] * w[u][2] + sv[u][p] * w[u][5];
+          }
         }
-        int ix;
-        bool in = true;
-        if (P.rx >= 0) {
-          int dj = j - jo;
-          dj = dj > nx / 2 ? dj - nx : (dj < -(nx / 2) ? dj + nx : dj);
-          in = dj >= -P.rx && dj <= P.rx;
-          ix = in ? dj + P.rx : 0;
-        } else {
-          ix = wrapi(j - jo, nx);
-        }
+      }
+      // observations past the lanes: read from the list
+      for (int t = o_beg + kWave; t < o_end; ++t) {
+        const int o = st_ent[t];
+        int ix, iy;
+        if (!window_offset(P, nx, ny, j, k, cells[2 * o], cells[2 * o + 1], ix, iy)) continue;
         const size_t idx = (size_t)iy * P.wx + ix;
-        float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f, w4 = 0.f, w5 = 0.f;
-        if (in) {
-          w0 = windows[idx];
-          w1 = windows[plane + idx];
-          w2 = windows[2 * plane + idx];
-          w3 = windows[3 * plane + idx];
-          w4 = windows[4 * plane + idx];
-          w5 = windows[5 * plane + idx];
-        }
+        float w[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) w[f] = windows[f * plane + idx];
 #pragma unroll
         for (int p = 0; p < kPB; ++p) {
           if (p < np) {
-            float su, sv;
-            if (q < kWave) {
-              su = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l_su[p]), q));
-              sv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l_sv[p]), q));
-            } else {
-              const double* s2 = sd + ((size_t)(p0 + p) * max_obs + o) * 2;
-              su = static_cast<float>(s2[0]);
-              sv = static_cast<float>(s2[1]);
-            }
-            ae[p] += su * w0 + sv * w3;
-            au[p] += su * w1 + sv * w4;
-            av[p] += su * w2 + sv * w5;
+            const double* s2 = sd + ((size_t)(p0 + p) * max_obs + o) * 2;
+            const float su = static_cast<float>(s2[0]), sv = static_cast<float>(s2[1]);
+            ae[p] += su * w[0] + sv * w[3];
+            au[p] += su * w[1] + sv * w[4];
+            av[p] += su * w[2] + sv * w[5];
           }
         }
       }

@@ -136,6 +136,26 @@ def test_analysis_parity_overlapping_drifters(torch_dev):
         assert err < TOL, (f, err)
 
 
+def test_analysis_parity_more_observations_than_lanes(torch_dev):
+    # 83 moorings on 64x48: every strip of the update sees more observations than a wave
+    # has lanes (the ones past 64 are read from the list), 5 particles (a partial group)
+    torch, dev = torch_dev
+    _say("analysis parity, 83 observations per strip (64x48)")
+    cfg = W.Config(nx=64, ny=48, dx=1e4, dy=1e4, c_omega=4, n_particles=5, me_std=2e-3)
+    ens, truth = _ensemble_near(cfg, 5, 0.003)
+    rng = np.random.default_rng(83)
+    flat = rng.choice(cfg.nx * cfg.ny, size=83, replace=False)
+    cells = np.stack([flat % cfg.nx, flat // cfg.nx], axis=1).astype(np.int32)
+    y = oobs.mooring_obs(truth, cells, cfg.H, cfg.obs_sigma, np.zeros((83, 2)))
+    got, stats, sc = _gpu_analysis(torch, dev, cfg, ens, cells, y, 3, 96)
+    ref, info = oiewpf.analysis(ens.astype(np.float64), cells, y, cfg, 3)
+    _check_scalars(stats, sc, info, cfg.n_psi)
+    for f in range(3):
+        err = np.abs(got[:, f] - ref[:, f]).max() / np.abs(ref[:, f]).max()
+        _say(f"  field {f} rel err {err}")
+        assert err < TOL, (f, err)
+
+
 def test_analysis_no_observations(torch_dev):
     torch, dev = torch_dev
     cfg = W.tiny().replace(n_particles=4)
