@@ -52,7 +52,8 @@ typedef struct iewpf_ctx iewpf_ctx;
  *   H, g, f            equilibrium depth, gravity, Coriolis parameter (eq. swe_full)
  *   dt, n_sub          model step and its number of equal scheme steps (eq. swecfl)
  *   theta              generalized-minmod limiter parameter of the scheme (1 <= theta <= 2)
- *   c_omega            coarsening of the random grid Omega^R (Section "Small scale model errors")
+ *   c_omega            coarsening of the random grid Omega^R (Section "Small scale model errors"),
+ *                      1 <= c_omega <= 16
  *   me_std, me_L0      model error: pointwise std of the coarse SOAR field and SOAR length
  *                      scale L0 (eq. soar_function); q0 = me_std / ||k||_2
  *   init_std, init_L0  same for the initial-state perturbation of iewpf_init_ensemble
@@ -91,8 +92,8 @@ typedef struct {
   int32_t n_obs;
 } iewpf_stats;
 
-/* Create a context: validates the config (nx, ny divisible by c_omega, >= 7 coarse points
- * per direction, obs/drifter capacity), computes in float64 on the host the SOAR stencils,
+/* Create a context: validates the config (c_omega <= 16, nx, ny divisible by c_omega, >= 7
+ * coarse points per direction, obs/drifter capacity), computes in float64 on the host the SOAR stencils,
  * the pull windows Q^{1/2} Q^{1/2,T} H^T e_b (eq. detailedOPDUpdate), S = (H Q H^T + R)^-1
  * by Cholesky (eq. S_extended), the local 49x49 A^{1/2} (eq. svdOfParenthesis), uploads
  * them and allocates the workspaces (one state-sized scratch buffer + coarse fields).

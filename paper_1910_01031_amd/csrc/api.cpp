@@ -478,6 +478,8 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
       !(f.obs_sigma > 0) || f.max_obs <= 0 || f.max_obs >= (1 << 22) || !(f.theta >= 1.0) ||
       !(f.theta <= 2.0) || f.me_std < 0 || f.init_std < 0)
     return fail(IEWPF_E_ARG, "invalid configuration value");
+  if (f.c_omega > kCrMaxC)
+    return fail(IEWPF_E_ARG, "c_omega above " + std::to_string(kCrMaxC) + " is not supported");
   if (f.nx % f.c_omega || f.ny % f.c_omega)
     return fail(IEWPF_E_SHAPE, "nx and ny must be divisible by c_omega");
   if (f.nx / f.c_omega < 7 || f.ny / f.c_omega < 7)
@@ -547,6 +549,7 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   c->cc.nry = c->nry;
   c->cc.gb_x = (float)(f.g * f.H / (2.0 * f.f * f.dx));
   c->cc.gb_y = (float)(f.g * f.H / (2.0 * f.f * f.dy));
+  fill_cr_table(c->c, S.cr);
   // pull windows and S
   const int r = 7 * c->c, W = 2 * r + 1;
   c->rx = W > f.nx ? -1 : r;

@@ -249,4 +249,12 @@ int build_local_block(const iewpf_ctx& ctx, double ahalf[49 * 49], double Sc[4])
   return 0;
 }
 
+void fill_cr_table(int c, CrTable& t) {
+  for (int p = 0; p < 2 * kCrMaxC; ++p) {
+    double w[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c <= kCrMaxC && p < 2 * c) cr_weights(static_cast<double>(p) / (2.0 * c), w);
+    for (int m = 0; m < 4; ++m) t.w[p][m] = static_cast<float>(w[m]);
+  }
+}
+
 }  // namespace iewpf

@@ -27,6 +27,15 @@ int fail(int code, const std::string& msg);
 
 // ---- constants passed by value to kernels ----------------------------------------------
 
+// Catmull-Rom weights of the interpolation I_Omega (taps -1, 0, 1, 2) at the phases
+// t = p / (2c), p = 0 .. 2c-1, of fine rows between coarse points (filled on the host in
+// float64, rounded once).  Contexts accept c <= kCrMaxC.
+constexpr int kCrMaxC = 16;
+struct CrTable {
+  float w[2 * kCrMaxC][4];
+};
+void fill_cr_table(int c, CrTable& t);
+
 // Shallow-water scheme constants (float32, as used by the stencil).
 struct SweConst {
   int nx, ny;
@@ -40,6 +49,7 @@ struct SweConst {
   // fused model error (last scheme step of a model step)
   int c, nrx, nry;     // coarsening and coarse grid
   float gb_x, gb_y;    // g H / (2 f dx), g H / (2 f dy)
+  CrTable cr;          // interpolation weights by phase
 };
 
 // One ensemble of a batched stencil launch (device-resident table).

@@ -24,8 +24,10 @@ __device__ __forceinline__ int floordiv(int a, int b) {  // b > 0
   return (a % b != 0 && a < 0) ? q - 1 : q;
 }
 
-// Catmull-Rom weights (taps -1, 0, 1, 2) at phase t.
-__device__ __forceinline__ void cr4(float t, float w[4]) {
+// Catmull-Rom weights (taps -1, 0, 1, 2) at phase p in [0, 2c) of a fine row or column,
+// t = p / (2c).
+__device__ __forceinline__ void cr_phase(const CoarseConst& C, int p, float w[4]) {
+  const float t = static_cast<float>(p) * (1.0f / static_cast<float>(2 * C.c));
   const float t2 = t * t, t3 = t2 * t;
   w[0] = 0.5f * (-t3 + 2.0f * t2 - t);
   w[1] = 0.5f * (3.0f * t3 - 5.0f * t2 + 2.0f);
@@ -62,7 +64,7 @@ struct CoarseWin {
       by = b;
     }
     float wy[4];
-    cr4(static_cast<float>(num - 2 * C.c * b) / static_cast<float>(2 * C.c), wy);
+    cr_phase(C, num - 2 * C.c * b, wy);
     return wy[0] * xr[0] + wy[1] * xr[1] + wy[2] * xr[2] + wy[3] * xr[3];
   }
 };
@@ -113,7 +115,7 @@ __device__ __forceinline__ float bicubic_at(const float* __restrict__ z, const C
   const int num = 2 * k + 1 - C.c;
   const int by = floordiv(num, 2 * C.c);
   float wy[4];
-  cr4(static_cast<float>(num - 2 * C.c * by) / static_cast<float>(2 * C.c), wy);
+  cr_phase(C, num - 2 * C.c * by, wy);
   float acc = 0.0f;
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, PullConst P,
   {
     const int num = 2 * jw + 1 - C.c;
     const int bx = floordiv(num, 2 * C.c);
-    cr4(static_cast<float>(num - 2 * C.c * bx) / static_cast<float>(2 * C.c), wx);
+    cr_phase(C, num - 2 * C.c * bx, wx);
 #pragma unroll
     for (int m = 0; m < 4; ++m) cx[m] = wrap1(bx + m - 1, C.nrx);
   }
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
   {
     const int num = 2 * jw + 1 - C.c;
     const int bx = floordiv(num, 2 * C.c);
-    cr4(static_cast<float>(num - 2 * C.c * bx) / static_cast<float>(2 * C.c), wx);
+    cr_phase(C, num - 2 * C.c * bx, wx);
 #pragma unroll
     for (int m = 0; m < 4; ++m) cx[m] = wrap1(bx + m - 1, C.nrx);
   }

@@ -250,8 +250,10 @@ struct CoarseRows {
       by = b;
       fetch(z, C, b + 3, nr);
     }
+    const int ph = ns - 2 * C.c * b;  // wave-uniform phase of the row, in [0, 2c)
     float wy[4];
-    cr_weights(static_cast<float>(ns - 2 * C.c * b) / static_cast<float>(2 * C.c), wy);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) wy[n] = C.cr.w[ph][n];
     return wy[0] * xr[0] + wy[1] * xr[1] + wy[2] * xr[2] + wy[3] * xr[3];
   }
 };

@@ -53,6 +53,7 @@ def test_struct_layouts_match_c(tmp_path):
     (dict(n_particles=0), abi.IEWPF_E_ARG),
     (dict(theta=0.5), abi.IEWPF_E_ARG),
     (dict(obs_sigma=0.0), abi.IEWPF_E_ARG),
+    (dict(nx=17 * 8, ny=17 * 8, c_omega=17), abi.IEWPF_E_ARG),  # coarsening above 16
 ])
 def test_invalid_configs_are_rejected(kw, code):
     lib = abi.load()
