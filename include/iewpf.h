@@ -131,11 +131,12 @@ int iewpf_set_scheme(iewpf_ctx* ctx, int scheme);
  * independently: S = (H Q H^T + R)^{-1} is the same 2x2 block for every observation (eq.
  * S_extended and the assumption after it that observations are far apart).  When on,
  * iewpf_assimilate uses S = (sym(H Q H^T) + R)^{-1} over all observations together
- * ([2 n_obs]^2, float64 Cholesky on the device) in the pull and in c_i; the posterior
+ * ([2 n_obs]^2, float64 Cholesky on the device, S d and c_i by triangular solves per
+ * particle) in the pull and in c_i; the posterior
  * perturbation keeps the paper's local blocks.  H Q H^T's entries are the pull windows read
  * at the offsets between observed cells; with c_Omega > 1 each observation's chain uses a
- * coarse grid aligned on its own cell, so its symmetric part is used.  S is rebuilt only
- * when the observed cells change (that call waits for the stream).  Requires
+ * coarse grid aligned on its own cell, so its symmetric part is used.  The factor is rebuilt
+ * only when the observed cells change (that call waits for the stream).  Requires
  * 2 max_obs <= 1024 (IEWPF_E_CAPACITY otherwise); allocates its buffers on the first call;
  * not available to batched cycles. */
 int iewpf_set_full_innovation(iewpf_ctx* ctx, int on);

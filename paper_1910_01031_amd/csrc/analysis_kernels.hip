@@ -314,77 +314,209 @@ __global__ void hqht_full_kernel(int n_obs, int nx, int ny, int rx, int ry, int 
   M[t] = 0.5 * (entry(r, col) + entry(col, r)) + (r == col ? sigma2 : 0.0);
 }
 
-// S = A^{-1} for a symmetric positive definite A [n][n] (n <= kCholThreads), one workgroup,
-// float64: Cholesky A = L L^T in place (right-looking, pivot column staged in LDS), X = L^{-1}
-// column by column (one thread per column), then S = X^T X written over A.  status[0] = 1
-// when a pivot is not positive.
+// Cholesky factor of a symmetric positive definite A [n][n] (n <= kCholThreads) in place,
+// one workgroup, float64.  Right-looking in panels of kCholPanel columns: the panel (rows
+// p0 .. n-1) is factored in LDS, written back, and the trailing lower triangle is updated
+// once per panel with kCholPanel-term dot products read from LDS.  On return the lower
+// triangle holds L and the strict upper triangle L^T (row r of the upper triangle is column
+// r of L), so both triangular solves read rows.  status[0] = 1 when a pivot is not positive.
 constexpr int kCholThreads = 1024;
-__global__ __launch_bounds__(kCholThreads) void chol_inverse_kernel(int n, double* __restrict__ A,
-                                                                    double* __restrict__ X,
-                                                                    int32_t* __restrict__ status) {
-  __shared__ double col[kCholThreads];
+constexpr int kCholPanel = 16;
+constexpr int kCholStride = kCholPanel + 1;  // LDS row stride (doubles)
+__global__ __launch_bounds__(kCholThreads) void chol_factor_kernel(int n, double* __restrict__ A,
+                                                                   int32_t* __restrict__ status) {
+  extern __shared__ double P[];  // [n - p0][kCholStride]
   const int tid = threadIdx.x;
+  const int sub = tid & (kCholPanel - 1), grp = tid / kCholPanel;  // 64 row groups of 16 lanes
+  constexpr int kGroups = kCholThreads / kCholPanel;
+  bool bad = false;
+  for (int p0 = 0; p0 < n; p0 += kCholPanel) {
+    const int pw = min(kCholPanel, n - p0);
+    const int m = n - p0;
+    for (int i = grp; i < m; i += kGroups)
+      if (sub < pw) P[i * kCholStride + sub] = A[(size_t)(p0 + i) * n + p0 + sub];
+    __syncthreads();
+    for (int c = 0; c < pw; ++c) {
+      const double d = P[c * kCholStride + c];
+      if (!(d > 0.0)) bad = true;
+      const double piv = sqrt(d > 0.0 ? d : 1.0);
+      __syncthreads();  // every thread has read the pivot before it is replaced
+      for (int i = c + tid; i < m; i += kCholThreads)
+        P[i * kCholStride + c] = i == c ? piv : P[i * kCholStride + c] / piv;
+      __syncthreads();
+      const int k = c + 1 + sub;  // remaining panel columns, rows i >= k
+      if (k < pw) {
+        const double lk = P[k * kCholStride + c];
+        for (int i = k + grp; i < m; i += kGroups)
+          P[i * kCholStride + k] -= P[i * kCholStride + c] * lk;
+      }
+      __syncthreads();
+    }
+    // write back L (lower) and L^T (upper rows p0 .. p0+pw-1)
+    for (int i = grp; i < m; i += kGroups) {
+      if (sub < pw && i >= sub) {
+        const double v = P[i * kCholStride + sub];
+        A[(size_t)(p0 + i) * n + p0 + sub] = v;
+        A[(size_t)(p0 + sub) * n + p0 + i] = v;
+      }
+    }
+    // trailing update of the lower triangle right of the panel
+    const int q0 = p0 + pw;
+    const int tx = tid & 31, ty = tid >> 5;
+    for (int i = q0 + ty; i < n; i += 32) {
+      const double* Pi = P + (i - p0) * kCholStride;
+      double* row = A + (size_t)i * n;
+      for (int k = q0 + tx; k <= i; k += 32) {
+        const double* Pk = P + (k - p0) * kCholStride;
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < kCholPanel; ++c)
+          if (c < pw) acc += Pi[c] * Pk[c];
+        row[k] -= acc;
+      }
+    }
+    __syncthreads();
+  }
   if (tid == 0) status[0] = 0;
-  for (int j = 0; j < n; ++j) {
-    __syncthreads();
-    if (tid == 0) {
-      const double d = A[(size_t)j * n + j];
-      if (!(d > 0.0)) status[0] = 1;
-      col[j] = sqrt(d > 0.0 ? d : 1.0);
-      A[(size_t)j * n + j] = col[j];
-    }
-    __syncthreads();
-    const double p = col[j];
-    for (int i = j + 1 + tid; i < n; i += kCholThreads) {
-      const double v = A[(size_t)i * n + j] / p;
-      A[(size_t)i * n + j] = v;
-      col[i] = v;
-    }
-    __syncthreads();
-    const int m = n - j - 1;
-    for (int t = tid; t < m * m; t += kCholThreads) {
-      const int i = j + 1 + t / m, k = j + 1 + t % m;
-      if (k <= i) A[(size_t)i * n + k] -= col[i] * col[k];
-    }
-  }
   __syncthreads();
-  if (tid < n) {  // column c of X = L^{-1}
-    const int c = tid;
-    for (int r = c; r < n; ++r) {
-      double s = r == c ? 1.0 : 0.0;
-      for (int j = c; j < r; ++j) s -= A[(size_t)r * n + j] * X[(size_t)j * n + c];
-      X[(size_t)r * n + c] = s / A[(size_t)r * n + r];
-    }
-  }
-  __syncthreads();
-  for (int t = tid; t < n * n; t += kCholThreads) {  // S[i][j] = sum_{k >= max(i, j)} X[k][i] X[k][j]
-    const int i = t / n, j = t - i * n;
-    double s = 0.0;
-    for (int k = i > j ? i : j; k < n; ++k) s += X[(size_t)k * n + i] * X[(size_t)k * n + j];
-    A[t] = s;  // L is no longer read: this phase reads X only
-  }
+  if (bad && tid == 0) status[0] = 1;
 }
 
-// sd = S d and c_i = d^T S d for every particle, with the full S [2 n_obs][2 n_obs].
-__global__ __launch_bounds__(kThreads) void sd_full_kernel(int n_obs, int max_obs,
-                                                           const double* __restrict__ S,
-                                                           const double* __restrict__ d,
-                                                           double* __restrict__ sd,
-                                                           double* __restrict__ cval) {
-  __shared__ double sh[kThreads];
-  const int i = blockIdx.x;
-  const int n = 2 * n_obs;
-  const double* di = d + (size_t)i * max_obs * 2;
-  double phi = 0.0;
-  for (int r = threadIdx.x; r < n; r += kThreads) {
-    const double* row = S + (size_t)r * n;
-    double s = 0.0;
-    for (int c = 0; c < n; ++c) s += row[c] * di[c];
-    sd[(size_t)i * max_obs * 2 + r] = s;
-    phi += di[r] * s;
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// Solves A x = b with the factor above for every right-hand side, one wave each:
+// L y = b by forward substitution, then L^T x = y by back substitution, both column by
+// column (x_j fixed, then subtracted from every later row), so every step reads one row of
+// a triangle; lane l keeps rows l, l + 64, ... (S slots).  The row of the next step is
+// loaded during the current one.  out = x (= S b), cval = y^T y (= b^T S b).
+// rhs == nullptr: b = e_w for wave w (the columns of S = A^{-1}).
+template <int S>
+__global__ __launch_bounds__(256) void chol_solve_kernel(int n, int nrhs, const double* __restrict__ A,
+                                                         const double* __restrict__ rhs, int rhs_stride,
+                                                         double* __restrict__ out, int out_stride,
+                                                         double* __restrict__ cval) {
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (w >= nrhs) return;
+  double b[S];
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    const int r = t * 64 + lane;
+    b[t] = 0.0;
+    if (r < n) b[t] = rhs ? rhs[(size_t)w * rhs_stride + r] : (r == w ? 1.0 : 0.0);
   }
-  phi = block_sum(phi, sh);
-  if (threadIdx.x == 0) cval[i] = phi;
+  double ss = 0.0;
+  double cur[S], nxt[S];
+  // forward: y_j = b_j / L_jj; b_r -= L_rj y_j (r > j), L_rj = A[j][r] (upper row j)
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    cur[t] = t * 64 + lane < n ? A[t * 64 + lane] : 0.0;
+    nxt[t] = 0.0;
+  }
+#pragma unroll
+  for (int js = 0; js < S; ++js) {
+    if (js * 64 < n) {
+      for (int jl = 0; jl < 64; ++jl) {
+        const int j = js * 64 + jl;
+        if (j >= n) break;
+        if (j + 1 < n) {
+#pragma unroll
+          for (int t = js; t < S; ++t) {
+            const int r = t * 64 + lane;
+            nxt[t] = r < n ? A[(size_t)(j + 1) * n + r] : 0.0;
+          }
+        }
+        const double yj = readlane_f64(b[js], jl) / readlane_f64(cur[js], jl);
+        ss += yj * yj;
+        if (lane == jl) b[js] = yj;
+#pragma unroll
+        for (int t = js; t < S; ++t) {
+          const int r = t * 64 + lane;
+          if (r > j && r < n) b[t] -= cur[t] * yj;
+        }
+#pragma unroll
+        for (int t = js; t < S; ++t) cur[t] = nxt[t];
+      }
+    }
+  }
+  // backward: x_j = y_j / L_jj; y_r -= L_jr x_j (r < j), L_jr = A[j][r] (lower row j)
+#pragma unroll
+  for (int t = 0; t < S; ++t)
+    cur[t] = t * 64 + lane < n ? A[(size_t)(n - 1) * n + t * 64 + lane] : 0.0;
+#pragma unroll
+  for (int js = S - 1; js >= 0; --js) {
+    if (js * 64 < n) {
+      for (int jl = 63; jl >= 0; --jl) {
+        const int j = js * 64 + jl;
+        if (j >= n) continue;
+        if (j > 0) {
+#pragma unroll
+          for (int t = 0; t <= js; ++t) {
+            const int r = t * 64 + lane;
+            nxt[t] = r < n ? A[(size_t)(j - 1) * n + r] : 0.0;
+          }
+        }
+        const double xj = readlane_f64(b[js], jl) / readlane_f64(cur[js], jl);
+        if (lane == jl) b[js] = xj;
+#pragma unroll
+        for (int t = 0; t <= js; ++t) {
+          const int r = t * 64 + lane;
+          if (r < j) b[t] -= cur[t] * xj;
+        }
+#pragma unroll
+        for (int t = 0; t <= js; ++t) cur[t] = nxt[t];
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    const int r = t * 64 + lane;
+    if (r < n) out[(size_t)w * out_stride + r] = b[t];
+  }
+  if (cval && lane == 0) cval[w] = ss;
+}
+
+// SD[p][r] = sum_c S[r][c] D[p][c] for every particle p and row r of the full S [n][n]
+// (rows of D and SD are `stride` apart): 16 x 16 tiles of (row, particle), c in chunks of 32
+// staged in LDS, each sum in increasing c.
+__global__ __launch_bounds__(256) void sd_gemm_kernel(int n, int ne, int stride,
+                                                      const double* __restrict__ S,
+                                                      const double* __restrict__ D,
+                                                      double* __restrict__ SD) {
+  __shared__ double Ts[16][33], Td[16][33];
+  const int tr = threadIdx.x & 15, tp = threadIdx.x >> 4;
+  const int r0 = blockIdx.x * 16, p0 = blockIdx.y * 16;
+  double acc = 0.0;
+  for (int c0 = 0; c0 < n; c0 += 32) {
+    for (int e = threadIdx.x; e < 512; e += 256) {
+      const int a = e >> 5, cc = e & 31, c = c0 + cc;
+      Ts[a][cc] = (r0 + a < n && c < n) ? S[(size_t)(r0 + a) * n + c] : 0.0;
+      Td[a][cc] = (p0 + a < ne && c < n) ? D[(size_t)(p0 + a) * stride + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cc = 0; cc < 32; ++cc) acc += Ts[tr][cc] * Td[tp][cc];
+    __syncthreads();
+  }
+  if (r0 + tr < n && p0 + tp < ne) SD[(size_t)(p0 + tp) * stride + r0 + tr] = acc;
+}
+
+// c_p = d_p^T (S d_p), one workgroup per particle, fixed-order sum.
+__global__ __launch_bounds__(kThreads) void dot_rows_kernel(int n, int stride,
+                                                            const double* __restrict__ D,
+                                                            const double* __restrict__ SD,
+                                                            double* __restrict__ cval) {
+  __shared__ double sh[kThreads];
+  const size_t o = (size_t)blockIdx.x * stride;
+  double v = 0.0;
+  for (int r = threadIdx.x; r < n; r += kThreads) v += D[o + r] * SD[o + r];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) cval[blockIdx.x] = v;
 }
 
 __global__ __launch_bounds__(kThreads) void posterior_coarse_kernel(
@@ -649,13 +781,34 @@ void launch_hqht_full(int n_obs, int nx, int ny, int rx, int ry, int wx, int wy,
 
 int chol_max_order() { return kCholThreads; }
 
-void launch_chol_inverse(int n, double* A, double* X, int32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(chol_inverse_kernel, dim3(1), dim3(kCholThreads), 0, s, n, A, X, status);
+void launch_chol_factor(int n, double* A, int32_t* status, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(chol_factor_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(double) * kCholThreads * kCholStride));
+    attr = true;
+  }
+  hipLaunchKernelGGL(chol_factor_kernel, dim3(1), dim3(kCholThreads),
+                     sizeof(double) * (size_t)n * kCholStride, s, n, A, status);
 }
 
-void launch_sd_full(int ne, int n_obs, int max_obs, const double* S, const double* d, double* sd,
+void launch_sd_full(int n, int ne, int stride, const double* S, const double* D, double* SD,
                     double* cval, hipStream_t s) {
-  hipLaunchKernelGGL(sd_full_kernel, dim3(ne), dim3(kThreads), 0, s, n_obs, max_obs, S, d, sd, cval);
+  hipLaunchKernelGGL(sd_gemm_kernel, dim3((n + 15) / 16, (ne + 15) / 16), dim3(256), 0, s, n, ne,
+                     stride, S, D, SD);
+  hipLaunchKernelGGL(dot_rows_kernel, dim3(ne), dim3(kThreads), 0, s, n, stride, D, SD, cval);
+}
+
+void launch_chol_solve(int n, int nrhs, const double* L, const double* rhs, int rhs_stride,
+                       double* out, int out_stride, double* cval, hipStream_t s) {
+  const int blocks = (nrhs + 3) / 4;
+  if (n <= 512)
+    hipLaunchKernelGGL(chol_solve_kernel<8>, dim3(blocks), dim3(256), 0, s, n, nrhs, L, rhs,
+                       rhs_stride, out, out_stride, cval);
+  else
+    hipLaunchKernelGGL(chol_solve_kernel<16>, dim3(blocks), dim3(256), 0, s, n, nrhs, L, rhs,
+                       rhs_stride, out, out_stride, cval);
 }
 
 void launch_observe(int n_obs, int nx, int ny, double H, double sigma, uint64_t seed,

@@ -264,13 +264,15 @@ int upload_observations(iewpf_ctx* c, int n_obs, bool with_y, hipStream_t s) {
 }
 
 // Full innovation covariance for the observed cells (already on the device): rebuilt and
-// inverted only when the cell set differs from the cached one; waits for the stream then.
+// factored only when the cell set differs from the cached one; waits for the stream then.
 int prepare_full_s(iewpf_ctx* c, const int32_t* cells, int n_obs, hipStream_t s) {
   if (n_obs == c->f_n && std::equal(cells, cells + 2 * n_obs, c->f_cells.begin())) return 0;
   const double s2 = c->cfg.obs_sigma * c->cfg.obs_sigma;
   launch_hqht_full(n_obs, c->nx, c->ny, c->rx, c->ry, c->wx, c->wy, c->windows64, c->obs_cells, s2,
                    c->fS, s);
-  launch_chol_inverse(2 * n_obs, c->fS, c->fX, c->fstatus, s);
+  launch_chol_factor(2 * n_obs, c->fS, c->fstatus, s);
+  // S = A^{-1} explicitly (columns from unit right-hand sides), kept with the factor
+  launch_chol_solve(2 * n_obs, 2 * n_obs, c->fS, nullptr, 0, c->fX, 2 * n_obs, nullptr, s);
   IEWPF_HIP_TRY(hipGetLastError());
   int32_t st = 0;
   IEWPF_HIP_TRY(hipMemcpyAsync(&st, c->fstatus, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -295,7 +297,7 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
       const double I2[4] = {1.0, 0.0, 0.0, 1.0};
       launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, I2, state, c->obs_cells,
                         c->obs_y, c->dinn, c->cval, s);
-      launch_sd_full(c->ne, n_obs, c->max_obs, c->fS, c->dinn, c->sd, c->cval, s);
+      launch_sd_full(2 * n_obs, c->ne, 2 * c->max_obs, c->fX, c->dinn, c->sd, c->cval, s);
     } else {
       launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, c->S, state,
                         c->obs_cells, c->obs_y, c->sd, c->cval, s);
@@ -1209,8 +1211,8 @@ int iewpf_read_buffer(iewpf_ctx* c, int which, void* host_out, size_t bytes, voi
     }
     case 9: {
       const size_t n = 2 * (size_t)(c->f_n > 0 ? c->f_n : 0);
-      if (!c->fS || n == 0 || !need(sizeof(double) * n * n)) break;
-      IEWPF_HIP_TRY(hipMemcpy(host_out, c->fS, sizeof(double) * n * n, hipMemcpyDeviceToHost));
+      if (!c->fX || n == 0 || !need(sizeof(double) * n * n)) break;
+      IEWPF_HIP_TRY(hipMemcpy(host_out, c->fX, sizeof(double) * n * n, hipMemcpyDeviceToHost));
       return 0;
     }
     case 8:

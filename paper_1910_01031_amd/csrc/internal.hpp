@@ -263,12 +263,17 @@ void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens
                       float* nu, double* part_dots, double* dots, hipStream_t s,
                       const uint64_t* dyn = nullptr);
 // Full innovation covariance: assemble sym(H Q H^T) + sigma^2 I [2 n_obs]^2 (float64) from the
-// float64 pull windows, invert it in one workgroup (n <= chol_max_order()), S d and c_i.
+// float64 pull windows, factor it A = L L^T in place in one workgroup (n <= chol_max_order();
+// lower triangle L, upper L^T), solve A x = b per right-hand side (rhs == nullptr gives the
+// columns of S = A^{-1}; with rhs, x = S b and cval = b^T S b), and S d, c_i = d^T S d for
+// every particle from the explicit S.
 void launch_hqht_full(int n_obs, int nx, int ny, int rx, int ry, int wx, int wy, const double* win,
                       const int32_t* cells, double sigma2, double* M, hipStream_t s);
 int chol_max_order();
-void launch_chol_inverse(int n, double* A, double* X, int32_t* status, hipStream_t s);
-void launch_sd_full(int ne, int n_obs, int max_obs, const double* S, const double* d, double* sd,
+void launch_chol_factor(int n, double* A, int32_t* status, hipStream_t s);
+void launch_chol_solve(int n, int nrhs, const double* L, const double* rhs, int rhs_stride,
+                       double* out, int out_stride, double* cval, hipStream_t s);
+void launch_sd_full(int n, int ne, int stride, const double* S, const double* D, double* SD,
                     double* cval, hipStream_t s);
 void launch_sync(int ne, double n_psi, double n_r, int one_stage, const double* cval,
                  const double* dots, double* alpha, double* cstar, double* scal, hipStream_t s);

@@ -75,6 +75,41 @@ def test_separated_observations_full_equals_blocks(torch_dev):
     assert np.abs(full - blk).max() < 1e-6 * np.abs(blk).max()
 
 
+def test_full_covariance_follows_moving_observations(torch_dev):
+    """Drifter-like use: the observed cells change between analyses, so the factor and S are
+    rebuilt for the second one; that analysis matches the oracle on the state the first one
+    left."""
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Context
+    _say("full covariance, observed cells moving between two analyses")
+    cfg = W.Config(nx=64, ny=48, dx=1e4, dy=1e4, c_omega=4, n_particles=5, me_std=2e-3)
+    ens, truth = _ensemble_near(cfg, 5, 0.003)
+    cells_a = np.array([[10, 10], [13, 11], [40, 30], [50, 8]], dtype=np.int32)
+    cells_b = np.array([[11, 10], [14, 12], [41, 31], [52, 9], [30, 40]], dtype=np.int32)
+    ctx = Context(cfg, max_obs=8)
+    ctx.set_full_innovation(True)
+    st = torch.from_numpy(np.ascontiguousarray(ens)).to(dev)
+    y_a = oobs.mooring_obs(truth, cells_a, cfg.H, cfg.obs_sigma, np.zeros((4, 2)))
+    ctx.assimilate(st, cells_a, y_a, analysis_index=1)
+    torch.cuda.synchronize()
+    mid = st.cpu().numpy().astype(np.float64)
+    y_b = oobs.mooring_obs(truth, cells_b, cfg.H, cfg.obs_sigma, np.zeros((5, 2)))
+    stats = ctx.assimilate(st, cells_b, y_b, analysis_index=2)
+    torch.cuda.synchronize()
+    sc = ctx.particle_scalars()
+    S = ctx.read_buffer(9, (10, 10), np.float64)
+    got = st.cpu().numpy().astype(np.float64)
+    ctx.close()
+    w = ome.model_error_stencil(cfg)
+    Sref = oiewpf.s_full(cfg, w, cells_b)
+    assert np.abs(S - Sref).max() < 1e-9 * np.abs(Sref).max()
+    ref, info = oiewpf.analysis(mid, cells_b, y_b, cfg, 2, full_innovation=True)
+    _check_scalars(stats, sc, info, cfg.n_psi)
+    for f in range(3):
+        err = np.abs(got[:, f] - ref[:, f]).max() / np.abs(ref[:, f]).max()
+        assert err < TOL, (f, err)
+
+
 def test_full_s_inverse_at_paper_scale(torch_dev):
     """225 buoys on 500x300 (neighbours 20 rows apart overlap): the device S (450x450) times
     the matrix assembled independently from the oracle's translation-invariant pull response
