@@ -519,16 +519,20 @@ __global__ __launch_bounds__(kThreads) void dot_rows_kernel(int n, int stride,
   if (threadIdx.x == 0) cval[blockIdx.x] = v;
 }
 
-__global__ __launch_bounds__(kThreads) void posterior_coarse_kernel(
+// One workgroup per 16 x 16 coarse points of one particle: r at the tile and a 6-point halo
+// (how far a 7x7 block reaches from any of its points) is formed once in LDS, then every
+// point adds the rows of the blocks that contain it (ascending observations).
+constexpr int kPcTile = 16, kPcHalo = 6, kPcW = kPcTile + 2 * kPcHalo;
+__global__ __launch_bounds__(kPcTile * kPcTile) void posterior_coarse_kernel(
     CoarseConst C, const float* __restrict__ xi, const float* __restrict__ nu,
     const double* __restrict__ dots, const double* __restrict__ alpha,
     const double* __restrict__ scal, const float* __restrict__ dmat,
     const int32_t* __restrict__ pt_off, const int32_t* __restrict__ pt_ent,
-    const int32_t* __restrict__ cells, float* __restrict__ rout) {
+    float* __restrict__ rout) {
+  __shared__ double rl[kPcW * kPcW];
   const int nr = C.nrx * C.nry;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  if (p >= nr) return;
+  const int i = blockIdx.z;
+  const int tx0 = blockIdx.x * kPcTile, ty0 = blockIdx.y * kPcTile;
   const double xx = dots[3 * i], nn = dots[3 * i + 1], nxv = dots[3 * i + 2];
   const double a = nxv / xx;
   const double sperp = sqrt(nn / (nn - a * nxv));
@@ -536,30 +540,28 @@ __global__ __launch_bounds__(kThreads) void posterior_coarse_kernel(
   const double sb = sqrt(fmax(beta, 0.0)) * sperp, sa = sqrt(alpha[i]);
   const float* X = xi + (size_t)i * nr;
   const float* N = nu + (size_t)i * nr;
-  auto r_at = [&](int q) -> double {
+  for (int e = threadIdx.x; e < kPcW * kPcW; e += kPcTile * kPcTile) {
+    const int ly = e / kPcW, lx = e - ly * kPcW;
+    const int q = wrapi(ty0 - kPcHalo + ly, C.nry) * C.nrx + wrapi(tx0 - kPcHalo + lx, C.nrx);
     const double xv = X[q], nv = N[q];
-    return sb * (nv - a * xv) + sa * xv;
-  };
-  double acc = r_at(p);
+    rl[e] = sb * (nv - a * xv) + sa * xv;
+  }
+  __syncthreads();
+  const int lx = threadIdx.x % kPcTile, ly = threadIdx.x / kPcTile;
+  const int px = tx0 + lx, py = ty0 + ly;
+  if (px >= C.nrx || py >= C.nry) return;
+  const int p = py * C.nrx + px;
+  const int cl = (ly + kPcHalo) * kPcW + lx + kPcHalo;
+  double acc = rl[cl];
   for (int t = pt_off[p]; t < pt_off[p + 1]; ++t) {
-    const int e = pt_ent[t];
-    const int o = e >> 8, row = e & 255;
-    const int ao = cells[2 * o] / C.c, bo = cells[2 * o + 1] / C.c;
+    const int row = pt_ent[t] & 255;  // this point's position in the block
     const float* drow = dmat + row * kBlockN;
-    int rb[7], ca[7];
-#pragma unroll
-    for (int d = 0; d < 7; ++d) {
-      int y = bo + d - 3, x = ao + d - 3;  // in [-3, n + 3), n >= 7
-      y = y < 0 ? y + C.nry : (y >= C.nry ? y - C.nry : y);
-      x = x < 0 ? x + C.nrx : (x >= C.nrx ? x - C.nrx : x);
-      rb[d] = y * C.nrx;
-      ca[d] = x;
-    }
+    const double* b0 = rl + cl - (row / 7) * kPcW - (row % 7);  // the block's corner
     double s = 0.0;
 #pragma unroll
     for (int dk = 0; dk < 7; ++dk)
 #pragma unroll
-      for (int dj = 0; dj < 7; ++dj) s += (double)drow[dk * 7 + dj] * r_at(rb[dk] + ca[dj]);
+      for (int dj = 0; dj < 7; ++dj) s += (double)drow[dk * 7 + dj] * b0[dk * kPcW + dj];
     acc += s;
   }
   rout[(size_t)i * nr + p] = static_cast<float>(acc);
@@ -765,11 +767,10 @@ void launch_sync(int ne, double n_psi, double n_r, int one_stage, const double* 
 void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,
                              const double* dots, const double* alpha, const double* scal,
                              const float* dmat, const int32_t* pt_off, const int32_t* pt_ent,
-                             const int32_t* cells, float* rout, hipStream_t s) {
-  const int nr = C.nrx * C.nry;
-  hipLaunchKernelGGL(posterior_coarse_kernel, dim3((nr + kThreads - 1) / kThreads, ne),
-                     dim3(kThreads), 0, s, C, xi, nu, dots, alpha, scal, dmat, pt_off, pt_ent,
-                     cells, rout);
+                             float* rout, hipStream_t s) {
+  const dim3 grid((C.nrx + kPcTile - 1) / kPcTile, (C.nry + kPcTile - 1) / kPcTile, ne);
+  hipLaunchKernelGGL(posterior_coarse_kernel, grid, dim3(kPcTile * kPcTile), 0, s, C, xi, nu,
+                     dots, alpha, scal, dmat, pt_off, pt_ent, rout);
 }
 
 void launch_hqht_full(int n_obs, int nx, int ny, int rx, int ry, int wx, int wy, const double* win,

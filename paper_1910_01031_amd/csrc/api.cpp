@@ -319,7 +319,7 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
   {
     TraceScope tr(c, kTrPosterior, s);
     launch_posterior_coarse(c->cc, c->ne, c->xi, c->nu, c->dots, c->alpha, c->scal, c->dmat,
-                            c->pt_off, c->pt_ent, c->obs_cells, c->coarse2, s);
+                            c->pt_off, c->pt_ent, c->coarse2, s);
   }
   {
     TraceScope tr(c, kTrSoar, s);

@@ -280,7 +280,7 @@ void launch_sync(int ne, double n_psi, double n_r, int one_stage, const double* 
 void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,
                              const double* dots, const double* alpha, const double* scal,
                              const float* dmat, const int32_t* pt_off, const int32_t* pt_ent,
-                             const int32_t* cells, float* rout, hipStream_t s);
+                             float* rout, hipStream_t s);
 void launch_observe(int n_obs, int nx, int ny, double H, double sigma, uint64_t seed,
                     uint64_t step, uint32_t ens, const float* truth, const int32_t* cells,
                     double* y, hipStream_t s);
