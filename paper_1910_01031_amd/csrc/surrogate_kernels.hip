@@ -189,6 +189,112 @@ constexpr int tile_lds_bytes() {
   return 2 * ((kTH + 2) * (kTW + 2) * TileGeom<CIN>::CP + NT * 16 * TileGeom<CIN>::WS);
 }
 
+// MFMA part of one tile for output row `wave` of the tile held in LDS: acc = W x inputs.
+template <int CIN, int NT, int kTW>
+__device__ __forceinline__ void tile_mfma(const uint16_t* tile, const uint16_t* wl, int wave,
+                                          int row, int kq, f32x4 (&acc)[NT][kTW / 16]) {
+  using G = TileGeom<CIN>;
+  constexpr int kTM = kTW / 16;
+#pragma unroll
+  for (int q = 0; q < NT; ++q)
+#pragma unroll
+    for (int m = 0; m < kTM; ++m) acc[q][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int kc = 0; kc < G::CHUNKS; ++kc) {
+    const int k = kc * 32 + kq * 8;
+    int tap, c0;
+    if (CIN == 48) {
+      tap = k / 48;
+      c0 = k - tap * 48;
+      if (k >= 9 * 48) {  // padding: zero weights times valid (finite) activations
+        tap = 8;
+        c0 = 0;
+      }
+    } else {
+      tap = k / 8;
+      c0 = 0;
+      if (tap > 8) tap = 8;  // padding taps: zero weights
+    }
+    const int dy = tap / 3, dx = tap - dy * 3;
+    const uint16_t* base = tile + ((wave + dy) * (kTW + 2) + dx + row) * G::CP + c0;
+    bf16x8 afr[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      u32x4 w = u32x4{0u, 0u, 0u, 0u};
+      if (kc * 32 + 32 <= G::KW || k < G::KW)  // the first test is compile-time
+        w = *reinterpret_cast<const u32x4*>(wl + (q * 16 + row) * G::WS + k);
+      afr[q] = __builtin_bit_cast(bf16x8, w);
+    }
+#pragma unroll
+    for (int m = 0; m < kTM; ++m) {
+      const bf16x8 bfr =
+          __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(base + m * 16 * G::CP));
+#pragma unroll
+      for (int q = 0; q < NT; ++q)
+        acc[q][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[q], bfr, acc[q][m], 0, 0, 0);
+    }
+  }
+}
+
+// The bias values of this lane's output channels (16 q + 4 kq .. + 3), loaded once.
+template <int NT>
+__device__ __forceinline__ void lane_bias(const ConvArgs& A, int kq, float (&bias)[NT][4]) {
+#pragma unroll
+  for (int q = 0; q < NT; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int n = NT == 1 ? e : q * 16 + kq * 4 + e;
+      bias[q][e] = (A.bias && n < A.cout) ? A.bias[n] : 0.0f;
+    }
+}
+
+// Epilogue of one tile row: bias, activation / mask / residual, stores.
+template <int NT, int OUT, int kTM>
+__device__ __forceinline__ void tile_store(const ConvArgs& A, const f32x4 (&acc)[NT][kTM],
+                                           const float (&bias)[NT][4], int b, int y, int x0,
+                                           int row, int kq) {
+  // lane: pixel x0 + 16 m + row, channels 16 q + 4 kq .. + 3
+#pragma unroll
+  for (int m = 0; m < kTM; ++m) {
+    const int x = x0 + m * 16 + row;
+    if (x >= A.W) continue;
+    const size_t cell = ((size_t)b * A.H + y) * A.W + x;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int n0 = q * 16 + kq * 4;
+      if (OUT == kOutReluBf16 || OUT == kOutMaskBf16) {
+        uint2 mk = make_uint2(0, 0);
+        if (OUT == kOutMaskBf16) mk = *reinterpret_cast<const uint2*>(A.mask + cell * A.cout + n0);
+        uint32_t h[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float v = acc[q][m][e] + bias[q][e];
+          if (OUT == kOutReluBf16) {
+            h[e] = f2bf(fmaxf(v, 0.0f));
+          } else {
+            const uint32_t word = e < 2 ? mk.x : mk.y;
+            const uint16_t me = (uint16_t)(e & 1 ? word >> 16 : word & 0xFFFFu);
+            h[e] = f2bf(bf2f(me) > 0.0f ? v : 0.0f);
+          }
+        }
+        *reinterpret_cast<uint2*>(static_cast<uint16_t*>(A.out) + cell * A.cout + n0) =
+            make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+      } else if (kq == 0) {  // NT == 1: channels 0..2 of the state
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          const float v = acc[q][m][e] + bias[q][e];
+          if (OUT == kOutF32) {
+            static_cast<float*>(A.out)[cell * 3 + e] = v;
+          } else {  // residual into the state: psi' = psi + s (net)
+            const size_t o = (((size_t)b * 3 + e) * A.H + y) * A.W + x;
+            static_cast<float*>(A.out)[o] = A.state_in[o] + A.s[e] * v;
+          }
+        }
+      }
+    }
+  }
+}
+
 template <int CIN, int NT, int IN, int OUT, int kTH, int kTW>
 __global__ __launch_bounds__(64 * kTH) void conv_tile_kernel(ConvArgs A, int ntiles) {
   constexpr int kTM = kTW / 16;
@@ -221,6 +327,8 @@ __global__ __launch_bounds__(64 * kTH) void conv_tile_kernel(ConvArgs A, int nti
   }
 
   const int xt = (A.W + kTW - 1) / kTW, yt = (A.H + kTH - 1) / kTH;
+  float bias[NT][4];
+  lane_bias<NT>(A, kq, bias);
 
   // registers holding the next tile's input
   constexpr int kVecs = IN == kInStateNorm ? kPix : kPix * G::VPP;
@@ -281,90 +389,10 @@ __global__ __launch_bounds__(64 * kTH) void conv_tile_kernel(ConvArgs A, int nti
     tile_origin<kTH, kTW>(t, xt, yt, b, y0, x0);
     const int y = y0 + wave;
     if (y < A.H) {  // wave-uniform
-    f32x4 acc[NT][kTM];
-#pragma unroll
-    for (int q = 0; q < NT; ++q)
-#pragma unroll
-      for (int m = 0; m < kTM; ++m) acc[q][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int kc = 0; kc < G::CHUNKS; ++kc) {
-      const int k = kc * 32 + kq * 8;
-      int tap, c0;
-      if (CIN == 48) {
-        tap = k / 48;
-        c0 = k - tap * 48;
-        if (k >= 9 * 48) {  // padding: zero weights times valid (finite) activations
-          tap = 8;
-          c0 = 0;
-        }
-      } else {
-        tap = k / 8;
-        c0 = 0;
-        if (tap > 8) tap = 8;  // padding taps: zero weights
-      }
-      const int dy = tap / 3, dx = tap - dy * 3;
-      const uint16_t* base = tile + ((wave + dy) * (kTW + 2) + dx + row) * G::CP + c0;
-      bf16x8 afr[NT];
-#pragma unroll
-      for (int q = 0; q < NT; ++q) {
-        u32x4 w = u32x4{0u, 0u, 0u, 0u};
-        if (kc * 32 + 32 <= G::KW || k < G::KW)  // the first test is compile-time
-          w = *reinterpret_cast<const u32x4*>(wl + (q * 16 + row) * G::WS + k);
-        afr[q] = __builtin_bit_cast(bf16x8, w);
-      }
-#pragma unroll
-      for (int m = 0; m < kTM; ++m) {
-        const bf16x8 bfr =
-            __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(base + m * 16 * G::CP));
-#pragma unroll
-        for (int q = 0; q < NT; ++q)
-          acc[q][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[q], bfr, acc[q][m], 0, 0, 0);
-      }
+      f32x4 acc[NT][kTM];
+      tile_mfma<CIN, NT, kTW>(tile, wl, wave, row, kq, acc);
+      tile_store<NT, OUT, kTM>(A, acc, bias, b, y, x0, row, kq);
     }
-    // lane: pixel x0 + 16 m + row, channels 16 q + 4 kq .. + 3
-#pragma unroll
-    for (int m = 0; m < kTM; ++m) {
-      const int x = x0 + m * 16 + row;
-      if (x >= A.W) continue;
-      const size_t cell = ((size_t)b * A.H + y) * A.W + x;
-#pragma unroll
-      for (int q = 0; q < NT; ++q) {
-        const int n0 = q * 16 + kq * 4;
-        if (OUT == kOutReluBf16 || OUT == kOutMaskBf16) {
-          float4 bn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-          if (A.bias) bn = *reinterpret_cast<const float4*>(A.bias + n0);
-          const float bias[4] = {bn.x, bn.y, bn.z, bn.w};
-          uint2 mk = make_uint2(0, 0);
-          if (OUT == kOutMaskBf16) mk = *reinterpret_cast<const uint2*>(A.mask + cell * A.cout + n0);
-          uint32_t h[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float v = acc[q][m][e] + bias[e];
-            if (OUT == kOutReluBf16) {
-              h[e] = f2bf(fmaxf(v, 0.0f));
-            } else {
-              const uint32_t word = e < 2 ? mk.x : mk.y;
-              const uint16_t me = (uint16_t)(e & 1 ? word >> 16 : word & 0xFFFFu);
-              h[e] = f2bf(bf2f(me) > 0.0f ? v : 0.0f);
-            }
-          }
-          *reinterpret_cast<uint2*>(static_cast<uint16_t*>(A.out) + cell * A.cout + n0) =
-              make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
-        } else if (kq == 0) {  // NT == 1: channels 0..2 of the state
-#pragma unroll
-          for (int e = 0; e < 3; ++e) {
-            const float v = acc[q][m][e] + (A.bias ? A.bias[e] : 0.0f);
-            if (OUT == kOutF32) {
-              static_cast<float*>(A.out)[cell * 3 + e] = v;
-            } else {  // residual into the state: psi' = psi + s (net)
-              const size_t o = (((size_t)b * 3 + e) * A.H + y) * A.W + x;
-              static_cast<float*>(A.out)[o] = A.state_in[o] + A.s[e] * v;
-            }
-          }
-        }
-      }
-    }
-    }  // y < H
   }
 }
 
