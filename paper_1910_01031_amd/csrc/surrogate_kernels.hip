@@ -335,6 +335,58 @@ __global__ __launch_bounds__(64 * kTH) void conv_tile_kernel(ConvArgs A, int nti
   constexpr int kPer = (kVecs + kTThreads - 1) / kTThreads;
   u32x4 pre[IN == kInStateNorm ? 1 : kPer];
   float pf[IN == kInStateNorm ? kPer : 1][3];
+  auto fetch = [&](int tn) {  // tile tn's input -> registers
+    int b, y0, x0;
+    tile_origin<kTH, kTW>(tn, xt, yt, b, y0, x0);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int v = threadIdx.x + i * kTThreads;
+      if (v < kVecs) {
+        if (IN == kInStateNorm) {
+          const int rr = v / (kTW + 2), cc = v - rr * (kTW + 2);
+          const int ys = wrapm(y0 - 1 + rr, A.H), xs = wrapm(x0 - 1 + cc, A.W);
+          const size_t plane = (size_t)A.H * A.W;
+          const float* st = static_cast<const float*>(A.in) + (size_t)b * 3 * plane + (size_t)ys * A.W + xs;
+          pf[i][0] = st[0];
+          pf[i][1] = st[plane];
+          pf[i][2] = st[2 * plane];
+        } else {
+          const int pix = v / G::VPP, cv = v - pix * G::VPP;
+          const int rr = pix / (kTW + 2), cc = pix - rr * (kTW + 2);
+          const int ys = wrapm(y0 - 1 + rr, A.H), xs = wrapm(x0 - 1 + cc, A.W);
+          pre[i] = *reinterpret_cast<const u32x4*>(static_cast<const uint16_t*>(A.in) +
+                                                   (((size_t)b * A.H + ys) * A.W + xs) * CIN + cv * 8);
+        }
+      }
+    }
+  };
+  auto commit = [&](uint16_t* dst) {  // registers -> LDS tile
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int v = threadIdx.x + i * kTThreads;
+      if (v < kVecs) {
+        if (IN == kInStateNorm) {
+          uint32_t h[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) h[c] = f2bf((pf[i][c] - A.mu[c]) * A.isig[c]);
+          *reinterpret_cast<uint4*>(dst + v * G::CP) = make_uint4(h[0] | (h[1] << 16), h[2], 0u, 0u);
+        } else {
+          const int pix = v / G::VPP, cv = v - pix * G::VPP;
+          *reinterpret_cast<u32x4*>(dst + pix * G::CP + cv * 8) = pre[i];
+        }
+      }
+    }
+  };
+  auto compute = [&](const uint16_t* src, int t) {
+    int b, y0, x0;
+    tile_origin<kTH, kTW>(t, xt, yt, b, y0, x0);
+    const int y = y0 + wave;
+    if (y < A.H) {  // wave-uniform
+      f32x4 acc[NT][kTM];
+      tile_mfma<CIN, NT, kTW>(src, wl, wave, row, kq, acc);
+      tile_store<NT, OUT, kTM>(A, acc, bias, b, y, x0, row, kq);
+    }
+  };
 
   // Iteration t: write tile t (fetched in the previous iteration) to LDS, start fetching
   // tile t + gridDim.x, compute tile t.  The first iteration only fetches.
@@ -342,57 +394,11 @@ __global__ __launch_bounds__(64 * kTH) void conv_tile_kernel(ConvArgs A, int nti
     const int tn = t + (int)gridDim.x;
     if (t >= 0) {  // uniform across the workgroup
       __syncthreads();  // weights written / the previous tile's LDS reads are done
-#pragma unroll
-      for (int i = 0; i < kPer; ++i) {
-        const int v = threadIdx.x + i * kTThreads;
-        if (v < kVecs) {
-          if (IN == kInStateNorm) {
-            uint32_t h[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) h[c] = f2bf((pf[i][c] - A.mu[c]) * A.isig[c]);
-            *reinterpret_cast<uint4*>(tile + v * G::CP) = make_uint4(h[0] | (h[1] << 16), h[2], 0u, 0u);
-          } else {
-            const int pix = v / G::VPP, cv = v - pix * G::VPP;
-            *reinterpret_cast<u32x4*>(tile + pix * G::CP + cv * 8) = pre[i];
-          }
-        }
-      }
+      commit(tile);
       __syncthreads();
     }
-    if (tn < ntiles) {  // in flight during the MFMAs below
-      int b, y0, x0;
-      tile_origin<kTH, kTW>(tn, xt, yt, b, y0, x0);
-#pragma unroll
-      for (int i = 0; i < kPer; ++i) {
-        const int v = threadIdx.x + i * kTThreads;
-        if (v < kVecs) {
-          if (IN == kInStateNorm) {
-            const int rr = v / (kTW + 2), cc = v - rr * (kTW + 2);
-            const int ys = wrapm(y0 - 1 + rr, A.H), xs = wrapm(x0 - 1 + cc, A.W);
-            const size_t plane = (size_t)A.H * A.W;
-            const float* st = static_cast<const float*>(A.in) + (size_t)b * 3 * plane + (size_t)ys * A.W + xs;
-            pf[i][0] = st[0];
-            pf[i][1] = st[plane];
-            pf[i][2] = st[2 * plane];
-          } else {
-            const int pix = v / G::VPP, cv = v - pix * G::VPP;
-            const int rr = pix / (kTW + 2), cc = pix - rr * (kTW + 2);
-            const int ys = wrapm(y0 - 1 + rr, A.H), xs = wrapm(x0 - 1 + cc, A.W);
-            pre[i] = *reinterpret_cast<const u32x4*>(static_cast<const uint16_t*>(A.in) +
-                                                     (((size_t)b * A.H + ys) * A.W + xs) * CIN + cv * 8);
-          }
-        }
-      }
-    }
-    if (t < 0) continue;
-    int b, y0, x0;
-    tile_origin<kTH, kTW>(t, xt, yt, b, y0, x0);
-    const int y = y0 + wave;
-    if (y < A.H) {  // wave-uniform
-      f32x4 acc[NT][kTM];
-      tile_mfma<CIN, NT, kTW>(tile, wl, wave, row, kq, acc);
-      tile_store<NT, OUT, kTM>(A, acc, bias, b, y, x0, row, kq);
-    }
+    if (tn < ntiles) fetch(tn);  // in flight during the MFMAs below
+    if (t >= 0) compute(tile, t);
   }
 }
 
