@@ -370,13 +370,17 @@ def main():
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps - 1)]
     e0.record()
-    for c in range(args.warmup, n_cycles - 1):
+    for i, c in enumerate(range(args.warmup, n_cycles - 1)):
         cycle(c)
+        marks[i].record()
     last = cycle(n_cycles - 1, stats=True)
     e1.record()
     torch.cuda.synchronize()
     ms_total = e0.elapsed_time(e1)
+    bounds = [e0] + marks + [e1]
+    per_cycle = sorted(bounds[i].elapsed_time(bounds[i + 1]) for i in range(args.steps))
     ms_per_step = ms_total / args.steps
     work = cfg.n_particles * cfg.nx * cfg.ny * cfg.n_sub * steps_per_cycle
     value = work * args.steps / (ms_total / 1e3)
@@ -415,6 +419,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "cycle_ms": {"min": per_cycle[0], "median": per_cycle[len(per_cycle) // 2],
+                     "max": per_cycle[-1]},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
