@@ -24,15 +24,42 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
-// Fixed-order block sum of one double per thread (blockDim.x == kThreads).
+constexpr int kWavesPerBlock = kThreads / 64;
+
+// Wave reductions by a butterfly of lane exchanges: at every level both partners add (or
+// compare) the same two values, so all lanes end with identical bits.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Fixed-order block sum of one double per thread (blockDim.x == kThreads): wave sums, then
+// the kWavesPerBlock wave sums in wave order.  sh holds at least kWavesPerBlock doubles.
 __device__ double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double r = sh[0];
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWavesPerBlock; ++w) r += sh[w];
+  __syncthreads();  // sh is free again
+  return r;
+}
+
+// Block minimum (exact in any order).
+__device__ double block_min(double v, double* sh) {
+  v = wave_min(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = sh[0];
+#pragma unroll
+  for (int w = 1; w < kWavesPerBlock; ++w) r = fmin(r, sh[w]);
   __syncthreads();
   return r;
 }
@@ -203,9 +230,9 @@ __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, do
                                                         double* __restrict__ alpha,
                                                         double* __restrict__ cstar,
                                                         double* __restrict__ scal) {
-  __shared__ double sh[kThreads];
-  __shared__ double shb[kThreads];
-  __shared__ int shi[kThreads];
+  __shared__ double sh[kWavesPerBlock];
+  __shared__ double shb[kWavesPerBlock];
+  __shared__ int shi[kWavesPerBlock];
   double s = 0.0;
   for (int i = threadIdx.x; i < ne; i += kThreads) s += cval[i];
   const double cmean = block_sum(s, sh) / ne;
@@ -222,24 +249,32 @@ __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, do
       imin = i;
     }
   }
-  shb[threadIdx.x] = bmin;
-  shi[threadIdx.x] = imin;
-  __syncthreads();
-  for (int st = kThreads / 2; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) {
-      const double b2 = shb[threadIdx.x + st];
-      const int i2 = shi[threadIdx.x + st];
-      if (b2 < shb[threadIdx.x] || (b2 == shb[threadIdx.x] && i2 < shi[threadIdx.x])) {
-        shb[threadIdx.x] = b2;
-        shi[threadIdx.x] = i2;
-      }
+  // smallest (b, i) in lexicographic order: exact, the same in every lane
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double b2 = __shfl_xor(bmin, o, 64);
+    const int i2 = __shfl_xor(imin, o, 64);
+    if (b2 < bmin || (b2 == bmin && i2 < imin)) {
+      bmin = b2;
+      imin = i2;
     }
-    __syncthreads();
   }
-  const double beta = one_stage ? 0.0 : shb[0];
-  const double cbar = one_stage ? -shb[0] : cmean;  // the target weight
-  const int argmin = shi[0];
+  if ((threadIdx.x & 63) == 0) {
+    shb[threadIdx.x >> 6] = bmin;
+    shi[threadIdx.x >> 6] = imin;
+  }
   __syncthreads();
+  double bb = shb[0];
+  int ii = shi[0];
+  for (int w = 1; w < kWavesPerBlock; ++w) {
+    if (shb[w] < bb || (shb[w] == bb && shi[w] < ii)) {
+      bb = shb[w];
+      ii = shi[w];
+    }
+  }
+  const double beta = one_stage ? 0.0 : bb;
+  const double cbar = one_stage ? -bb : cmean;  // the target weight
+  const int argmin = ii;
   double amin = 1e300, amax = -1e300, csmax = 0.0, cmin = 1e300, cmax = -1e300;
   for (int i = threadIdx.x; i < ne; i += kThreads) {
     const double gamma = dots[3 * i] * scale;
@@ -255,18 +290,10 @@ __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, do
     cmax = fmax(cmax, cval[i]);
   }
   // min / max reductions (order independent)
-  double vals[5] = {amin, -amax, -csmax, cmin, -cmax};
+  const double vals[5] = {amin, -amax, -csmax, cmin, -cmax};
   double outv[5];
-  for (int q = 0; q < 5; ++q) {
-    sh[threadIdx.x] = vals[q];
-    __syncthreads();
-    for (int st = kThreads / 2; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + st]);
-      __syncthreads();
-    }
-    outv[q] = sh[0];
-    __syncthreads();
-  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) outv[q] = block_min(vals[q], sh);
   if (threadIdx.x == 0) {
     scal[0] = cbar;
     scal[1] = beta;

@@ -254,6 +254,31 @@ def test_training_reduces_loss():
     ctx.close()
 
 
+def test_trained_network_beats_persistence_on_held_out_windows():
+    """What the learned part adds: after training on windows the solver generates, the
+    network's 5-minute forecast of held-out states (another ensemble stream) is much closer
+    to the solver's than keeping the state unchanged (persistence)."""
+    _need_gpu()
+    from paper_1910_01031_amd import Net
+    from paper_1910_01031_amd import surrogate as sur
+    cfg = wl.tiny().replace(dx=5e3, dy=5e3, n_sub=2, init_std=0.3)
+    base = wl.jet_state(cfg)
+    train = sur.make_pairs(torch, cfg, 1024, base, group=128, spinup_steps=6, windows_per_group=4,
+                           stream_base=300)
+    held = sur.make_pairs(torch, cfg, 256, base, group=128, spinup_steps=6, windows_per_group=2,
+                          stream_base=900)
+    net = Net(64 * cfg.n_cells)
+    net.set_params(sur.init_params(5))
+    sur.train(net, train, n_steps=400, batch=32, lr=2e-3, lr_final=2e-4, seed=5)
+    rmse, persist = sur.evaluate(torch, net, held, batch=64)
+    print("held-out RMSE (eta, hu, hv)", rmse, "persistence", persist, flush=True)
+    assert np.all(np.isfinite(rmse))
+    # the momenta change most over the window; eta only has to stay near persistence
+    assert np.all(rmse[1:] < 0.5 * persist[1:]), (rmse, persist)
+    assert rmse[0] < 1.5 * persist[0], (rmse, persist)
+    net.close()
+
+
 def _window_setup(n_particles=6):
     from paper_1910_01031_amd import Context, Net
     cfg = wl.tiny().replace(dx=5e3, dy=5e3, n_sub=2, n_particles=n_particles, init_std=0.3)
