@@ -110,15 +110,16 @@ def test_full_covariance_follows_moving_observations(torch_dev):
         assert err < TOL, (f, err)
 
 
-def test_full_s_inverse_at_paper_scale(torch_dev):
-    """225 buoys on 500x300 (neighbours 20 rows apart overlap): the device S (450x450) times
-    the matrix assembled independently from the oracle's translation-invariant pull response
-    is the identity."""
+@pytest.mark.parametrize("bx,by", [(15, 15), (20, 15)])
+def test_full_s_inverse_at_paper_scale(torch_dev, bx, by):
+    """225 (300) buoys on 500x300 (neighbours 20 rows apart overlap): the device S (450x450;
+    600x600 takes the 16-slot solve) times the matrix assembled independently from the
+    oracle's translation-invariant pull response is the identity."""
     torch, dev = torch_dev
     from paper_1910_01031_amd import Context
-    _say("full S at paper scale (225 buoys)")
+    _say(f"full S at paper scale ({bx * by} buoys)")
     cfg = W.paper_scale(2)
-    cells = W.buoy_cells(cfg.nx, cfg.ny, 15, 15)
+    cells = W.buoy_cells(cfg.nx, cfg.ny, bx, by)
     ctx = Context(cfg, max_obs=len(cells))
     ctx.set_full_innovation(True)
     st = torch.from_numpy(W.as_f32(np.stack([W.jet_state(cfg)] * 2))).to(dev)
