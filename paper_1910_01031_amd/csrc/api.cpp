@@ -36,6 +36,12 @@ struct iewpf_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_steps = -1;
+  // side streams (default priority) for the per-ensemble work that does not depend on the
+  // other ensembles (model-error fields, analyses): forked from and joined back into the
+  // cycle's stream, so in a captured graph they become parallel branches
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> fork_ev;  // one per fork point
+  std::vector<hipEvent_t> join_ev;  // one per side stream and fork point
 };
 
 namespace iewpf {
@@ -374,6 +380,33 @@ int model_steps(iewpf_ctx* c, float* state, int n_steps, uint64_t first_step, in
   return 0;
 }
 
+// Runs body(e, stream) for every ensemble e, spread over the batch's side streams after
+// everything already on s, and makes s wait for all of them.  `point` numbers the fork so
+// that every fork of one cycle has its own events.
+template <class F>
+int batch_fork(iewpf_batch* b, int point, hipStream_t s, F&& body) {
+  const int k = (int)b->side.size();
+  while ((int)b->fork_ev.size() <= point) {
+    hipEvent_t ev;
+    IEWPF_HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    b->fork_ev.push_back(ev);
+    for (int i = 0; i < k; ++i) {
+      IEWPF_HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      b->join_ev.push_back(ev);
+    }
+  }
+  IEWPF_HIP_TRY(hipEventRecord(b->fork_ev[point], s));
+  for (int i = 0; i < k; ++i) IEWPF_HIP_TRY(hipStreamWaitEvent(b->side[i], b->fork_ev[point], 0));
+  for (int e = 0; e < b->n; ++e)
+    if (int rc = body(e, b->side[e % k])) return rc;
+  for (int i = 0; i < k; ++i) {
+    hipEvent_t j = b->join_ev[(size_t)point * k + i];
+    IEWPF_HIP_TRY(hipEventRecord(j, b->side[i]));
+    IEWPF_HIP_TRY(hipStreamWaitEvent(s, j, 0));
+  }
+  return 0;
+}
+
 // Model steps of every ensemble of a batch; dyn != nullptr reads the first step index
 // from dyn[0] (the kernels then see step offsets only).
 int batch_model_steps(iewpf_batch* b, int n_steps, uint64_t first_step, const uint64_t* dyn,
@@ -382,12 +415,14 @@ int batch_model_steps(iewpf_batch* b, int n_steps, uint64_t first_step, const ui
   for (int st = 0; st < n_steps; ++st) {
     const bool noise = st < n_steps - 1;
     if (noise) {
-      for (int e = 0; e < b->n; ++e) {
+      const int rc = batch_fork(b, st, s, [&](int e, hipStream_t es) {
         iewpf_ctx* c = b->ctx[e];
         launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, (dyn ? 0 : first_step) + st,
-                       kTagModelError, c->cfg.ensemble_id, s, dyn);
-        launch_soar(c->cc, c->soar_me_f, c->ne, c->xi, c->coarse, s);
-      }
+                       kTagModelError, c->cfg.ensemble_id, es, dyn);
+        launch_soar(c->cc, c->soar_me_f, c->ne, c->xi, c->coarse, es);
+        return 0;
+      });
+      if (rc) return rc;
     }
     for (int sub = 0; sub < b->n_sub; ++sub) {
       const bool fuse = noise && sub == b->n_sub - 1;
@@ -407,10 +442,9 @@ int batch_model_steps(iewpf_batch* b, int n_steps, uint64_t first_step, const ui
 int batch_cycle_body(iewpf_batch* b, int n_steps, uint64_t first_step, uint64_t analysis_index,
                      const uint64_t* dyn, hipStream_t s) {
   if (int rc = batch_model_steps(b, n_steps, first_step, dyn, s)) return rc;
-  for (int e = 0; e < b->n; ++e)
-    if (int rc = launch_analysis(b->ctx[e], b->state[e], b->n_obs[e], dyn ? 0 : analysis_index, dyn, s))
-      return rc;
-  return 0;
+  return batch_fork(b, n_steps, s, [&](int e, hipStream_t es) {
+    return launch_analysis(b->ctx[e], b->state[e], b->n_obs[e], dyn ? 0 : analysis_index, dyn, es);
+  });
 }
 
 void free_batch(iewpf_batch* b) {
@@ -426,6 +460,9 @@ void free_batch(iewpf_batch* b) {
   if (b->in_ev) (void)hipEventDestroy(b->in_ev);
   if (b->out_ev) (void)hipEventDestroy(b->out_ev);
   if (b->gs) (void)hipStreamDestroy(b->gs);
+  for (hipStream_t x : b->side) (void)hipStreamDestroy(x);
+  for (hipEvent_t x : b->fork_ev) (void)hipEventDestroy(x);
+  for (hipEvent_t x : b->join_ev) (void)hipEventDestroy(x);
   delete b;
 }
 
@@ -944,6 +981,14 @@ int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewp
             hipEventCreateWithFlags(&b->in_ev, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&b->out_ev, hipEventDisableTiming) == hipSuccess &&
             hipStreamCreateWithFlags(&b->gs, hipStreamNonBlocking) == hipSuccess &&
+            [&] {
+              for (int i = 0; i < std::min(n, 4); ++i) {
+                hipStream_t x = nullptr;
+                if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) return false;
+                b->side.push_back(x);
+              }
+              return true;
+            }() &&
             hipMemcpy(b->tab_plain, &plain, sizeof(SweJobTable), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(b->tab_noise, &noise, sizeof(SweJobTable), hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) {
