@@ -381,9 +381,20 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
   step(k0 + 1, Full{}, Store{}, false);
   step(k0 + 2, Full{}, NoFlux{}, false);
   step(k0 + 3, Full{}, FluxOnly{}, false);
-  // four rows per trip (the period of the row rotation), so the pipeline registers are
-  // renamed instead of moved
+  // eight rows per trip (a multiple of the period of the row rotation, so the pipeline
+  // registers are renamed instead of moved; the loop head's waits for loads in flight come
+  // once per eight rows), then four, then single rows
   int m = k0 + 4;
+  for (; m + 7 <= k_end + 3; m += 8) {
+    step(m, Full{}, Full{}, true);
+    step(m + 1, Full{}, Full{}, true);
+    step(m + 2, Full{}, Full{}, true);
+    step(m + 3, Full{}, Full{}, true);
+    step(m + 4, Full{}, Full{}, true);
+    step(m + 5, Full{}, Full{}, true);
+    step(m + 6, Full{}, Full{}, true);
+    step(m + 7, Full{}, Full{}, true);
+  }
   for (; m + 3 <= k_end + 3; m += 4) {
     step(m, Full{}, Full{}, true);
     step(m + 1, Full{}, Full{}, true);
