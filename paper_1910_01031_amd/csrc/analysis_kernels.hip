@@ -713,7 +713,7 @@ __global__ void drift_k2_kernel(int ne, int nd, int nx, int ny, double dx, doubl
 // are integer and sequential over at most a few thousand particles.
 __global__ void resample_kernel(int ne, uint64_t seed, uint64_t step, uint32_t ens,
                                 const double* __restrict__ logw, int32_t* __restrict__ parents,
-                                int32_t* __restrict__ counts) {
+                                int32_t* __restrict__ counts, double* __restrict__ cum) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   double m = logw[0];
   for (int i = 1; i < ne; ++i) m = fmax(m, logw[i]);
@@ -723,32 +723,34 @@ __global__ void resample_kernel(int ne, uint64_t seed, uint64_t step, uint32_t e
     for (int i = 0; i < ne; ++i) parents[i] = i;
     return;
   }
+  // copies floor(N w_i); cum[i] = residuals r_0 + ... + r_i, summed left to right
   int used = 0;
-  double total = 0.0;
+  double total = 0.0, acc = 0.0;
   for (int i = 0; i < ne; ++i) {
     const double x = (double)ne * exp(logw[i] - m) / s;
     const double n = (x >= 0.0 && x <= (double)ne) ? floor(x) : 0.0;
     counts[i] = (int)n;
     used += (int)n;
     total += (x >= 0.0 && x <= (double)ne) ? x - n : 0.0;
+    acc += x - floor(x);
+    cum[i] = acc;
   }
+  // residual draws by inverse CDF: the first i with target < cum[i] (cum is non-decreasing)
   const int n_res = used <= ne ? ne - used : 0;
   for (int kdraw = 0; kdraw < n_res; ++kdraw) {
     const U64x4 w = philox4x64_10((uint64_t)(kdraw / 4), step, stream_word(6u, ens), 0, seed, 0);
     const uint64_t words[4] = {w.x0, w.x1, w.x2, w.x3};
     const double u = (double)(words[kdraw % 4] >> 11) * 0x1.0p-53;
     const double target = u * total;
-    int pick = ne - 1;
-    double acc = 0.0;
-    for (int i = 0; i < ne; ++i) {
-      const double x = (double)ne * exp(logw[i] - m) / s;
-      acc += x - floor(x);
-      if (target < acc) {
-        pick = i;
-        break;
-      }
+    int lo = 0, hi = ne;  // search [lo, hi)
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (target < cum[mid])
+        hi = mid;
+      else
+        lo = mid + 1;
     }
-    counts[pick] += 1;
+    counts[lo < ne ? lo : ne - 1] += 1;
   }
   int t = 0;
   for (int i = 0; i < ne; ++i)
@@ -884,9 +886,9 @@ void launch_gather_particles(int ne, size_t per_particle, const int32_t* parents
 }
 
 void launch_resample(int ne, uint64_t seed, uint64_t step, uint32_t ens, const double* logw,
-                     int32_t* parents, int32_t* counts, hipStream_t s) {
+                     int32_t* parents, int32_t* counts, double* cum, hipStream_t s) {
   hipLaunchKernelGGL(resample_kernel, dim3(1), dim3(64), 0, s, ne, seed, step, ens, logw, parents,
-                     counts);
+                     counts, cum);
 }
 
 }  // namespace iewpf

@@ -113,7 +113,7 @@ void free_ctx(iewpf_ctx* c) {
                   c->coarse, c->coarse2, c->windows,
                   c->dmat,    c->sd,     c->cval,   c->dots,   c->alpha,   c->cstar,
                   c->scal,    c->obs_cells, c->obs_y, c->pt_off, c->pt_ent, c->st_off,
-                  c->st_ent,  c->dk1,    c->dpstar, c->dobs,   c->cflmax,  c->dparents};
+                  c->st_ent,  c->dk1,    c->dpstar, c->dobs,   c->cflmax,  c->dparents, c->dcum};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
@@ -647,6 +647,7 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   rc |= dev_alloc(&c->dobs, (size_t)c->max_obs * 2);
   rc |= dev_alloc(&c->cflmax, 2);
   rc |= dev_alloc(&c->dparents, (size_t)c->ne);
+  rc |= dev_alloc(&c->dcum, (size_t)c->ne);
   if (rc) {
     free_ctx(c);
     return IEWPF_E_HIP;
@@ -880,7 +881,7 @@ int iewpf_resample(iewpf_ctx* c, float* state, const double* logw, uint64_t anal
   if (!c || !state || !logw || !parents) return fail(IEWPF_E_ARG, "NULL argument");
   hipStream_t s = as_stream(stream);
   launch_resample(c->ne, c->cfg.seed, analysis_index, c->cfg.ensemble_id, logw, parents,
-                  c->dparents, s);
+                  c->dparents, c->dcum, s);
   const size_t per = 3 * c->ncell;
   if (per % 4 == 0) {
     launch_gather_particles(c->ne, per, parents, state, c->scratch, s);

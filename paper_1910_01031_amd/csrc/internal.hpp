@@ -134,7 +134,8 @@ struct iewpf_ctx {
   double* dpstar = nullptr;      // drifter p*  [ne][max_obs][2]
   double* dobs = nullptr;        // observation synthesis output [max_obs][2]
   unsigned* cflmax = nullptr;    // 2 words
-  int32_t* dparents = nullptr;   // resampling scratch [ne]
+  int32_t* dparents = nullptr;  // resampling scratch [ne]
+  double* dcum = nullptr;       // resampling: cumulative residuals [ne]
   // pinned host staging
   unsigned char* h_stage = nullptr;
   size_t stage_bytes = 0;
@@ -294,7 +295,7 @@ void launch_drift_k2(int ne, int nd, int nx, int ny, double dx, double dy, doubl
                      const float* psi, double* pos, const double* k1, const double* pstar,
                      double* traj, hipStream_t s, const float* psi_b = nullptr, double w = 0.0);
 void launch_resample(int ne, uint64_t seed, uint64_t step, uint32_t ens, const double* logw,
-                     int32_t* parents, int32_t* counts, hipStream_t s);
+                     int32_t* parents, int32_t* counts, double* cum, hipStream_t s);
 void launch_gather_particles(int ne, size_t per_particle, const int32_t* parents, const float* in,
                              float* out, hipStream_t s);
 }  // namespace iewpf
