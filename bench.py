@@ -57,6 +57,35 @@ def _kernel_source_hash():
     return h.hexdigest()
 
 
+def gpu_state(torch):
+    """Clock, power and temperature of cuda:0 from the driver's metrics table (amdsmi).
+
+    The device is matched by PCI domain and bus.  Fields the table leaves out are null; any
+    failure is reported as {"error": ...} and never stops the benchmark.
+    """
+    try:
+        import amdsmi
+    except ImportError as e:
+        return {"error": f"amdsmi not importable: {e}"}
+    keep = ("current_gfxclk", "average_gfxclk_frequency", "current_uclk", "current_socket_power",
+            "average_socket_power", "temperature_hotspot", "temperature_mem")
+    try:
+        amdsmi.amdsmi_init()
+        try:
+            prop = torch.cuda.get_device_properties(0)
+            want = (prop.pci_domain_id, prop.pci_bus_id)
+            for h in amdsmi.amdsmi_get_processor_handles():
+                dom, bus = amdsmi.amdsmi_get_gpu_device_bdf(h).split(":")[:2]
+                if (int(dom, 16), int(bus, 16)) == want:
+                    m = amdsmi.amdsmi_get_gpu_metrics_info(h)
+                    return {k: m.get(k) for k in keep}
+            return {"error": "no amdsmi device on the PCI bus of cuda:0"}
+        finally:
+            amdsmi.amdsmi_shut_down()
+    except Exception as e:  # noqa: BLE001 - reported, not raised
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,6 +394,7 @@ def main():
     for c in range(args.warmup):
         cycle(c)
     torch.cuda.synchronize()
+    state_idle = gpu_state(torch)
 
     # timed region: K whole cycles
     e0 = torch.cuda.Event(enable_timing=True)
@@ -387,9 +417,16 @@ def main():
     finite = bool(torch.isfinite(ens).all().item())
 
     # per-kernel durations: the same cycles again with an event pair around every launch
+    # (the clock and power state is read half-way, outside the timed region)
     ctx.set_trace(True)
+    mid = torch.cuda.Event()
+    state_during, busy = None, None
     for c in range(args.warmup, n_cycles):
         cycle(c)
+        if c == args.warmup + args.steps // 2:
+            mid.record()
+            busy = not mid.query()
+            state_during = gpu_state(torch)
     torch.cuda.synchronize()
     tr = ctx.trace_read()
     ctx.set_trace(False)
@@ -435,6 +472,8 @@ def main():
                                 "alpha_min": last["alpha_min"], "alpha_max": last["alpha_max"]},
         "state_finite": finite,
         "kernel_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in tr.items()},
+        "gpu_state": {"before_timed_region": state_idle, "during_same_cycles_traced": state_during,
+                      "gpu_busy_when_read": busy},
         "roofline": {"bound": "alu", "kernel": "swe_substep_kernel<false> (scheme step)",
                      "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,

@@ -93,7 +93,8 @@ typedef struct {
 } iewpf_stats;
 
 /* Create a context: validates the config (c_omega <= 16, nx, ny divisible by c_omega, >= 7
- * coarse points per direction, obs/drifter capacity), computes in float64 on the host the SOAR stencils,
+ * coarse points per direction, nx ny < 178,956,970 cells per particle, obs/drifter
+ * capacity; IEWPF_E_SHAPE for the grid limits), computes in float64 on the host the SOAR stencils,
  * the pull windows Q^{1/2} Q^{1/2,T} H^T e_b (eq. detailedOPDUpdate), S = (H Q H^T + R)^-1
  * by Cholesky (eq. S_extended), the local 49x49 A^{1/2} (eq. svdOfParenthesis), uploads
  * them and allocates the workspaces (one state-sized scratch buffer + coarse fields).

@@ -523,6 +523,8 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
     return fail(IEWPF_E_SHAPE, "nx and ny must be divisible by c_omega");
   if (f.nx / f.c_omega < 7 || f.ny / f.c_omega < 7)
     return fail(IEWPF_E_SHAPE, "the coarse grid needs at least 7 points per direction");
+  if (12.0 * f.nx * f.ny >= 2147483648.0)  // the scheme kernel addresses a particle's state in 31-bit bytes
+    return fail(IEWPF_E_SHAPE, "nx ny above 178,956,970 cells per particle is not supported");
   iewpf_ctx* c = new iewpf_ctx();
   c->cfg = f;
   c->nx = f.nx;
@@ -1100,11 +1102,10 @@ int iewpf_surrogate_window(iewpf_ctx* c, iewpf_net* net, float* state, int n_mod
     return fail(IEWPF_E_ARG, "invalid argument");
   hipStream_t s = as_stream(stream);
   const size_t per = 3 * c->ncell;
-  if (!c->saved) {
-    IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->saved), sizeof(float) * per * c->ne));
-    IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->sdrift), sizeof(double) * c->ne));
-    IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->sflags), sizeof(int32_t) * c->ne));
-  }
+  // each buffer on its own, so a call after a failed allocation retries what is missing
+  if (!c->saved) IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->saved), sizeof(float) * per * c->ne));
+  if (!c->sdrift) IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->sdrift), sizeof(double) * c->ne));
+  if (!c->sflags) IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->sflags), sizeof(int32_t) * c->ne));
   IEWPF_HIP_TRY(hipMemcpyAsync(c->saved, state, sizeof(float) * per * c->ne, hipMemcpyDeviceToDevice, s));
   // the network runs on as many particles at a time as its workspaces hold
   const int chunk = net_max_cells(net) / (int)std::min<size_t>(c->ncell, (size_t)INT32_MAX);

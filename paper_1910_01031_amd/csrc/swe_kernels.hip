@@ -190,6 +190,25 @@ __device__ __forceinline__ int wrap(int i, int n) {
 // i in [-n, 2n)
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// One particle's [3][ny][nx] state as a raw buffer: every load and store takes a wave-uniform
+// byte offset (field and row, an SGPR) and this lane's column byte offset (one VGPR for all
+// rows and fields), so no per-access address arithmetic runs on the vector ALU.  Word 3 is
+// the gfx9-family raw-buffer format (32-bit data, no swizzle); accesses past the
+// 12 nx ny bytes of the particle read zero and write nothing.
+constexpr int kRawBufferWord3 = 0x00020000;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const float* base, size_t ncell) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), static_cast<short>(0),
+                                           static_cast<int>(12 * ncell), kRawBufferWord3);
+}
+__device__ __forceinline__ float ld_buf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(voff),
+                                                              static_cast<int>(soff), 0));
+}
+__device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, static_cast<int>(voff),
+                                        static_cast<int>(soff), 0);
+}
+
 __device__ __forceinline__ void cr_weights(float t, float w[4]) {
   const float t2 = t * t, t3 = t2 * t;
   w[0] = 0.5f * (-t3 + 2.0f * t2 - t);
@@ -281,16 +300,17 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
   const int sx = rem - sy * C.n_strip_x;
   const int nx = C.nx, ny = C.ny;
   const size_t ncell = (size_t)nx * ny;
-  const float* Ein = in + (size_t)particle * 3 * ncell;
-  const float* Qin = Ein + ncell;
-  const float* Rin = Qin + ncell;
-  float* Eout = out + (size_t)particle * 3 * ncell;
-  float* Qout = Eout + ncell;
-  float* Rout = Qout + ncell;
+  // byte offsets below 12 nx ny < 2^31 (checked when the context is created)
+  const __amdgpu_buffer_rsrc_t bin = state_rsrc(in + (size_t)particle * 3 * ncell, ncell);
+  const __amdgpu_buffer_rsrc_t bout = state_rsrc(out + (size_t)particle * 3 * ncell, ncell);
+  const unsigned fq = 4u * static_cast<unsigned>(ncell), fr = 2u * fq;  // field byte offsets
+  const unsigned brow = 4u * static_cast<unsigned>(nx);                  // row stride in bytes
 
   const int j = sx * kSweOut + lane - kSweHalo;  // unwrapped column
   const int jw = wrap(j, nx);
   const bool writer = lane >= kSweHalo && lane < kWave - kSweHalo && j < nx;
+  const unsigned bjw = 4u * static_cast<unsigned>(jw);  // byte offset of the lane's column
+  const unsigned bj = 4u * static_cast<unsigned>(j);    // (writers only: 0 <= j < nx)
   const int k0 = sy * C.strip_h;
   const int k_end = min(k0 + C.strip_h, ny);  // exclusive
 
@@ -312,10 +332,10 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
   float ne_[kPf], nq_[kPf], nr_[kPf];
 #pragma unroll
   for (int i = 0; i < kPf; ++i) {
-    const size_t off = (size_t)wrap(k0 - 4 + i, ny) * nx + jw;
-    ne_[i] = Ein[off];
-    nq_[i] = Qin[off];
-    nr_[i] = Rin[off];
+    const unsigned off = static_cast<unsigned>(wrap(k0 - 4 + i, ny)) * brow;
+    ne_[i] = ld_buf(bin, bjw, off);
+    nq_[i] = ld_buf(bin, bjw, off + fq);
+    nr_[i] = ld_buf(bin, bjw, off + fr);
   }
 
   // Rows m = k0-4 .. k0-1: stage 1 only; k0 .. k0+3: both stages, no output yet;
@@ -332,10 +352,10 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
       nr_[i] = nr_[i + 1];
     }
     // m + kPf < ny + 3 + kPf < 3 ny (ny >= 7): two conditional wraps suffice
-    const size_t o2 = (size_t)wrap1(wrap1(m + kPf, ny), ny) * nx + jw;
-    ne_[kPf - 1] = Ein[o2];
-    nq_[kPf - 1] = Qin[o2];
-    nr_[kPf - 1] = Rin[o2];
+    const unsigned o2 = static_cast<unsigned>(wrap1(wrap1(m + kPf, ny), ny)) * brow;
+    ne_[kPf - 1] = ld_buf(bin, bjw, o2);
+    nq_[kPf - 1] = ld_buf(bin, bjw, o2 + fq);
+    nr_[kPf - 1] = ld_buf(bin, bjw, o2 + fr);
     float se, sq, sr;
     s1.template push<M1>(e, q, r, C, se, sq, sr);  // psi* of row m - 2
     const float qe4 = pe4, qq4 = pq4, qr4 = pr4;
@@ -356,10 +376,10 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
           orr += C.gb_x * (lane_next(dB) - lane_prev(dB));
         }
         if (writer) {
-          const size_t o = (size_t)(m - 4) * nx + j;
-          Eout[o] = oe;
-          Qout[o] = oq;
-          Rout[o] = orr;
+          const unsigned o = static_cast<unsigned>(m - 4) * brow;
+          st_buf(bout, bj, o, oe);
+          st_buf(bout, bj, o + fq, oq);
+          st_buf(bout, bj, o + fr, orr);
         }
       }
     }
