@@ -48,10 +48,11 @@ MEASURED_TRAFFIC = {"bytes": 2 * 147830.5 * 1024 + 180085.4 * 1024,
 
 
 def _kernel_source_hash():
-    """SHA-256 over the scheme kernel's source, its header and the build flags."""
+    """SHA-256 over the scheme kernel's source, its headers and the build flags."""
     import hashlib
     h = hashlib.sha256()
-    for rel in (("csrc", "swe_kernels.hip"), ("csrc", "internal.hpp"), ("build.py",)):
+    for rel in (("csrc", "swe_kernels.hip"), ("csrc", "internal.hpp"), ("csrc", "buffer_dev.hpp"),
+                ("build.py",)):
         with open(os.path.join(ROOT, "paper_1910_01031_amd", *rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()

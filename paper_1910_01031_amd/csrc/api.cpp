@@ -597,6 +597,10 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   c->ry = W > f.ny ? -1 : r;
   c->wx = W > f.nx ? f.nx : W;
   c->wy = W > f.ny ? f.ny : W;
+  if (24.0 * c->wx * c->wy >= 2147483648.0) {  // the update kernel reads the windows in 31-bit bytes
+    free_ctx(c);
+    return fail(IEWPF_E_SHAPE, "pull windows above 2^31 bytes are not supported");
+  }
   std::vector<double> win((size_t)6 * c->wx * c->wy);
   build_pull_windows(*c, win.data(), c->Mfine);
   const double s2 = f.obs_sigma * f.obs_sigma;

@@ -7,6 +7,7 @@
 // output element per work-item, perturbation never stored), Section "Optimal proposal
 // particles" (pull chain, eq. detailedOPDUpdate) and "Posterior particle states"
 // (eq. optUpdateEquationTwoStage).
+#include "buffer_dev.hpp"
 #include "internal.hpp"
 #include "philox_dev.hpp"
 
@@ -291,6 +292,19 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
   const int j = sx * kGbOut + lane - kGbHalo;
   const int jw = wrapi(j, nx);
   const bool writer = lane >= kGbHalo && lane < kWave - kGbHalo && j < nx;
+  // State and windows as raw buffers (byte offsets < 2^31, checked when the context is
+  // created): state rows by a scalar offset and one lane offset, which switches the lanes
+  // that write nothing off (reads zero, writes dropped); a group's missing particles get
+  // an empty buffer.
+  const unsigned bj = writer ? 4u * static_cast<unsigned>(j) : kBufferOff;
+  const unsigned brow = 4u * static_cast<unsigned>(nx);
+  const unsigned fq = 4u * static_cast<unsigned>(ncell), fr = 2u * fq;
+  __amdgpu_buffer_rsrc_t bs[kPB];
+#pragma unroll
+  for (int p = 0; p < kPB; ++p)
+    bs[p] = make_rsrc(psi + (size_t)min(p0 + p, ne - 1) * 3 * ncell, p < np ? 12 * ncell : 0);
+  const __amdgpu_buffer_rsrc_t bw = make_rsrc(windows, 24 * plane);
+  const unsigned plane_b = 4u * static_cast<unsigned>(plane);
   int cx[4];
   float wx[4];
   {
@@ -303,10 +317,11 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
   const int k0 = sy * P.strip_h;
   const int k_end = min(k0 + P.strip_h, ny);
   const int o_beg = st_off[strip], o_end = st_off[strip + 1];
-  // The strip's observation list, one entry per lane (first 64 entries): cell and S d of
-  // each particle of the group, so the row loop reads them with lane broadcasts instead of
-  // dependent global loads.
-  int l_jo = 0, l_ko = 0;
+  // The strip's observation list, one entry per lane (first 64 entries): the first column
+  // and row of each observation's window on the torus (the observed cell minus the
+  // radius; the cell itself for a window folded onto the whole period) and S d of each
+  // particle of the group, so the row loop reads them with lane broadcasts.
+  int l_js = 0, l_ks = 0;
   float l_su[kPB], l_sv[kPB];
   {
     const int t = o_beg + lane;
@@ -314,8 +329,10 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
 #pragma unroll
     for (int p = 0; p < kPB; ++p) l_su[p] = l_sv[p] = 0.0f;
     if (o >= 0) {
-      l_jo = cells[2 * o];
-      l_ko = cells[2 * o + 1];
+      l_js = cells[2 * o] - (P.rx >= 0 ? P.rx : 0);  // radius < nx / 2
+      l_js += l_js < 0 ? nx : 0;
+      l_ks = cells[2 * o + 1] - (P.ry >= 0 ? P.ry : 0);
+      l_ks += l_ks < 0 ? ny : 0;
 #pragma unroll
       for (int p = 0; p < kPB; ++p) {
         if (p < np) {
@@ -342,16 +359,12 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
       const int k = m - 1;
       float ae[kPB], au[kPB], av[kPB];
       float se[kPB], su_[kPB], sv_[kPB];  // state values, loaded before the observation loop
-      const size_t off = (size_t)k * nx + j;
+      const unsigned srow = static_cast<unsigned>(k) * brow;
 #pragma unroll
       for (int p = 0; p < kPB; ++p) {
-        se[p] = su_[p] = sv_[p] = 0.0f;
-        if (writer && p < np) {
-          const float* E = psi + (size_t)(p0 + p) * 3 * ncell;
-          se[p] = E[off];
-          su_[p] = E[ncell + off];
-          sv_[p] = E[2 * ncell + off];
-        }
+        se[p] = ld_buf(bs[p], bj, srow);
+        su_[p] = ld_buf(bs[p], bj, srow + fq);
+        sv_[p] = ld_buf(bs[p], bj, srow + fr);
       }
 #pragma unroll
       for (int p = 0; p < kPB; ++p) {
@@ -367,14 +380,20 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
         float su[kObsBatch][kPB], sv[kObsBatch][kPB];
 #pragma unroll
         for (int u = 0; u < kObsBatch; ++u) {
-          const int q = q0 + u < n_lane ? q0 + u : n_lane - 1;  // wave-uniform
-          const int jo = __builtin_amdgcn_readlane(l_jo, q);
-          const int ko = __builtin_amdgcn_readlane(l_ko, q);
-          int ix, iy;
-          const bool in = q0 + u < n_lane && window_offset(P, nx, ny, j, k, jo, ko, ix, iy);
-          const size_t idx = (size_t)iy * P.wx + ix;
+          const bool valid = q0 + u < n_lane;  // wave-uniform
+          const int q = valid ? q0 + u : n_lane - 1;
+          const int js = __builtin_amdgcn_readlane(l_js, q);
+          const int ks = __builtin_amdgcn_readlane(l_ks, q);
+          // window offset on the torus: 0 <= k, ks < ny and 0 <= jw, js < nx
+          int iy = k - ks;  // wave-uniform
+          iy += iy < 0 ? ny : 0;
+          int ix = jw - js;
+          ix += ix < 0 ? nx : 0;
+          const bool in_y = valid && iy < P.wy;
+          const unsigned voff = in_y && ix < P.wx ? 4u * static_cast<unsigned>(ix) : kBufferOff;
+          const unsigned soff = in_y ? 4u * static_cast<unsigned>(iy * P.wx) : 0u;
 #pragma unroll
-          for (int f = 0; f < 6; ++f) w[u][f] = in ? windows[f * plane + idx] : 0.0f;
+          for (int f = 0; f < 6; ++f) w[u][f] = ld_buf(bw, voff, soff + f * plane_b);
 #pragma unroll
           for (int p = 0; p < kPB; ++p) {
             su[u][p] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l_su[p]), q));
@@ -385,9 +404,9 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
         for (int u = 0; u < kObsBatch; ++u) {
 #pragma unroll
           for (int p = 0; p < kPB; ++p) {
-            ae[p] += su[u][p] * w[u][0] + sv[u][p] * w[u][3];
-            au[p] += su[u][p] * w[u][1] + sv[u][p] * w[u][4];
-            av[p] += su[u][p] * w[u][2] + sv[u][p] * w[u][5];
+            ae[p] = fmaf(sv[u][p], w[u][3], fmaf(su[u][p], w[u][0], ae[p]));
+            au[p] = fmaf(sv[u][p], w[u][4], fmaf(su[u][p], w[u][1], au[p]));
+            av[p] = fmaf(sv[u][p], w[u][5], fmaf(su[u][p], w[u][2], av[p]));
           }
         }
       }
@@ -405,22 +424,17 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
           if (p < np) {
             const double* s2 = sd + ((size_t)(p0 + p) * max_obs + o) * 2;
             const float su = static_cast<float>(s2[0]), sv = static_cast<float>(s2[1]);
-            ae[p] += su * w[0] + sv * w[3];
-            au[p] += su * w[1] + sv * w[4];
-            av[p] += su * w[2] + sv * w[5];
+            ae[p] = fmaf(sv, w[3], fmaf(su, w[0], ae[p]));
+            au[p] = fmaf(sv, w[4], fmaf(su, w[1], au[p]));
+            av[p] = fmaf(sv, w[5], fmaf(su, w[2], av[p]));
           }
         }
       }
-      if (writer) {
 #pragma unroll
-        for (int p = 0; p < kPB; ++p) {
-          if (p < np) {
-            float* E = psi + (size_t)(p0 + p) * 3 * ncell;
-            E[off] = se[p] + ae[p];
-            E[ncell + off] = su_[p] + au[p];
-            E[2 * ncell + off] = sv_[p] + av[p];
-          }
-        }
+      for (int p = 0; p < kPB; ++p) {
+        st_buf(bs[p], bj, srow, se[p] + ae[p]);
+        st_buf(bs[p], bj, srow + fq, su_[p] + au[p]);
+        st_buf(bs[p], bj, srow + fr, sv_[p] + av[p]);
       }
     }
 #pragma unroll

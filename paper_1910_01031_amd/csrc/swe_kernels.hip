@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "buffer_dev.hpp"
 #include "internal.hpp"
 
 namespace iewpf {
@@ -190,23 +191,10 @@ __device__ __forceinline__ int wrap(int i, int n) {
 // i in [-n, 2n)
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// One particle's [3][ny][nx] state as a raw buffer: every load and store takes a wave-uniform
-// byte offset (field and row, an SGPR) and this lane's column byte offset (one VGPR for all
-// rows and fields), so no per-access address arithmetic runs on the vector ALU.  Word 3 is
-// the gfx9-family raw-buffer format (32-bit data, no swizzle); accesses past the
-// 12 nx ny bytes of the particle read zero and write nothing.
-constexpr int kRawBufferWord3 = 0x00020000;
+// One particle's [3][ny][nx] state as a raw buffer: the field and row go into the scalar
+// offset, the lane's column into one VGPR set up once per wave.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const float* base, size_t ncell) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), static_cast<short>(0),
-                                           static_cast<int>(12 * ncell), kRawBufferWord3);
-}
-__device__ __forceinline__ float ld_buf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(voff),
-                                                              static_cast<int>(soff), 0));
-}
-__device__ __forceinline__ void st_buf(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, static_cast<int>(voff),
-                                        static_cast<int>(soff), 0);
+  return make_rsrc(base, 12 * ncell);
 }
 
 __device__ __forceinline__ void cr_weights(float t, float w[4]) {
