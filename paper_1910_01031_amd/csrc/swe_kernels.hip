@@ -298,7 +298,10 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
   const int jw = wrap(j, nx);
   const bool writer = lane >= kSweHalo && lane < kWave - kSweHalo && j < nx;
   const unsigned bjw = 4u * static_cast<unsigned>(jw);  // byte offset of the lane's column
-  const unsigned bj = 4u * static_cast<unsigned>(j);    // (writers only: 0 <= j < nx)
+  // With model error, lanes that write nothing get an offset past the buffer (their stores
+  // are dropped), so the row store needs no branch; the plain step keeps the branch, which
+  // measured faster there (the branch-free form let the scheduler raise register use).
+  const unsigned bj = (NOISE && !writer) ? kBufferOff : 4u * static_cast<unsigned>(j);
   const int k0 = sy * C.strip_h;
   const int k_end = min(k0 + C.strip_h, ny);  // exclusive
 
@@ -352,7 +355,9 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
     pe2 = pe1; pq2 = pq1; pr2 = pr1;
     pe1 = e; pq1 = q; pr1 = r;
     float dC = 0.0f;
-    if (NOISE && stage2 && m >= k0 + 2) dC = cr.at(z, C, m - 3);  // d_eta row m-3 (>= k0-1)
+    // d_eta row m-3, needed from m = k0 + 2 on (row k0 - 1), the first row pushed into
+    // stage 2 with a mode other than Store: a compile-time test instead of a run-time one
+    if (NOISE && M2 > kPushStore) dC = cr.at(z, C, m - 3);
     if (stage2) {
       float te, tq, tr;
       s2.template push<(M2 < 0 ? kPushStore : M2)>(se, sq, sr, C, te, tq, tr);  // row m - 4
@@ -363,7 +368,7 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
           oq += -C.gb_y * (dC - dA);
           orr += C.gb_x * (lane_next(dB) - lane_prev(dB));
         }
-        if (writer) {
+        if (NOISE || writer) {
           const unsigned o = static_cast<unsigned>(m - 4) * brow;
           st_buf(bout, bj, o, oe);
           st_buf(bout, bj, o + fq, oq);
