@@ -11,6 +11,8 @@
 //                         from eq. nuPerpendicular, then r' = r + sum_o (A^{1/2} - I) r on
 //                         the 7x7 block of every observation (gathered, order fixed)
 // All reductions use fixed trees, so results do not depend on scheduling.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "philox_dev.hpp"
 
@@ -94,12 +96,13 @@ __global__ __launch_bounds__(kThreads) void innovation_kernel(
   if (threadIdx.x == 0) cval[i] = phi;
 }
 
-// grid (kDotParts, ne): part q of particle i handles Philox blocks q*kThreads + t + k*stride;
-// partial sums go to part_dots[i][q][3] and are added in the fixed order q = 0.. by
-// reduce_dots_kernel.
-constexpr int kDotParts = 8;
+// grid (parts, ne): part q of particle i handles Philox blocks q*kThreads + t + k*stride
+// (stride = parts*kThreads); partial sums go to part_dots[i][q][3] and are added in the
+// fixed order q = 0.. by reduce_dots_kernel.  The host picks parts so that one pass covers
+// the grid when it can (each thread then draws its normals once), at most kDotParts.
+constexpr int kDotParts = 16;
 
-__global__ __launch_bounds__(kThreads) void rand_dots_kernel(int nr, uint64_t seed, uint64_t step,
+__global__ __launch_bounds__(kThreads) void rand_dots_kernel(int nr, int parts, uint64_t seed, uint64_t step,
                                                              uint32_t ens, float* __restrict__ xi,
                                                              float* __restrict__ nu,
                                                              double* __restrict__ part_dots,
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void rand_dots_kernel(int nr, uint64_t se
   float* N = nu + (size_t)i * nr;
   double xx = 0.0, nn = 0.0, nxv = 0.0;
   const int nblk = (nr + 3) / 4;
-  for (int b = q * kThreads + threadIdx.x; b < nblk; b += kThreads * kDotParts) {
+  for (int b = q * kThreads + threadIdx.x; b < nblk; b += kThreads * parts) {
     double zx[4], zn[4];
     normals4(b, step, 2u, ens, i, seed, zx);
     normals4(b, step, 3u, ens, i, seed, zn);
@@ -133,20 +136,20 @@ __global__ __launch_bounds__(kThreads) void rand_dots_kernel(int nr, uint64_t se
   nn = block_sum(nn, sh);
   nxv = block_sum(nxv, sh);
   if (threadIdx.x == 0) {
-    double* o = part_dots + ((size_t)i * kDotParts + q) * 3;
+    double* o = part_dots + ((size_t)i * parts + q) * 3;
     o[0] = xx;
     o[1] = nn;
     o[2] = nxv;
   }
 }
 
-__global__ void reduce_dots_kernel(int ne, const double* __restrict__ part_dots,
+__global__ void reduce_dots_kernel(int ne, int parts, const double* __restrict__ part_dots,
                                    double* __restrict__ dots) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ne) return;
   double a = 0.0, b = 0.0, c = 0.0;
-  for (int q = 0; q < kDotParts; ++q) {
-    const double* o = part_dots + ((size_t)i * kDotParts + q) * 3;
+  for (int q = 0; q < parts; ++q) {
+    const double* o = part_dots + ((size_t)i * parts + q) * 3;
     a += o[0];
     b += o[1];
     c += o[2];
@@ -173,6 +176,12 @@ __device__ double xm1_minus_log(double e) {
 // alpha = -(N/gamma) W_0(-(gamma/N) e^{-gamma/N} e^{-c*/N}).  With y = -W_0 = alpha gamma/N:
 // y - ln y = 1 + rho, rho = (gamma/N - 1 - ln(gamma/N)) + c*/N.  Halley iterations on
 // delta = 1 - y near the branch point (rho < 1/2), on y otherwise.
+// Stop once a Halley step is below 2^-44 of the iterate: convergence is cubic, so the
+// iterate after such a step sits at the rounding floor of f (about 1e-13 relative near the
+// branch point, where f cancels to O(d^2)); a tighter test can stall on rounding noise and
+// run to the iteration cap.
+constexpr double kHalleyStop = 0x1p-44;
+
 __device__ double alpha_solve(double gamma, double cstar, double N) {
   const double x = gamma / N;
   const double cn = fmax(cstar, 0.0) / N;
@@ -194,7 +203,7 @@ __device__ double alpha_solve(double gamma, double cstar, double N) {
       double dn = d - step;
       if (dn <= 0.0) dn = 0.5 * d;
       if (dn >= 1.0) dn = 0.5 * (d + 1.0);
-      const bool done = fabs(dn - d) <= 1e-16 * d;
+      const bool done = fabs(dn - d) <= kHalleyStop * d;
       d = dn;
       if (done) break;
     }
@@ -211,7 +220,7 @@ __device__ double alpha_solve(double gamma, double cstar, double N) {
       double yn = y - step;
       if (yn <= 0.0) yn = 0.5 * y;
       if (yn >= 1.0) yn = 0.5 * (y + 1.0);
-      const bool done = fabs(yn - y) <= 1e-16 * y;
+      const bool done = fabs(yn - y) <= kHalleyStop * y;
       y = yn;
       if (done) break;
     }
@@ -782,9 +791,12 @@ int rand_dots_parts() { return kDotParts; }
 
 void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens, float* xi,
                       float* nu, double* part_dots, double* dots, hipStream_t s, const uint64_t* dyn) {
-  hipLaunchKernelGGL(rand_dots_kernel, dim3(kDotParts, ne), dim3(kThreads), 0, s, nr, seed, step, ens,
-                     xi, nu, part_dots, dyn);
-  hipLaunchKernelGGL(reduce_dots_kernel, dim3((ne + 127) / 128), dim3(128), 0, s, ne, part_dots, dots);
+  const int nblk = (nr + 3) / 4;
+  const int parts = std::min(kDotParts, std::max(1, (nblk + kThreads - 1) / kThreads));
+  hipLaunchKernelGGL(rand_dots_kernel, dim3(parts, ne), dim3(kThreads), 0, s, nr, parts, seed, step,
+                     ens, xi, nu, part_dots, dyn);
+  hipLaunchKernelGGL(reduce_dots_kernel, dim3((ne + 127) / 128), dim3(128), 0, s, ne, parts, part_dots,
+                     dots);
 }
 
 void launch_sync(int ne, double n_psi, double n_r, int one_stage, const double* cval,
