@@ -58,7 +58,7 @@ typedef struct iewpf_ctx iewpf_ctx;
  *                      scale L0 (eq. soar_function); q0 = me_std / ||k||_2
  *   init_std, init_L0  same for the initial-state perturbation of iewpf_init_ensemble
  *   obs_sigma          observation error std, R = obs_sigma^2 I
- *   n_particles        ensemble size N_e
+ *   n_particles        ensemble size N_e, 1 .. 65535
  *   max_obs            capacity for observations / drifters per call
  *   seed, ensemble_id  Philox key word 0 and counter word 2 (low half)          */
 typedef struct {
@@ -97,7 +97,8 @@ typedef struct {
  * capacity; IEWPF_E_SHAPE for the grid limits), computes in float64 on the host the SOAR stencils,
  * the pull windows Q^{1/2} Q^{1/2,T} H^T e_b (eq. detailedOPDUpdate), S = (H Q H^T + R)^-1
  * by Cholesky (eq. S_extended), the local 49x49 A^{1/2} (eq. svdOfParenthesis), uploads
- * them and allocates the workspaces (one state-sized scratch buffer + coarse fields).
+ * them and allocates the workspaces (one state-sized scratch buffer, coarse fields, and the
+ * model-error fields of up to 16 model steps drawn ahead, about 64 MB at most).
  * *out receives the context; destroy with iewpf_destroy.  Uses the current HIP device. */
 int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out);
 void iewpf_destroy(iewpf_ctx* ctx);

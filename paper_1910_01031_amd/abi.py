@@ -40,7 +40,8 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_set_full_innovation", "iewpf_set_scheme", "iewpf_last_error")
 
 TRACE_KINDS = ("scheme_step", "me_normals", "soar", "gb_add", "innovation", "rand_dots",
-               "beta_alpha", "posterior_coarse", "analysis_update", "scheme_step_noise")
+               "beta_alpha", "posterior_coarse", "analysis_update", "scheme_step_noise",
+               "soar_model_error")
 
 
 class IewpfConfig(ctypes.Structure):

@@ -108,7 +108,7 @@ int env_int(const char* name, int def) {
 
 void free_ctx(iewpf_ctx* c) {
   if (!c) return;
-  void* bufs[] = {c->windows64, c->fS, c->fX, c->dinn, c->fstatus,
+  void* bufs[] = {c->windows64, c->fS, c->fX, c->dinn, c->fstatus, c->me_xi, c->me_coarse,
                   c->wstart, c->saved, c->sdrift, c->sflags, c->scratch, c->part_dots, c->xi, c->nu,
                   c->coarse, c->coarse2, c->windows,
                   c->dmat,    c->sd,     c->cval,   c->dots,   c->alpha,   c->cstar,
@@ -353,22 +353,30 @@ int model_steps(iewpf_ctx* c, float* state, int n_steps, uint64_t first_step, in
                 hipStream_t s) {
   float* cur = state;
   float* other = c->scratch;
+  const size_t field = (size_t)c->ne * c->nr;
+  const int n_noise = noise_on_last ? n_steps : n_steps - 1;  // model error after steps 0 .. n_noise-1
+  int chunk0 = 0, chunk_n = 0;  // the fields of steps chunk0 .. chunk0 + chunk_n - 1 are drawn
   for (int st = 0; st < n_steps; ++st) {
-    const bool noise = (st < n_steps - 1) || noise_on_last;
-    if (noise) {  // coarse field z = SOAR xi, added by the last scheme step of this model step
+    const bool noise = st < n_noise;
+    if (noise && st >= chunk0 + chunk_n) {
+      // coarse fields z = SOAR xi of the next model steps, each added by the last scheme
+      // step of its model step; one launch of each kernel for the whole chunk
+      chunk0 = st;
+      chunk_n = std::min(c->me_chunk, n_noise - st);
       {
         TraceScope t(c, kTrNormals, s);
-        launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, first_step + st, kTagModelError,
-                       c->cfg.ensemble_id, s);
+        launch_normals(c->me_xi, c->nr, c->ne, c->cfg.seed, first_step + st, kTagModelError,
+                       c->cfg.ensemble_id, s, nullptr, chunk_n);
       }
-      TraceScope t(c, kTrSoar, s);
-      launch_soar(c->cc, c->soar_me_f, c->ne, c->xi, c->coarse, s);
+      TraceScope t(c, kTrSoarMe, s);
+      launch_soar(c->cc, c->soar_me_f, c->ne * chunk_n, c->me_xi, c->me_coarse, s);
     }
+    const float* z = noise ? c->me_coarse + (size_t)(st - chunk0) * field : nullptr;
     for (int sub = 0; sub < c->cfg.n_sub; ++sub) {
       const bool fuse = noise && sub == c->cfg.n_sub - 1;
       {
         TraceScope t(c, fuse ? kTrSubstepNoise : kTrSubstep, s);
-        launch_swe_substep(c->swe, c->ne, cur, other, fuse ? c->coarse : nullptr, s);
+        launch_swe_substep(c->swe, c->ne, cur, other, fuse ? z : nullptr, s);
       }
       std::swap(cur, other);
     }
@@ -515,7 +523,7 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   if (f.nx <= 0 || f.ny <= 0 || f.c_omega <= 0 || f.n_particles <= 0 || f.n_sub <= 0 ||
       !(f.dt > 0) || !(f.dx > 0) || !(f.dy > 0) || !(f.H > 0) || !(f.g > 0) || f.f == 0.0 ||
       !(f.obs_sigma > 0) || f.max_obs <= 0 || f.max_obs >= (1 << 22) || !(f.theta >= 1.0) ||
-      !(f.theta <= 2.0) || f.me_std < 0 || f.init_std < 0)
+      !(f.theta <= 2.0) || f.me_std < 0 || f.init_std < 0 || f.n_particles > 65535)
     return fail(IEWPF_E_ARG, "invalid configuration value");
   if (f.c_omega > kCrMaxC)
     return fail(IEWPF_E_ARG, "c_omega above " + std::to_string(kCrMaxC) + " is not supported");
@@ -633,6 +641,16 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   rc |= dev_alloc(&c->nu, (size_t)c->ne * c->nr);
   rc |= dev_alloc(&c->coarse, (size_t)c->ne * c->nr);
   rc |= dev_alloc(&c->coarse2, (size_t)c->ne * c->nr);
+  {
+    // model-error fields drawn ahead: up to 16 model steps in about 64 MB, and at most 65535
+    // fields per launch (the grid's y and z extents)
+    const double field_bytes = 4.0 * c->ne * c->nr;
+    const int cap = std::max(1, std::min(16, env_int("IEWPF_ME_CHUNK", 16)));
+    c->me_chunk = (int)std::max(1.0, std::min((double)cap, std::floor(64.0 * (1 << 20) / field_bytes)));
+    c->me_chunk = std::max(1, std::min(c->me_chunk, 65535 / c->ne));
+  }
+  rc |= dev_alloc(&c->me_xi, (size_t)c->me_chunk * c->ne * c->nr);
+  rc |= dev_alloc(&c->me_coarse, (size_t)c->me_chunk * c->ne * c->nr);
   rc |= dev_alloc(&c->windows, win.size());
   rc |= dev_alloc(&c->dmat, (size_t)kBlockN * kBlockN);
   rc |= dev_alloc(&c->sd, (size_t)c->ne * c->max_obs * 2);

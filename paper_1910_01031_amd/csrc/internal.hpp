@@ -113,6 +113,11 @@ struct iewpf_ctx {
   float* nu = nullptr;         // [ne][nr]
   float* coarse = nullptr;     // [ne][nr] SOAR output / r'
   float* coarse2 = nullptr;    // [ne][nr]
+  // model-error fields of up to me_chunk consecutive model steps, drawn by one normals and
+  // one SOAR launch: [me_chunk][ne][nr] each
+  float* me_xi = nullptr;
+  float* me_coarse = nullptr;
+  int me_chunk = 1;
   float* windows = nullptr;    // [6][wy][wx]: (s_u, s_v) x (eta, hu, hv)
   float* dmat = nullptr;       // A^{1/2} - I, float32 [49][49]
   double* sd = nullptr;        // [ne][max_obs][2]
@@ -171,7 +176,7 @@ namespace iewpf {
 constexpr int kTraceMax = 8192;
 enum TraceKind {
   kTrSubstep = 0, kTrNormals, kTrSoar, kTrGbAdd, kTrInnov, kTrRandDots, kTrSync,
-  kTrPosterior, kTrUpdate, kTrSubstepNoise, kTrKinds
+  kTrPosterior, kTrUpdate, kTrSubstepNoise, kTrSoarMe, kTrKinds
 };
 // Records a start event (returns the slot or -1) and the matching stop event.
 int trace_begin(iewpf_ctx* c, int kind, hipStream_t s);
@@ -245,8 +250,9 @@ void launch_swe_batch(const SweJobTable* tab, int total_waves, int parity, bool 
 // z != nullptr: also add the model error Q_GB I_Omega z (z: [ne][nry][nrx] SOAR field)
 void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, const float* z,
                         hipStream_t s);
+// n_steps fields [n_steps][ne][n], field t drawn for step index step + t
 void launch_normals(float* out, int n, int ne, uint64_t seed, uint64_t step, uint32_t tag,
-                    uint32_t ens, hipStream_t s, const uint64_t* dyn = nullptr);
+                    uint32_t ens, hipStream_t s, const uint64_t* dyn = nullptr, int n_steps = 1);
 void launch_soar(const CoarseConst& C, const float* w25, int ne, const float* in, float* out,
                  hipStream_t s);
 // psi (+)= Q_GB I_Omega z  [+ pull];  base != nullptr: psi = base + ...

@@ -83,8 +83,8 @@ __global__ __launch_bounds__(256) void normals_kernel(float* __restrict__ out, i
   const int particle = blockIdx.y;
   if (4 * blk >= n) return;
   double z[4];
-  normals4(blk, step + (dyn ? dyn[0] : 0), tag, ens, particle, seed, z);
-  float* o = out + (size_t)particle * n;
+  normals4(blk, step + blockIdx.z + (dyn ? dyn[0] : 0), tag, ens, particle, seed, z);
+  float* o = out + ((size_t)blockIdx.z * gridDim.y + particle) * n;
 #pragma unroll
   for (int l = 0; l < 4; ++l)
     if (4 * blk + l < n) o[4 * blk + l] = static_cast<float>(z[l]);
@@ -448,10 +448,10 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
 }  // namespace
 
 void launch_normals(float* out, int n, int ne, uint64_t seed, uint64_t step, uint32_t tag,
-                    uint32_t ens, hipStream_t s, const uint64_t* dyn) {
+                    uint32_t ens, hipStream_t s, const uint64_t* dyn, int n_steps) {
   const int nblk = (n + 3) / 4;
-  hipLaunchKernelGGL(normals_kernel, dim3((nblk + 255) / 256, ne), dim3(256), 0, s, out, n, seed,
-                     step, tag, ens, dyn);
+  hipLaunchKernelGGL(normals_kernel, dim3((nblk + 255) / 256, ne, n_steps), dim3(256), 0, s, out, n,
+                     seed, step, tag, ens, dyn);
 }
 
 void launch_soar(const CoarseConst& C, const float* w25, int ne, const float* in, float* out,
