@@ -184,6 +184,39 @@ def test_strip_heights_identical_and_match_oracle(torch_dev):
     ctx.close()
 
 
+def test_model_error_chunks_identical_and_match_oracle(torch_dev, monkeypatch):
+    """The model-error fields of several model steps drawn by one launch give the same bits
+    as one model step per call, for chunks of 16, 3 and 1 steps (a chunk boundary inside the
+    call and a last chunk shorter than the others), and the result matches the oracle."""
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Context
+    cfg = W.tiny().replace(n_particles=3, me_std=0.01)
+    rng = np.random.default_rng(77)
+    ens = W.as_f32(np.stack([W.random_state(cfg, rng) for _ in range(3)]))
+    n_steps, first = 7, 5
+    outs = {}
+    for chunk in (16, 3, 1):
+        _say(f"model-error chunk {chunk}: {n_steps} steps in one call")
+        monkeypatch.setenv("IEWPF_ME_CHUNK", str(chunk))
+        outs[chunk] = _run_steps(torch, dev, cfg, ens, n_steps, first_step=first,
+                                 noise_on_last=False)
+    monkeypatch.delenv("IEWPF_ME_CHUNK")
+    _say("model-error chunks: one step per call")
+    ctx = Context(cfg, max_obs=4)
+    st = torch.from_numpy(np.ascontiguousarray(ens)).to(dev)
+    for k in range(n_steps):
+        ctx.step_ensemble(st, 1, first_step=first + k, noise_on_last=k < n_steps - 1)
+    torch.cuda.synchronize()
+    per_step = st.cpu().numpy().astype(np.float64)
+    ctx.close()
+    for chunk, o in outs.items():
+        assert np.array_equal(o, per_step), chunk
+    for i in range(3):
+        ref = oens.step_member(ens[i], cfg, i, first, n_steps, noise_on_last=False)
+        err = _rel(per_step[i], ref)
+        assert max(err) < 5 * TOL, (i, err)
+
+
 def test_deterministic_repeat(torch_dev):
     torch, dev = torch_dev
     cfg = W.tiny().replace(n_particles=3)
