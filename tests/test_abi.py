@@ -54,6 +54,8 @@ def test_struct_layouts_match_c(tmp_path):
     (dict(theta=0.5), abi.IEWPF_E_ARG),
     (dict(obs_sigma=0.0), abi.IEWPF_E_ARG),
     (dict(nx=17 * 8, ny=17 * 8, c_omega=17), abi.IEWPF_E_ARG),  # coarsening above 16
+    (dict(n_particles=65536), abi.IEWPF_E_ARG),     # above the launch grids' y extent
+    (dict(nx=16384, ny=10928), abi.IEWPF_E_SHAPE),  # 12 nx ny bytes >= 2^31 per particle
 ])
 def test_invalid_configs_are_rejected(kw, code):
     lib = abi.load()
