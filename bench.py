@@ -482,7 +482,10 @@ def main():
                      "algorithmic_flops_per_launch": flops_per_launch,
                      "hbm": {"achieved_gbs": achieved_gbs, "peak_gbs": HBM_PEAK_GBS,
                              "frac": achieved_gbs / HBM_PEAK_GBS,
-                             "algorithmic_bytes_per_launch": bytes_per_launch},
+                             "algorithmic_bytes_per_launch": bytes_per_launch,
+                             # measured HBM bytes (counters) per launch over the same duration
+                             "traffic_gbs": (traffic / (plain_ms / 1e3) / 1e9
+                                             if traffic is not None else None)},
                      "avg_launch_ms_with_model_error": (tr["scheme_step_noise"][0] /
                                                         max(tr["scheme_step_noise"][1], 1))},
     }
