@@ -10,7 +10,7 @@ synthesised before the timed region (inputs resident when timing starts).
 value = particle-cell-scheme-steps per second over the whole cycle (forecast + analysis):
   n_particles * nx * ny * 20 * K / elapsed.
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -361,7 +361,7 @@ def surrogate_leg(torch, dev, ctx, ens, cfg, train_steps: int):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_1910_01031_amd import Context, abi

@@ -4,7 +4,7 @@ drifters and residual resampling against the FP64 oracle, through the C ABI.
 Tolerances: float64 host precompute 1e-12 relative; float64 per-particle scalars
 (c_i, gamma, zeta, alpha, beta) 1e-9 relative (the only float32 inputs are the state
 values and the normals, both identical on the two sides up to the float32 rounding of
-the normals); float32 state 1e-5 relative per field (the benchmark spec); integers bit-exact."""
+the normals); float32 state 1e-5 relative per field; integers bit-exact."""
 import sys
 
 import numpy as np

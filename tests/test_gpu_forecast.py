@@ -1,5 +1,5 @@
 """GPU parity of the forecast path (scheme step, model error, initial ensemble) against the
-FP64 oracle, through the C ABI.  Tolerance (the benchmark spec): per field,
+FP64 oracle, through the C ABI.  Tolerance: per field,
 max |gpu - oracle| / max |oracle| <= 1e-5 after one model step from the same
 FP32-representable input."""
 import sys
