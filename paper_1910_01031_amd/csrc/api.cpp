@@ -112,8 +112,8 @@ void free_ctx(iewpf_ctx* c) {
                   c->wstart, c->saved, c->sdrift, c->sflags, c->scratch, c->part_dots, c->xi, c->nu,
                   c->coarse, c->coarse2, c->windows,
                   c->dmat,    c->sd,     c->cval,   c->dots,   c->alpha,   c->cstar,
-                  c->scal,    c->obs_cells, c->obs_y, c->pt_off, c->pt_ent, c->st_off,
-                  c->st_ent,  c->dk1,    c->dpstar, c->dobs,   c->cflmax,  c->dparents, c->dcum};
+                  c->scal,    c->d_stage, c->dk1,    c->dpstar, c->dobs,   c->cflmax,  c->dparents,
+                  c->dcum};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
@@ -249,20 +249,19 @@ int upload_observations(iewpf_ctx* c, int n_obs, bool with_y, hipStream_t s) {
       st_off[sy * nsx + sx + 1] = t;
     }
   }
-  if (n_obs > 0) {
-    IEWPF_HIP_TRY(hipMemcpyAsync(c->obs_cells, cells, sizeof(int32_t) * 2 * n_obs,
+  // One copy of the staging area up to the last used list entry (the device block has the
+  // same layout): small transfers each cost a fixed latency on the stream, so one copy of
+  // the whole prefix beats six copies of the used parts.  Without y, the y block is skipped
+  // (the caller uploads y itself) with a second copy from pt_off on.
+  const size_t end = L.st_ent + sizeof(int32_t) * (size_t)t;
+  if (with_y) {
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->d_stage, c->h_stage, end, hipMemcpyHostToDevice, s));
+  } else {
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->d_stage + L.cells, c->h_stage + L.cells, L.y - L.cells,
                                  hipMemcpyHostToDevice, s));
-    if (with_y)
-      IEWPF_HIP_TRY(hipMemcpyAsync(c->obs_y, y, sizeof(double) * 2 * n_obs, hipMemcpyHostToDevice, s));
-    IEWPF_HIP_TRY(hipMemcpyAsync(c->pt_ent, pt_ent, sizeof(int32_t) * pt_off[c->nr],
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->d_stage + L.pt_off, c->h_stage + L.pt_off, end - L.pt_off,
                                  hipMemcpyHostToDevice, s));
   }
-  IEWPF_HIP_TRY(hipMemcpyAsync(c->pt_off, pt_off, sizeof(int32_t) * (c->nr + 1),
-                               hipMemcpyHostToDevice, s));
-  IEWPF_HIP_TRY(hipMemcpyAsync(c->st_off, st_off, sizeof(int32_t) * (c->n_upd_strips + 1),
-                               hipMemcpyHostToDevice, s));
-  if (t > 0)
-    IEWPF_HIP_TRY(hipMemcpyAsync(c->st_ent, st_ent, sizeof(int32_t) * t, hipMemcpyHostToDevice, s));
   IEWPF_HIP_TRY(hipEventRecord(c->stage_ev, s));
   c->stage_pending = true;
   c->last_n_obs = n_obs;
@@ -660,12 +659,8 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   rc |= dev_alloc(&c->alpha, c->ne);
   rc |= dev_alloc(&c->cstar, c->ne);
   rc |= dev_alloc(&c->scal, 16);
-  rc |= dev_alloc(&c->obs_cells, (size_t)2 * c->max_obs);
-  rc |= dev_alloc(&c->obs_y, (size_t)2 * c->max_obs);
-  rc |= dev_alloc(&c->pt_off, (size_t)c->nr + 1);
-  rc |= dev_alloc(&c->pt_ent, (size_t)c->max_obs * kBlockN);
-  rc |= dev_alloc(&c->st_off, (size_t)c->n_upd_strips + 1);
-  rc |= dev_alloc(&c->st_ent, (size_t)c->n_upd_strips * c->max_obs);
+  c->stage_bytes = stage_layout(*c).total;
+  rc |= dev_alloc(&c->d_stage, c->stage_bytes);
   rc |= dev_alloc(&c->dk1, (size_t)c->ne * c->max_obs * 2);
   rc |= dev_alloc(&c->dpstar, (size_t)c->ne * c->max_obs * 2);
   rc |= dev_alloc(&c->dobs, (size_t)c->max_obs * 2);
@@ -676,7 +671,15 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
     free_ctx(c);
     return IEWPF_E_HIP;
   }
-  c->stage_bytes = stage_layout(*c).total;
+  {
+    const StageLayout L = stage_layout(*c);
+    c->obs_cells = reinterpret_cast<int32_t*>(c->d_stage + L.cells);
+    c->obs_y = reinterpret_cast<double*>(c->d_stage + L.y);
+    c->pt_off = reinterpret_cast<int32_t*>(c->d_stage + L.pt_off);
+    c->pt_ent = reinterpret_cast<int32_t*>(c->d_stage + L.pt_ent);
+    c->st_off = reinterpret_cast<int32_t*>(c->d_stage + L.st_off);
+    c->st_ent = reinterpret_cast<int32_t*>(c->d_stage + L.st_ent);
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_stage), c->stage_bytes) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_small),
                     sizeof(double) * std::max<size_t>(64, std::max<size_t>(2 * c->max_obs, 8 * (size_t)c->ne))) !=

@@ -144,6 +144,9 @@ struct iewpf_ctx {
   // pinned host staging
   unsigned char* h_stage = nullptr;
   size_t stage_bytes = 0;
+  // device copy of the staging area, same layout: obs_cells, obs_y, pt_off, pt_ent, st_off
+  // and st_ent point into it, so one analysis uploads its observation lists in one copy
+  unsigned char* d_stage = nullptr;
   hipEvent_t stage_ev = nullptr;
   bool stage_pending = false;
   double* h_small = nullptr;     // small pinned readback buffer
