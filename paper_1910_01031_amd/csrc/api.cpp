@@ -210,7 +210,17 @@ void add_scaled_noise(iewpf_ctx* c, float* psi, uint64_t step, double scale, hip
 int upload_observations(iewpf_ctx* c, int n_obs, bool with_y, hipStream_t s) {
   const StageLayout L = stage_layout(*c);
   int32_t* cells = reinterpret_cast<int32_t*>(c->h_stage + L.cells);
-  double* y = reinterpret_cast<double*>(c->h_stage + L.y);
+  if (with_y && n_obs == c->list_n &&
+      std::equal(cells, cells + 2 * n_obs, c->list_cells.begin())) {
+    // same cells as the lists on the device (moorings): only the values go up
+    if (n_obs > 0)
+      IEWPF_HIP_TRY(hipMemcpyAsync(c->d_stage + L.y, c->h_stage + L.y, sizeof(double) * 2 * n_obs,
+                                   hipMemcpyHostToDevice, s));
+    IEWPF_HIP_TRY(hipEventRecord(c->stage_ev, s));
+    c->stage_pending = true;
+    c->last_n_obs = n_obs;
+    return 0;
+  }
   int32_t* pt_off = reinterpret_cast<int32_t*>(c->h_stage + L.pt_off);
   int32_t* pt_ent = reinterpret_cast<int32_t*>(c->h_stage + L.pt_ent);
   std::fill(pt_off, pt_off + c->nr + 1, 0);
@@ -265,6 +275,8 @@ int upload_observations(iewpf_ctx* c, int n_obs, bool with_y, hipStream_t s) {
   IEWPF_HIP_TRY(hipEventRecord(c->stage_ev, s));
   c->stage_pending = true;
   c->last_n_obs = n_obs;
+  c->list_cells.assign(cells, cells + 2 * n_obs);
+  c->list_n = n_obs;
   return 0;
 }
 
@@ -848,6 +860,7 @@ int iewpf_observe_moorings(iewpf_ctx* c, const float* truth, const int32_t* cell
   const StageLayout L = stage_layout(*c);
   int32_t* cells = reinterpret_cast<int32_t*>(c->h_stage + L.cells);
   std::memcpy(cells, cells_host, sizeof(int32_t) * 2 * n_obs);
+  c->list_n = -1;  // the device cells no longer match the device lists
   IEWPF_HIP_TRY(hipMemcpyAsync(c->obs_cells, cells, sizeof(int32_t) * 2 * n_obs,
                                hipMemcpyHostToDevice, s));
   launch_observe(n_obs, c->nx, c->ny, c->cfg.H, c->cfg.obs_sigma, c->cfg.seed, analysis_index,

@@ -172,6 +172,9 @@ struct iewpf_ctx {
   int32_t* fstatus = nullptr;
   std::vector<int32_t> f_cells;  // cells the cached S was built for
   int f_n = -1;
+  // cells whose observation lists (and cells) are on the device in d_stage; -1: none
+  std::vector<int32_t> list_cells;
+  int list_n = -1;
   std::vector<double> h_win64;  // float64 pull windows [2][3][wy][wx] (host copy)
 };
 

@@ -120,6 +120,36 @@ def test_analysis_parity_tiny(torch_dev):
         assert err < TOL
 
 
+def test_repeated_cells_reuse_lists_bit_identical(torch_dev):
+    """Analyses on one context whose cells repeat (the device lists are reused, only y is
+    uploaded), change, return, and follow an observation synthesis that rewrites the device
+    cells: each equals the same analysis on a fresh context, bit for bit."""
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Context
+    cfg = W.tiny()
+    ens, truth = _ensemble_near(cfg, cfg.n_particles, 0.003)
+    cells_a = np.array([[8, 8], [24, 8], [8, 24], [24, 24]], dtype=np.int32)
+    cells_b = np.array([[3, 30], [17, 5], [29, 12]], dtype=np.int32)
+    plan = [(cells_a, 1), (cells_a, 2), (cells_b, 3), (cells_a, 4), ("observe", 5), (cells_a, 6)]
+    ctx = Context(cfg, max_obs=8)
+    tr = torch.from_numpy(np.ascontiguousarray(W.as_f32(truth[None]))).to(dev)
+    st = torch.from_numpy(np.ascontiguousarray(ens)).to(dev)
+    for cells, aidx in plan:
+        if isinstance(cells, str):
+            _say("  observation synthesis on the same context (cells b)")
+            ctx.observe_moorings(tr, cells_b, analysis_index=aidx)
+            continue
+        _say(f"  analysis {aidx}: {len(cells)} cells")
+        noise = ophil.normals(2 * len(cells), cfg.seed, aidx, ophil.TAG_OBS, 77, 0).reshape(-1, 2)
+        y = oobs.mooring_obs(truth, cells, cfg.H, cfg.obs_sigma, noise)
+        before = st.cpu().numpy()
+        ctx.assimilate(st, cells, y, analysis_index=aidx)
+        torch.cuda.synchronize()
+        fresh, _, _ = _gpu_analysis(torch, dev, cfg, before, cells, y, aidx, 8)
+        assert np.array_equal(st.cpu().numpy().astype(np.float64), fresh), aidx
+    ctx.close()
+
+
 def test_analysis_parity_overlapping_drifters(torch_dev):
     # drifters closer than the pull radius, two in the same cell, blocks overlapping
     torch, dev = torch_dev
