@@ -22,8 +22,12 @@ such a scheme (documented reading; both the oracle and the HIP path follow it):
 
 The scheme is exactly steady for lake at rest and for axis-aligned jets in the discrete
 balance g (eta_{k+1} - eta_k) = -f dy (u_k + u_{k+1})/2 (well-balanced w.r.t. eq.
-geostrophic_balance_cont).  Beyond its invariants the scheme is "parity unpinned"
-against the paper: the paper prints no scheme, so this definition is the reference.
+geostrophic_balance_cont).  The paper prints no scheme, so this definition is the
+reference; its pins (tests/test_oracle_swe.py) are mass conservation, the two steady
+states, second-order convergence, translation and reflection symmetry, the inertia-
+gravity dispersion relation, and, without rotation, convergence to the exact dam-break
+(Riemann) solution.  The rotating reconstruction itself (the local Coriolis potential)
+is pinned only through the steady jets and the dispersion relation.
 """
 from __future__ import annotations
 

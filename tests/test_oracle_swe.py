@@ -1,4 +1,5 @@
-"""Pins of the oracle's shallow-water scheme (invariants, symmetries, closed forms).
+"""Pins of the oracle's shallow-water scheme (invariants, symmetries, closed forms, the
+exact dam-break solution).
 
 The paper cites its scheme without printing it, so these checks pin the properties any
 correct well-balanced central-upwind SSP-RK2 scheme for eq. swe_full must have."""
@@ -128,3 +129,57 @@ def test_cfl_substeps_for_workloads():
         p = swe.SweParams.of(cfg)
         base = W.jet_state(cfg)
         assert swe.n_substeps(base, p, cfg.dt, cfg.courant) <= nsub == cfg.n_sub
+
+
+def _dam_break_exact(xi, hL, hR, g):
+    """Exact depth of the wet dam break (still water of depth hL left of the dam, hR < hL
+    right of it) at x / t = xi: a rarefaction into hL, the middle state, a shock into hR
+    (Stoker's solution).  The middle depth equates the rarefaction's velocity
+    2 (sqrt(g hL) - sqrt(g hm)) and the shock's (hm - hR) sqrt(g/2 (1/hm + 1/hR))."""
+    cL = math.sqrt(g * hL)
+
+    def gap(hm):
+        return 2.0 * (cL - math.sqrt(g * hm)) - (hm - hR) * math.sqrt(0.5 * g * (1 / hm + 1 / hR))
+
+    lo, hi = hR, hL
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if gap(mid) > 0 else (lo, mid)
+    hm = 0.5 * (lo + hi)
+    cm = math.sqrt(g * hm)
+    um = 2.0 * (cL - cm)
+    s = hm * um / (hm - hR)  # shock speed from the mass jump
+    h = np.where(xi < -cL, hL, 0.0)
+    fan = (xi >= -cL) & (xi < um - cm)
+    h = np.where(fan, (2.0 * cL - xi) ** 2 / (9.0 * g), h)
+    h = np.where((xi >= um - cm) & (xi < s), hm, h)
+    return np.where(xi >= s, hR, h)
+
+
+def _dam_break_error(nx):
+    """L1 error of the depth against the exact dam-break solution, without rotation: the
+    flux, wave-speed bounds, limiter and time stepping all enter.  A periodic strip holds
+    two dams (at L/2 and at 0); the comparison covers [L/4, 3L/4], which only the dam at
+    L/2 reaches before the end time."""
+    L, H, g = 2.0, 1.0, 9.81
+    hL, hR = 2.0, 1.0
+    dx = L / nx
+    p = swe.SweParams(H=H, g=g, f=0.0, dx=dx, dy=dx)
+    x = (np.arange(nx) + 0.5) * dx
+    psi = np.zeros((3, 4, nx))
+    psi[0] = np.where(x < L / 2, hL - H, hR - H)[None, :]
+    t_end = 0.08  # the waves of the two dams meet after ~0.11
+    n = int(math.ceil(t_end / swe.cfl_dt(psi, p)))
+    for _ in range(n):
+        psi = swe.substep(psi, p, t_end / n)
+    assert np.abs(psi[:, 1:] - psi[:, :1]).max() < 1e-12  # stays uniform across the strip
+    assert np.abs(psi[2]).max() < 1e-12
+    win = (x >= L / 4) & (x < 3 * L / 4)
+    exact = _dam_break_exact((x[win] - L / 2) / t_end, hL, hR, g)
+    return np.abs(H + psi[0, 0, win] - exact).mean() / hR
+
+
+def test_dam_break_converges_to_exact_riemann_solution():
+    e1, e2 = _dam_break_error(200), _dam_break_error(400)
+    assert e2 < 4e-3, (e1, e2)
+    assert e1 / e2 > 1.5, (e1, e2)
