@@ -43,8 +43,8 @@ SURROGATE_FLOPS_PER_PIXEL = 171_072
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, the scale factors a plain device copy of known size
 # reads), with the SHA-256 of the kernel source they were taken on: reported only while
 # the source is unchanged.
-MEASURED_TRAFFIC = {"bytes": 2 * 147998.9 * 1024 + 180130.4 * 1024,
-                    "source_sha256": "4d9f795288e8683346f9c581507ac322c88c5f394da51aec5d202d13b8f82d1a"}
+MEASURED_TRAFFIC = {"bytes": 2 * 147998.6 * 1024 + 180132.2 * 1024,
+                    "source_sha256": "63a37d5ef03e7951467b434ef509fbd7d4b5522d0e57b6d2d1a040bb7ad2c6bc"}
 
 
 def _kernel_source_hash():
