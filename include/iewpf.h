@@ -147,7 +147,9 @@ int iewpf_set_full_innovation(iewpf_ctx* ctx, int on);
  * implementation of the IEWPF scheme"): innovations, pull, perpendicular xi/nu (streams
  * (analysis_index, tags 2 and 3)), beta, alpha (Lambert W_0), local P^{1/2} and the
  * posterior update.  obs_host: n_obs host records (copied; the pointer may be reused
- * when the call returns).  stats_out: host pointer or NULL; when non-NULL the call waits
+ * when the call returns).  The per-call observation index lists are built on the host
+ * and uploaded with the values in one copy; when the cells equal the previous call's
+ * (moorings), only the values are uploaded.  stats_out: host pointer or NULL; when non-NULL the call waits
  * for the stream and fills it.  beta <= 0 is reported through stats (beta) and by the
  * return code IEWPF_E_BETA only when stats_out is non-NULL. */
 int iewpf_assimilate(iewpf_ctx* ctx, float* state, const iewpf_obs* obs_host, int n_obs,
