@@ -133,8 +133,9 @@ int iewpf_set_scheme(iewpf_ctx* ctx, int scheme);
  * independently: S = (H Q H^T + R)^{-1} is the same 2x2 block for every observation (eq.
  * S_extended and the assumption after it that observations are far apart).  When on,
  * iewpf_assimilate uses S = (sym(H Q H^T) + R)^{-1} over all observations together
- * ([2 n_obs]^2, float64 Cholesky on the device, S d and c_i by triangular solves per
- * particle) in the pull and in c_i; the posterior
+ * ([2 n_obs]^2, float64 Cholesky on the device, S formed from the factor by triangular
+ * solves of the unit vectors, then S d and c_i by one float64 product per analysis) in the
+ * pull and in c_i; the posterior
  * perturbation keeps the paper's local blocks.  H Q H^T's entries are the pull windows read
  * at the offsets between observed cells; with c_Omega > 1 each observation's chain uses a
  * coarse grid aligned on its own cell, so its symmetric part is used.  The factor is rebuilt
