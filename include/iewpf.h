@@ -22,7 +22,10 @@
  *   - Return value: 0 on success, a negative IEWPF_E_* code on failure (nothing is
  *     thrown across the ABI); iewpf_last_error() returns a thread-local message.
  *   - Host precompute (SOAR weights, pull windows, S, the local A^{1/2}) happens once in
- *     iewpf_create; no later call allocates device memory.
+ *     iewpf_create, which allocates the workspaces.  Later calls allocate device memory
+ *     only where their description says so: the first call of an optional path (full
+ *     innovation covariance, surrogate window, surrogate drifter forecast) and batch and
+ *     network creation.
  *   - The context owns its constants and workspaces; calls on one context must not
  *     overlap in time (they share the workspaces).
  */
