@@ -52,10 +52,13 @@ __device__ __forceinline__ float minmod3(float a, float b, float c) {
   return __builtin_amdgcn_fmed3f(lo, hi, 0.0f);
 }
 
-// Twice the limited slope, minmod(2 theta (q0 - qm), qp - qm, 2 theta (qp - q0)): the
-// factor 2 is exact, so the half-slope face offsets below round as with the slope itself.
-__device__ __forceinline__ float limited2(float qm, float q0, float qp, float theta2) {
-  return minmod3(theta2 * (q0 - qm), qp - qm, theta2 * (qp - q0));
+// The limited slope divided by theta: minmod(theta a, c, theta b) = theta minmod(a, c /
+// theta, b) for theta > 0, with a = q0 - qm, b = qp - q0 and c = (qp - qm) / 2, so the
+// minmod takes the two one-sided differences as they are and only the central one is
+// scaled (by 1/(2 theta)); theta goes into the constants that turn the slope into face
+// offsets.
+__device__ __forceinline__ float limited_t(float qm, float q0, float qp, float k2t) {
+  return minmod3(q0 - qm, (qp - qm) * k2t, qp - q0);
 }
 
 // Central-upwind flux between a left (-) and right (+) face state (eta, normal velocity,
@@ -91,14 +94,14 @@ __device__ __forceinline__ void x_divergence(float e, float u, float v, const Sw
   const float Kc = C.g * e;
   const float Kp = C.g * eE_ - C.hfdx * (v + vE_);
   const float Km = C.g * eW_ + C.hfdx * (v + vW_);
-  const float theta2 = 2.0f * C.theta;
-  const float sK = limited2(Km, Kc, Kp, theta2);  // all three slopes doubled
-  const float su = limited2(uW_, u, uE_, theta2);
-  const float sv = limited2(vW_, v, vE_, theta2);
-  const float off = (sK + (2.0f * C.fdx) * v) * (0.5f * C.inv2g);
+  const float sK = limited_t(Km, Kc, Kp, C.k2t);  // slopes divided by theta
+  const float su = limited_t(uW_, u, uE_, C.k2t);
+  const float sv = limited_t(vW_, v, vE_, C.k2t);
+  // eta^{E,W} = eta +- (theta sK + f dx v) / (2 g); u, v faces +- theta s / 2
+  const float off = C.tg * sK + C.fxg * v;
   const float eEf = e + off, eWf = e - off;
-  const float uEf = u + 0.25f * su, uWf = u - 0.25f * su;
-  const float vEf = v + 0.25f * sv, vWf = v - 0.25f * sv;
+  const float uEf = u + C.ht * su, uWf = u - C.ht * su;
+  const float vEf = v + C.ht * sv, vWf = v - C.ht * sv;
   // face j+1/2: left = east face of this cell, right = west face of cell j+1
   float F0, F1, F2;
   cu_flux(eEf, uEf, vEf, lane_next(eWf), lane_next(uWf), lane_next(vWf), C, F0, F1, F2);
@@ -118,18 +121,17 @@ struct YFace {
 __device__ __forceinline__ void y_recon(float e, float u, float v, float dLm, float dum, float dvm,
                                         float dLp, float dup, float dvp, const SweConst& C,
                                         YFace& N, YFace& S) {
-  const float theta2 = 2.0f * C.theta;
-  // doubled slopes minmod(2 theta a, a + b, 2 theta b)
-  const float sL = minmod3(theta2 * dLm, dLm + dLp, theta2 * dLp);
-  const float su = minmod3(theta2 * dum, dum + dup, theta2 * dup);
-  const float sv = minmod3(theta2 * dvm, dvm + dvp, theta2 * dvp);
-  const float off = (sL - (2.0f * C.fdy) * u) * (0.5f * C.inv2g);
+  // slopes divided by theta: minmod(a, (a + b) / (2 theta), b)
+  const float sL = minmod3(dLm, (dLm + dLp) * C.k2t, dLp);
+  const float su = minmod3(dum, (dum + dup) * C.k2t, dup);
+  const float sv = minmod3(dvm, (dvm + dvp) * C.k2t, dvp);
+  const float off = C.tg * sL - C.fyg * u;
   N.e = e + off;
   S.e = e - off;
-  N.n = v + 0.25f * sv;
-  S.n = v - 0.25f * sv;
-  N.t = u + 0.25f * su;
-  S.t = u - 0.25f * su;
+  N.n = v + C.ht * sv;
+  S.n = v - C.ht * sv;
+  N.t = u + C.ht * su;
+  S.t = u - C.ht * su;
 }
 
 // One RK stage as a row pipeline: push row m (eta, hu, hv), emit row m-2 of
