@@ -596,7 +596,6 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   S.theta = (float)f.theta;
   S.k2t = (float)(1.0 / (2.0 * f.theta));
   S.ht = (float)(0.5 * f.theta);
-  S.tg = (float)(f.theta / (2.0 * f.g));
   S.fxg = (float)(f.f * f.dx / (2.0 * f.g));
   S.fyg = (float)(f.f * f.dy / (2.0 * f.g));
   S.dt = (float)(f.dt / f.n_sub);

@@ -48,7 +48,7 @@ struct SweConst {
   // the limiter works on slopes divided by theta; these fold theta back in
   float k2t;           // 1 / (2 theta): the central difference's weight in the minmod
   float ht;            // theta / 2: face offset of u, v per limited slope
-  float tg, fxg, fyg;  // theta / (2 g), f dx / (2 g), f dy / (2 g): face offset of eta
+  float fxg, fyg;      // f dx / (2 g), f dy / (2 g): Coriolis potential / g increments
   float dt, idx, idy;  // scheme step, 1/dx, 1/dy
   // fused model error (last scheme step of a model step)
   int c, nrx, nry;     // coarsening and coarse grid

@@ -91,14 +91,16 @@ __device__ __forceinline__ void x_divergence(float e, float u, float v, const Sw
   const float eW_ = lane_prev(e), eE_ = lane_next(e);
   const float uW_ = lane_prev(u), uE_ = lane_next(u);
   const float vW_ = lane_prev(v), vE_ = lane_next(v);
-  const float Kc = C.g * e;
-  const float Kp = C.g * eE_ - C.hfdx * (v + vE_);
-  const float Km = C.g * eW_ + C.hfdx * (v + vW_);
+  // K / g = eta - V / g: the potential in units of eta (V / g = +-f dx (v + v_nb) / (2 g))
+  const float Kc = e;
+  const float Kp = eE_ - C.fxg * (v + vE_);
+  const float Km = eW_ + C.fxg * (v + vW_);
   const float sK = limited_t(Km, Kc, Kp, C.k2t);  // slopes divided by theta
   const float su = limited_t(uW_, u, uE_, C.k2t);
   const float sv = limited_t(vW_, v, vE_, C.k2t);
-  // eta^{E,W} = eta +- (theta sK + f dx v) / (2 g); u, v faces +- theta s / 2
-  const float off = C.tg * sK + C.fxg * v;
+  // eta^{E,W} = eta +- (sigma_K + f dx v) / (2 g) = eta +- (theta sK / 2 + f dx v / (2 g));
+  // u, v faces +- theta s / 2
+  const float off = C.ht * sK + C.fxg * v;
   const float eEf = e + off, eWf = e - off;
   const float uEf = u + C.ht * su, uWf = u - C.ht * su;
   const float vEf = v + C.ht * sv, vWf = v - C.ht * sv;
@@ -112,7 +114,7 @@ __device__ __forceinline__ void x_divergence(float e, float u, float v, const Sw
 
 // y reconstruction of row k: north and south face states (eta, v = normal, u = tangential)
 // from the differences to row k-1 (dLm, dum, dvm) and to row k+1 (dLp, dup, dvp), with
-// L = g (eta + U) and U the Coriolis potential local to row k.  The difference between rows
+// L = g (eta + U) and U the Coriolis potential local to row k, carried as L / g.  The difference between rows
 // k and k+1 is the same whichever of the two rows the potential is local to, so each one is
 // computed once and serves both rows.
 struct YFace {
@@ -125,7 +127,7 @@ __device__ __forceinline__ void y_recon(float e, float u, float v, float dLm, fl
   const float sL = minmod3(dLm, (dLm + dLp) * C.k2t, dLp);
   const float su = minmod3(dum, (dum + dup) * C.k2t, dup);
   const float sv = minmod3(dvm, (dvm + dvp) * C.k2t, dvp);
-  const float off = C.tg * sL - C.fyg * u;
+  const float off = C.ht * sL - C.fyg * u;  // sL: slope of L / g divided by theta
   N.e = e + off;
   S.e = e - off;
   N.n = v + C.ht * sv;
@@ -157,7 +159,7 @@ struct StagePipe {
                                        float& oq, float& orr) {
     const float rh = rcpf(C.H + e);
     const float u = q * rh, v = r * rh;
-    const float dLn = C.g * (e - eb) + C.hfdy * (ub + u);  // rows m and m-1
+    const float dLn = (e - eb) + C.fyg * (ub + u);  // L / g, rows m and m-1
     const float dun = u - ub, dvn = v - vb;
     YFace Nb = {}, Sb = {};
     if (MODE != kPushStore) y_recon(eb, ub, vb, dL, du, dv, dLn, dun, dvn, C, Nb, Sb);  // row m-1
