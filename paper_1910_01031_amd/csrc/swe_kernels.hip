@@ -52,14 +52,10 @@ __device__ __forceinline__ float minmod3(float a, float b, float c) {
   return __builtin_amdgcn_fmed3f(lo, hi, 0.0f);
 }
 
-// The limited slope divided by theta: minmod(theta a, c, theta b) = theta minmod(a, c /
-// theta, b) for theta > 0, with a = q0 - qm, b = qp - q0 and c = (qp - qm) / 2, so the
-// minmod takes the two one-sided differences as they are and only the central one is
-// scaled (by 1/(2 theta)); theta goes into the constants that turn the slope into face
-// offsets.
-__device__ __forceinline__ float limited_t(float qm, float q0, float qp, float k2t) {
-  return minmod3(q0 - qm, (qp - qm) * k2t, qp - q0);
-}
+// The limiters below work on the slope divided by theta: minmod(theta a, c, theta b) =
+// theta minmod(a, c / theta, b) for theta > 0, with the one-sided differences a, b and the
+// central one c = (a + b) / 2, so only the central difference is scaled (by 1/(2 theta));
+// theta goes into the constants that turn the slope into face offsets.
 
 // Central-upwind flux between a left (-) and right (+) face state (eta, normal velocity,
 // tangential velocity).  Outputs mass, normal-momentum and tangential-momentum fluxes.
@@ -88,16 +84,18 @@ __device__ __forceinline__ void cu_flux(float eL, float nL, float tL, float eR, 
 // x-direction flux divergence F_{j+1/2} - F_{j-1/2} of one row (mass, hu, hv).
 __device__ __forceinline__ void x_divergence(float e, float u, float v, const SweConst& C,
                                              float& d0, float& d1, float& d2) {
-  const float eW_ = lane_prev(e), eE_ = lane_next(e);
-  const float uW_ = lane_prev(u), uE_ = lane_next(u);
-  const float vW_ = lane_prev(v), vE_ = lane_next(v);
-  // K / g = eta - V / g: the potential in units of eta (V / g = +-f dx (v + v_nb) / (2 g))
-  const float Kc = e;
-  const float Kp = eE_ - C.fxg * (v + vE_);
-  const float Km = eW_ + C.fxg * (v + vW_);
-  const float sK = limited_t(Km, Kc, Kp, C.k2t);  // slopes divided by theta
-  const float su = limited_t(uW_, u, uE_, C.k2t);
-  const float sv = limited_t(vW_, v, vE_, C.k2t);
+  const float eE_ = lane_next(e), uE_ = lane_next(u), vE_ = lane_next(v);
+  // Differences to the next cell, of K / g = eta - V / g (the potential in units of eta,
+  // V / g = +-f dx (v + v_nb) / (2 g)), u and v.  The difference between cells j and j+1 is
+  // the same whichever of the two the potential is local to, so the difference to the
+  // previous cell is the previous lane's.
+  const float bK = (eE_ - e) - C.fxg * (v + vE_);
+  const float bu = uE_ - u, bv = vE_ - v;
+  const float aK = lane_prev(bK), au = lane_prev(bu), av = lane_prev(bv);
+  // slopes divided by theta: minmod(a, (a + b) / (2 theta), b)
+  const float sK = minmod3(aK, (aK + bK) * C.k2t, bK);
+  const float su = minmod3(au, (au + bu) * C.k2t, bu);
+  const float sv = minmod3(av, (av + bv) * C.k2t, bv);
   // eta^{E,W} = eta +- (sigma_K + f dx v) / (2 g) = eta +- (theta sK / 2 + f dx v / (2 g));
   // u, v faces +- theta s / 2
   const float off = C.ht * sK + C.fxg * v;
