@@ -44,12 +44,12 @@ __device__ __forceinline__ float lane_next(float x) { return __shfl_down(x, 1, k
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float sqrtf_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// Generalized minmod of three slopes: the smallest if all three are positive, the largest if
-// all are negative, else 0 -- which is the median of (min, max, 0).
-__device__ __forceinline__ float minmod3(float a, float b, float c) {
-  const float lo = fminf(a, fminf(b, c));
-  const float hi = fmaxf(a, fmaxf(b, c));
-  return __builtin_amdgcn_fmed3f(lo, hi, 0.0f);
+// Generalized minmod of (a, c, b) where c has the sign of a + b (c = (a + b) / (2 theta)):
+// 0 unless a and b share a sign, else the one of the three nearest to 0, i.e.
+// minmod(minmod(a, b), c) with minmod(x, y) = median(x, y, 0).  The result is one of the
+// inputs or 0, so it is exact; two v_med3_f32.
+__device__ __forceinline__ float minmod3(float a, float c, float b) {
+  return __builtin_amdgcn_fmed3f(__builtin_amdgcn_fmed3f(a, b, 0.0f), c, 0.0f);
 }
 
 // The limiters below work on the slope divided by theta: minmod(theta a, c, theta b) =
