@@ -601,6 +601,9 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   S.dt = (float)(f.dt / f.n_sub);
   S.idx = (float)(1.0 / f.dx);
   S.idy = (float)(1.0 / f.dy);
+  S.dtidx = (float)(f.dt / f.n_sub / f.dx);
+  S.dtidy = (float)(f.dt / f.n_sub / f.dy);
+  S.dtf = (float)(f.dt / f.n_sub * f.f);
   S.c = c->c;
   S.nrx = c->nrx;
   S.nry = c->nry;

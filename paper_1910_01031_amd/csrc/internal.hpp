@@ -50,6 +50,7 @@ struct SweConst {
   float ht;            // theta / 2: face offset of u, v per limited slope
   float fxg, fyg;      // f dx / (2 g), f dy / (2 g): Coriolis potential / g increments
   float dt, idx, idy;  // scheme step, 1/dx, 1/dy
+  float dtidx, dtidy, dtf;  // dt/dx, dt/dy, dt f
   // fused model error (last scheme step of a model step)
   int c, nrx, nry;     // coarsening and coarse grid
   float gb_x, gb_y;    // g H / (2 f dx), g H / (2 f dy)

@@ -167,10 +167,11 @@ struct StagePipe {
     if (MODE == kPushFull) {
       float x0, x1, x2;
       x_divergence(ea, ua, va, C, x0, x1, x2);  // row m-2
-      const float dt = C.dt;
-      oe = ea + dt * (-x0 * C.idx - (G0 - g0) * C.idy);
-      oq = qa + dt * (-x1 * C.idx - (G2 - g2) * C.idy + C.f * ra);
-      orr = ra + dt * (-x2 * C.idx - (G1 - g1) * C.idy - C.f * qa);
+      // psi + dt L(psi) with dt/dx, dt/dy and dt f as constants (one fused multiply-add per
+      // term)
+      oe = ea - C.dtidx * x0 - C.dtidy * (G0 - g0);
+      oq = qa + C.dtf * ra - C.dtidx * x1 - C.dtidy * (G2 - g2);
+      orr = ra - C.dtf * qa - C.dtidx * x2 - C.dtidy * (G1 - g1);
     } else {
       oe = oq = orr = 0.0f;
     }
