@@ -148,7 +148,7 @@ struct StagePipe {
   // rows m-2 ("a") and m-1 ("b")
   float ea, qa, ra, ua, va;
   float eb, qb, rb, ub, vb;
-  float dL, du, dv;  // y differences between rows m-1 and m-2 (potential local to either)
+  float dL, du, dv;  // y differences of L / g, u, v between rows m-1 and m-2 (potential local to either)
   YFace Na;          // north face state of row m-2
   float g0, g1, g2;  // y flux at face (m-2) - 1/2: mass, hv (normal), hu (tangential)
 
