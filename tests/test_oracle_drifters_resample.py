@@ -101,3 +101,17 @@ def test_sir_log_weights():
     d = np.array([[[1.0, 2.0]], [[0.0, 0.0]]])
     lw = resample.sir_log_weights(d, 2.0)
     assert np.allclose(lw, [-0.5 * 5 / 4, 0.0])
+
+
+def test_sir_weights_are_the_normalised_gaussian_likelihood():
+    # eq. standardParticleFilterWeight: w_i proportional to p(y | psi_i), Gaussian with
+    # R = sigma^2 I; held against scipy's normal density of every innovation component
+    from scipy.stats import norm
+    rng = np.random.default_rng(12)
+    d = rng.normal(scale=1.3, size=(9, 6, 2))
+    for sigma in (0.8, 1.0, 2.5):
+        lw = resample.sir_log_weights(d, sigma)
+        w = np.exp(lw - lw.max())
+        w /= w.sum()
+        lik = np.prod(norm.pdf(d, loc=0.0, scale=sigma), axis=(1, 2))
+        assert np.abs(w - lik / lik.sum()).max() < 1e-13
