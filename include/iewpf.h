@@ -128,8 +128,15 @@ int iewpf_perturb(iewpf_ctx* ctx, float* state, uint64_t step_index, void* strea
  * one-stage IEWPF of Appendix A (eq. iewpfUpdateAgain: no nu term; target weight
  * max_i c_i, eq. iewpf_targetWeight; c*_i = target - c_i, eq. iewpfCStar; alpha_i by eq.
  * iewpfAlphaSol).  With 1, stats_out->cbar is the target weight, beta is 0 and argmin_beta
- * is the particle with the largest c_i.  A batch's graph keeps the scheme its contexts had
- * at its first cycle. */
+ * is the particle with the largest c_i.  2 the standard particle filter (Section "Standard
+ * particle filter"): log-weights l_i = -1/2 sum_o d^T R^{-1} d from the eta-compensated
+ * innovations (eq. standardParticleFilterWeight), residual resampling with uniforms from
+ * stream (analysis_index, tag 6) and the parents' states copied in (their indices: buffer 10
+ * of iewpf_read_buffer); stats_out then has c_min / c_max = the range of -2 l_i,
+ * argmin_beta = the particle of largest weight and the IEWPF fields 0; a non-finite l_i
+ * leaves the state untouched and returns IEWPF_E_NONFINITE.  Scheme 2 needs 3 nx ny to be a
+ * multiple of 4 (IEWPF_E_SHAPE) and is not available to batches.  A batch's graph keeps the
+ * scheme its contexts had at its first cycle. */
 int iewpf_set_scheme(iewpf_ctx* ctx, int scheme);
 
 /* Full innovation covariance on (1) or off (0, the default).  The paper treats observations
@@ -153,9 +160,13 @@ int iewpf_set_full_innovation(iewpf_ctx* ctx, int on);
  * posterior update.  obs_host: n_obs host records (copied; the pointer may be reused
  * when the call returns).  The per-call observation index lists are built on the host
  * and uploaded with the values in one copy; when the cells equal the previous call's
- * (moorings), only the values are uploaded.  stats_out: host pointer or NULL; when non-NULL the call waits
- * for the stream and fills it.  beta <= 0 is reported through stats (beta) and by the
- * return code IEWPF_E_BETA only when stats_out is non-NULL. */
+ * (moorings), only the values are uploaded.  stats_out: host pointer or NULL (filled when
+ * non-NULL).  The call waits for the analysis to finish and checks its status words:
+ *   IEWPF_E_BETA       beta <= 0 (eq. betaTwoStage: the ensemble violates N_psi >> N_y);
+ *                      the state is left untouched (stats_out still holds beta)
+ *   IEWPF_E_NONFINITE  a non-finite c_i, gamma_i, zeta_i, c*_i or alpha_i (the state is left
+ *                      untouched), or a non-finite value in an updated particle (the state
+ *                      is updated; the message names the first such particle). */
 int iewpf_assimilate(iewpf_ctx* ctx, float* state, const iewpf_obs* obs_host, int n_obs,
                      uint64_t analysis_index, iewpf_stats* stats_out, void* stream);
 
@@ -170,6 +181,26 @@ int iewpf_particle_scalars(iewpf_ctx* ctx, double* out, void* stream);
 int iewpf_observe_moorings(iewpf_ctx* ctx, const float* truth, const int32_t* cells_host,
                            int n_obs, uint64_t analysis_index, iewpf_obs* obs_host,
                            void* stream);
+
+/* Drifter observations of a truth run (eq. drifterObservation): drifter d at unwrapped
+ * positions pos_prev and pos_now (device float64 [n][2], metres) at two observation times
+ * dt_obs seconds apart observes y_d = (pos_now - pos_prev) / dt_obs * H + obs_sigma * n, n from
+ * stream (analysis_index, tag 4, ensemble_id, particle word 1), normals 2d and 2d+1; its
+ * observed cell is (floor(x/dx) mod nx, floor(y/dy) mod ny) of pos_now (eq.
+ * stateObservation).  Writes n records to obs_host (waits for the stream).  n <= max_obs
+ * (IEWPF_E_CAPACITY), dt_obs > 0. */
+int iewpf_observe_drifters(iewpf_ctx* ctx, const double* pos_now, const double* pos_prev, int n,
+                           double dt_obs, uint64_t analysis_index, iewpf_obs* obs_host,
+                           void* stream);
+
+/* Log-weights of the standard particle filter (Section "Standard particle filter", eq.
+ * standardParticleFilterWeight): l_i = -1/2 sum_o d_io^T R^{-1} d_io with the eta-compensated
+ * innovations d (eq. etaCompensatedInnovation) and R = r_scale obs_sigma^2 I, float64.
+ * logw: device float64 [n_particles]; w_out: device float64 [n_particles] or NULL, the
+ * normalised weights exp(l_i - max l) / sum_j exp(l_j - max l).  obs_host is copied (n_obs <=
+ * max_obs).  Feeds iewpf_resample. */
+int iewpf_sir_log_weights(iewpf_ctx* ctx, const float* state, const iewpf_obs* obs_host, int n_obs,
+                          double r_scale, double* logw, double* w_out, void* stream);
 
 /* Drifter forecast: n_model_steps stochastic model steps (model error after every step,
  * stream first_step + s) while n_drifters drifters per particle are advected by Heun's
@@ -200,7 +231,8 @@ int iewpf_check_cfl(iewpf_ctx* ctx, const float* state, double* dt_out, void* st
  * which: 0 xi [Ne][NR] f32, 1 nu~ [Ne][NR] f32, 2 r' [Ne][NR] f32, 3 S 2x2 f64,
  * 4 S_c 2x2 f64, 5 A^{1/2} 49x49 f64, 6 pull windows [2][3][W][W] f32 with W given by
  * iewpf_window_size, 7 S d of the last analysis [Ne][n_obs][2] f64, 8 model-error SOAR
- * stencil 5x5 f64, 9 the full S [2 n_obs][2 n_obs] f64 of the last full-covariance analysis.
+ * stencil 5x5 f64, 9 the full S [2 n_obs][2 n_obs] f64 of the last full-covariance analysis,
+ * 10 the parents [Ne] int32 of the last standard-particle-filter analysis (scheme 2).
  * bytes must equal the buffer size. */
 int iewpf_read_buffer(iewpf_ctx* ctx, int which, void* host_out, size_t bytes, void* stream);
 
@@ -237,7 +269,10 @@ int iewpf_batch_set_cells(iewpf_batch* b, int e, const int32_t* cells_host, int 
  * [n_obs_e][2] for the cells set above).  use_graph != 0: the first call captures the whole
  * cycle into one hipGraph (on an internal stream ordered after `stream`) and later calls
  * replay it; the step and analysis indices are then read from device memory and y is
- * copied in before each replay.  A different n_model_steps recaptures. */
+ * copied in before each replay.  A different n_model_steps recaptures.  The call waits for
+ * the cycle and returns the first ensemble's analysis error as iewpf_assimilate does
+ * (IEWPF_E_BETA, IEWPF_E_NONFINITE; the message names the ensemble; an ensemble whose
+ * analysis stopped before writing keeps its forecast). */
 int iewpf_batch_cycle(iewpf_batch* b, int n_model_steps, uint64_t first_step,
                       uint64_t analysis_index, const double* const* y_host, int use_graph,
                       void* stream);
@@ -261,6 +296,10 @@ int iewpf_net_set_params(iewpf_net* net, const float* host, size_t count, void* 
 int iewpf_net_get_params(iewpf_net* net, float* host, size_t count, void* stream);
 /* Per-channel normalisation mu, sigma (inputs) and output scale s (3 floats each, host). */
 int iewpf_net_set_norm(iewpf_net* net, const float* mu, const float* sigma, const float* scale);
+/* Number of model steps one application of the network stands in for (the forecast window
+ * of its training pairs; 10 at creation).  The surrogate window and the surrogate drifter
+ * forecast refuse other window lengths (IEWPF_E_ARG).  n_model_steps >= 1. */
+int iewpf_net_set_horizon(iewpf_net* net, int n_model_steps);
 /* state_out = state_in + s * net((state_in - mu) / sigma); device [B][3][H][W] float32 each
  * (state_out may equal state_in). */
 int iewpf_net_forward(iewpf_net* net, const float* state_in, float* state_out, int B, int H,
@@ -282,7 +321,8 @@ int iewpf_net_read_activation(iewpf_net* net, int layer, uint16_t* host, size_t 
 int iewpf_net_gradients(iewpf_net* net, const float* x, const float* target, int B, int H, int W,
                         float* grads_host, float* loss_out, float* y_host, void* stream);
 /* One surrogate forecast window of the ensemble in place: the network replaces
- * n_model_steps deterministic model steps; every particle whose relative mass drift
+ * n_model_steps deterministic model steps (n_model_steps must equal the network's horizon,
+ * IEWPF_E_ARG otherwise); every particle whose relative mass drift
  * |sum(H + eta') - sum(H + eta)| / sum(H + eta) exceeds drift_tol is re-stepped by the
  * plain solver from its saved state; then one model-error draw (stream first_step +
  * n_model_steps - 1) scaled by noise_scale is added to all particles.  n_fallback_out: host,

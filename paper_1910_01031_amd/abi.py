@@ -37,7 +37,8 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_net_forward", "iewpf_net_train_step", "iewpf_net_read_activation",
             "iewpf_net_gradients",
             "iewpf_surrogate_window", "iewpf_forecast_drifters_surrogate",
-            "iewpf_set_full_innovation", "iewpf_set_scheme", "iewpf_last_error")
+            "iewpf_set_full_innovation", "iewpf_set_scheme", "iewpf_last_error",
+            "iewpf_observe_drifters", "iewpf_sir_log_weights", "iewpf_net_set_horizon")
 
 TRACE_KINDS = ("scheme_step", "me_normals", "soar", "gb_add", "innovation", "rand_dots",
                "beta_alpha", "posterior_coarse", "analysis_update", "scheme_step_noise",
@@ -140,6 +141,11 @@ def load(path: str = LIB_PATH):
                                                       ctypes.POINTER(ctypes.c_int32), vp]
     lib.iewpf_set_full_innovation.argtypes = [vp, i32]
     lib.iewpf_set_scheme.argtypes = [vp, i32]
+    lib.iewpf_observe_drifters.argtypes = [vp, vp, vp, i32, ctypes.c_double, u64,
+                                           ctypes.POINTER(IewpfObs), vp]
+    lib.iewpf_sir_log_weights.argtypes = [vp, vp, ctypes.POINTER(IewpfObs), i32, ctypes.c_double,
+                                          vp, vp, vp]
+    lib.iewpf_net_set_horizon.argtypes = [vp, i32]
     lib.iewpf_set_trace.argtypes = [vp, i32]
     lib.iewpf_trace_read.argtypes = [vp, f64p, vp, i32]
     lib.iewpf_net_num_params.restype = ctypes.c_size_t
@@ -244,9 +250,14 @@ class Context:
                                        _stream(stream)))
         return st.as_dict() if want_stats else None
 
-    def set_scheme(self, one_stage: bool):
-        """False: two-stage IEWPF (default); True: the one-stage scheme."""
-        _check(load().iewpf_set_scheme(self.h, 1 if one_stage else 0))
+    def set_scheme(self, scheme):
+        """0 / False: two-stage IEWPF (default); 1 / True: the one-stage scheme; 2: the
+        standard particle filter (SIR weights and residual resampling)."""
+        _check(load().iewpf_set_scheme(self.h, int(scheme)))
+
+    def sir_parents(self) -> np.ndarray:
+        """Parents of the last standard-particle-filter analysis (buffer 10)."""
+        return self.read_buffer(10, (self.cfg.n_particles,), np.int32)
 
     def set_full_innovation(self, on: bool):
         _check(load().iewpf_set_full_innovation(self.h, 1 if on else 0))
@@ -263,6 +274,26 @@ class Context:
         _check(load().iewpf_observe_moorings(self.h, _ptr(truth), cells.ctypes.data, n,
                                              analysis_index, arr, _stream(stream)))
         return np.array([[arr[o].y_hu, arr[o].y_hv] for o in range(n)])
+
+    def observe_drifters(self, pos_now, pos_prev, dt_obs: float, analysis_index: int,
+                         stream=None):
+        """Drifter observations (device float64 [n][2] positions): returns (cells int32
+        [n][2], y float64 [n][2])."""
+        n = int(pos_now.shape[0])
+        arr = (IewpfObs * max(n, 1))()
+        _check(load().iewpf_observe_drifters(self.h, _ptr(pos_now), _ptr(pos_prev), n, dt_obs,
+                                             analysis_index, arr, _stream(stream)))
+        cells = np.array([[arr[o].j, arr[o].k] for o in range(n)], dtype=np.int32).reshape(n, 2)
+        y = np.array([[arr[o].y_hu, arr[o].y_hv] for o in range(n)]).reshape(n, 2)
+        return cells, y
+
+    def sir_log_weights(self, state, cells: np.ndarray, y: np.ndarray, logw, w=None,
+                        r_scale: float = 1.0, stream=None):
+        """Standard-particle-filter log-weights into logw (device float64 [Ne]) and, when
+        given, the normalised weights into w."""
+        n = len(cells)
+        _check(load().iewpf_sir_log_weights(self.h, _ptr(state), obs_array(cells, y), n,
+                                            float(r_scale), _ptr(logw), _ptr(w), _stream(stream)))
 
     def forecast_drifters(self, state, pos, n_model_steps: int, first_step: int, traj=None,
                           stream=None):
@@ -386,6 +417,10 @@ class Net:
         out = np.zeros(self.num_params, dtype=np.float32)
         _check(load().iewpf_net_get_params(self.h, out.ctypes.data, out.size, _stream(stream)))
         return out
+
+    def set_horizon(self, n_model_steps: int):
+        """Model steps one application of the network stands in for (10 at creation)."""
+        _check(load().iewpf_net_set_horizon(self.h, int(n_model_steps)))
 
     def set_norm(self, mu, sigma, scale):
         arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (mu, sigma, scale)]

@@ -71,9 +71,9 @@ struct Mat2 {
 };
 
 __global__ __launch_bounds__(kThreads) void innovation_kernel(
-    int n_obs, int max_obs, int nx, int ny, double H, Mat2 S, const float* __restrict__ psi,
-    const int32_t* __restrict__ cells, const double* __restrict__ y, double* __restrict__ sd,
-    double* __restrict__ cval) {
+    int n_obs, int max_obs, int nx, int ny, double H, Mat2 S, double out_scale,
+    const float* __restrict__ psi, const int32_t* __restrict__ cells, const double* __restrict__ y,
+    double* __restrict__ sd, double* __restrict__ cval) {
   __shared__ double sh[kThreads];
   const int i = blockIdx.x;
   const size_t ncell = (size_t)nx * ny;
@@ -93,7 +93,43 @@ __global__ __launch_bounds__(kThreads) void innovation_kernel(
     phi += d0 * s0 + d1 * s1;
   }
   phi = block_sum(phi, sh);
-  if (threadIdx.x == 0) cval[i] = phi;
+  if (threadIdx.x == 0) cval[i] = out_scale * phi;
+}
+
+// Normalised weights of the standard particle filter from log-weights (one workgroup):
+// w_i = exp(l_i - max l) / sum_j exp(l_j - max l), the sum in a fixed order.
+__global__ __launch_bounds__(kThreads) void sir_normalise_kernel(int ne, const double* __restrict__ logw,
+                                                                 double* __restrict__ w) {
+  __shared__ double sh[kWavesPerBlock];
+  double m = -INFINITY;
+  for (int i = threadIdx.x; i < ne; i += kThreads) m = fmax(m, logw[i]);
+  m = -block_min(-m, sh);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < ne; i += kThreads) s += exp(logw[i] - m);
+  s = block_sum(s, sh);
+  for (int i = threadIdx.x; i < ne; i += kThreads) w[i] = exp(logw[i] - m) / s;
+}
+
+// Drifter observations (eq. drifterObservation): displacement over the observation interval
+// times the equilibrium depth, plus noise from stream (step, tag 4, ens, particle word 1);
+// the observed cell is the one holding the current position (eq. stateObservation).
+__global__ void observe_drifters_kernel(int n, int nx, int ny, double dx, double dy, double H,
+                                        double sigma, double dt_obs, uint64_t seed, uint64_t step,
+                                        uint32_t ens, const double* __restrict__ pos_now,
+                                        const double* __restrict__ pos_prev,
+                                        int32_t* __restrict__ cells, double* __restrict__ y) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= n) return;
+  const double px = pos_now[2 * d], py = pos_now[2 * d + 1];
+  long long j = (long long)floor(px / dx) % nx;
+  long long k = (long long)floor(py / dy) % ny;
+  cells[2 * d] = (int32_t)(j < 0 ? j + nx : j);
+  cells[2 * d + 1] = (int32_t)(k < 0 ? k + ny : k);
+  double z[4];
+  normals4((2 * d) / 4, step, 4u, ens, 1, seed, z);
+  const int l = (2 * d) % 4;
+  y[2 * d] = (px - pos_prev[2 * d]) / dt_obs * H + sigma * z[l];
+  y[2 * d + 1] = (py - pos_prev[2 * d + 1]) / dt_obs * H + sigma * z[l + 1];
 }
 
 // grid (parts, ne): part q of particle i handles Philox blocks q*kThreads + t + k*stride
@@ -285,6 +321,7 @@ __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, do
   const double cbar = one_stage ? -bb : cmean;  // the target weight
   const int argmin = ii;
   double amin = 1e300, amax = -1e300, csmax = 0.0, cmin = 1e300, cmax = -1e300;
+  double first_bad = 1e300;  // smallest particle with a non-finite scalar
   for (int i = threadIdx.x; i < ne; i += kThreads) {
     const double gamma = dots[3 * i] * scale;
     const double zeta = dots[3 * i + 1] * scale;
@@ -297,13 +334,27 @@ __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, do
     csmax = fmax(csmax, cs);
     cmin = fmin(cmin, cval[i]);
     cmax = fmax(cmax, cval[i]);
+    // fmax/fmin drop NaN operands, so non-finite values are caught here, not by the ranges
+    const bool finite = isfinite(cval[i]) && isfinite(gamma) && isfinite(zeta) && isfinite(cs) &&
+                        isfinite(a);
+    if (!finite) first_bad = fmin(first_bad, (double)i);
   }
   // min / max reductions (order independent)
-  const double vals[5] = {amin, -amax, -csmax, cmin, -cmax};
-  double outv[5];
+  const double vals[6] = {amin, -amax, -csmax, cmin, -cmax, first_bad};
+  double outv[6];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) outv[q] = block_min(vals[q], sh);
+  for (int q = 0; q < 6; ++q) outv[q] = block_min(vals[q], sh);
   if (threadIdx.x == 0) {
+    // status words read by the posterior and update kernels (which write nothing when an
+    // error bit is set) and by the host after the analysis
+    int32_t* st = reinterpret_cast<int32_t*>(scal + kScalStatus);
+    int flags = 0;
+    if (outv[5] < 1e300) flags |= kStatNonfiniteScalar;
+    if (!one_stage && !(beta > 0.0)) flags |= kStatBeta;
+    st[0] = flags;
+    st[1] = outv[5] < 1e300 ? static_cast<int32_t>(outv[5]) : -1;
+    st[2] = 0;           // set by the update kernel when a written value is not finite
+    st[3] = 0x7fffffff;  // smallest such particle (atomic minimum)
     scal[0] = cbar;
     scal[1] = beta;
     scal[2] = outv[0];
@@ -566,6 +617,7 @@ __global__ __launch_bounds__(kPcTile * kPcTile) void posterior_coarse_kernel(
     const int32_t* __restrict__ pt_off, const int32_t* __restrict__ pt_ent,
     float* __restrict__ rout) {
   __shared__ double rl[kPcW * kPcW];
+  if (reinterpret_cast<const int32_t*>(scal + kScalStatus)[0] & kStatSkipUpdate) return;
   const int nr = C.nrx * C.nry;
   const int i = blockIdx.z;
   const int tx0 = blockIdx.x * kPcTile, ty0 = blockIdx.y * kPcTile;
@@ -720,10 +772,37 @@ __global__ void drift_k2_kernel(int ne, int nd, int nx, int ny, double dx, doubl
 
 // Residual resampling (Section "Standard particle filter"), one work-item: the decisions
 // are integer and sequential over at most a few thousand particles.
+// scal != nullptr (the SIR analysis): also writes the analysis scalars (c_min / c_max =
+// range of -2 l_i, argmin_beta = the particle of largest weight, the IEWPF fields 0) and the
+// status words; a non-finite log-weight flags the analysis and keeps the ensemble as it is.
 __global__ void resample_kernel(int ne, uint64_t seed, uint64_t step, uint32_t ens,
                                 const double* __restrict__ logw, int32_t* __restrict__ parents,
-                                int32_t* __restrict__ counts, double* __restrict__ cum) {
+                                int32_t* __restrict__ counts, double* __restrict__ cum,
+                                double* __restrict__ scal) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  if (scal) {
+    int bad = -1, best = 0;
+    double lo = logw[0], hi = logw[0];
+    for (int i = 0; i < ne; ++i) {
+      if (!isfinite(logw[i]) && bad < 0) bad = i;
+      if (logw[i] > logw[best]) best = i;
+      lo = fmin(lo, logw[i]);
+      hi = fmax(hi, logw[i]);
+    }
+    for (int q = 0; q < 5; ++q) scal[q] = 0.0;
+    scal[5] = -2.0 * hi;
+    scal[6] = -2.0 * lo;
+    scal[7] = (double)best;
+    int32_t* st = reinterpret_cast<int32_t*>(scal + kScalStatus);
+    st[0] = bad >= 0 ? kStatNonfiniteScalar : 0;
+    st[1] = bad;
+    st[2] = 0;
+    st[3] = 0x7fffffff;
+    if (bad >= 0) {
+      for (int i = 0; i < ne; ++i) parents[i] = i;
+      return;
+    }
+  }
   double m = logw[0];
   for (int i = 1; i < ne; ++i) m = fmax(m, logw[i]);
   double s = 0.0;
@@ -781,10 +860,22 @@ __global__ void gather_kernel(size_t per_particle4, const int32_t* __restrict__ 
 
 void launch_innovation(int ne, int n_obs, int max_obs, int nx, int ny, double H, const double S[4],
                        const float* psi, const int32_t* cells, const double* y, double* sd,
-                       double* cval, hipStream_t s) {
+                       double* cval, hipStream_t s, double out_scale) {
   Mat2 M{{S[0], S[1], S[2], S[3]}};
   hipLaunchKernelGGL(innovation_kernel, dim3(ne), dim3(kThreads), 0, s, n_obs, max_obs, nx, ny, H,
-                     M, psi, cells, y, sd, cval);
+                     M, out_scale, psi, cells, y, sd, cval);
+}
+
+void launch_sir_normalise(int ne, const double* logw, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(sir_normalise_kernel, dim3(1), dim3(kThreads), 0, s, ne, logw, w);
+}
+
+void launch_observe_drifters(int n, int nx, int ny, double dx, double dy, double H, double sigma,
+                             double dt_obs, uint64_t seed, uint64_t step, uint32_t ens,
+                             const double* pos_now, const double* pos_prev, int32_t* cells,
+                             double* y, hipStream_t s) {
+  hipLaunchKernelGGL(observe_drifters_kernel, dim3((n + 127) / 128), dim3(128), 0, s, n, nx, ny, dx,
+                     dy, H, sigma, dt_obs, seed, step, ens, pos_now, pos_prev, cells, y);
 }
 
 int rand_dots_parts() { return kDotParts; }
@@ -885,8 +976,6 @@ void launch_drift_k2(int ne, int nd, int nx, int ny, double dx, double dy, doubl
                      H, dt, psi, psi_b ? psi_b : psi, psi_b ? w : 0.0, pos, k1, pstar, traj);
 }
 
-void launch_resample(int ne, uint64_t seed, uint64_t step, uint32_t ens, const double* logw,
-                     int32_t* parents, int32_t* counts, hipStream_t s);
 
 void launch_gather_particles(int ne, size_t per_particle, const int32_t* parents, const float* in,
                              float* out, hipStream_t s) {
@@ -898,9 +987,9 @@ void launch_gather_particles(int ne, size_t per_particle, const int32_t* parents
 }
 
 void launch_resample(int ne, uint64_t seed, uint64_t step, uint32_t ens, const double* logw,
-                     int32_t* parents, int32_t* counts, double* cum, hipStream_t s) {
+                     int32_t* parents, int32_t* counts, double* cum, hipStream_t s, double* scal) {
   hipLaunchKernelGGL(resample_kernel, dim3(1), dim3(64), 0, s, ne, seed, step, ens, logw, parents,
-                     counts, cum);
+                     counts, cum, scal);
 }
 
 }  // namespace iewpf

@@ -28,6 +28,7 @@ struct iewpf_batch {
   uint64_t* d_dyn = nullptr;      // device counters: first step, analysis index
   uint64_t* h_dyn = nullptr;      // pinned
   double* h_y = nullptr;          // pinned observation values
+  int32_t* h_status = nullptr;    // pinned analysis status words, 4 per ensemble
   size_t h_y_len = 0;
   hipEvent_t copy_ev = nullptr;
   bool copy_pending = false;
@@ -113,7 +114,7 @@ void free_ctx(iewpf_ctx* c) {
                   c->coarse, c->coarse2, c->windows,
                   c->dmat,    c->sd,     c->cval,   c->dots,   c->alpha,   c->cstar,
                   c->scal,    c->d_stage, c->dk1,    c->dpstar, c->dobs,   c->cflmax,  c->dparents,
-                  c->dcum};
+                  c->dcum,    c->sir_parents, c->dobs_cells};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
@@ -303,10 +304,41 @@ int prepare_full_s(iewpf_ctx* c, const int32_t* cells, int n_obs, hipStream_t s)
   return 0;
 }
 
+// Return code of an analysis from its status words (host copy): non-finite scalars first
+// (nothing was written), then beta <= 0 (nothing was written), then non-finite values written
+// by the update.  `who` prefixes the message (the ensemble of a batch).
+int analysis_status(const int32_t* st, const std::string& who) {
+  if (st[0] & kStatNonfiniteScalar)
+    return fail(IEWPF_E_NONFINITE, who + "non-finite c_i, gamma_i, zeta_i, c*_i or alpha_i in particle " +
+                                       std::to_string(st[1]) + "; the state was not updated");
+  if (st[0] & kStatBeta)
+    return fail(IEWPF_E_BETA, who + "beta <= 0: ensemble violates N_psi >> N_y; the state was not updated");
+  if (st[2] & kStatNonfiniteState)
+    return fail(IEWPF_E_NONFINITE, who + "non-finite value in the analysed state of particle " +
+                                       std::to_string(st[3]));
+  return 0;
+}
+
 // The analysis kernels of one ensemble on the observations already on the device.
 // dyn: device counters (dyn[1] = analysis index added to analysis_index) or nullptr.
 int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_index,
                     const uint64_t* dyn, hipStream_t s) {
+  if (c->sir) {
+    // standard particle filter: l_i = -1/2 sum_o d^T R^{-1} d, residual resampling, and the
+    // parents' states gathered through the scratch buffer
+    const double r = c->cfg.obs_sigma * c->cfg.obs_sigma;
+    const double Rinv[4] = {1.0 / r, 0.0, 0.0, 1.0 / r};
+    launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, Rinv, state, c->obs_cells,
+                      c->obs_y, c->sd, c->cval, s, -0.5);
+    launch_resample(c->ne, c->cfg.seed, analysis_index, c->cfg.ensemble_id, c->cval, c->sir_parents,
+                    c->dparents, c->dcum, s, c->scal);
+    const size_t per = 3 * c->ncell;
+    launch_gather_particles(c->ne, per, c->sir_parents, state, c->scratch, s);
+    IEWPF_HIP_TRY(hipMemcpyAsync(state, c->scratch, sizeof(float) * per * c->ne,
+                                 hipMemcpyDeviceToDevice, s));
+    IEWPF_HIP_TRY(hipGetLastError());
+    return 0;
+  }
   // stages 1-2: innovations, S d, c_i
   {
     TraceScope tr(c, kTrInnov, s);
@@ -354,7 +386,7 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
   {
     TraceScope tr(c, kTrUpdate, s);
     launch_analysis_update(c->cc, P, c->ne, c->coarse, c->windows, c->sd, c->max_obs, c->obs_cells,
-                           c->st_off, c->st_ent, state, s);
+                           c->st_off, c->st_ent, state, c->scal, s);
   }
   IEWPF_HIP_TRY(hipGetLastError());
   return 0;
@@ -466,6 +498,20 @@ int batch_cycle_body(iewpf_batch* b, int n_steps, uint64_t first_step, uint64_t 
   });
 }
 
+// Status words of every ensemble's analysis after a cycle on s: copied to pinned host memory,
+// then waited for; returns the first ensemble's error (an ensemble whose analysis failed
+// before writing keeps its forecast state).
+int batch_status(iewpf_batch* b, hipStream_t s) {
+  for (int e = 0; e < b->n; ++e)
+    IEWPF_HIP_TRY(hipMemcpyAsync(b->h_status + 4 * e, b->ctx[e]->scal + kScalStatus,
+                                 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  for (int e = 0; e < b->n; ++e)
+    if (int rc = analysis_status(b->h_status + 4 * e, "ensemble " + std::to_string(e) + ": "))
+      return rc;
+  return 0;
+}
+
 void free_batch(iewpf_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -475,6 +521,7 @@ void free_batch(iewpf_batch* b) {
   if (b->d_dyn) (void)hipFree(b->d_dyn);
   if (b->h_dyn) (void)hipHostFree(b->h_dyn);
   if (b->h_y) (void)hipHostFree(b->h_y);
+  if (b->h_status) (void)hipHostFree(b->h_status);
   if (b->copy_ev) (void)hipEventDestroy(b->copy_ev);
   if (b->in_ev) (void)hipEventDestroy(b->in_ev);
   if (b->out_ev) (void)hipEventDestroy(b->out_ev);
@@ -544,6 +591,9 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
     return fail(IEWPF_E_SHAPE, "the coarse grid needs at least 7 points per direction");
   if (12.0 * f.nx * f.ny >= 2147483648.0)  // the scheme kernel addresses a particle's state in 31-bit bytes
     return fail(IEWPF_E_SHAPE, "nx ny above 178,956,970 cells per particle is not supported");
+  // strip height of the scheme kernel (rows per wave); the environment may force it
+  const int forced = env_int("IEWPF_SWE_STRIP", 32);
+  if (forced < 1) return fail(IEWPF_E_ARG, "IEWPF_SWE_STRIP must be a positive number of rows");
   iewpf_ctx* c = new iewpf_ctx();
   c->cfg = f;
   c->nx = f.nx;
@@ -577,7 +627,6 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
     // (each wave marches strip_h + 8 rows of stage 1 and strip_h + 4 of stage 2)
     // 32 rows measured best on gfx950 at 500x300x100 (16..100 all within 10%); the
     // occupancy model only takes over when that would leave the GPU under-filled
-    const int forced = env_int("IEWPF_SWE_STRIP", 32);
     const int slots = device_slots(swe_waves_per_cu());
     int n_ys = (f.ny + forced - 1) / forced;
     if ((long long)S.n_strip_x * f.n_particles * n_ys < slots)
@@ -686,6 +735,8 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   rc |= dev_alloc(&c->cflmax, 2);
   rc |= dev_alloc(&c->dparents, (size_t)c->ne);
   rc |= dev_alloc(&c->dcum, (size_t)c->ne);
+  rc |= dev_alloc(&c->sir_parents, (size_t)c->ne);
+  rc |= dev_alloc(&c->dobs_cells, (size_t)c->max_obs * 2);
   if (rc) {
     free_ctx(c);
     return IEWPF_E_HIP;
@@ -763,8 +814,11 @@ int iewpf_perturb(iewpf_ctx* c, float* state, uint64_t step_index, void* stream)
 }
 
 int iewpf_set_scheme(iewpf_ctx* c, int scheme) {
-  if (!c || (scheme != 0 && scheme != 1)) return fail(IEWPF_E_ARG, "scheme must be 0 or 1");
-  c->one_stage = scheme;
+  if (!c || scheme < 0 || scheme > 2) return fail(IEWPF_E_ARG, "scheme must be 0, 1 or 2");
+  if (scheme == 2 && (3 * c->ncell) % 4 != 0)
+    return fail(IEWPF_E_SHAPE, "3 nx ny must be a multiple of 4 for the particle gather");
+  c->one_stage = scheme == 1;
+  c->sir = scheme == 2;
   return 0;
 }
 
@@ -809,14 +863,16 @@ int iewpf_assimilate(iewpf_ctx* c, float* state, const iewpf_obs* obs, int n_obs
   }
   if (int rc = check_cells(c, cells, n_obs)) return rc;
   if (int rc = upload_observations(c, n_obs, true, s)) return rc;
-  if (c->full_innov && n_obs > 0) {
+  if (c->full_innov && !c->sir && n_obs > 0) {
     if (int rc = prepare_full_s(c, cells, n_obs, s)) return rc;
   }
   if (int rc = launch_analysis(c, state, n_obs, analysis_index, nullptr, s)) return rc;
+  // scalars and status words of this analysis (one copy), then wait for it
+  IEWPF_HIP_TRY(hipMemcpyAsync(c->h_small, c->scal, sizeof(double) * (kScalStatus + 2),
+                               hipMemcpyDeviceToHost, s));
+  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  const double* v = c->h_small;
   if (stats_out) {
-    IEWPF_HIP_TRY(hipMemcpyAsync(c->h_small, c->scal, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
-    IEWPF_HIP_TRY(hipStreamSynchronize(s));
-    const double* v = c->h_small;
     stats_out->cbar = v[0];
     stats_out->beta = v[1];
     stats_out->alpha_min = v[2];
@@ -826,10 +882,8 @@ int iewpf_assimilate(iewpf_ctx* c, float* state, const iewpf_obs* obs, int n_obs
     stats_out->c_max = v[6];
     stats_out->argmin_beta = (int32_t)v[7];
     stats_out->n_obs = n_obs;
-    if (!c->one_stage && !(v[1] > 0.0))
-      return fail(IEWPF_E_BETA, "beta <= 0: ensemble violates N_psi >> N_y");
   }
-  return 0;
+  return analysis_status(reinterpret_cast<const int32_t*>(v + kScalStatus), "");
 }
 
 int iewpf_particle_scalars(iewpf_ctx* c, double* out, void* stream) {
@@ -882,6 +936,67 @@ int iewpf_observe_moorings(iewpf_ctx* c, const float* truth, const int32_t* cell
     obs_host[o].y_hu = c->h_small[2 * o];
     obs_host[o].y_hv = c->h_small[2 * o + 1];
   }
+  return 0;
+}
+
+int iewpf_observe_drifters(iewpf_ctx* c, const double* pos_now, const double* pos_prev, int n,
+                           double dt_obs, uint64_t analysis_index, iewpf_obs* obs_host,
+                           void* stream) {
+  if (!c || !pos_now || !pos_prev || !obs_host || n < 0 || !(dt_obs > 0))
+    return fail(IEWPF_E_ARG, "invalid argument");
+  if (n > c->max_obs) return fail(IEWPF_E_CAPACITY, "more drifters than max_obs");
+  if (n == 0) return 0;
+  hipStream_t s = as_stream(stream);
+  const auto& f = c->cfg;
+  launch_observe_drifters(n, c->nx, c->ny, f.dx, f.dy, f.H, f.obs_sigma, dt_obs, f.seed,
+                          analysis_index, f.ensemble_id, pos_now, pos_prev, c->dobs_cells, c->dobs, s);
+  IEWPF_HIP_TRY(hipGetLastError());
+  // y then the cells, one pinned buffer (h_small holds at least 2 max_obs doubles; the cells
+  // take max_obs more)
+  std::vector<int32_t> cells(2 * (size_t)n);
+  IEWPF_HIP_TRY(hipMemcpyAsync(c->h_small, c->dobs, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, s));
+  IEWPF_HIP_TRY(hipMemcpyAsync(cells.data(), c->dobs_cells, sizeof(int32_t) * 2 * n,
+                               hipMemcpyDeviceToHost, s));
+  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  for (int d = 0; d < n; ++d) {
+    obs_host[d].j = cells[2 * d];
+    obs_host[d].k = cells[2 * d + 1];
+    obs_host[d].y_hu = c->h_small[2 * d];
+    obs_host[d].y_hv = c->h_small[2 * d + 1];
+  }
+  return 0;
+}
+
+int iewpf_sir_log_weights(iewpf_ctx* c, const float* state, const iewpf_obs* obs, int n_obs,
+                          double r_scale, double* logw, double* w_out, void* stream) {
+  if (!c || !state || !logw || (n_obs > 0 && !obs) || n_obs < 0 || !(r_scale > 0))
+    return fail(IEWPF_E_ARG, "invalid argument");
+  if (n_obs > c->max_obs) return fail(IEWPF_E_CAPACITY, "more observations than max_obs");
+  hipStream_t s = as_stream(stream);
+  if (int rc = wait_stage(c)) return rc;
+  const StageLayout L = stage_layout(*c);
+  int32_t* cells = reinterpret_cast<int32_t*>(c->h_stage + L.cells);
+  double* y = reinterpret_cast<double*>(c->h_stage + L.y);
+  for (int o = 0; o < n_obs; ++o) {
+    cells[2 * o] = obs[o].j;
+    cells[2 * o + 1] = obs[o].k;
+    y[2 * o] = obs[o].y_hu;
+    y[2 * o + 1] = obs[o].y_hv;
+  }
+  if (int rc = check_cells(c, cells, n_obs)) return rc;
+  // cells and values only: the device lists no longer match the device cells
+  c->list_n = -1;
+  if (n_obs > 0)
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->d_stage, c->h_stage, L.y + sizeof(double) * 2 * n_obs,
+                                 hipMemcpyHostToDevice, s));
+  IEWPF_HIP_TRY(hipEventRecord(c->stage_ev, s));
+  c->stage_pending = true;
+  const double r = r_scale * c->cfg.obs_sigma * c->cfg.obs_sigma;
+  const double Rinv[4] = {1.0 / r, 0.0, 0.0, 1.0 / r};
+  launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, Rinv, state, c->obs_cells,
+                    c->obs_y, c->sd, logw, s, -0.5);
+  if (w_out) launch_sir_normalise(c->ne, logw, w_out, s);
+  IEWPF_HIP_TRY(hipGetLastError());
   return 0;
 }
 
@@ -990,6 +1105,7 @@ int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewp
       return fail(IEWPF_E_ARG, "batched ensembles need the same dt and n_sub");
     if (ctxs[e]->full_innov)
       return fail(IEWPF_E_ARG, "batched cycles use the independent-block innovation covariance");
+    if (ctxs[e]->sir) return fail(IEWPF_E_ARG, "batched cycles run the IEWPF, not the SIR filter");
   }
   iewpf_batch* b = new iewpf_batch();
   b->n = n;
@@ -1025,6 +1141,7 @@ int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewp
             hipHostMalloc(reinterpret_cast<void**>(&b->h_dyn), 2 * sizeof(uint64_t)) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void**>(&b->h_y), sizeof(double) * std::max<size_t>(ylen, 1)) ==
                 hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&b->h_status), sizeof(int32_t) * 4 * n) == hipSuccess &&
             hipEventCreateWithFlags(&b->copy_ev, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&b->in_ev, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&b->out_ev, hipEventDisableTiming) == hipSuccess &&
@@ -1106,7 +1223,10 @@ int iewpf_batch_cycle(iewpf_batch* b, int n_model_steps, uint64_t first_step,
   }
   IEWPF_HIP_TRY(hipEventRecord(b->copy_ev, run));
   b->copy_pending = true;
-  if (!use_graph) return batch_cycle_body(b, n_model_steps, first_step, analysis_index, nullptr, s);
+  if (!use_graph) {
+    if (int rc = batch_cycle_body(b, n_model_steps, first_step, analysis_index, nullptr, s)) return rc;
+    return batch_status(b, s);
+  }
 
   if (!b->exec || b->graph_steps != n_model_steps) {
     if (b->exec) {
@@ -1137,7 +1257,7 @@ int iewpf_batch_cycle(iewpf_batch* b, int n_model_steps, uint64_t first_step,
   IEWPF_HIP_TRY(hipGraphLaunch(b->exec, run));
   IEWPF_HIP_TRY(hipEventRecord(b->out_ev, run));
   IEWPF_HIP_TRY(hipStreamWaitEvent(s, b->out_ev, 0));
-  return 0;
+  return batch_status(b, run);
 }
 
 int iewpf_surrogate_window(iewpf_ctx* c, iewpf_net* net, float* state, int n_model_steps,
@@ -1145,6 +1265,10 @@ int iewpf_surrogate_window(iewpf_ctx* c, iewpf_net* net, float* state, int n_mod
                            int32_t* n_fallback_out, double* drift_out, void* stream) {
   if (!c || !net || !state || !n_fallback_out || n_model_steps < 1 || !(drift_tol >= 0))
     return fail(IEWPF_E_ARG, "invalid argument");
+  if (n_model_steps != net_horizon(net))
+    return fail(IEWPF_E_ARG, "n_model_steps (" + std::to_string(n_model_steps) +
+                                 ") differs from the network's horizon (" +
+                                 std::to_string(net_horizon(net)) + " model steps)");
   hipStream_t s = as_stream(stream);
   const size_t per = 3 * c->ncell;
   // each buffer on its own, so a call after a failed allocation retries what is missing
@@ -1310,6 +1434,10 @@ int iewpf_read_buffer(iewpf_ctx* c, int which, void* host_out, size_t bytes, voi
     case 8:
       if (!need(25 * sizeof(double))) break;
       std::memcpy(host_out, c->soar_me, bytes);
+      return 0;
+    case 10:
+      if (!need(sizeof(int32_t) * (size_t)c->ne)) break;
+      IEWPF_HIP_TRY(hipMemcpy(host_out, c->sir_parents, bytes, hipMemcpyDeviceToHost));
       return 0;
     default:
       return fail(IEWPF_E_ARG, "unknown buffer id");

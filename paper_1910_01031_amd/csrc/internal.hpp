@@ -88,6 +88,17 @@ struct PullConst {
   int strip_h, n_strip_x, n_strip_y;
 };
 
+// Analysis status words: int32 [4] at byte offset 8 * kScalStatus of the analysis scalars
+// (scal): [0] flags set by the sync kernel, [1] the first particle with a non-finite scalar
+// (or -1), [2] flags set by the update pass, [3] the first particle with a non-finite
+// updated value (0x7fffffff if none).  The posterior and update kernels write nothing when
+// [0] has kStatSkipUpdate bits, so such an analysis leaves the state untouched.
+constexpr int kScalStatus = 8;
+constexpr int kStatBeta = 1;             // two-stage beta <= 0 (eq. betaTwoStage)
+constexpr int kStatNonfiniteScalar = 2;  // c_i, gamma_i, zeta_i, c*_i or alpha_i not finite
+constexpr int kStatSkipUpdate = kStatBeta | kStatNonfiniteScalar;
+constexpr int kStatNonfiniteState = 4;   // a value written by the update is not finite
+
 constexpr int kWave = 64;
 constexpr int kSweHalo = 4;                   // lanes lost per side by the fused RK stages
 constexpr int kSweOut = kWave - 2 * kSweHalo;  // 56 output columns per wave
@@ -145,6 +156,8 @@ struct iewpf_ctx {
   double* dobs = nullptr;        // observation synthesis output [max_obs][2]
   unsigned* cflmax = nullptr;    // 2 words
   int32_t* dparents = nullptr;  // resampling scratch [ne]
+  int32_t* sir_parents = nullptr;  // parents of the last SIR analysis [ne]
+  int32_t* dobs_cells = nullptr;   // drifter observation synthesis: cells [max_obs][2]
   double* dcum = nullptr;       // resampling: cumulative residuals [ne]
   // pinned host staging
   unsigned char* h_stage = nullptr;
@@ -170,6 +183,7 @@ struct iewpf_ctx {
   // work matrix, raw innovations, status word
   bool full_innov = false;
   int one_stage = 0;  // 1: the one-stage scheme (target max c, no nu term)
+  int sir = 0;        // 1: the standard particle filter (SIR weights, residual resampling)
   double* windows64 = nullptr;
   double* fS = nullptr;
   double* fX = nullptr;
@@ -230,6 +244,7 @@ struct ConvArgs {
 };
 void launch_conv(const ConvArgs& A, int in_mode, int out_mode, hipStream_t s);
 int net_max_cells(const iewpf_net* n);
+int net_horizon(const iewpf_net* n);
 void launch_wgrad(const ConvArgs& A, int in_mode, const uint16_t* g, int gch, int cells_per_chunk,
                   float* part, hipStream_t s);
 void launch_bgrad(const uint16_t* g, int gch, int ncells, int cells_per_chunk, float* part,
@@ -272,10 +287,17 @@ void launch_gb_add(const CoarseConst& C, int ne, const float* z, const float* ba
 void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, const float* z,
                             const float* windows, const double* sd, int max_obs,
                             const int32_t* obs_cells, const int32_t* st_off,
-                            const int32_t* st_ent, float* psi, hipStream_t s);
+                            const int32_t* st_ent, float* psi, double* scal, hipStream_t s);
+// c_i = out_scale * sum_o d^T S d (out_scale = -1/2 and S = R^{-1} give the log-weights of
+// the standard particle filter)
 void launch_innovation(int ne, int n_obs, int max_obs, int nx, int ny, double H, const double S[4],
                        const float* psi, const int32_t* cells, const double* y, double* sd,
-                       double* cval, hipStream_t s);
+                       double* cval, hipStream_t s, double out_scale = 1.0);
+void launch_sir_normalise(int ne, const double* logw, double* w, hipStream_t s);
+void launch_observe_drifters(int n, int nx, int ny, double dx, double dy, double H, double sigma,
+                             double dt_obs, uint64_t seed, uint64_t step, uint32_t ens,
+                             const double* pos_now, const double* pos_prev, int32_t* cells,
+                             double* y, hipStream_t s);
 int rand_dots_parts();
 void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens, float* xi,
                       float* nu, double* part_dots, double* dots, hipStream_t s,
@@ -293,6 +315,8 @@ void launch_chol_solve(int n, int nrhs, const double* L, const double* rhs, int 
                        double* out, int out_stride, double* cval, hipStream_t s);
 void launch_sd_full(int n, int ne, int stride, const double* S, const double* D, double* SD,
                     double* cval, hipStream_t s);
+// Also writes the analysis status words (kScalStatus) that the posterior and update kernels
+// check before writing.
 void launch_sync(int ne, double n_psi, double n_r, int one_stage, const double* cval,
                  const double* dots, double* alpha, double* cstar, double* scal, hipStream_t s);
 void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,
@@ -312,7 +336,8 @@ void launch_drift_k2(int ne, int nd, int nx, int ny, double dx, double dy, doubl
                      const float* psi, double* pos, const double* k1, const double* pstar,
                      double* traj, hipStream_t s, const float* psi_b = nullptr, double w = 0.0);
 void launch_resample(int ne, uint64_t seed, uint64_t step, uint32_t ens, const double* logw,
-                     int32_t* parents, int32_t* counts, double* cum, hipStream_t s);
+                     int32_t* parents, int32_t* counts, double* cum, hipStream_t s,
+                     double* scal = nullptr);
 void launch_gather_particles(int ne, size_t per_particle, const int32_t* parents, const float* in,
                              float* out, hipStream_t s);
 }  // namespace iewpf

@@ -273,11 +273,13 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
     CoarseConst C, PullConst P, int ne, int total_waves, const float* __restrict__ zall,
     float* __restrict__ psi, const float* __restrict__ windows, const double* __restrict__ sd,
     int max_obs, const int32_t* __restrict__ cells, const int32_t* __restrict__ st_off,
-    const int32_t* __restrict__ st_ent) {
+    const int32_t* __restrict__ st_ent, double* __restrict__ scal) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave));
   if (wave >= total_waves) return;
+  int32_t* status = reinterpret_cast<int32_t*>(scal + kScalStatus);
+  if (status[0] & kStatSkipUpdate) return;  // beta <= 0 or non-finite scalars: state untouched
   const int per_group = P.n_strip_x * P.n_strip_y;
   const int group = wave / per_group;
   const int strip = wave - group * per_group;
@@ -344,9 +346,11 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
     }
   }
   float dm2[kPB], dm1[kPB];
+  float chk[kPB];  // stays 0 while every written value is finite (x * 0 is NaN for inf, NaN)
   CoarseWin win[kPB];
 #pragma unroll
   for (int p = 0; p < kPB; ++p) {
+    chk[p] = 0.0f;
     dm2[p] = dm1[p] = 0.0f;
     win[p].init(zall + (size_t)min(p0 + p, ne - 1) * C.nrx * C.nry, C, cx, wx, k0 - 1);
   }
@@ -432,15 +436,27 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
       }
 #pragma unroll
       for (int p = 0; p < kPB; ++p) {
-        st_buf(bs[p], bj, srow, se[p] + ae[p]);
-        st_buf(bs[p], bj, srow + fq, su_[p] + au[p]);
-        st_buf(bs[p], bj, srow + fr, sv_[p] + av[p]);
+        const float oe = se[p] + ae[p], ou = su_[p] + au[p], ov = sv_[p] + av[p];
+        st_buf(bs[p], bj, srow, oe);
+        st_buf(bs[p], bj, srow + fq, ou);
+        st_buf(bs[p], bj, srow + fr, ov);
+        chk[p] = fmaf(ov, 0.0f, fmaf(ou, 0.0f, fmaf(oe, 0.0f, chk[p])));
       }
     }
 #pragma unroll
     for (int p = 0; p < kPB; ++p) {
       dm2[p] = dm1[p];
       dm1[p] = d0[p];
+    }
+  }
+  // a particle with a non-finite written value: flag it (rare; the atomic minimum gives the
+  // same particle whatever the order of the waves)
+#pragma unroll
+  for (int p = 0; p < kPB; ++p) {
+    const bool bad = writer && p < np && !isfinite(chk[p]);
+    if (__ballot(bad) != 0 && lane == 0) {
+      atomicOr(status + 2, kStatNonfiniteState);
+      atomicMin(status + 3, p0 + p);
     }
   }
 }
@@ -486,11 +502,11 @@ int update_particle_group() { return kPB; }
 void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, const float* z,
                             const float* windows, const double* sd, int max_obs,
                             const int32_t* obs_cells, const int32_t* st_off,
-                            const int32_t* st_ent, float* psi, hipStream_t s) {
+                            const int32_t* st_ent, float* psi, double* scal, hipStream_t s) {
   const int groups = (ne + kPB - 1) / kPB;
   const int total = groups * P.n_strip_x * P.n_strip_y;
   hipLaunchKernelGGL(analysis_update_kernel, dim3((total + 3) / 4), dim3(256), 0, s, C, P, ne, total,
-                     z, psi, windows, sd, max_obs, obs_cells, st_off, st_ent);
+                     z, psi, windows, sd, max_obs, obs_cells, st_off, st_ent, scal);
 }
 
 }  // namespace iewpf

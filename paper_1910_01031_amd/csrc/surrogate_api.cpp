@@ -43,6 +43,7 @@ struct iewpf_net {
   float* h_loss = nullptr;
   int loss_blocks = 256;
   float mu[3] = {0, 0, 0}, sig[3] = {1, 1, 1}, s[3] = {1, 1, 1};
+  int horizon = 10;  // model steps one application of the network stands in for
 };
 
 namespace iewpf {
@@ -147,6 +148,7 @@ void forward_backward(iewpf_net* n, const float* x, const float* tgt, int B, int
 }  // namespace
 
 int net_max_cells(const iewpf_net* n) { return n ? n->max_cells : 0; }
+int net_horizon(const iewpf_net* n) { return n ? n->horizon : 0; }
 
 }  // namespace iewpf
 
@@ -242,6 +244,12 @@ int iewpf_net_set_norm(iewpf_net* n, const float* mu, const float* sigma, const 
     n->sig[c] = sigma[c];
     n->s[c] = scale[c];
   }
+  return 0;
+}
+
+int iewpf_net_set_horizon(iewpf_net* n, int n_model_steps) {
+  if (!n || n_model_steps < 1) return fail(IEWPF_E_ARG, "the horizon must be at least one model step");
+  n->horizon = n_model_steps;
   return 0;
 }
 

@@ -9,18 +9,19 @@ rank_histograms: independent data-assimilation experiments, each with its own tr
   gives flat histograms.  Experiments run 16 at a time as one batch (one hipGraph replay
   per cycle).
 
-sir_collapse: an ensemble assimilates drifters with the IEWPF, runs to the next
-  observation time, and the standard particle filter's normalised weights (depending on the
-  innovations and R only) are computed for random subsets of the drifters.  For each subset
-  size, the mean number of particles whose weight exceeds 1/N_e (those residual resampling
-  is guaranteed to keep) is reported, for R and for 10 R.
+sir_collapse: an ensemble assimilates drifter observations with the IEWPF, runs to the
+  next observation time, and the standard particle filter's normalised weights (depending on
+  the innovations and R only, computed by the library) are taken for random subsets of the
+  drifters.  For each subset size, the mean number of particles whose weight exceeds 1/N_e
+  (those residual resampling is guaranteed to keep) is reported, for R and for 10 R.
 
 drift_forecast: the large-ensemble drift forecast (1000 particles, 24 h of analyses on the
   225 moorings, then 12 h of drifter forecast with the plain model and the surrogate side by
   side): forecast error and spread per hour, throughput.
 
-Every model step and analysis runs in the library's kernels.  The ranks and weights are
-computed here from a handful of values read back.
+Every model step, analysis, observation and weight runs in the library's kernels; the
+ranks and the counts of weights above 1/N_e are taken here from a handful of values read
+back.
 Run as `python -m paper_1910_01031_amd.experiments` from the repository root (it uses the
 seeded workload recipes in `workloads/`).
 """
@@ -116,7 +117,13 @@ def rank_histograms(torch, n_experiments: int = 128, n_particles: int = 40, da_h
 def sir_collapse(torch, n_particles: int = 100, da_hours: float = 6.0, n_drifters: int = 64,
                  max_observed: int = 10, subsets: int = 50, seed: int = 0):
     """Mean number of particles with standard-particle-filter weight > 1/N_e for 1..max_observed
-    observed drifters (random subsets), with R and with 10 R."""
+    observed drifters (random subsets), with R and with 10 R.
+
+    The truth's drifters observe the current (eq. drifterObservation, observations every
+    5 minutes from the displacement over the interval); the ensemble assimilates all of
+    them with the IEWPF for da_hours and runs to the next observation time, where the
+    library computes the standard filter's normalised weights (eq.
+    standardParticleFilterWeight) from the eta-compensated innovations of each subset."""
     W = _workloads()
     dev = torch.device("cuda")
     cfg = W.paper_scale(n_particles)
@@ -129,41 +136,29 @@ def sir_collapse(torch, n_particles: int = 100, da_hours: float = 6.0, n_drifter
     tctx.init_ensemble(truth, base, stream_index=1)
     side = int(round(math.sqrt(n_drifters)))
     pos = torch.from_numpy(W.drifter_lattice(cfg, side, side)[None]).to(dev)
-    steps = 10
-
-    def drifter_cells():
-        p = pos[0].cpu().numpy()
-        j = np.floor(p[:, 0] / cfg.dx).astype(np.int64) % cfg.nx
-        k = np.floor(p[:, 1] / cfg.dy).astype(np.int64) % cfg.ny
-        return np.stack([j, k], axis=1).astype(np.int32)
+    steps = cfg.obs_every
 
     n_cyc = int(round(da_hours * 12))
     for cyc in range(n_cyc + 1):
+        prev = pos.clone()
         tctx.forecast_drifters(truth, pos, steps, first_step=cyc * steps)  # truth and drifters
-        cells = drifter_cells()
-        y = tctx.observe_moorings(truth, cells, analysis_index=cyc)
+        cells, y = tctx.observe_drifters(pos[0], prev[0], steps * cfg.dt, analysis_index=cyc)
         ctx.step_ensemble(ens, steps, first_step=cyc * steps, noise_on_last=False)
         if cyc < n_cyc:
             ctx.assimilate(ens, cells, y, analysis_index=cyc, want_stats=False)
-    torch.cuda.synchronize()
-    # innovations of every particle at every drifter (eq. etaCompensatedInnovation)
-    jj, kk = cells[:, 0], cells[:, 1]
-    st = ens[:, :, kk, jj].double().cpu().numpy()                 # [N_e][3][n_drifters]
-    scale = (cfg.H + st[:, 0]) / cfg.H
-    d = np.stack([y[None, :, 0] * scale - st[:, 1], y[None, :, 1] * scale - st[:, 2]], axis=2)
     rng = np.random.default_rng(seed)
+    lw = torch.zeros(n_particles, dtype=torch.float64, device=dev)
+    w = torch.zeros_like(lw)
     out = {"n_particles": n_particles, "da_hours": da_hours, "n_drifters": n_drifters,
-           "observed": list(range(1, max_observed + 1))}
-    for label, r in (("R", cfg.obs_sigma ** 2), ("10R", 10 * cfg.obs_sigma ** 2)):
+           "observed": list(range(1, max_observed + 1)), "observation": "drifters"}
+    for label, r_scale in (("R", 1.0), ("10R", 10.0)):
         means = []
         for m in range(1, max_observed + 1):
             kept = []
             for _ in range(subsets):
-                sub = rng.choice(n_drifters, size=m, replace=False)
-                logw = -0.5 * np.sum(d[:, sub, :] ** 2, axis=(1, 2)) / r
-                w = np.exp(logw - logw.max())
-                w /= w.sum()
-                kept.append(int(np.sum(w > 1.0 / n_particles)))
+                sub = np.sort(rng.choice(n_drifters, size=m, replace=False))
+                ctx.sir_log_weights(ens, cells[sub], y[sub], lw, w, r_scale=r_scale)
+                kept.append(int(np.sum(w.cpu().numpy() > 1.0 / n_particles)))
             means.append(float(np.mean(kept)))
         out[f"kept_{label}"] = means
     ctx.close()

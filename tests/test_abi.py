@@ -66,3 +66,17 @@ def test_invalid_configs_are_rejected(kw, code):
     assert rc == code
     assert lib.iewpf_last_error().decode()
     assert not h.value
+
+
+@pytest.mark.parametrize("value", ["0", "-3", "rows"])
+def test_forced_strip_height_must_be_positive(value, monkeypatch):
+    # the environment's strip height divides the grid height; non-positive values are
+    # refused before any HIP call
+    monkeypatch.setenv("IEWPF_SWE_STRIP", value)
+    lib = abi.load()
+    c = abi.make_config(W.tiny(), 16)
+    h = ctypes.c_void_p()
+    rc = lib.iewpf_create(ctypes.byref(c), ctypes.byref(h))
+    assert rc == abi.IEWPF_E_ARG
+    assert "IEWPF_SWE_STRIP" in lib.iewpf_last_error().decode()
+    assert not h.value

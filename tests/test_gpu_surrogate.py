@@ -325,6 +325,7 @@ def test_forced_drift_falls_back_to_the_plain_solver():
     forced = params[:5] + [(w5, b5 + np.array([1e3, 0.0, 0.0]))]
     net.set_params(_flat(forced).astype(np.float32))
     net.set_norm(*NORM)
+    net.set_horizon(1)  # the network stands in for one model step here
     st = x.clone()
     nf, drift = surrogate_window(ctx, net, st, 1, 0, drift_tol=1e-4, noise_scale=0.0)
     torch.cuda.synchronize()
@@ -384,7 +385,35 @@ def test_rejects_oversized_and_invalid_calls():
         net.set_params(np.zeros(net.num_params - 1, np.float32))
     with pytest.raises(IewpfError):
         net.set_norm([0, 0, 0], [1, 0, 1], [1, 1, 1])
+    with pytest.raises(IewpfError):
+        net.set_horizon(0)
     net.close()
+
+
+def test_window_length_must_match_the_horizon():
+    # a network trained for 10-step windows refuses other window lengths, for the window and
+    # the drifter forecast alike, and accepts them once its horizon says so
+    _need_gpu()
+    from paper_1910_01031_amd import IewpfError, forecast_drifters_surrogate, surrogate_window
+    from paper_1910_01031_amd import abi
+    cfg, ctx, net, params, x = _window_setup(n_particles=2)
+    net.set_params(_flat(params).astype(np.float32))
+    net.set_norm(*NORM)
+    st = x.clone()
+    with pytest.raises(IewpfError) as e:
+        surrogate_window(ctx, net, st, 5, 0, drift_tol=1e30, noise_scale=0.0)
+    assert e.value.code == abi.IEWPF_E_ARG
+    p = torch.from_numpy(np.stack([wl.drifter_lattice(cfg, 2, 2)] * 2)).cuda()
+    with pytest.raises(IewpfError) as e:
+        forecast_drifters_surrogate(ctx, net, st, p, 1, 5, 40, drift_tol=1e30, noise_scale=0.0)
+    assert e.value.code == abi.IEWPF_E_ARG
+    torch.cuda.synchronize()
+    assert torch.equal(st, x)  # nothing ran
+    net.set_horizon(5)
+    nf, _ = surrogate_window(ctx, net, st, 5, 0, drift_tol=1e30, noise_scale=0.0)
+    assert nf == 0
+    net.close()
+    ctx.close()
 
 
 def test_surrogate_drifter_forecast_matches_interpolated_heun():
