@@ -30,6 +30,11 @@ import workloads as W  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+N_CU, CLOCK_GHZ = 256, 2.4
+# VALU wave-instructions issued per clock per CU by a probe of eight independent non-packed
+# FP32 FMA chains per wave at 8 waves per SIMD: the attainable issue ceiling of a kernel
+# built without packed FP32 (1.27 at 4 waves per SIMD)
+VALU_ISSUE_CEILING = 1.49
 # Algorithmic work of one scheme step (both SSP-RK2 stages) per cell: read eta, hu, hv
 # once and write them once (float32) ...
 BYTES_PER_CELL_STEP = 24.0
@@ -39,12 +44,13 @@ BYTES_PER_CELL_STEP = 24.0
 FLOPS_PER_CELL_STEP = 498.0
 # Network forward: 2 x (27 x 48 + 4 x 432 x 48 + 432 x 3) multiply-adds per pixel.
 SURROGATE_FLOPS_PER_PIXEL = 171_072
-# HBM bytes per launch of the plain scheme step on this workload, from rocprofv3 counters
-# (FETCH_SIZE x 2 + WRITE_SIZE x 1, the scale factors a plain device copy of known size
-# reads), with the SHA-256 of the kernel source they were taken on: reported only while
-# the source is unchanged.
-MEASURED_TRAFFIC = {"bytes": 2 * 147934.3 * 1024 + 180157.0 * 1024,
-                    "source_sha256": "de17eed7e694c198e472e4ceeea9c3f5c010a5fe8372cd590c262c7c5bf9a148"}
+# Counters of one launch of the plain scheme step on this workload (rocprofv3 --pmc):
+# HBM bytes = FETCH_SIZE x 2 + WRITE_SIZE x 1 KiB (the scale factors a plain device copy of
+# known size reads) and SQ_INSTS_VALU, with the SHA-256 of the kernel source they were taken
+# on: reported only while the source is unchanged.
+MEASURED_COUNTERS = {"hbm_bytes": 2 * 147934.3 * 1024 + 180157.0 * 1024,
+                     "valu_insts": 90.3e6,
+                     "source_sha256": "de17eed7e694c198e472e4ceeea9c3f5c010a5fe8372cd590c262c7c5bf9a148"}
 
 
 def _kernel_source_hash():
@@ -102,30 +108,117 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(cfg, cells, n_particles=2):
-    """The FP64 oracle on a bounded sample of the workload: n_particles particles of the
-    same grid through one full cycle (10 model steps + analysis with the 225 buoys)."""
+def _oracle_forecast_task(args):
+    """Oracle model steps of one particle of the paper-scale ensemble (one process)."""
+    cfg, particle, n_steps = args
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ensemble as oens
+    with threadpool_limits(1):
+        psi = oens.init_member(cfg, W.jet_state(cfg), 0, particle)
+        t0 = time.perf_counter()
+        oens.step_member(psi, cfg, particle, 0, n_steps, noise_on_last=False)
+        return time.perf_counter() - t0
+
+
+def _oracle_analysis_task(args):
+    """Oracle analysis of the paper-scale ensemble with the 225 buoys, the state update
+    (stage 6) restricted to `particles` (stages 1-5 always cover the whole ensemble)."""
+    cfg, cells, particles = args
+    from threadpoolctl import threadpool_limits
+
     from oracle import ensemble as oens
     from oracle import iewpf as oiewpf
     from oracle import observe as oobs
     from oracle import philox as ophil
-    sub = cfg.replace(n_particles=n_particles)
-    jet = W.jet_state(sub)
-    ens = np.stack([oens.init_member(sub, jet, 0, i) for i in range(n_particles)])
-    truth = oens.init_member(sub.replace(ensemble_id=0x7FFF), jet, 1, 0)
-    noise = ophil.normals(2 * len(cells), sub.seed, 0, ophil.TAG_OBS, 0x7FFF, 0).reshape(-1, 2)
-    y = oobs.mooring_obs(truth, cells, sub.H, sub.obs_sigma, noise)
-    consts = oiewpf.AnalysisConstants(sub)
+    with threadpool_limits(1):
+        jet = W.jet_state(cfg)
+        ens = np.stack([oens.init_member(cfg, jet, 0, i) for i in range(cfg.n_particles)])
+        truth = oens.init_member(cfg.replace(ensemble_id=0x7FFF), jet, 1, 0)
+        noise = ophil.normals(2 * len(cells), cfg.seed, 0, ophil.TAG_OBS, 0x7FFF, 0).reshape(-1, 2)
+        y = oobs.mooring_obs(truth, cells, cfg.H, cfg.obs_sigma, noise)
+        consts = oiewpf.AnalysisConstants(cfg)
+        t0 = time.perf_counter()
+        oiewpf.analysis(ens, cells, y, cfg, 0, consts=consts, particles=list(particles))
+        return time.perf_counter() - t0
+
+
+def _oracle_tiny_end_to_end():
+    """The tiny drifter-observing run on the oracle: 32x32, 10 particles, 4 drifters, 12
+    cycles of 10 model steps and one analysis (truth and observations included)."""
+    from oracle import drifters as odr
+    from oracle import ensemble as oens
+    from oracle import iewpf as oiewpf
+    from oracle import observe as oobs
+    from oracle import philox as ophil
+    cfg = W.tiny()
+    steps = cfg.obs_every
     t0 = time.perf_counter()
-    fc = np.stack([oens.step_member(ens[i], sub, i, 0, 10, noise_on_last=False)
-                   for i in range(n_particles)])
-    oiewpf.analysis(fc, cells, y, sub, 0, consts=consts)
-    dt = time.perf_counter() - t0
-    work = n_particles * sub.nx * sub.ny * sub.n_sub * 10
-    return {"value": work / dt, "unit": "particle-cell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_particles} of {cfg.n_particles} particles, one 5-min cycle (10 model "
-                      f"steps x {sub.n_sub} scheme steps + IEWPF analysis, {len(cells)} buoys), "
-                      f"single process, {dt:.1f} s"}
+    base = oens.init_member(cfg, None, 0, 999)
+    small = cfg.replace(init_std=0.003)
+    ens = np.stack([oens.init_member(small, base, 1, i) for i in range(cfg.n_particles)])
+    truth = oens.init_member(small.replace(ensemble_id=77), base, 1, 0)
+    tcfg = cfg.replace(ensemble_id=77)
+    pos = W.drifter_lattice(cfg, 2, 2)
+    consts = oiewpf.AnalysisConstants(cfg)
+    for c in range(12):
+        prev = pos.copy()
+        for s in range(steps):
+            nxt = oens.step_member(truth, tcfg, 0, c * steps + s, 1, noise_on_last=True)
+            pos = odr.heun_step(pos, truth, nxt, cfg, cfg.dt)
+            truth = nxt
+        noise = ophil.normals(2 * len(pos), cfg.seed, c, ophil.TAG_OBS, 77, 1).reshape(-1, 2)
+        y = oobs.drifter_obs(pos, prev, steps * cfg.dt, cfg.H, cfg.obs_sigma, noise)
+        cells = oobs.obs_cell(pos, cfg.dx, cfg.dy, cfg.nx, cfg.ny)
+        fc = np.stack([oens.step_member(ens[i], cfg, i, c * steps, steps, noise_on_last=False)
+                       for i in range(cfg.n_particles)])
+        ens, _ = oiewpf.analysis(fc, cells, y, cfg, c, consts=consts)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(cfg, cells):
+    """The FP64 oracle on a bounded sample of the paper-scale cycle, on the host's cores.
+
+    N = the cores this process may run on (at most 16, the host share of one GPU), one
+    single-threaded process each.  Measured: 4 model steps of one particle alone and of N
+    particles at once (one per process); the analysis's whole-ensemble stages 1-5 alone; the
+    state update of one particle alone and of N particles at once.  The cycle of all 100
+    particles (10 model steps + one analysis) is extrapolated from them: per particle the
+    model steps scale linearly, and the updates run in ceil(100 / N) rounds of N.  The tiny
+    drifter-observing run (12 cycles) is timed whole on one core."""
+    import multiprocessing as mp
+    n_cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    ne = cfg.n_particles
+    steps = 4
+    fc1 = _oracle_forecast_task((cfg, 0, steps))
+    an0 = _oracle_analysis_task((cfg, cells, []))
+    an1 = _oracle_analysis_task((cfg, cells, [0])) - an0
+    with mp.get_context("fork").Pool(n_cores) as pool:
+        t0 = time.perf_counter()
+        pool.map(_oracle_forecast_task, [(cfg, i, steps) for i in range(n_cores)])
+        fcn = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        times = pool.map(_oracle_analysis_task, [(cfg, cells, [i]) for i in range(n_cores)])
+        ann = max(times) - an0  # each process ran stages 1-5 once before its update
+    tiny_s = _oracle_tiny_end_to_end()
+    rounds = -(-ne // n_cores)
+    per_model_step = 10 / steps
+    cycle_1 = ne * fc1 * per_model_step + an0 + ne * an1
+    cycle_n = rounds * fcn * per_model_step + an0 + rounds * ann
+    work = ne * cfg.nx * cfg.ny * cfg.n_sub * 10
+    return {"value": work / cycle_n, "unit": "particle-cell-steps/s", "cores": n_cores,
+            "kind": "oracle", "value_per_core": work / cycle_1,
+            "cycle_s_extrapolated": {"1_core": cycle_1, f"{n_cores}_cores": cycle_n},
+            "analysis_s_extrapolated": {"1_core": an0 + ne * an1,
+                                        f"{n_cores}_cores": an0 + rounds * ann},
+            "tiny_drifter_run_s_1_core": tiny_s,
+            "sample": (f"paper-scale cycle ({ne} particles, 500x300, 225 buoys) extrapolated "
+                       f"from: {steps} model steps of 1 particle ({fc1:.2f} s) and of "
+                       f"{n_cores} particles on {n_cores} processes ({fcn:.2f} s); analysis "
+                       f"stages 1-5 ({an0:.2f} s) and the state update of 1 particle "
+                       f"({an1:.2f} s) and of {n_cores} on {n_cores} processes "
+                       f"({ann:.2f} s); the tiny drifter run (12 cycles, 10 particles) "
+                       f"timed whole ({tiny_s:.2f} s)")}
 
 
 def batched_leg(torch, dev, steps: int):
@@ -363,13 +456,15 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    cfg = W.paper_scale(args.particles)
+    cells = W.buoy_cells(cfg.nx, cfg.ny, 15, 15)
+    # the oracle's worker processes are forked before anything touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, cells)
     import torch
     from paper_1910_01031_amd import Context, abi
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    cfg = W.paper_scale(args.particles)
-    cells = W.buoy_cells(cfg.nx, cfg.ny, 15, 15)
     n_cycles = args.warmup + args.steps
     steps_per_cycle = 10
 
@@ -440,8 +535,10 @@ def main():
     flops_per_launch = FLOPS_PER_CELL_STEP * launch_cells
     achieved_tflops = flops_per_launch / (plain_ms / 1e3) / 1e12
     achieved_gbs = bytes_per_launch / (plain_ms / 1e3) / 1e9
-    traffic = (MEASURED_TRAFFIC["bytes"]
-               if MEASURED_TRAFFIC["source_sha256"] == _kernel_source_hash() else None)
+    counters_current = MEASURED_COUNTERS["source_sha256"] == _kernel_source_hash()
+    traffic = MEASURED_COUNTERS["hbm_bytes"] if counters_current else None
+    valu = MEASURED_COUNTERS["valu_insts"] if counters_current else None
+    issue = valu / (plain_ms * 1e-3 * CLOCK_GHZ * 1e9 * N_CU) if valu is not None else None
 
     if args.copy_calibration:
         a = torch.empty(90_000_000, dtype=torch.float32, device=dev)
@@ -475,17 +572,24 @@ def main():
         "kernel_ms": {k: (v[0] / v[1] if v[1] else None) for k, v in tr.items()},
         "gpu_state": {"before_timed_region": state_idle, "during_same_cycles_traced": state_during,
                       "gpu_busy_when_read": busy},
-        "roofline": {"bound": "alu", "kernel": "swe_substep_kernel<false> (scheme step)",
-                     "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic, "avg_launch_ms": plain_ms,
-                     "algorithmic_flops_per_launch": flops_per_launch,
-                     "hbm": {"achieved_gbs": achieved_gbs, "peak_gbs": HBM_PEAK_GBS,
-                             "frac": achieved_gbs / HBM_PEAK_GBS,
-                             "algorithmic_bytes_per_launch": bytes_per_launch,
-                             # measured HBM bytes (counters) per launch over the same duration
-                             "traffic_gbs": (traffic / (plain_ms / 1e3) / 1e9
-                                             if traffic is not None else None)},
+        # the stencil's bound: HBM, 24 B per cell and scheme step (one read and one write of
+        # eta, hu, hv); the instruction-issue figure beside it
+        "roofline": {"bound": "hbm", "kernel": "swe_substep_kernel<false> (scheme step)",
+                     "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_launch_ms": plain_ms,
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     # measured HBM bytes (counters) per launch over the same duration
+                     "traffic_gbs": (traffic / (plain_ms / 1e3) / 1e9
+                                     if traffic is not None else None),
+                     "alu": {"valu_insts_per_launch": valu,
+                             "valu_issue_per_clk_per_cu": issue,
+                             "issue_ceiling_measured": VALU_ISSUE_CEILING,
+                             "issue_frac": (issue / VALU_ISSUE_CEILING
+                                            if issue is not None else None),
+                             "algorithmic_flops_per_launch": flops_per_launch,
+                             "achieved_tflops": achieved_tflops,
+                             "fp32_vector_peak_tflops": FP32_VECTOR_PEAK_TFLOPS},
                      "avg_launch_ms_with_model_error": (tr["scheme_step_noise"][0] /
                                                         max(tr["scheme_step_noise"][1], 1))},
     }
@@ -495,8 +599,8 @@ def main():
         out["batched"] = batched_leg(torch, dev, 3)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(torch, dev, ctx, ens, cfg, args.surrogate_train_steps)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, cells)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
