@@ -222,6 +222,27 @@ int iewpf_advect_drifters(iewpf_ctx* ctx, const float* psi_n, const float* psi_n
 int iewpf_resample(iewpf_ctx* ctx, float* state, const double* logw, uint64_t analysis_index,
                    int32_t* parents, void* stream);
 
+/* Residual resampling for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same draws,
+ * parents and copies as iewpf_resample without a context, out of place, with its partial
+ * results (floor counts, cumulative residuals) in a fixed device array of the library
+ * (768 KiB per GPU, held until the process ends; its address is looked up once per device).
+ * The call allocates nothing and does not wait.
+ *   n_particles          1 .. 65535 (the array's size; IEWPF_E_CAPACITY above)
+ *   floats_per_particle  floats of one particle's state (3 nx ny), a multiple of 4
+ *                        (IEWPF_E_SHAPE otherwise)
+ *   seed, ensemble_id    the Philox key word 0 and counter word 2 of iewpf_config
+ *   logw                 device float64 [n_particles] natural log-weights
+ *   state_in, state_out  device float32 [n_particles][floats_per_particle]; must not overlap
+ *                        (IEWPF_E_ARG); state_out[i] = state_in[parents[i]]
+ *   parents              device int32 [n_particles], ascending
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU (on
+ * different streams or threads) race and must be serialised by the caller. */
+int iewpf_resample_noalloc(int n_particles, size_t floats_per_particle, uint64_t seed,
+                           uint32_t ensemble_id, uint64_t analysis_index, const double* logw,
+                           const float* state_in, float* state_out, int32_t* parents,
+                           void* stream);
+
 /* Largest admissible scheme step of the current ensemble by eq. swecfl with Courant 0.8:
  * 0.8 * 1/4 * min(dx / max(|u| + c), dy / max(|v| + c)).  Waits for the stream.  Returns
  * IEWPF_E_CFL (and still writes *dt_out) when dt / n_sub exceeds it. */

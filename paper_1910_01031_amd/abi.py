@@ -38,7 +38,8 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_net_gradients",
             "iewpf_surrogate_window", "iewpf_forecast_drifters_surrogate",
             "iewpf_set_full_innovation", "iewpf_set_scheme", "iewpf_last_error",
-            "iewpf_observe_drifters", "iewpf_sir_log_weights", "iewpf_net_set_horizon")
+            "iewpf_observe_drifters", "iewpf_sir_log_weights", "iewpf_net_set_horizon",
+            "iewpf_resample_noalloc")
 
 TRACE_KINDS = ("scheme_step", "me_normals", "soar", "gb_add", "innovation", "rand_dots",
                "beta_alpha", "posterior_coarse", "analysis_update", "scheme_step_noise",
@@ -146,6 +147,8 @@ def load(path: str = LIB_PATH):
     lib.iewpf_sir_log_weights.argtypes = [vp, vp, ctypes.POINTER(IewpfObs), i32, ctypes.c_double,
                                           vp, vp, vp]
     lib.iewpf_net_set_horizon.argtypes = [vp, i32]
+    lib.iewpf_resample_noalloc.argtypes = [i32, ctypes.c_size_t, u64, ctypes.c_uint32, u64, vp, vp,
+                                           vp, vp, vp]
     lib.iewpf_set_trace.argtypes = [vp, i32]
     lib.iewpf_trace_read.argtypes = [vp, f64p, vp, i32]
     lib.iewpf_net_num_params.restype = ctypes.c_size_t
@@ -456,6 +459,16 @@ class Net:
         _check(load().iewpf_net_gradients(self.h, _ptr(x), _ptr(target), B, H, W, g.ctypes.data,
                                           ctypes.byref(loss), y.ctypes.data, _stream(stream)))
         return g, loss.value, y
+
+
+def resample_noalloc(logw, state_in, state_out, parents, seed: int, ensemble_id: int,
+                     analysis_index: int, stream=None):
+    """Residual resampling without allocation (iewpf_resample_noalloc): out of place."""
+    n = int(state_in.shape[0])
+    per = int(state_in[0].numel())
+    _check(load().iewpf_resample_noalloc(n, per, seed, ensemble_id, analysis_index, _ptr(logw),
+                                         _ptr(state_in), _ptr(state_out), _ptr(parents),
+                                         _stream(stream)))
 
 
 def surrogate_window(ctx, net, state, n_model_steps: int, first_step: int, drift_tol: float,

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libiewpf.so")
 SOURCES = ["api.cpp", "host_precompute.cpp", "surrogate_api.cpp", "swe_kernels.hip",
-           "noise_kernels.hip", "analysis_kernels.hip", "surrogate_kernels.hip"]
+           "noise_kernels.hip", "analysis_kernels.hip", "surrogate_kernels.hip", "noalloc.hip"]
 ARCH = os.environ.get("IEWPF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
