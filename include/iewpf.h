@@ -338,9 +338,18 @@ int iewpf_net_read_activation(iewpf_net* net, int layer, uint16_t* host, size_t 
                               void* stream);
 /* Loss gradient with respect to every parameter (host float [num_params]), without an
  * update; also the loss and the raw network output y (host float [B*H*W][3], NHWC, or
- * NULL).  Waits for the stream. */
+ * NULL).  Keeps every layer's pre-activation gradient for iewpf_net_read_gradient_signal
+ * (five [cells][48] BF16 buffers, allocated when a call has more cells than any before).
+ * Waits for the stream. */
 int iewpf_net_gradients(iewpf_net* net, const float* x, const float* target, int B, int H, int W,
                         float* grads_host, float* loss_out, float* y_host, void* stream);
+/* BF16 bits of the loss gradient with respect to the pre-activation of layer `layer`
+ * (0..5; layer 5's is the rounded loss gradient of the output) from the last
+ * iewpf_net_gradients call, NHWC [cells][C_out] with C_out 48 (layers 0..4) or 3 (layer 5),
+ * copied to host uint16 [count]; count must equal C_out x the cells of that call.  Waits for
+ * the stream.  For inspection and testing of the mixed-precision backward pass. */
+int iewpf_net_read_gradient_signal(iewpf_net* net, int layer, uint16_t* host, size_t count,
+                                   void* stream);
 /* One surrogate forecast window of the ensemble in place: the network replaces
  * n_model_steps deterministic model steps (n_model_steps must equal the network's horizon,
  * IEWPF_E_ARG otherwise); every particle whose relative mass drift

@@ -39,7 +39,7 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_surrogate_window", "iewpf_forecast_drifters_surrogate",
             "iewpf_set_full_innovation", "iewpf_set_scheme", "iewpf_last_error",
             "iewpf_observe_drifters", "iewpf_sir_log_weights", "iewpf_net_set_horizon",
-            "iewpf_resample_noalloc")
+            "iewpf_resample_noalloc", "iewpf_net_read_gradient_signal")
 
 TRACE_KINDS = ("scheme_step", "me_normals", "soar", "gb_add", "innovation", "rand_dots",
                "beta_alpha", "posterior_coarse", "analysis_update", "scheme_step_noise",
@@ -147,6 +147,7 @@ def load(path: str = LIB_PATH):
     lib.iewpf_sir_log_weights.argtypes = [vp, vp, ctypes.POINTER(IewpfObs), i32, ctypes.c_double,
                                           vp, vp, vp]
     lib.iewpf_net_set_horizon.argtypes = [vp, i32]
+    lib.iewpf_net_read_gradient_signal.argtypes = [vp, i32, vp, ctypes.c_size_t, vp]
     lib.iewpf_resample_noalloc.argtypes = [i32, ctypes.c_size_t, u64, ctypes.c_uint32, u64, vp, vp,
                                            vp, vp, vp]
     lib.iewpf_set_trace.argtypes = [vp, i32]
@@ -448,6 +449,14 @@ class Net:
         out = np.zeros((cells, 48), dtype=np.uint16)
         _check(load().iewpf_net_read_activation(self.h, layer, out.ctypes.data, out.size,
                                                 _stream(stream)))
+        return out
+
+    def read_gradient_signal(self, layer: int, cells: int, stream=None) -> np.ndarray:
+        """BF16 bits (uint16 [cells][C_out]) of the pre-activation gradient of layer `layer`
+        (0..5) from the last gradients call."""
+        out = np.zeros((cells, 3 if layer == 5 else 48), dtype=np.uint16)
+        _check(load().iewpf_net_read_gradient_signal(self.h, layer, out.ctypes.data, out.size,
+                                                     _stream(stream)))
         return out
 
     def gradients(self, x, target, stream=None):

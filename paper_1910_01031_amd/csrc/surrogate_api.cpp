@@ -44,6 +44,11 @@ struct iewpf_net {
   int loss_blocks = 256;
   float mu[3] = {0, 0, 0}, sig[3] = {1, 1, 1}, s[3] = {1, 1, 1};
   int horizon = 10;  // model steps one application of the network stands in for
+  // pre-activation gradients of layers 0..4 kept by iewpf_net_gradients ([cells][48] BF16
+  // each, allocated on its first call for that call's cells); layer 5's is g5
+  uint16_t* gkeep[kLayers - 1] = {};
+  long long gkeep_cells = 0;
+  long long gkeep_last = 0;  // cells of the last iewpf_net_gradients call
 };
 
 namespace iewpf {
@@ -54,6 +59,8 @@ void free_net(iewpf_net* n) {
   void* bufs[] = {n->p, n->g, n->m, n->v, n->y, n->g5, n->ga, n->gb, n->wpart, n->bpart, n->lpart};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  for (int i = 0; i < kLayers - 1; ++i)
+    if (n->gkeep[i]) (void)hipFree(n->gkeep[i]);
   for (int i = 0; i < kLayers; ++i) {
     if (n->wf[i]) (void)hipFree(n->wf[i]);
     if (n->wd[i]) (void)hipFree(n->wd[i]);
@@ -102,8 +109,10 @@ void prep_all(iewpf_net* n, hipStream_t s) {
 }
 
 // Forward (training output), MSE and backward: fills n->g; loss partials in n->lpart.
+// keep: the pre-activation gradient of layer L - 1 goes to keep[L - 1] instead of the
+// ping-pong buffers (inspection).
 void forward_backward(iewpf_net* n, const float* x, const float* tgt, int B, int H, int W,
-                      hipStream_t s) {
+                      hipStream_t s, uint16_t* const* keep = nullptr) {
   const int cells = B * H * W;
   forward_hidden(n, x, B, H, W, s);
   ConvArgs A5 = conv_args(n, 5, B, H, W);
@@ -137,7 +146,7 @@ void forward_backward(iewpf_net* n, const float* x, const float* tgt, int B, int
     D.bias = nullptr;
     D.in = gz;
     D.mask = n->act[L];
-    uint16_t* out = bufs[L & 1];
+    uint16_t* out = keep ? keep[L - 1] : bufs[L & 1];
     D.out = out;
     launch_conv(D, gch % 8 == 0 ? kInNhwcVec : kInNhwcSmall, kOutMaskBf16, s);
     gz = out;
@@ -299,12 +308,37 @@ int iewpf_net_read_activation(iewpf_net* n, int layer, uint16_t* host, size_t co
   return 0;
 }
 
+int iewpf_net_read_gradient_signal(iewpf_net* n, int layer, uint16_t* host, size_t count,
+                                   void* stream) {
+  if (!n || !host || layer < 0 || layer > 5) return fail(IEWPF_E_ARG, "invalid argument");
+  const size_t ch = layer == 5 ? 3 : 48;
+  if (n->gkeep_last == 0 || count != ch * (size_t)n->gkeep_last)
+    return fail(IEWPF_E_ARG, "count must be C_out x the cells of the last iewpf_net_gradients call");
+  IEWPF_HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
+  const uint16_t* src = layer == 5 ? n->g5 : n->gkeep[layer];
+  IEWPF_HIP_TRY(hipMemcpy(host, src, count * 2, hipMemcpyDeviceToHost));
+  return 0;
+}
+
 int iewpf_net_gradients(iewpf_net* n, const float* x, const float* target, int B, int H, int W,
                         float* grads_host, float* loss_out, float* y_host, void* stream) {
   if (!n || !x || !target || !grads_host) return fail(IEWPF_E_ARG, "invalid argument");
   if ((long long)B * H * W > n->max_cells) return fail(IEWPF_E_CAPACITY, "more cells than max_cells");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  forward_backward(n, x, target, B, H, W, s);
+  const long long cells = (long long)B * H * W;
+  if (cells > n->gkeep_cells) {
+    IEWPF_HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < kLayers - 1; ++i) {
+      if (n->gkeep[i]) IEWPF_HIP_TRY(hipFree(n->gkeep[i]));
+      n->gkeep[i] = nullptr;
+    }
+    n->gkeep_cells = 0;
+    for (int i = 0; i < kLayers - 1; ++i)
+      IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&n->gkeep[i]), (size_t)cells * 48 * 2));
+    n->gkeep_cells = cells;
+  }
+  forward_backward(n, x, target, B, H, W, s, n->gkeep);
+  n->gkeep_last = cells;
   IEWPF_HIP_TRY(hipGetLastError());
   IEWPF_HIP_TRY(hipStreamSynchronize(s));
   IEWPF_HIP_TRY(hipMemcpy(grads_host, n->g, n->np * 4, hipMemcpyDeviceToHost));

@@ -150,3 +150,67 @@ def test_autotune_keeps_results(torch_dev):
     b.step_ensemble(tb, 2, 0, True)
     torch.cuda.synchronize()
     assert torch.equal(ta, tb)  # the strip height does not change results
+
+
+def test_batched_paper_shapes_sampled_parity(torch_dev):
+    """The eight ensembles of the batched workload (200x120, 256x256, 300x200, 500x300 twice,
+    400x400, 128x512, 350x250 with c = 5; 50 to 200 particles, 30 to 225 buoys; 850 particles)
+    through one graph replay of a cycle (two model steps, one analysis per ensemble):
+    bit-equal to the single-context path at these shapes; for one sampled particle per
+    ensemble, the single-context forecast against the oracle's forecast of the same input,
+    and the analysis of that forecast against the oracle's (its stages 1-5 over the whole
+    ensemble, so beta is checked too)."""
+    torch, dev = torch_dev
+    from paper_1910_01031_amd import Batch, Context
+    rng = np.random.default_rng(44)
+    specs = W.batched()
+    cfgs, ens, cells, ys = [], [], [], []
+    for cfg, lat in specs:
+        jet = W.jet_state(cfg)
+        p1 = W.random_state(cfg, rng, eta_amp=0.01, q_amp=1.0)
+        p2 = W.random_state(cfg, rng, eta_amp=0.01, q_amp=1.0)
+        a, b2 = rng.normal(size=cfg.n_particles), rng.normal(size=cfg.n_particles)
+        x = W.as_f32(jet[None] + a[:, None, None, None] * p1[None] + b2[:, None, None, None] * p2[None])
+        cl = W.buoy_cells(cfg.nx, cfg.ny, *lat)
+        truth = jet + 0.5 * p1 - 0.5 * p2
+        ys.append(oobs.mooring_obs(truth, cl, cfg.H, cfg.obs_sigma, np.zeros((len(cl), 2))))
+        cfgs.append(cfg)
+        ens.append(x)
+        cells.append(cl)
+    _say(f"batched paper shapes: {sum(c.n_particles for c in cfgs)} particles")
+    ctx_b = [Context(cfg, max_obs=len(cl)) for cfg, cl in zip(cfgs, cells)]
+    st_b = [torch.from_numpy(x).to(dev) for x in ens]
+    bt = Batch(ctx_b, st_b)
+    for e, cl in enumerate(cells):
+        bt.set_cells(e, cl)
+    bt.cycle(2, 40, 5, ys, use_graph=True)
+    torch.cuda.synchronize()
+    for e, cfg in enumerate(cfgs):
+        ctx = Context(cfg, max_obs=len(cells[e]))
+        st = torch.from_numpy(ens[e]).to(dev)
+        ctx.step_ensemble(st, 2, first_step=40, noise_on_last=False)
+        fc = st.cpu().numpy()
+        stats = ctx.assimilate(st, cells[e], ys[e], analysis_index=5)
+        torch.cuda.synchronize()
+        assert torch.equal(st, st_b[e]), e
+        i = cfg.n_particles // 2
+        ref_f = oens.step_member(ens[e][i], cfg, i, 40, 2, noise_on_last=False)
+        for f in range(3):
+            # 1e-5 per model step (two here): hv is ~100x smaller than hu in the zonal jet, so
+            # its relative error carries the rounding of the hu-sized Coriolis terms
+            err = np.abs(fc[i, f] - ref_f[f]).max() / np.abs(ref_f[f]).max()
+            assert err < 2e-5, (e, "forecast", f, err)
+        ref, info = oiewpf.analysis(fc.astype(np.float64), cells[e], ys[e], cfg, 5, particles=[i])
+        got = st[i].cpu().numpy().astype(np.float64)
+        for f in range(3):
+            err = np.abs(got[f] - ref[0, f]).max() / np.abs(ref[0, f]).max()
+            assert err < 1e-5, (e, "analysis", f, err)
+        # the float32 normals bound beta's error by 2^-23 |beta - 1| (twice that here)
+        assert abs(stats["beta"] - info["beta"]) < 2.0 ** -22 * abs(info["beta"] - 1.0) + 1e-12
+        _say(f"  ensemble {e} ({cfg.nx}x{cfg.ny}, {cfg.n_particles} particles, "
+             f"{len(cells[e])} buoys): beta {stats['beta']:.6f}")
+        ctx.close()
+        del st, fc
+    bt.close()
+    for c in ctx_b:
+        c.close()

@@ -16,9 +16,14 @@ one BF16 ulp (2^-8 relative) and the later layers carry that on; the end-to-end 
 therefore compared statistically (99.9 % of them within 2^-6 of the output RMS, all within
 2^-4, mean deviation below 2^-11 of it; observed: 99.9 % within 2^-7.8, all within 2^-6.6).
 
-Gradients are compared per tensor in relative Frobenius norm (1e-2): the loss gradient and
-every pre-activation gradient are rounded to BF16 on both sides, so the same boundary cases
-are the only source of difference.
+Backward pass, layer by layer (the exact check).  Fed the GPU's own BF16 layer inputs and
+pre-activation gradients, every weight and bias gradient lies within the FP32 summation bound
+of the oracle's FP64 sum, and every pre-activation gradient between the BF16 roundings of
+the bounds of its FP64 value (test_backward_layerwise_exact).
+
+Backward pass, end to end.  The gradients of the whole network are also compared per tensor
+in relative Frobenius norm (1e-2): the loss gradient and every pre-activation gradient are
+rounded to BF16 on both sides, so the same boundary cases are the only source of difference.
 """
 import numpy as np
 import pytest
@@ -195,6 +200,87 @@ def test_gradients_match_oracle(B, H, W):
             rel = np.linalg.norm(a - o) / max(np.linalg.norm(o), 1e-30)
             assert rel <= 1e-2, (i, n, rel)
             off += n
+    net.close()
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 16, 16), (1, 12, 40), (1, 5, 7)])
+def test_backward_layerwise_exact(B, H, W):
+    """Every element of the backward pass against the oracle fed the GPU's own BF16
+    intermediates (layer inputs and pre-activation gradients), so the only differences left
+    are the FP32 summations and the BF16 roundings, each bounded per element:
+      loss gradient     bf16 of 2 (y - (target - x)/s) / n, whose FP32 evaluation errs by at
+                        most (2/n)(3u|t| + 2u|d|) + 4u|v| (u = 2^-24): the GPU's value lies
+                        between the roundings of v -+ that bound;
+      weight and bias   sum over cells of dz a (BF16 x BF16 products are exact in FP32): within
+      gradients         (cells + 2) 2u sum |dz a| of the FP64 sum;
+      input gradient    dz of layer L-1 = bf16(mask * sum_k w dz), the K = 9 C_out term FP32
+                        sum within (K + 2) 2u sum |w dz|: between the roundings of the bounds,
+                        zero where layer L-1's ReLU output is zero.
+    The matrix-core sums are bounded with 2u per addition (an ulp: the bound holds whether
+    the hardware rounds to nearest or truncates)."""
+    _need_gpu()
+    from paper_1910_01031_amd import Net
+    u = 2.0 ** -24
+    params = _params(5 + W, last_scale=0.5)
+    psi = _states(B, H, W, 41 + W)
+    tgt = psi + _states(B, H, W, 42) * np.array([0.01, 0.5, 0.5], np.float32)[None, :, None, None]
+    net = Net(B * H * W)
+    net.set_params(_flat(params).astype(np.float32))
+    net.set_norm(*NORM)
+    g, loss, y = net.gradients(torch.from_numpy(psi).cuda(), torch.from_numpy(tgt).cuda())
+    cells = B * H * W
+
+    def nchw(a, ch):
+        return a.reshape(B, H, W, ch).transpose(0, 3, 1, 2)
+
+    acts = [None] + [nchw(_bf16_bits_to_f64(net.read_activation(L, cells)), 48)
+                     for L in range(1, 6)]
+    mu, sig, sc = NORM
+    x32 = (psi - mu[None, :, None, None]) * (np.float32(1.0) / sig)[None, :, None, None]
+    acts[0] = osur.bf16_round(x32)
+    dz = [nchw(_bf16_bits_to_f64(net.read_gradient_signal(L, cells)), 3 if L == 5 else 48)
+          for L in range(6)]
+    # loss gradient
+    yv = nchw(y.astype(np.float64), 3)
+    t = (tgt.astype(np.float64) - psi.astype(np.float64)) / sc.astype(np.float64)[None, :, None, None]
+    d = yv - t
+    n = 3.0 * cells
+    v = 2.0 * d / n
+    dv = (2.0 / n) * (3 * u * np.abs(t) + 2 * u * np.abs(d)) + 4 * u * np.abs(v)
+    assert np.all((dz[5] >= osur.bf16_round(v - dv)) & (dz[5] <= osur.bf16_round(v + dv)))
+    off = 0
+    offs = []
+    for i in range(6):
+        cin, cout = osur.CHANNELS[i], osur.CHANNELS[i + 1]
+        offs.append((off, off + cout * cin * 9))
+        off += cout * cin * 9 + cout
+    n_boundary = 0
+    for L in range(5, -1, -1):
+        w, bias = params[L]
+        wq = osur.bf16_round(w)
+        cin, cout = osur.CHANNELS[L], osur.CHANNELS[L + 1]
+        gw = sum(osur.conv3x3_weight_grad(dz[L][b], acts[L][b]) for b in range(B))
+        gwa = sum(osur.conv3x3_weight_grad(np.abs(dz[L][b]), np.abs(acts[L][b])) for b in range(B))
+        gb = dz[L].sum(axis=(0, 2, 3))
+        gba = np.abs(dz[L]).sum(axis=(0, 2, 3))
+        w0, b0 = offs[L]
+        got_w = g[w0:b0].astype(np.float64).reshape(cout, cin, 3, 3)
+        got_b = g[b0:b0 + cout].astype(np.float64)
+        assert np.all(np.abs(got_w - gw) <= (cells + 2) * 2 * u * gwa), (L, "weights")
+        assert np.all(np.abs(got_b - gb) <= (cells + 2) * 2 * u * gba), (L, "biases")
+        if L == 0:
+            break
+        K = 9 * cout
+        for b in range(B):
+            s_ = osur.conv3x3_input_grad(dz[L][b], wq)
+            delta = (K + 2) * 2 * u * osur.conv3x3_input_grad(np.abs(dz[L][b]), np.abs(wq))
+            on = acts[L][b] > 0.0
+            lo = np.where(on, osur.bf16_round(s_ - delta), 0.0)
+            hi = np.where(on, osur.bf16_round(s_ + delta), 0.0)
+            got = dz[L - 1][b]
+            assert np.all((got >= lo) & (got <= hi)), (L, b)
+            n_boundary += int(np.sum(got != np.where(on, osur.bf16_round(s_), 0.0)))
+    assert n_boundary <= max(4, 1e-4 * 5 * 48 * cells), n_boundary
     net.close()
 
 
@@ -454,5 +540,42 @@ def test_surrogate_drifter_forecast_matches_interpolated_heun():
                 pos = odr.heun_step(pos, pa, pb, cfg, cfg.dt)
                 assert np.abs(got[w * 10 + s + 1, i] - pos).max() < 1e-8, (i, w, s)
     assert np.abs(p.cpu().numpy()[i] - pos).max() < 1e-8
+    net.close()
+    ctx.close()
+
+
+def test_analysis_runs_on_the_surrogate_output():
+    """The IEWPF analysis takes the surrogate's forecast as it is: a guarded window of the
+    network followed by an analysis equals the oracle's analysis of the same forecast (1e-5
+    per field), with beta within its float32-normals bound and equal realised weights."""
+    _need_gpu()
+    from oracle import iewpf as oiewpf
+    from oracle import observe as oobs
+    from paper_1910_01031_amd import Context, surrogate_window
+    cfg, ctx, net, params, x = _window_setup(n_particles=8)
+    net.set_params(_flat(params).astype(np.float32))
+    net.set_norm(*NORM)
+    st = x.clone()
+    nf, _ = surrogate_window(ctx, net, st, 10, 0, drift_tol=1e30, noise_scale=0.0)
+    assert nf == 0
+    torch.cuda.synchronize()
+    fc = st.cpu().numpy().astype(np.float64)
+    acfg = cfg.replace(obs_sigma=20.0)
+    actx = Context(acfg, max_obs=4)
+    rng = np.random.default_rng(3)
+    truth = wl.jet_state(cfg) + 0.1 * wl.random_state(cfg, rng)
+    cells = np.array([[5, 6], [21, 9], [12, 25], [28, 28]], dtype=np.int32)
+    y = oobs.mooring_obs(truth, cells, cfg.H, acfg.obs_sigma, np.zeros((4, 2)))
+    stats = actx.assimilate(st, cells, y, analysis_index=3)
+    sc = actx.particle_scalars()
+    got = st.cpu().numpy().astype(np.float64)
+    ref, info = oiewpf.analysis(fc, cells, y, acfg, 3)
+    for f in range(3):
+        err = np.abs(got[:, f] - ref[:, f]).max() / np.abs(ref[:, f]).max()
+        assert err < 1e-5, (f, err)
+    assert abs(stats["beta"] - info["beta"]) < 2.0 ** -22 * abs(info["beta"] - 1.0) + 1e-12
+    w = oiewpf.realized_weight(sc[:, 3], sc[:, 1], sc[:, 2], stats["beta"], sc[:, 0], acfg.n_psi)
+    assert np.abs(w - stats["cbar"]).max() < 1e-9 * acfg.n_psi
+    actx.close()
     net.close()
     ctx.close()
