@@ -574,7 +574,8 @@ def main():
                       "gpu_busy_when_read": busy},
         # the stencil's bound: HBM, 24 B per cell and scheme step (one read and one write of
         # eta, hu, hv); the instruction-issue figure beside it
-        "roofline": {"bound": "hbm", "kernel": "swe_substep_kernel<false> (scheme step)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "swe_row_kernel<false, 512> (scheme step, full-row form)",
                      "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": plain_ms,

@@ -535,6 +535,42 @@ void free_batch(iewpf_batch* b) {
 }  // namespace
 }  // namespace iewpf
 
+namespace iewpf {
+namespace {
+// The fastest strip height of one form of the scheme step on `state` (writes go to the
+// context's scratch buffer).
+int tune_strip(iewpf_ctx* c, const SweConst& form, const float* state, hipStream_t s,
+               SweConst* best) {
+  const int cands[] = {16, 24, 32, 40, 48, 60, 64, 75, 96};
+  hipEvent_t e0, e1;
+  IEWPF_HIP_TRY(hipEventCreate(&e0));
+  IEWPF_HIP_TRY(hipEventCreate(&e1));
+  *best = form;
+  float best_ms = 1e30f;
+  for (int h : cands) {
+    if (h > c->ny && h != cands[0]) break;
+    SweConst C = form;
+    C.strip_h = std::min(h, c->ny);
+    C.n_strip_y = (c->ny + C.strip_h - 1) / C.strip_h;
+    launch_swe_substep(C, c->ne, state, c->scratch, nullptr, s);  // warm
+    IEWPF_HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < 4; ++r) launch_swe_substep(C, c->ne, state, c->scratch, nullptr, s);
+    IEWPF_HIP_TRY(hipEventRecord(e1, s));
+    IEWPF_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    IEWPF_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      *best = C;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return 0;
+}
+}  // namespace
+}  // namespace iewpf
+
 using namespace iewpf;
 
 extern "C" {
@@ -622,6 +658,7 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   S.nx = f.nx;
   S.ny = f.ny;
   S.n_strip_x = (f.nx + kSweOut - 1) / kSweOut;
+  S.row = 0;
   {
     // rows per wave strip: fit the waves of all particles to the resident wave slots
     // (each wave marches strip_h + 8 rows of stage 1 and strip_h + 4 of stage 2)
@@ -658,6 +695,34 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   S.nry = c->nry;
   S.gb_x = (float)(f.g * f.H / (2.0 * f.f * f.dx));
   S.gb_y = (float)(f.g * f.H / (2.0 * f.f * f.dy));
+  c->swe_halo = S;
+  {
+    // Full-row form for rows of at most 512 columns when it computes sufficiently fewer
+    // columns than the strip form (its three barriers per row cost ~10 % of issue rate):
+    // lane use nx / (64 ceil(nx / 64)) against nx / (64 ceil(nx / 56)).
+    const double use_row = (double)f.nx / (64.0 * ((f.nx + 63) / 64));
+    const double use_halo = (double)f.nx / (64.0 * S.n_strip_x);
+    const int choice = env_int("IEWPF_SWE_ROW", -1);
+    const bool row = f.nx <= 512 && (choice == 1 || (choice < 0 && use_row >= 1.08 * use_halo));
+    if (row) {
+      // strips of rows: minimise (launch rounds) x (rows per workgroup + prologue rows)
+      S.row = 1;
+      const int forced_row = env_int("IEWPF_SWE_ROW_STRIP", 0);
+      int n_ys;
+      if (forced_row > 0) {
+        n_ys = (f.ny + forced_row - 1) / forced_row;
+      } else {
+        int cus = 256, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+          cus = 256;
+        n_ys = choose_row_strips(f.n_particles, f.ny, cus * swe_row_blocks_per_cu(f.nx), 8, 8);
+      }
+      S.strip_h = (f.ny + n_ys - 1) / n_ys;
+      S.n_strip_y = (f.ny + S.strip_h - 1) / S.strip_h;
+    }
+  }
   c->cc.nx = f.nx;
   c->cc.ny = f.ny;
   c->cc.c = c->c;
@@ -666,6 +731,7 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   c->cc.gb_x = (float)(f.g * f.H / (2.0 * f.f * f.dx));
   c->cc.gb_y = (float)(f.g * f.H / (2.0 * f.f * f.dy));
   fill_cr_table(c->c, S.cr);
+  c->swe_halo.cr = S.cr;
   // pull windows and S
   const int r = 7 * c->c, W = 2 * r + 1;
   c->rx = W > f.nx ? -1 : r;
@@ -1056,43 +1122,31 @@ int iewpf_resample(iewpf_ctx* c, float* state, const double* logw, uint64_t anal
   return 0;
 }
 
+
 int iewpf_autotune(iewpf_ctx* c, const float* state, int32_t* strip_out, void* stream) {
   if (!c || !state || !strip_out) return fail(IEWPF_E_ARG, "NULL argument");
   hipStream_t s = as_stream(stream);
-  const int cands[] = {16, 24, 32, 40, 48, 64, 96};
-  hipEvent_t e0, e1;
-  IEWPF_HIP_TRY(hipEventCreate(&e0));
-  IEWPF_HIP_TRY(hipEventCreate(&e1));
-  SweConst best = c->swe;
-  float best_ms = 1e30f;
-  for (int h : cands) {
-    if (h > c->ny && h != cands[0]) break;
-    SweConst C = c->swe;
-    C.strip_h = std::min(h, c->ny);
-    C.n_strip_y = (c->ny + C.strip_h - 1) / C.strip_h;
-    launch_swe_substep(C, c->ne, state, c->scratch, nullptr, s);  // warm
-    IEWPF_HIP_TRY(hipEventRecord(e0, s));
-    for (int r = 0; r < 4; ++r) launch_swe_substep(C, c->ne, state, c->scratch, nullptr, s);
-    IEWPF_HIP_TRY(hipEventRecord(e1, s));
-    IEWPF_HIP_TRY(hipEventSynchronize(e1));
-    float ms = 0.0f;
-    IEWPF_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = C;
-    }
+  // the strip form (batched launches use it) and, when the context runs the full-row form,
+  // that form too
+  SweConst best;
+  if (int rc = tune_strip(c, c->swe_halo, state, s, &best)) return rc;
+  c->swe_halo = best;
+  if (c->swe.row) {
+    if (int rc = tune_strip(c, c->swe, state, s, &best)) return rc;
+    c->swe = best;
+  } else {
+    c->swe = c->swe_halo;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  c->swe = best;
-  *strip_out = best.strip_h;
+  *strip_out = c->swe.strip_h;
   return 0;
 }
 
 int iewpf_set_strip_rows(iewpf_ctx* c, int rows) {
   if (!c || rows < 1) return fail(IEWPF_E_ARG, "strip rows must be >= 1");
-  c->swe.strip_h = std::min(rows, c->ny);
-  c->swe.n_strip_y = (c->ny + c->swe.strip_h - 1) / c->swe.strip_h;
+  for (SweConst* C : {&c->swe, &c->swe_halo}) {
+    C->strip_h = std::min(rows, c->ny);
+    C->n_strip_y = (c->ny + C->strip_h - 1) / C->strip_h;
+  }
   return 0;
 }
 
@@ -1122,7 +1176,7 @@ int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewp
     b->y_off.push_back(ylen);
     ylen += 2 * (size_t)c->max_obs;
     SweJob J{};
-    J.C = c->swe;
+    J.C = c->swe_halo;
     J.z = nullptr;
     J.buf_a = states[e];
     J.buf_b = c->scratch;
@@ -1130,7 +1184,7 @@ int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewp
     plain.job[e] = J;
     J.z = c->coarse;
     noise.job[e] = J;
-    w += c->ne * c->swe.n_strip_x * c->swe.n_strip_y;
+    w += c->ne * c->swe_halo.n_strip_x * c->swe_halo.n_strip_y;
   }
   plain.total_waves = noise.total_waves = w;
   b->total_waves = w;

@@ -39,6 +39,7 @@ void fill_cr_table(int c, CrTable& t);
 // Shallow-water scheme constants (float32, as used by the stencil).
 struct SweConst {
   int nx, ny;
+  int row;             // 1: full-row form (one workgroup per row strip, nx <= 512)
   int strip_h;         // rows per wave strip
   int n_strip_x, n_strip_y;
   float H, g, inv2g, f;
@@ -120,7 +121,8 @@ struct iewpf_ctx {
   double S[4], Sc[4], Mfine[4];
   double ahalf[iewpf::kBlockN * iewpf::kBlockN];
   int wx, wy, rx, ry;      // pull window geometry
-  iewpf::SweConst swe;
+  iewpf::SweConst swe;       // the scheme step's form for this context's launches
+  iewpf::SweConst swe_halo;  // the strip form (batched launches use it)
   iewpf::CoarseConst cc;
   float soar_me_f[25], soar_init_f[25];
   // device workspaces
@@ -265,6 +267,8 @@ void launch_mass_drift(const float* before, const float* after, int ne, int ncel
 namespace iewpf {
 // resident waves per compute unit of the stencil / analysis-update kernels (occupancy)
 int swe_waves_per_cu();
+// workgroups of the full-row form (nx columns) resident per compute unit
+int swe_row_blocks_per_cu(int nx);
 int update_waves_per_cu();
 int update_particle_group();
 // Number of row strips for a wave-per-strip kernel: minimises (launch rounds) x (rows a

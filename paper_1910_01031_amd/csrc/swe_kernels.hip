@@ -449,6 +449,309 @@ __global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_batch_kernel(
   substep_wave<NOISE>(in, out, J.z, J.C, wave - J.wave_begin);
 }
 
+// ---- full-row form: one workgroup of W = ceil(nx / 64) waves owns whole rows ------------
+// Thread t of the workgroup is column t (t < nx), so the periodic row needs no halo columns
+// and no column is computed twice.  The x-neighbours travel through LDS; the x passes of the
+// two RK stages (stage 1 on psi row m-2, stage 2 on psi* row m-4) are independent within a
+// step, so they share each exchange: three exchanges and three barriers per row.  The
+// arithmetic is the strip form's, term for term (the difference to the previous cell is
+// formed from the exchanged values exactly as the neighbour forms its own), so the results
+// are bit-identical to it.
+
+// One RK stage with the push split around the x pass: ypart() takes the new row (primitive
+// variables, y reconstruction of row m-1, y flux at face (m-2)+1/2); finish() applies the x
+// divergence of row m-2 and advances the rows.
+struct RowStage {
+  float ea, qa, ra, ua, va;
+  float eb, qb, rb, ub, vb;
+  float dL, du, dv;
+  YFace Na;
+  float g0, g1, g2;
+  float un, vn, dLn, dun, dvn;  // of the row being pushed
+  YFace Nb;
+  float G0, G1, G2;
+
+  template <int MODE>
+  __device__ __forceinline__ void ypart(float e, float q, float r, const SweConst& C) {
+    const float rh = rcpf(C.H + e);
+    un = q * rh;
+    vn = r * rh;
+    dLn = (e - eb) + C.fyg * (ub + un);
+    dun = un - ub;
+    dvn = vn - vb;
+    YFace Sb = {};
+    Nb = {};
+    if (MODE != kPushStore) y_recon(eb, ub, vb, dL, du, dv, dLn, dun, dvn, C, Nb, Sb);
+    G0 = G1 = G2 = 0.0f;
+    if (MODE == kPushFluxOnly || MODE == kPushFull)
+      cu_flux(Na.e, Na.n, Na.t, Sb.e, Sb.n, Sb.t, C, G0, G1, G2);
+  }
+  template <int MODE>
+  __device__ __forceinline__ void finish(float e, float q, float r, float x0, float x1, float x2,
+                                         const SweConst& C, float& oe, float& oq, float& orr) {
+    if (MODE == kPushFull) {
+      oe = ea - C.dtidx * x0 - C.dtidy * (G0 - g0);
+      oq = qa + C.dtf * ra - C.dtidx * x1 - C.dtidy * (G2 - g2);
+      orr = ra - C.dtf * qa - C.dtidx * x2 - C.dtidy * (G1 - g1);
+    } else {
+      oe = oq = orr = 0.0f;
+    }
+    ea = eb; qa = qb; ra = rb; ua = ub; va = vb;
+    eb = e; qb = q; rb = r; ub = un; vb = vn;
+    dL = dLn; du = dun; dv = dvn;
+    Na = Nb;
+    g0 = G0; g1 = G1; g2 = G2;
+  }
+};
+
+// Face states of a row from its own values and its two x-neighbours' (x_divergence's
+// reconstruction with the neighbour lanes' values supplied).
+struct XFaces {
+  float eE, uE, vE, eW, uW, vW;
+};
+__device__ __forceinline__ XFaces x_faces(float e, float u, float v, float eE_, float uE_, float vE_,
+                                          float eW_, float uW_, float vW_, const SweConst& C) {
+  const float bK = (eE_ - e) - C.fxg * (v + vE_);
+  const float bu = uE_ - u, bv = vE_ - v;
+  // the previous cell's differences to this one, formed as that cell forms them
+  const float aK = (e - eW_) - C.fxg * (vW_ + v);
+  const float au = u - uW_, av = v - vW_;
+  const float sK = minmod3(aK, (aK + bK) * C.k2t, bK);
+  const float su = minmod3(au, (au + bu) * C.k2t, bu);
+  const float sv = minmod3(av, (av + bv) * C.k2t, bv);
+  const float off = C.ht * sK + C.fxg * v;
+  XFaces F;
+  F.eE = e + off;
+  F.eW = e - off;
+  F.uE = u + C.ht * su;
+  F.uW = u - C.ht * su;
+  F.vE = v + C.ht * sv;
+  F.vW = v - C.ht * sv;
+  return F;
+}
+
+template <bool NOISE, int STRIDE>
+__device__ __forceinline__ void row_strip(const float* __restrict__ in, float* __restrict__ out,
+                                          const float* __restrict__ zall, const SweConst& C,
+                                          int particle, int sy, float* __restrict__ xl) {
+  const int j = threadIdx.x;
+  const int nx = C.nx, ny = C.ny;
+  const size_t ncell = (size_t)nx * ny;
+  const bool active = j < nx;
+  // neighbour columns on the torus (an idle thread past the row reads its own slot)
+  const int jn = !active ? j : (j + 1 == nx ? 0 : j + 1);
+  const int jp = !active ? j : (j == 0 ? nx - 1 : j - 1);
+  const __amdgpu_buffer_rsrc_t bin = state_rsrc(in + (size_t)particle * 3 * ncell, ncell);
+  const __amdgpu_buffer_rsrc_t bout = state_rsrc(out + (size_t)particle * 3 * ncell, ncell);
+  const unsigned fq = 4u * static_cast<unsigned>(ncell), fr = 2u * fq;
+  const unsigned brow = 4u * static_cast<unsigned>(nx);
+  // idle threads read zeros and write nothing
+  const unsigned bj = active ? 4u * static_cast<unsigned>(j) : kBufferOff;
+  const int k0 = sy * C.strip_h;
+  const int k_end = min(k0 + C.strip_h, ny);
+
+  const float* z = nullptr;
+  CoarseRows cr;
+  if (NOISE) {
+    z = zall + (size_t)particle * C.nrx * C.nry;
+    cr.init(z, C, active ? j : j % nx, k0 - 1);
+  }
+  // LDS: three regions (one per exchange of a row) of 7 quantities x STRIDE columns
+  auto slot = [&](int region, int qn) { return xl + (region * 7 + qn) * STRIDE; };
+
+  RowStage s1 = {}, s2 = {};
+  float pe4 = 0, pq4 = 0, pr4 = 0, pe3 = 0, pq3 = 0, pr3 = 0, pe2 = 0, pq2 = 0, pr2 = 0;
+  float pe1 = 0, pq1 = 0, pr1 = 0;
+  float dA = 0.0f, dB = 0.0f;
+
+  constexpr int kPf = IEWPF_SWE_PREFETCH;
+  float ne_[kPf], nq_[kPf], nr_[kPf];
+#pragma unroll
+  for (int i = 0; i < kPf; ++i) {
+    const unsigned off = static_cast<unsigned>(wrap(k0 - 4 + i, ny)) * brow;
+    ne_[i] = ld_buf(bin, bj, off);
+    nq_[i] = ld_buf(bin, bj, off + fq);
+    nr_[i] = ld_buf(bin, bj, off + fr);
+  }
+
+  auto step = [&](int m, auto mode1, auto mode2, bool emit) {
+    constexpr int M1 = decltype(mode1)::value, M2 = decltype(mode2)::value;
+    constexpr bool stage2 = M2 >= 0;
+    constexpr bool x1 = M1 == kPushFull, x2 = M2 == kPushFull;
+    const float e = ne_[0], q = nq_[0], r = nr_[0];
+#pragma unroll
+    for (int i = 0; i + 1 < kPf; ++i) {
+      ne_[i] = ne_[i + 1];
+      nq_[i] = nq_[i + 1];
+      nr_[i] = nr_[i + 1];
+    }
+    const unsigned o2 = static_cast<unsigned>(wrap1(wrap1(m + kPf, ny), ny)) * brow;
+    ne_[kPf - 1] = ld_buf(bin, bj, o2);
+    nq_[kPf - 1] = ld_buf(bin, bj, o2 + fq);
+    nr_[kPf - 1] = ld_buf(bin, bj, o2 + fr);
+    s1.template ypart<M1>(e, q, r, C);
+    // x passes: stage 1 on its row m-2, stage 2 on its row m-4 (both rows pushed earlier)
+    float a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0, dBn = 0, dBp = 0;
+    if (x1 || x2) {
+      float* R0 = slot(0, 0);
+      if (x1) {
+        R0[j] = s1.ea;
+        R0[STRIDE + j] = s1.ua;
+        R0[2 * STRIDE + j] = s1.va;
+      }
+      if (x2) {
+        R0[3 * STRIDE + j] = s2.ea;
+        R0[4 * STRIDE + j] = s2.ua;
+        R0[5 * STRIDE + j] = s2.va;
+      }
+      if (NOISE && x2) R0[6 * STRIDE + j] = dB;
+      __syncthreads();
+      XFaces f1 = {}, f2 = {};
+      if (x1)
+        f1 = x_faces(s1.ea, s1.ua, s1.va, R0[jn], R0[STRIDE + jn], R0[2 * STRIDE + jn], R0[jp],
+                     R0[STRIDE + jp], R0[2 * STRIDE + jp], C);
+      if (x2)
+        f2 = x_faces(s2.ea, s2.ua, s2.va, R0[3 * STRIDE + jn], R0[4 * STRIDE + jn],
+                     R0[5 * STRIDE + jn], R0[3 * STRIDE + jp], R0[4 * STRIDE + jp],
+                     R0[5 * STRIDE + jp], C);
+      if (NOISE && x2) {
+        dBn = R0[6 * STRIDE + jn];
+        dBp = R0[6 * STRIDE + jp];
+      }
+      float* R1 = slot(1, 0);
+      if (x1) {
+        R1[j] = f1.eW;
+        R1[STRIDE + j] = f1.uW;
+        R1[2 * STRIDE + j] = f1.vW;
+      }
+      if (x2) {
+        R1[3 * STRIDE + j] = f2.eW;
+        R1[4 * STRIDE + j] = f2.uW;
+        R1[5 * STRIDE + j] = f2.vW;
+      }
+      __syncthreads();
+      float F10 = 0, F11 = 0, F12 = 0, F20 = 0, F21 = 0, F22 = 0;
+      if (x1)
+        cu_flux(f1.eE, f1.uE, f1.vE, R1[jn], R1[STRIDE + jn], R1[2 * STRIDE + jn], C, F10, F11, F12);
+      if (x2)
+        cu_flux(f2.eE, f2.uE, f2.vE, R1[3 * STRIDE + jn], R1[4 * STRIDE + jn], R1[5 * STRIDE + jn],
+                C, F20, F21, F22);
+      float* R2 = slot(2, 0);
+      if (x1) {
+        R2[j] = F10;
+        R2[STRIDE + j] = F11;
+        R2[2 * STRIDE + j] = F12;
+      }
+      if (x2) {
+        R2[3 * STRIDE + j] = F20;
+        R2[4 * STRIDE + j] = F21;
+        R2[5 * STRIDE + j] = F22;
+      }
+      __syncthreads();
+      if (x1) {
+        a0 = F10 - R2[jp];
+        a1 = F11 - R2[STRIDE + jp];
+        a2 = F12 - R2[2 * STRIDE + jp];
+      }
+      if (x2) {
+        b0 = F20 - R2[3 * STRIDE + jp];
+        b1 = F21 - R2[4 * STRIDE + jp];
+        b2 = F22 - R2[5 * STRIDE + jp];
+      }
+    }
+    float se, sq, sr;
+    s1.template finish<M1>(e, q, r, a0, a1, a2, C, se, sq, sr);  // psi* of row m - 2
+    const float qe4 = pe4, qq4 = pq4, qr4 = pr4;
+    pe4 = pe3; pq4 = pq3; pr4 = pr3;
+    pe3 = pe2; pq3 = pq2; pr3 = pr2;
+    pe2 = pe1; pq2 = pq1; pr2 = pr1;
+    pe1 = e; pq1 = q; pr1 = r;
+    float dC = 0.0f;
+    if (NOISE && M2 > kPushStore) dC = cr.at(z, C, m - 3);
+    if (stage2) {
+      constexpr int M2s = M2 < 0 ? kPushStore : M2;
+      float te, tq, tr;
+      s2.template ypart<M2s>(se, sq, sr, C);
+      s2.template finish<M2s>(se, sq, sr, b0, b1, b2, C, te, tq, tr);  // row m - 4
+      if (emit) {
+        float oe = 0.5f * (qe4 + te), oq = 0.5f * (qq4 + tq), orr = 0.5f * (qr4 + tr);
+        if (NOISE) {
+          oe += dB;
+          oq += -C.gb_y * (dC - dA);
+          orr += C.gb_x * (dBn - dBp);
+        }
+        const unsigned o = static_cast<unsigned>(m - 4) * brow;
+        st_buf(bout, bj, o, oe);
+        st_buf(bout, bj, o + fq, oq);
+        st_buf(bout, bj, o + fr, orr);
+      }
+    }
+    if (NOISE) {
+      dA = dB;
+      dB = dC;
+    }
+  };
+  using Off = PushMode<-1>;
+  using Store = PushMode<kPushStore>;
+  using NoFlux = PushMode<kPushNoFlux>;
+  using FluxOnly = PushMode<kPushFluxOnly>;
+  using Full = PushMode<kPushFull>;
+  step(k0 - 4, Store{}, Off{}, false);
+  step(k0 - 3, Store{}, Off{}, false);
+  step(k0 - 2, NoFlux{}, Off{}, false);
+  step(k0 - 1, FluxOnly{}, Off{}, false);
+  step(k0, Full{}, Store{}, false);
+  step(k0 + 1, Full{}, Store{}, false);
+  step(k0 + 2, Full{}, NoFlux{}, false);
+  step(k0 + 3, Full{}, FluxOnly{}, false);
+  int m = k0 + 4;
+  for (; m + 7 <= k_end + 3; m += 8) {
+    step(m, Full{}, Full{}, true);
+    step(m + 1, Full{}, Full{}, true);
+    step(m + 2, Full{}, Full{}, true);
+    step(m + 3, Full{}, Full{}, true);
+    step(m + 4, Full{}, Full{}, true);
+    step(m + 5, Full{}, Full{}, true);
+    step(m + 6, Full{}, Full{}, true);
+    step(m + 7, Full{}, Full{}, true);
+  }
+  for (; m + 3 <= k_end + 3; m += 4) {
+    step(m, Full{}, Full{}, true);
+    step(m + 1, Full{}, Full{}, true);
+    step(m + 2, Full{}, Full{}, true);
+    step(m + 3, Full{}, Full{}, true);
+  }
+  for (; m <= k_end + 3; ++m) step(m, Full{}, Full{}, true);
+}
+
+#ifndef IEWPF_ROW_MIN_WAVES
+#define IEWPF_ROW_MIN_WAVES 4
+#endif
+
+// grid: n_particles x n_strip_y workgroups of W x 64 threads (W x 64 <= STRIDE)
+template <bool NOISE, int STRIDE>
+__global__ __launch_bounds__(STRIDE, IEWPF_ROW_MIN_WAVES) void swe_row_kernel(
+    const float* __restrict__ in, float* __restrict__ out, const float* __restrict__ zall,
+    SweConst C) {
+  __shared__ float xl[3 * 7 * STRIDE];
+  const int b = blockIdx.x;
+  const int particle = b / C.n_strip_y;
+  const int sy = b - particle * C.n_strip_y;
+  row_strip<NOISE, STRIDE>(in, out, zall, C, particle, sy, xl);
+}
+
+template <int STRIDE>
+void launch_row(const SweConst& C, int ne, const float* in, float* out, const float* z,
+                hipStream_t s) {
+  const int threads = ((C.nx + 63) / 64) * 64;
+  const int blocks = ne * C.n_strip_y;
+  if (z)
+    hipLaunchKernelGGL((swe_row_kernel<true, STRIDE>), dim3(blocks), dim3(threads), 0, s, in, out, z, C);
+  else
+    hipLaunchKernelGGL((swe_row_kernel<false, STRIDE>), dim3(blocks), dim3(threads), 0, s, in, out, z,
+                       C);
+}
+
 }  // namespace
 
 int swe_waves_per_cu() {
@@ -457,6 +760,21 @@ int swe_waves_per_cu() {
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, swe_substep_kernel<false>, 256, 0) != hipSuccess)
     return 16;
   return 4 * std::max(1, std::min(a, b));
+}
+
+int swe_row_blocks_per_cu(int nx) {
+  const int threads = ((nx + 63) / 64) * 64;
+  int a = 0, b = 0;
+  hipError_t e1, e2;
+  if (nx <= 256) {
+    e1 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, swe_row_kernel<true, 256>, threads, 0);
+    e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, swe_row_kernel<false, 256>, threads, 0);
+  } else {
+    e1 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, swe_row_kernel<true, 512>, threads, 0);
+    e2 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, swe_row_kernel<false, 512>, threads, 0);
+  }
+  if (e1 != hipSuccess || e2 != hipSuccess) return 1;
+  return std::max(1, std::min(a, b));
 }
 
 void launch_swe_batch(const SweJobTable* tab, int total_waves, int parity, bool noise,
@@ -470,6 +788,13 @@ void launch_swe_batch(const SweJobTable* tab, int total_waves, int parity, bool 
 
 void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, const float* z,
                         hipStream_t s) {
+  if (C.row) {  // full-row form (nx <= 512)
+    if (C.nx <= 256)
+      launch_row<256>(C, ne, in, out, z, s);
+    else
+      launch_row<512>(C, ne, in, out, z, s);
+    return;
+  }
   const int total = ne * C.n_strip_x * C.n_strip_y;
   const int blocks = (total + 3) / 4;
   if (z)
