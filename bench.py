@@ -54,10 +54,11 @@ MEASURED_COUNTERS = {"hbm_bytes": 2 * 147934.3 * 1024 + 180157.0 * 1024,
 
 
 def _kernel_source_hash():
-    """SHA-256 over the scheme kernel's source, its headers and the build flags."""
+    """SHA-256 over the scheme kernels' source, the headers their code depends on and the
+    build flags."""
     import hashlib
     h = hashlib.sha256()
-    for rel in (("csrc", "swe_kernels.hip"), ("csrc", "internal.hpp"), ("csrc", "buffer_dev.hpp"),
+    for rel in (("csrc", "swe_kernels.hip"), ("csrc", "swe_const.hpp"), ("csrc", "buffer_dev.hpp"),
                 ("build.py",)):
         with open(os.path.join(ROOT, "paper_1910_01031_amd", *rel), "rb") as f:
             h.update(f.read())
@@ -102,6 +103,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched leg (3 graph replays), e.g. under a profiler")
     ap.add_argument("--surrogate-train-steps", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 360 MB device copy (counter calibration)")
@@ -459,12 +462,15 @@ def main():
     cfg = W.paper_scale(args.particles)
     cells = W.buoy_cells(cfg.nx, cfg.ny, 15, 15)
     # the oracle's worker processes are forked before anything touches the GPU
-    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, cells)
+    cpu = None if (args.no_cpu_baseline or args.batched_only) else cpu_baseline(cfg, cells)
     import torch
     from paper_1910_01031_amd import Context, abi
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.batched_only:
+        print(json.dumps({"batched": batched_leg(torch, dev, 3)}), flush=True)
+        return
     n_cycles = args.warmup + args.steps
     steps_per_cycle = 10
 

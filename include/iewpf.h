@@ -270,11 +270,15 @@ int iewpf_autotune(iewpf_ctx* ctx, const float* state, int32_t* strip_out, void*
  * batches created before keep the height they were built with.  IEWPF_E_ARG for rows < 1. */
 int iewpf_set_strip_rows(iewpf_ctx* ctx, int rows);
 
-/* ---- several ensembles of uneven grid and size, one launch per scheme step ------------
- * A batch groups n contexts (same dt and n_sub) and their state buffers.  Every scheme
- * step of all ensembles is one kernel launch over a device table of (grid, buffers, wave
- * range) jobs; model error and analysis run per ensemble.  Contexts and states are owned
- * by the caller and must outlive the batch.  n <= 16. */
+/* ---- several ensembles of uneven grid and size in one captured cycle ------------------
+ * A batch groups n contexts (same dt and n_sub) and their state buffers.  Each scheme step
+ * launches every ensemble's own kernel (in the form its context chose) on up to eight side
+ * streams forked from the cycle's stream and joined back, so a captured graph runs them as
+ * parallel branches; with IEWPF_BATCH_SPLIT=0 in the environment at creation, one launch
+ * over a device table of (grid, buffers, wave range) jobs covers all ensembles instead (the
+ * strip form).  The model-error fields of all noisy model steps of a cycle are drawn ahead
+ * per ensemble, and the analyses run per ensemble on the side streams.  Contexts and states
+ * are owned by the caller and must outlive the batch.  n <= 16. */
 typedef struct iewpf_batch iewpf_batch;
 int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewpf_batch** out);
 void iewpf_batch_destroy(iewpf_batch* b);

@@ -24,6 +24,7 @@ struct iewpf_batch {
   iewpf::SweJobTable* tab_plain = nullptr;  // device tables
   iewpf::SweJobTable* tab_noise = nullptr;
   int total_waves = 0;
+  bool split = false;             // one launch per ensemble (each in its own form) per scheme step
   int n_sub = 1;
   uint64_t* d_dyn = nullptr;      // device counters: first step, analysis index
   uint64_t* h_dyn = nullptr;      // pinned
@@ -463,21 +464,43 @@ int batch_fork(iewpf_batch* b, int point, hipStream_t s, F&& body) {
 int batch_model_steps(iewpf_batch* b, int n_steps, uint64_t first_step, const uint64_t* dyn,
                       hipStream_t s) {
   int parity = 0;
+  const int n_noise = n_steps - 1;  // model error after every step but the last
+  int chunk_max = n_noise;
+  for (int e = 0; e < b->n; ++e) chunk_max = std::min(chunk_max, b->ctx[e]->me_chunk);
+  int chunk0 = 0, chunk_n = 0, fork = 0;
   for (int st = 0; st < n_steps; ++st) {
-    const bool noise = st < n_steps - 1;
-    if (noise) {
-      const int rc = batch_fork(b, st, s, [&](int e, hipStream_t es) {
+    const bool noise = st < n_noise;
+    if (noise && st >= chunk0 + chunk_n) {
+      // the model-error fields of the next model steps of every ensemble, drawn ahead by one
+      // normals and one SOAR launch per ensemble (the same draws as one launch per step)
+      chunk0 = st;
+      chunk_n = std::min(chunk_max, n_noise - st);
+      const int rc = batch_fork(b, fork++, s, [&](int e, hipStream_t es) {
         iewpf_ctx* c = b->ctx[e];
-        launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, (dyn ? 0 : first_step) + st,
-                       kTagModelError, c->cfg.ensemble_id, es, dyn);
-        launch_soar(c->cc, c->soar_me_f, c->ne, c->xi, c->coarse, es);
+        launch_normals(c->me_xi, c->nr, c->ne, c->cfg.seed, (dyn ? 0 : first_step) + st,
+                       kTagModelError, c->cfg.ensemble_id, es, dyn, chunk_n);
+        launch_soar(c->cc, c->soar_me_f, c->ne * chunk_n, c->me_xi, c->me_coarse, es);
         return 0;
       });
       if (rc) return rc;
     }
     for (int sub = 0; sub < b->n_sub; ++sub) {
       const bool fuse = noise && sub == b->n_sub - 1;
-      launch_swe_batch(fuse ? b->tab_noise : b->tab_plain, b->total_waves, parity, fuse, s);
+      if (b->split) {
+        // every ensemble's own launch, in its own form, as parallel branches
+        const int rc = batch_fork(b, n_steps + 1 + st * b->n_sub + sub, s, [&](int e, hipStream_t es) {
+          iewpf_ctx* c = b->ctx[e];
+          float* in = parity ? c->scratch : b->state[e];
+          float* out = parity ? b->state[e] : c->scratch;
+          const float* z = fuse ? c->me_coarse + (size_t)(st - chunk0) * c->ne * c->nr : nullptr;
+          launch_swe_substep(c->swe, c->ne, in, out, z, es);
+          return 0;
+        });
+        if (rc) return rc;
+      } else {
+        launch_swe_batch(fuse ? b->tab_noise : b->tab_plain, b->total_waves, parity, fuse,
+                         fuse ? st - chunk0 : 0, s);
+      }
       parity ^= 1;
     }
   }
@@ -493,6 +516,7 @@ int batch_model_steps(iewpf_batch* b, int n_steps, uint64_t first_step, const ui
 int batch_cycle_body(iewpf_batch* b, int n_steps, uint64_t first_step, uint64_t analysis_index,
                      const uint64_t* dyn, hipStream_t s) {
   if (int rc = batch_model_steps(b, n_steps, first_step, dyn, s)) return rc;
+  // fork points 0 .. n_steps - 1 are the model-error chunks (at most one per model step)
   return batch_fork(b, n_steps, s, [&](int e, hipStream_t es) {
     return launch_analysis(b->ctx[e], b->state[e], b->n_obs[e], dyn ? 0 : analysis_index, dyn, es);
   });
@@ -1164,6 +1188,7 @@ int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewp
   iewpf_batch* b = new iewpf_batch();
   b->n = n;
   b->n_sub = ctxs[0]->cfg.n_sub;
+  b->split = env_int("IEWPF_BATCH_SPLIT", 1) != 0;
   SweJobTable plain{}, noise{};
   plain.n = noise.n = n;
   int w = 0;
@@ -1178,11 +1203,13 @@ int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewp
     SweJob J{};
     J.C = c->swe_halo;
     J.z = nullptr;
+    J.z_field = 0;
     J.buf_a = states[e];
     J.buf_b = c->scratch;
     J.wave_begin = w;
     plain.job[e] = J;
-    J.z = c->coarse;
+    J.z = c->me_coarse;
+    J.z_field = (size_t)c->ne * c->nr;
     noise.job[e] = J;
     w += c->ne * c->swe_halo.n_strip_x * c->swe_halo.n_strip_y;
   }
@@ -1201,7 +1228,8 @@ int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewp
             hipEventCreateWithFlags(&b->out_ev, hipEventDisableTiming) == hipSuccess &&
             hipStreamCreateWithFlags(&b->gs, hipStreamNonBlocking) == hipSuccess &&
             [&] {
-              for (int i = 0; i < std::min(n, 4); ++i) {
+              const int n_side = std::max(1, std::min(n, env_int("IEWPF_BATCH_STREAMS", 8)));
+              for (int i = 0; i < n_side; ++i) {
                 hipStream_t x = nullptr;
                 if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) return false;
                 b->side.push_back(x);

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "iewpf.h"
+#include "swe_const.hpp"
 
 #include <vector>
 
@@ -26,52 +27,6 @@ int fail(int code, const std::string& msg);
   } while (0)
 
 // ---- constants passed by value to kernels ----------------------------------------------
-
-// Catmull-Rom weights of the interpolation I_Omega (taps -1, 0, 1, 2) at the phases
-// t = p / (2c), p = 0 .. 2c-1, of fine rows between coarse points (filled on the host in
-// float64, rounded once).  Contexts accept c <= kCrMaxC.
-constexpr int kCrMaxC = 16;
-struct CrTable {
-  float w[2 * kCrMaxC][4];
-};
-void fill_cr_table(int c, CrTable& t);
-
-// Shallow-water scheme constants (float32, as used by the stencil).
-struct SweConst {
-  int nx, ny;
-  int row;             // 1: full-row form (one workgroup per row strip, nx <= 512)
-  int strip_h;         // rows per wave strip
-  int n_strip_x, n_strip_y;
-  float H, g, inv2g, f;
-  float hfdx, hfdy;    // f dx / 2, f dy / 2 (Coriolis potential increments)
-  float fdx, fdy;      // f dx, f dy
-  float theta;
-  // the limiter works on slopes divided by theta; these fold theta back in
-  float k2t;           // 1 / (2 theta): the central difference's weight in the minmod
-  float ht;            // theta / 2: face offset of u, v per limited slope
-  float fxg, fyg;      // f dx / (2 g), f dy / (2 g): Coriolis potential / g increments
-  float dt, idx, idy;  // scheme step, 1/dx, 1/dy
-  float dtidx, dtidy, dtf;  // dt/dx, dt/dy, dt f
-  // fused model error (last scheme step of a model step)
-  int c, nrx, nry;     // coarsening and coarse grid
-  float gb_x, gb_y;    // g H / (2 f dx), g H / (2 f dy)
-  CrTable cr;          // interpolation weights by phase
-};
-
-// One ensemble of a batched stencil launch (device-resident table).
-struct SweJob {
-  SweConst C;
-  const float* z;   // fused model-error field of this launch or nullptr
-  float* buf_a;     // the caller's state
-  float* buf_b;     // the context's scratch state
-  int wave_begin;
-};
-constexpr int kMaxBatch = 16;
-struct SweJobTable {
-  int n;
-  int total_waves;
-  SweJob job[kMaxBatch];
-};
 
 // Coarse random grid and covariance stencils.
 struct CoarseConst {
@@ -100,9 +55,6 @@ constexpr int kStatNonfiniteScalar = 2;  // c_i, gamma_i, zeta_i, c*_i or alpha_
 constexpr int kStatSkipUpdate = kStatBeta | kStatNonfiniteScalar;
 constexpr int kStatNonfiniteState = 4;   // a value written by the update is not finite
 
-constexpr int kWave = 64;
-constexpr int kSweHalo = 4;                   // lanes lost per side by the fused RK stages
-constexpr int kSweOut = kWave - 2 * kSweHalo;  // 56 output columns per wave
 constexpr int kGbHalo = 1;                    // lanes lost per side by the geostrophic stencil
 constexpr int kGbOut = kWave - 2 * kGbHalo;    // 62 output columns per wave
 constexpr int kBlockN = 49;                   // 7x7 local block of the posterior operator
@@ -275,7 +227,8 @@ int update_particle_group();
 // wave marches), rounds = ceil(columns * n_strips / slots), rows = ceil(ny / n_strips) +
 // halo_rows.  columns = strips per row of strips (all particles).
 int choose_row_strips(int columns, int ny, int slots, int halo_rows, int min_rows);
-void launch_swe_batch(const SweJobTable* tab, int total_waves, int parity, bool noise,
+// noise: each job adds the model-error field zstep of its chunk (job.z + zstep job.z_field)
+void launch_swe_batch(const SweJobTable* tab, int total_waves, int parity, bool noise, int zstep,
                       hipStream_t s);
 // z != nullptr: also add the model error Q_GB I_Omega z (z: [ne][nry][nrx] SOAR field)
 void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, const float* z,

@@ -437,7 +437,7 @@ __global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_substep_kernel(
 // tables that way).
 template <bool NOISE>
 __global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_batch_kernel(
-    const SweJobTable* __restrict__ tab, int parity) {
+    const SweJobTable* __restrict__ tab, int parity, int zstep) {
   const int wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave));
   if (wave >= tab->total_waves) return;
@@ -446,7 +446,9 @@ __global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_batch_kernel(
   const SweJob& J = tab->job[e];
   const float* in = parity ? J.buf_b : J.buf_a;
   float* out = parity ? J.buf_a : J.buf_b;
-  substep_wave<NOISE>(in, out, J.z, J.C, wave - J.wave_begin);
+  // with NOISE, the field of model step zstep of the chunk drawn ahead
+  substep_wave<NOISE>(in, out, NOISE ? J.z + (size_t)zstep * J.z_field : nullptr, J.C,
+                      wave - J.wave_begin);
 }
 
 // ---- full-row form: one workgroup of W = ceil(nx / 64) waves owns whole rows ------------
@@ -777,13 +779,13 @@ int swe_row_blocks_per_cu(int nx) {
   return std::max(1, std::min(a, b));
 }
 
-void launch_swe_batch(const SweJobTable* tab, int total_waves, int parity, bool noise,
+void launch_swe_batch(const SweJobTable* tab, int total_waves, int parity, bool noise, int zstep,
                       hipStream_t s) {
   const int blocks = (total_waves + 3) / 4;
   if (noise)
-    hipLaunchKernelGGL(swe_batch_kernel<true>, dim3(blocks), dim3(256), 0, s, tab, parity);
+    hipLaunchKernelGGL(swe_batch_kernel<true>, dim3(blocks), dim3(256), 0, s, tab, parity, zstep);
   else
-    hipLaunchKernelGGL(swe_batch_kernel<false>, dim3(blocks), dim3(256), 0, s, tab, parity);
+    hipLaunchKernelGGL(swe_batch_kernel<false>, dim3(blocks), dim3(256), 0, s, tab, parity, 0);
 }
 
 void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, const float* z,
