@@ -31,10 +31,11 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 N_CU, CLOCK_GHZ = 256, 2.4
-# VALU wave-instructions issued per clock per CU by a probe of eight independent non-packed
-# FP32 FMA chains per wave at 8 waves per SIMD: the attainable issue ceiling of a kernel
-# built without packed FP32 (1.27 at 4 waves per SIMD)
-VALU_ISSUE_CEILING = 1.49
+# VALU wave-instructions issued per clock per CU (at the nominal 2.4 GHz) by a probe of
+# eight independent non-packed FP32 multiply-add chains per wave at 8 waves per SIMD: the
+# attainable issue rate of a kernel built without packed FP32 (0.91 at 5 waves per SIMD;
+# square roots and reciprocals issue at about half that rate)
+VALU_ISSUE_CEILING = 0.94
 # Algorithmic work of one scheme step (both SSP-RK2 stages) per cell: read eta, hu, hv
 # once and write them once (float32) ...
 BYTES_PER_CELL_STEP = 24.0
@@ -48,9 +49,9 @@ SURROGATE_FLOPS_PER_PIXEL = 171_072
 # HBM bytes = FETCH_SIZE x 2 + WRITE_SIZE x 1 KiB (the scale factors a plain device copy of
 # known size reads) and SQ_INSTS_VALU, with the SHA-256 of the kernel source they were taken
 # on: reported only while the source is unchanged.
-MEASURED_COUNTERS = {"hbm_bytes": 2 * 147934.3 * 1024 + 180157.0 * 1024,
-                     "valu_insts": 90.3e6,
-                     "source_sha256": "de17eed7e694c198e472e4ceeea9c3f5c010a5fe8372cd590c262c7c5bf9a148"}
+MEASURED_COUNTERS = {"hbm_bytes": (2 * 104329 + 175839) * 1024,
+                     "valu_insts": 78.388e6,
+                     "source_sha256": "1d15d97f6e2295ee75514f74033c6a6c90eecf5187c79760d0120be10c24a46b"}
 
 
 def _kernel_source_hash():
