@@ -104,6 +104,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-large-ensemble", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched leg (3 graph replays), e.g. under a profiler")
     ap.add_argument("--surrogate-train-steps", type=int, default=1000)
@@ -367,7 +368,20 @@ def drifter_comparison(torch, dev, ctx, net, start, cfg, windows: int = 12):
             "spread_plain_m": spread, "surrogate_fallbacks": runs["surrogate"][1]}
 
 
-def surrogate_leg(torch, dev, ctx, ens, cfg, train_steps: int):
+def large_ensemble_leg(torch, net):
+    """The large-ensemble drift forecast at reduced duration: 1000 particles on the 500x300
+    grid through 2 h of IEWPF on the 225 moorings (24 analyses), then a 1 h forecast of 64
+    drifters per particle with the plain model and with the surrogate (the network of the
+    surrogate leg), side by side: E(t), RMSE(t) per hour, throughput."""
+    from paper_1910_01031_amd import experiments as ex
+    r = ex.drift_forecast(torch, n_particles=1000, da_hours=2.0, forecast_hours=1.0,
+                          n_drifters=64, net=net)
+    r["workload"] = ("1000 particles, 500x300, 2 h of IEWPF on 225 moorings, then 1 h of "
+                     "64 drifters per particle, plain and surrogate")
+    return r
+
+
+def surrogate_leg(torch, dev, ctx, ens, cfg, train_steps: int, keep_net: bool = False):
     """Learned surrogate of the 5-minute window on the paper-scale ensemble.  Training pairs
     (psi, ten deterministic model steps of psi) come from the same workload's own forecast:
     four windows of a 100-particle ensemble drawn around the jet with its own random
@@ -437,9 +451,10 @@ def surrogate_leg(torch, dev, ctx, ens, cfg, train_steps: int):
     eta_drift = float(((out[:, 0] - start[:, 0]).double().mean(dim=(1, 2)).abs()).max() / cfg.H)
     drift = drifter_comparison(torch, dev, ctx, net, start, cfg)
     ens.copy_(start)
-    net.close()
+    if not keep_net:
+        net.close()
     flop = SURROGATE_FLOPS_PER_PIXEL * cfg.n_particles * cfg.n_cells
-    return {"train_states": 400, "train_cells": 400 * cfg.n_cells, "train_steps": train_steps,
+    res = {"train_states": 400, "train_cells": 400 * cfg.n_cells, "train_steps": train_steps,
             "batch_states": 1, "pair_generation_s": gen_s, "train_s": train_s,
             "loss_history": hist,
             "heldout_rmse_eta_hu_hv": rmse.tolist(),
@@ -453,6 +468,7 @@ def surrogate_leg(torch, dev, ctx, ens, cfg, train_steps: int):
             "fallbacks_deterministic": nf_det,
             "max_mass_drift": float(np.max(drift_w)), "max_mean_eta_drift_over_H": eta_drift,
             "drifters_1h": drift}
+    return (res, net) if keep_net else res
 
 
 def main():
@@ -606,7 +622,14 @@ def main():
     if not args.no_batched:
         out["batched"] = batched_leg(torch, dev, 3)
     if not args.no_surrogate:
-        out["surrogate"] = surrogate_leg(torch, dev, ctx, ens, cfg, args.surrogate_train_steps)
+        out["surrogate"], net = surrogate_leg(torch, dev, ctx, ens, cfg, args.surrogate_train_steps,
+                                              keep_net=True)
+        ctx.close()
+        tctx.close()
+        del ens, truth
+        if not args.no_large_ensemble:
+            out["large_ensemble"] = large_ensemble_leg(torch, net)
+        net.close()
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -182,13 +182,16 @@ def _errors(torch, pos, truth_pos, lx, ly):
 
 def drift_forecast(torch, n_particles: int = 1000, da_hours: float = 24.0,
                    forecast_hours: float = 12.0, n_drifters: int = 64, train_steps: int = 1000,
-                   net_particles: int = 100):
+                   net_particles: int = 100, net=None, keep_positions: bool = False):
     """The large-ensemble drift forecast: n_particles through da_hours of two-stage IEWPF on
     the 225 moorings, then a forecast of n_drifters drifters per particle (bilinear velocity,
     Heun, dt = 30 s) with the plain model and with the surrogate (trained first on the
-    workload's own forecast windows, plain re-step above a mass drift of 1e-4, one
-    model-error draw scaled by 3 per window).  Reports, per forecast hour, the forecast error
-    E(t) against the true drifters and the spread RMSE(t) for both, and the throughput."""
+    workload's own forecast windows unless a trained `net` is given, plain re-step above a
+    mass drift of 1e-4, one model-error draw scaled by 3 per window).  Reports, per forecast
+    hour, the forecast error E(t) against the true drifters and the spread RMSE(t) for both
+    (eq. errorPerEnsembleDrifter, eq. errorNorm; minimum-image distances), and the
+    throughput.  keep_positions: also return the positions of every hour (float64 arrays:
+    truth [hours][n_drifters][2], each form [hours][n_particles][n_drifters][2])."""
     import time
     W = _workloads()
     from . import surrogate as sur
@@ -217,12 +220,16 @@ def drift_forecast(torch, n_particles: int = 1000, da_hours: float = 24.0,
     torch.cuda.synchronize()
     da_s = time.perf_counter() - t0
     # surrogate trained on the workload's own windows (a 100-particle ensemble of this grid)
-    pairs = sur.make_pairs(torch, cfg.replace(n_particles=net_particles), 4 * net_particles,
-                           W.jet_state(cfg), group=net_particles, spinup_steps=10,
-                           windows_per_group=4, stream_base=100)
-    net = abi.Net(net_particles * cfg.n_cells)
-    net.set_params(sur.init_params(0))
-    sur.train(net, pairs, train_steps, batch=1)
+    pairs = None
+    if net is None:
+        pairs = sur.make_pairs(torch, cfg.replace(n_particles=net_particles), 4 * net_particles,
+                               W.jet_state(cfg), group=net_particles, spinup_steps=10,
+                               windows_per_group=4, stream_base=100)
+    own_net = net is None
+    if own_net:
+        net = abi.Net(net_particles * cfg.n_cells)
+        net.set_params(sur.init_params(0))
+        sur.train(net, pairs, train_steps, batch=1)
     del pairs
     side = int(round(math.sqrt(n_drifters)))
     lattice = torch.from_numpy(W.drifter_lattice(cfg, side, side)).to(dev)
@@ -237,6 +244,7 @@ def drift_forecast(torch, n_particles: int = 1000, da_hours: float = 24.0,
            "da_particle_cell_steps_per_s": n_particles * cfg.n_cells * cfg.n_sub * steps * n_cyc / da_s,
            "hour": list(range(1, hours + 1)), "plain": {"E": [], "RMSE": [], "seconds": 0.0},
            "surrogate": {"E": [], "RMSE": [], "seconds": 0.0, "fallbacks": 0}}
+    kept = {"truth": [], "plain": [], "surrogate": []}
     for h in range(hours):
         f0 = first + h * 12 * steps
         tctx.forecast_drifters(truth, pos_t, 12 * steps, first_step=f0)
@@ -253,13 +261,20 @@ def drift_forecast(torch, n_particles: int = 1000, da_hours: float = 24.0,
             e, r = _errors(torch, pos, pos_t[0], lx, ly)
             out[name]["E"].append(e)
             out[name]["RMSE"].append(r)
+            if keep_positions:
+                kept[name].append(pos.cpu().numpy())
+        if keep_positions:
+            kept["truth"].append(pos_t[0].cpu().numpy())
     cells_steps = n_particles * cfg.n_cells * cfg.n_sub * steps * 12 * hours
     for name in runs:
         out[name]["particle_cell_steps_per_s"] = cells_steps / out[name]["seconds"]
     out["speedup"] = out["plain"]["seconds"] / out["surrogate"]["seconds"]
-    net.close()
+    if own_net:
+        net.close()
     ctx.close()
     tctx.close()
+    if keep_positions:
+        out["positions"] = {k: np.stack(v) for k, v in kept.items()}
     return out
 
 
