@@ -387,7 +387,7 @@ int iewpf_forecast_drifters_surrogate(iewpf_ctx* ctx, iewpf_net* net, float* sta
  * iewpf_trace_read waits for the recorded events and returns, per kernel kind, the total
  * milliseconds and launch count since the last start.  Kinds: 0 scheme step (both RK
  * stages), 1 model-error normals, 2 SOAR, 3 geostrophic add (model error / initial state),
- * 4 innovations, 5 xi/nu draws + dot products, 6 beta/alpha, 7 coarse posterior field,
+ * 4 innovations (full-covariance path), 5 innovations (other paths) + xi/nu draws + dot products, 6 beta/alpha, 7 coarse posterior field,
  * 8 analysis update pass, 9 scheme step with the model error of its model step fused in.
  * n_kinds <= 16.  At most 8192 launches are recorded; later
  * launches are not timed. */

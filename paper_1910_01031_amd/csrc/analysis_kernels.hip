@@ -70,12 +70,11 @@ struct Mat2 {
   double a[4];
 };
 
-__global__ __launch_bounds__(kThreads) void innovation_kernel(
-    int n_obs, int max_obs, int nx, int ny, double H, Mat2 S, double out_scale,
+// particle i's innovations, S d and c_i (one workgroup)
+__device__ __forceinline__ void innovation_body(
+    int i, int n_obs, int max_obs, int nx, int ny, double H, const Mat2& S, double out_scale,
     const float* __restrict__ psi, const int32_t* __restrict__ cells, const double* __restrict__ y,
-    double* __restrict__ sd, double* __restrict__ cval) {
-  __shared__ double sh[kThreads];
-  const int i = blockIdx.x;
+    double* __restrict__ sd, double* __restrict__ cval, double* sh) {
   const size_t ncell = (size_t)nx * ny;
   const float* E = psi + (size_t)i * 3 * ncell;
   double phi = 0.0;
@@ -94,6 +93,14 @@ __global__ __launch_bounds__(kThreads) void innovation_kernel(
   }
   phi = block_sum(phi, sh);
   if (threadIdx.x == 0) cval[i] = out_scale * phi;
+}
+
+__global__ __launch_bounds__(kThreads) void innovation_kernel(
+    int n_obs, int max_obs, int nx, int ny, double H, Mat2 S, double out_scale,
+    const float* __restrict__ psi, const int32_t* __restrict__ cells, const double* __restrict__ y,
+    double* __restrict__ sd, double* __restrict__ cval) {
+  __shared__ double sh[kThreads];
+  innovation_body(blockIdx.x, n_obs, max_obs, nx, ny, H, S, out_scale, psi, cells, y, sd, cval, sh);
 }
 
 // Normalised weights of the standard particle filter from log-weights (one workgroup):
@@ -134,19 +141,17 @@ __global__ void observe_drifters_kernel(int n, int nx, int ny, double dx, double
 
 // grid (parts, ne): part q of particle i handles Philox blocks q*kThreads + t + k*stride
 // (stride = parts*kThreads); partial sums go to part_dots[i][q][3] and are added in the
-// fixed order q = 0.. by reduce_dots_kernel.  The host picks parts so that one pass covers
+// fixed order q = 0.. by the sync kernel.  The host picks parts so that one pass covers
 // the grid when it can (each thread then draws its normals once), at most kDotParts.
 constexpr int kDotParts = 16;
 
-__global__ __launch_bounds__(kThreads) void rand_dots_kernel(int nr, int parts, uint64_t seed, uint64_t step,
-                                                             uint32_t ens, float* __restrict__ xi,
-                                                             float* __restrict__ nu,
-                                                             double* __restrict__ part_dots,
-                                                             const uint64_t* __restrict__ dyn) {
-  __shared__ double sh[kThreads];
+// part q of particle i's draws and dot products (one workgroup)
+__device__ __forceinline__ void rand_dots_body(int i, int q, int nr, int parts, uint64_t seed,
+                                               uint64_t step, uint32_t ens, float* __restrict__ xi,
+                                               float* __restrict__ nu,
+                                               double* __restrict__ part_dots,
+                                               const uint64_t* __restrict__ dyn, double* sh) {
   if (dyn) step += dyn[1];  // analysis index from device memory (captured graphs)
-  const int i = blockIdx.y;
-  const int q = blockIdx.x;
   float* X = xi + (size_t)i * nr;
   float* N = nu + (size_t)i * nr;
   double xx = 0.0, nn = 0.0, nxv = 0.0;
@@ -179,21 +184,31 @@ __global__ __launch_bounds__(kThreads) void rand_dots_kernel(int nr, int parts, 
   }
 }
 
-__global__ void reduce_dots_kernel(int ne, int parts, const double* __restrict__ part_dots,
-                                   double* __restrict__ dots) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ne) return;
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int q = 0; q < parts; ++q) {
-    const double* o = part_dots + ((size_t)i * parts + q) * 3;
-    a += o[0];
-    b += o[1];
-    c += o[2];
-  }
-  dots[3 * i] = a;
-  dots[3 * i + 1] = b;
-  dots[3 * i + 2] = c;
+__global__ __launch_bounds__(kThreads) void rand_dots_kernel(int nr, int parts, uint64_t seed,
+                                                             uint64_t step, uint32_t ens,
+                                                             float* __restrict__ xi,
+                                                             float* __restrict__ nu,
+                                                             double* __restrict__ part_dots,
+                                                             const uint64_t* __restrict__ dyn) {
+  __shared__ double sh[kThreads];
+  rand_dots_body(blockIdx.y, blockIdx.x, nr, parts, seed, step, ens, xi, nu, part_dots, dyn, sh);
 }
+
+// Stages 1-3 in one launch: grid (parts + 1, ne); workgroup x = parts computes particle y's
+// innovations, the others its draws (the two are independent).
+__global__ __launch_bounds__(kThreads) void innov_draws_kernel(
+    int n_obs, int max_obs, int nx, int ny, double H, Mat2 S, const float* __restrict__ psi,
+    const int32_t* __restrict__ cells, const double* __restrict__ y, double* __restrict__ sd,
+    double* __restrict__ cval, int nr, int parts, uint64_t seed, uint64_t step, uint32_t ens,
+    float* __restrict__ xi, float* __restrict__ nu, double* __restrict__ part_dots,
+    const uint64_t* __restrict__ dyn) {
+  __shared__ double sh[kThreads];
+  if ((int)blockIdx.x == parts)
+    innovation_body(blockIdx.y, n_obs, max_obs, nx, ny, H, S, 1.0, psi, cells, y, sd, cval, sh);
+  else
+    rand_dots_body(blockIdx.y, blockIdx.x, nr, parts, seed, step, ens, xi, nu, part_dots, dyn, sh);
+}
+
 
 // (x - 1) - ln x for x = 1 + e, accurate for small e.
 __device__ double xm1_minus_log(double e) {
@@ -271,13 +286,28 @@ __device__ double alpha_solve(double gamma, double cstar, double N) {
 __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, double n_r,
                                                         int one_stage,
                                                         const double* __restrict__ cval,
-                                                        const double* __restrict__ dots,
+                                                        const double* __restrict__ part_dots,
+                                                        int parts, double* __restrict__ dots,
                                                         double* __restrict__ alpha,
                                                         double* __restrict__ cstar,
                                                         double* __restrict__ scal) {
   __shared__ double sh[kWavesPerBlock];
   __shared__ double shb[kWavesPerBlock];
   __shared__ int shi[kWavesPerBlock];
+  // the draws' dot products: the parts of each particle added in the fixed order q = 0..
+  // (each thread sums and later reads only its own particles)
+  for (int i = threadIdx.x; i < ne; i += kThreads) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int q = 0; q < parts; ++q) {
+      const double* o = part_dots + ((size_t)i * parts + q) * 3;
+      a += o[0];
+      b += o[1];
+      c += o[2];
+    }
+    dots[3 * i] = a;
+    dots[3 * i + 1] = b;
+    dots[3 * i + 2] = c;
+  }
   double s = 0.0;
   for (int i = threadIdx.x; i < ne; i += kThreads) s += cval[i];
   const double cmean = block_sum(s, sh) / ne;
@@ -880,20 +910,35 @@ void launch_observe_drifters(int n, int nx, int ny, double dx, double dy, double
 
 int rand_dots_parts() { return kDotParts; }
 
-void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens, float* xi,
-                      float* nu, double* part_dots, double* dots, hipStream_t s, const uint64_t* dyn) {
+int rand_dots_parts_for(int nr) {
   const int nblk = (nr + 3) / 4;
-  const int parts = std::min(kDotParts, std::max(1, (nblk + kThreads - 1) / kThreads));
-  hipLaunchKernelGGL(rand_dots_kernel, dim3(parts, ne), dim3(kThreads), 0, s, nr, parts, seed, step,
-                     ens, xi, nu, part_dots, dyn);
-  hipLaunchKernelGGL(reduce_dots_kernel, dim3((ne + 127) / 128), dim3(128), 0, s, ne, parts, part_dots,
-                     dots);
+  return std::min(kDotParts, std::max(1, (nblk + kThreads - 1) / kThreads));
 }
 
-void launch_sync(int ne, double n_psi, double n_r, int one_stage, const double* cval,
-                 const double* dots, double* alpha, double* cstar, double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(sync_kernel, dim3(1), dim3(kThreads), 0, s, ne, n_psi, n_r, one_stage, cval,
-                     dots, alpha, cstar, scal);
+void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens, float* xi,
+                      float* nu, double* part_dots, hipStream_t s, const uint64_t* dyn) {
+  const int parts = rand_dots_parts_for(nr);
+  hipLaunchKernelGGL(rand_dots_kernel, dim3(parts, ne), dim3(kThreads), 0, s, nr, parts, seed, step,
+                     ens, xi, nu, part_dots, dyn);
+}
+
+void launch_innov_draws(int ne, int n_obs, int max_obs, int nx, int ny, double H,
+                        const double S[4], const float* psi, const int32_t* cells, const double* y,
+                        double* sd, double* cval, int nr, uint64_t seed, uint64_t step,
+                        uint32_t ens, float* xi, float* nu, double* part_dots, hipStream_t s,
+                        const uint64_t* dyn) {
+  Mat2 M{{S[0], S[1], S[2], S[3]}};
+  const int parts = rand_dots_parts_for(nr);
+  hipLaunchKernelGGL(innov_draws_kernel, dim3(parts + 1, ne), dim3(kThreads), 0, s, n_obs, max_obs,
+                     nx, ny, H, M, psi, cells, y, sd, cval, nr, parts, seed, step, ens, xi, nu,
+                     part_dots, dyn);
+}
+
+void launch_sync(int ne, int nr, double n_psi, int one_stage, const double* cval,
+                 const double* part_dots, double* dots, double* alpha, double* cstar,
+                 double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(sync_kernel, dim3(1), dim3(kThreads), 0, s, ne, n_psi, (double)nr, one_stage,
+                     cval, part_dots, rand_dots_parts_for(nr), dots, alpha, cstar, scal);
 }
 
 void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,

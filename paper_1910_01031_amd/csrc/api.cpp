@@ -340,30 +340,31 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
     IEWPF_HIP_TRY(hipGetLastError());
     return 0;
   }
-  // stages 1-2: innovations, S d, c_i
-  {
-    TraceScope tr(c, kTrInnov, s);
-    if (c->full_innov && n_obs > 0) {  // raw d, then S d and c_i with the full S
+  if (c->full_innov && n_obs > 0) {
+    // stages 1-2: raw d, then S d and c_i with the full S
+    {
+      TraceScope tr(c, kTrInnov, s);
       const double I2[4] = {1.0, 0.0, 0.0, 1.0};
       launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, I2, state, c->obs_cells,
                         c->obs_y, c->dinn, c->cval, s);
       launch_sd_full(2 * n_obs, c->ne, 2 * c->max_obs, c->fX, c->dinn, c->sd, c->cval, s);
-    } else {
-      launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, c->S, state,
-                        c->obs_cells, c->obs_y, c->sd, c->cval, s);
     }
-  }
-  // stage 3: xi, nu~ and their dot products
-  {
+    // stage 3: xi, nu~ and their dot products
     TraceScope tr(c, kTrRandDots, s);
     launch_rand_dots(c->ne, c->nr, c->cfg.seed, analysis_index, c->cfg.ensemble_id, c->xi, c->nu,
-                     c->part_dots, c->dots, s, dyn);
+                     c->part_dots, s, dyn);
+  } else {
+    // stages 1-3 in one launch: innovations, S d, c_i and the draws with their dot products
+    TraceScope tr(c, kTrRandDots, s);
+    launch_innov_draws(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, c->S, state,
+                       c->obs_cells, c->obs_y, c->sd, c->cval, c->nr, c->cfg.seed, analysis_index,
+                       c->cfg.ensemble_id, c->xi, c->nu, c->part_dots, s, dyn);
   }
   // stages 4-5: cbar, beta, c*, alpha (the one ensemble-wide step)
   {
     TraceScope tr(c, kTrSync, s);
-    launch_sync(c->ne, c->n_psi, (double)c->nr, c->one_stage, c->cval, c->dots, c->alpha, c->cstar,
-                c->scal, s);
+    launch_sync(c->ne, c->nr, c->n_psi, c->one_stage, c->cval, c->part_dots, c->dots, c->alpha,
+                c->cstar, c->scal, s);
   }
   // stage 6: r' on the coarse grid, SOAR, then one fused pass over the state
   {

@@ -256,9 +256,15 @@ void launch_observe_drifters(int n, int nx, int ny, double dx, double dy, double
                              const double* pos_now, const double* pos_prev, int32_t* cells,
                              double* y, hipStream_t s);
 int rand_dots_parts();
+// innovations, S d, c_i and the draws with their per-part dot products in one launch
+void launch_innov_draws(int ne, int n_obs, int max_obs, int nx, int ny, double H,
+                        const double S[4], const float* psi, const int32_t* cells, const double* y,
+                        double* sd, double* cval, int nr, uint64_t seed, uint64_t step,
+                        uint32_t ens, float* xi, float* nu, double* part_dots, hipStream_t s,
+                        const uint64_t* dyn = nullptr);
+// xi, nu~ and their per-part dot products (summed by the sync kernel)
 void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens, float* xi,
-                      float* nu, double* part_dots, double* dots, hipStream_t s,
-                      const uint64_t* dyn = nullptr);
+                      float* nu, double* part_dots, hipStream_t s, const uint64_t* dyn = nullptr);
 // Full innovation covariance: assemble sym(H Q H^T) + sigma^2 I [2 n_obs]^2 (float64) from the
 // float64 pull windows, factor it A = L L^T in place in one workgroup (n <= chol_max_order();
 // lower triangle L, upper L^T), solve A x = b per right-hand side (rhs == nullptr gives the
@@ -274,8 +280,9 @@ void launch_sd_full(int n, int ne, int stride, const double* S, const double* D,
                     double* cval, hipStream_t s);
 // Also writes the analysis status words (kScalStatus) that the posterior and update kernels
 // check before writing.
-void launch_sync(int ne, double n_psi, double n_r, int one_stage, const double* cval,
-                 const double* dots, double* alpha, double* cstar, double* scal, hipStream_t s);
+void launch_sync(int ne, int nr, double n_psi, int one_stage, const double* cval,
+                 const double* part_dots, double* dots, double* alpha, double* cstar,
+                 double* scal, hipStream_t s);
 void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,
                              const double* dots, const double* alpha, const double* scal,
                              const float* dmat, const int32_t* pt_off, const int32_t* pt_ent,

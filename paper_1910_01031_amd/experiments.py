@@ -3,8 +3,8 @@
 
 rank_histograms: independent data-assimilation experiments, each with its own truth drawn
   from the same prior as its ensemble.  Moorings in the western half of the domain are
-  assimilated every 5 minutes, then a 1-hour forecast follows.  For hu and hv at cells
-  (100, y), y = 0, 50, ..., 250, the rank of the observed truth (truth + observation error)
+  assimilated every 5 minutes, then a 1-hour forecast follows.  For hu and hv at six cells
+  at least 80 cells apart, the rank of the observed truth (truth + observation error)
   among the ensemble values (member + observation error) is recorded.  A correct filter
   gives flat histograms.  Experiments run 16 at a time as one batch (one hipGraph replay
   per cycle).
@@ -41,7 +41,7 @@ def _workloads():
 
 def rank_histograms(torch, n_experiments: int = 128, n_particles: int = 40, da_hours: float = 6.0,
                     forecast_hours: float = 1.0, spinup_hours: float = 1.0, batch: int = 16,
-                    seed: int = 0):
+                    seed: int = 0, probe=None):
     """Returns dict(hist=[2][6][N_e+1] int (hu, hv x cells), accumulated=[2][N_e+1],
     chi2 / p-value of each accumulated histogram against the uniform one)."""
     W = _workloads()
@@ -49,7 +49,8 @@ def rank_histograms(torch, n_experiments: int = 128, n_particles: int = 40, da_h
     dev = torch.device("cuda")
     cfg0 = W.paper_scale(n_particles)
     cells = W.buoy_cells(cfg0.nx // 2, cfg0.ny, 8, 15)  # 120 moorings, western half
-    probe = [(100, y) for y in range(0, cfg0.ny, 50)]
+    if probe is None:  # six cells at least 80 cells apart, inside and east of the moorings
+        probe = [(40, 20), (120, 120), (200, 220), (60, 270), (180, 50), (300, 170)]
     base = torch.from_numpy(W.as_f32(W.jet_state(cfg0))).to(dev)
     steps = 10                                          # model steps per 5-minute cycle
     n_spin = int(round(spinup_hours * 12)) * steps
