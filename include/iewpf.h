@@ -319,6 +319,13 @@ size_t iewpf_net_num_params(const iewpf_net* net);
 /* Copy host parameters in (resets the Adam state) / out; wait for the stream. */
 int iewpf_net_set_params(iewpf_net* net, const float* host, size_t count, void* stream);
 int iewpf_net_get_params(iewpf_net* net, float* host, size_t count, void* stream);
+/* Normalisation statistics of training pairs x, target (device float32 [B][3][H][W] each),
+ * per channel in float64: stats_out (host double [9]) = mu[3] (mean of x), sigma[3] (standard
+ * deviation of x, n - 1 in the denominator, plus 1e-6), scale[3] (standard deviation of
+ * target - x, plus 1e-9): the arguments of iewpf_net_set_norm.  Allocates and frees a small
+ * device buffer; waits for the stream. */
+int iewpf_norm_stats(const float* x, const float* target, int B, int H, int W, double* stats_out,
+                     void* stream);
 /* Per-channel normalisation mu, sigma (inputs) and output scale s (3 floats each, host). */
 int iewpf_net_set_norm(iewpf_net* net, const float* mu, const float* sigma, const float* scale);
 /* Number of model steps one application of the network stands in for (the forecast window

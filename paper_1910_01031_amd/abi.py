@@ -39,7 +39,7 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_surrogate_window", "iewpf_forecast_drifters_surrogate",
             "iewpf_set_full_innovation", "iewpf_set_scheme", "iewpf_last_error",
             "iewpf_observe_drifters", "iewpf_sir_log_weights", "iewpf_net_set_horizon",
-            "iewpf_resample_noalloc", "iewpf_net_read_gradient_signal")
+            "iewpf_resample_noalloc", "iewpf_net_read_gradient_signal", "iewpf_norm_stats")
 
 TRACE_KINDS = ("scheme_step", "me_normals", "soar", "gb_add", "innovation", "rand_dots",
                "beta_alpha", "posterior_coarse", "analysis_update", "scheme_step_noise",
@@ -148,6 +148,7 @@ def load(path: str = LIB_PATH):
                                           vp, vp, vp]
     lib.iewpf_net_set_horizon.argtypes = [vp, i32]
     lib.iewpf_net_read_gradient_signal.argtypes = [vp, i32, vp, ctypes.c_size_t, vp]
+    lib.iewpf_norm_stats.argtypes = [vp, vp, i32, i32, i32, f64p, vp]
     lib.iewpf_resample_noalloc.argtypes = [i32, ctypes.c_size_t, u64, ctypes.c_uint32, u64, vp, vp,
                                            vp, vp, vp]
     lib.iewpf_set_trace.argtypes = [vp, i32]
@@ -468,6 +469,15 @@ class Net:
         _check(load().iewpf_net_gradients(self.h, _ptr(x), _ptr(target), B, H, W, g.ctypes.data,
                                           ctypes.byref(loss), y.ctypes.data, _stream(stream)))
         return g, loss.value, y
+
+
+def norm_stats(x, target, stream=None):
+    """Per-channel (mu, sigma, scale) of training pairs (device float32 [B][3][H][W])."""
+    B, _, H, W = x.shape
+    out = np.zeros(9)
+    _check(load().iewpf_norm_stats(_ptr(x), _ptr(target), B, H, W, out.ctypes.data,
+                                   _stream(stream)))
+    return out[0:3].copy(), out[3:6].copy(), out[6:9].copy()
 
 
 def resample_noalloc(logw, state_in, state_out, parents, seed: int, ensemble_id: int,

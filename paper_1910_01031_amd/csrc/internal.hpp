@@ -213,6 +213,11 @@ void launch_prep_weights(const float* w, int cin, int cout, int Kf, int Npf, int
                          uint16_t* wf, uint16_t* wd, hipStream_t s);
 void launch_mass_drift(const float* before, const float* after, int ne, int ncell, double H,
                        double tol, double* drift, int32_t* flags, hipStream_t s);
+// per-channel normalisation statistics of training pairs: out = {mu[3], sigma[3], scale[3]}
+// (float64, device); part holds channel_stats_parts() doubles
+int channel_stats_parts();
+void launch_channel_stats(const float* x, const float* t, int B, int hw, double* part, double* out,
+                          hipStream_t s);
 }  // namespace iewpf
 
 // ---- launchers (kernels in *.hip) ---------------------------------------------------------

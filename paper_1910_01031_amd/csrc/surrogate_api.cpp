@@ -256,6 +256,23 @@ int iewpf_net_set_norm(iewpf_net* n, const float* mu, const float* sigma, const 
   return 0;
 }
 
+int iewpf_norm_stats(const float* x, const float* target, int B, int H, int W, double* stats_out,
+                     void* stream) {
+  if (!x || !target || !stats_out || B < 1 || H < 1 || W < 1 || (long long)B * H * W < 2)
+    return fail(IEWPF_E_ARG, "invalid argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  double* buf = nullptr;
+  IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&buf), sizeof(double) * (channel_stats_parts() + 9)));
+  launch_channel_stats(x, target, B, H * W, buf, buf + channel_stats_parts(), s);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(stats_out, buf + channel_stats_parts(), sizeof(double) * 9,
+                                          hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(IEWPF_E_HIP, std::string("normalisation statistics: ") + hipGetErrorString(e));
+  return 0;
+}
+
 int iewpf_net_set_horizon(iewpf_net* n, int n_model_steps) {
   if (!n || n_model_steps < 1) return fail(IEWPF_E_ARG, "the horizon must be at least one model step");
   n->horizon = n_model_steps;

@@ -78,6 +78,60 @@ __device__ __forceinline__ bf16x8 load_a(const ConvArgs& A, int b, int y, int x,
   }
 }
 
+// Per-channel moments of training pairs (x, t) [B][3][HW]: workgroup (g, c) sums x, x^2,
+// t - x, (t - x)^2 of channel c over its slice (images and cells strided by the grid) in
+// float64; part[c][g][4].
+constexpr int kStatBlocks = 64;
+__global__ __launch_bounds__(256) void channel_moments_kernel(const float* __restrict__ x,
+                                                              const float* __restrict__ t, int B,
+                                                              int hw, double* __restrict__ part) {
+  __shared__ double sh[4][256];
+  const int c = blockIdx.y, g = blockIdx.x;
+  const size_t n = (size_t)B * hw;
+  double a = 0.0, a2 = 0.0, d = 0.0, d2 = 0.0;
+  for (size_t e = (size_t)g * 256 + threadIdx.x; e < n; e += (size_t)kStatBlocks * 256) {
+    const size_t b = e / hw, r = e - b * hw;
+    const size_t o = (b * 3 + c) * hw + r;
+    const double xv = x[o], dv = (double)t[o] - xv;
+    a += xv;
+    a2 += xv * xv;
+    d += dv;
+    d2 += dv * dv;
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = a2;
+  sh[2][threadIdx.x] = d;
+  sh[3][threadIdx.x] = d2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[((size_t)c * kStatBlocks + g) * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// The parts summed in a fixed order; mean, standard deviation (n - 1 in the denominator) of
+// x plus 1e-6, and of t - x plus 1e-9 (guards against constant channels):
+// out = {mu[3], sigma[3], scale[3]}.
+__global__ void channel_moments_finish_kernel(const double* __restrict__ part, double n,
+                                              double* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= 3) return;
+  double a = 0.0, a2 = 0.0, d = 0.0, d2 = 0.0;
+  for (int g = 0; g < kStatBlocks; ++g) {
+    const double* p = part + ((size_t)c * kStatBlocks + g) * 4;
+    a += p[0];
+    a2 += p[1];
+    d += p[2];
+    d2 += p[3];
+  }
+  const double m = a / n, md = d / n;
+  out[c] = m;
+  out[3 + c] = sqrt(fmax(a2 - n * m * m, 0.0) / (n - 1.0)) + 1e-6;
+  out[6 + c] = sqrt(fmax(d2 - n * md * md, 0.0) / (n - 1.0)) + 1e-9;
+}
+
 template <int IN, int OUT, int NT>
 __global__ __launch_bounds__(256) void conv3x3_mfma_kernel(ConvArgs A, int total_waves) {
   const int lane = threadIdx.x & 63;
@@ -745,6 +799,16 @@ void launch_prep_weights(const float* w, int cin, int cout, int Kf, int Npf, int
   const int n = Npf * Kf + (wd ? Npd * Kd : 0);
   hipLaunchKernelGGL(prep_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w, cin, cout, Kf,
                      Npf, Kd, Npd, wf, wd);
+}
+
+int channel_stats_parts() { return 3 * kStatBlocks * 4; }
+
+void launch_channel_stats(const float* x, const float* t, int B, int hw, double* part, double* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(channel_moments_kernel, dim3(kStatBlocks, 3), dim3(256), 0, s, x, t, B, hw,
+                     part);
+  hipLaunchKernelGGL(channel_moments_finish_kernel, dim3(1), dim3(64), 0, s, part,
+                     (double)B * hw, out);
 }
 
 void launch_mass_drift(const float* before, const float* after, int ne, int ncell, double H,

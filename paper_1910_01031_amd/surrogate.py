@@ -5,10 +5,11 @@ finite-volume scheme).  Training pairs come from ensembles on a grid of the targ
 scheme step (a 3x3 convolutional network is translation invariant, so it applies to any grid
 of that spacing; the states should resemble the ones it will see): each ensemble is drawn
 around a balanced base state, spun up with stochastic model steps, and then paired window by
-window with its deterministic ten-step forecast.  Every arithmetic step runs in the library's
-kernels (ensemble generation, scheme, network forward/backward, Adam); this module only orders
-the calls and slices device buffers.  `python -m paper_1910_01031_amd.surrogate` times the
-forward pass.
+window with its deterministic ten-step forecast.  Every arithmetic step of the method runs in
+the library's kernels (ensemble generation, scheme, normalisation statistics, network
+forward/backward, Adam); this module orders the calls, slices device buffers and computes the
+learning-rate schedule (a scalar per step) and the evaluation RMSEs (torch reductions over
+outputs, for reporting).  `python -m paper_1910_01031_amd.surrogate` times the forward pass.
 """
 from __future__ import annotations
 
@@ -60,9 +61,7 @@ def make_pairs(torch, cfg, n_pairs: int, base: np.ndarray, group: int = 1000,
     finally:
         ctx.close()
     xs, ts = xs[:n_pairs].contiguous(), ts[:n_pairs].contiguous()
-    mu = xs.mean(dim=(0, 2, 3)).double().cpu().numpy()
-    sigma = xs.std(dim=(0, 2, 3)).double().cpu().numpy() + 1e-6
-    scale = (ts - xs).std(dim=(0, 2, 3)).double().cpu().numpy() + 1e-9
+    mu, sigma, scale = abi.norm_stats(xs, ts)
     return PairSet(xs, ts, mu, sigma, scale)
 
 

@@ -14,7 +14,7 @@ def test_rank_histograms_and_sir_collapse_small():
     r = ex.rank_histograms(torch, n_experiments=3, n_particles=6, da_hours=0.25,
                            forecast_hours=1.0 / 12, spinup_hours=1.0 / 12, batch=2)
     h = np.array(r["hist"])
-    assert h.shape == (2, 6, 7) and np.all(h >= 0)
+    assert h.shape == (2, 6, 7) and np.all(h >= 0)  # six probe cells
     assert np.all(h.sum(axis=2) == 3)
     assert 0.0 <= r["p_hu"] <= 1.0 and 0.0 <= r["p_hv"] <= 1.0
     s = ex.sir_collapse(torch, n_particles=12, da_hours=0.25, n_drifters=16, max_observed=3,

@@ -579,3 +579,25 @@ def test_analysis_runs_on_the_surrogate_output():
     actx.close()
     net.close()
     ctx.close()
+
+
+def test_normalisation_statistics_match_their_definition():
+    """iewpf_norm_stats: per-channel mean and standard deviation (n - 1) of the inputs plus
+    1e-6 and of the increments plus 1e-9, against numpy in float64 (1e-10 relative), on a
+    ragged size (the workgroups' slices end mid-image)."""
+    _need_gpu()
+    from paper_1910_01031_amd import abi
+    B, H, W = 3, 37, 53
+    x = _states(B, H, W, 61)
+    t = x + _states(B, H, W, 62) * np.array([0.01, 0.5, 0.5], np.float32)[None, :, None, None]
+    mu, sigma, scale = abi.norm_stats(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    x64, d64 = x.astype(np.float64), t.astype(np.float64) - x.astype(np.float64)
+    ref_mu = x64.mean(axis=(0, 2, 3))
+    ref_sig = x64.std(axis=(0, 2, 3), ddof=1) + 1e-6
+    ref_sc = d64.std(axis=(0, 2, 3), ddof=1) + 1e-9
+    # the mean to float64 summation error (relative to the largest value), the deviations
+    # to 1e-10 relative
+    amax = np.abs(x64).max(axis=(0, 2, 3))
+    assert np.all(np.abs(mu - ref_mu) <= 1e-12 * amax), (mu, ref_mu)
+    for got, ref in ((sigma, ref_sig), (scale, ref_sc)):
+        assert np.all(np.abs(got - ref) <= 1e-10 * np.abs(ref)), (got, ref)
