@@ -74,7 +74,8 @@ struct Mat2 {
 __device__ __forceinline__ void innovation_body(
     int i, int n_obs, int max_obs, int nx, int ny, double H, const Mat2& S, double out_scale,
     const float* __restrict__ psi, const int32_t* __restrict__ cells, const double* __restrict__ y,
-    double* __restrict__ sd, double* __restrict__ cval, double* sh) {
+    double* __restrict__ sd, float* __restrict__ sdf, int ne4, double* __restrict__ cval,
+    double* sh) {
   const size_t ncell = (size_t)nx * ny;
   const float* E = psi + (size_t)i * 3 * ncell;
   double phi = 0.0;
@@ -89,6 +90,10 @@ __device__ __forceinline__ void innovation_body(
     const double s1 = S.a[2] * d0 + S.a[3] * d1;
     sd[((size_t)i * max_obs + o) * 2] = s0;
     sd[((size_t)i * max_obs + o) * 2 + 1] = s1;
+    if (sdf) {
+      sdf[((size_t)o * ne4 + i) * 2] = static_cast<float>(s0);
+      sdf[((size_t)o * ne4 + i) * 2 + 1] = static_cast<float>(s1);
+    }
     phi += d0 * s0 + d1 * s1;
   }
   phi = block_sum(phi, sh);
@@ -98,9 +103,10 @@ __device__ __forceinline__ void innovation_body(
 __global__ __launch_bounds__(kThreads) void innovation_kernel(
     int n_obs, int max_obs, int nx, int ny, double H, Mat2 S, double out_scale,
     const float* __restrict__ psi, const int32_t* __restrict__ cells, const double* __restrict__ y,
-    double* __restrict__ sd, double* __restrict__ cval) {
+    double* __restrict__ sd, float* __restrict__ sdf, int ne4, double* __restrict__ cval) {
   __shared__ double sh[kThreads];
-  innovation_body(blockIdx.x, n_obs, max_obs, nx, ny, H, S, out_scale, psi, cells, y, sd, cval, sh);
+  innovation_body(blockIdx.x, n_obs, max_obs, nx, ny, H, S, out_scale, psi, cells, y, sd, sdf, ne4,
+                  cval, sh);
 }
 
 // Normalised weights of the standard particle filter from log-weights (one workgroup):
@@ -199,12 +205,13 @@ __global__ __launch_bounds__(kThreads) void rand_dots_kernel(int nr, int parts, 
 __global__ __launch_bounds__(kThreads) void innov_draws_kernel(
     int n_obs, int max_obs, int nx, int ny, double H, Mat2 S, const float* __restrict__ psi,
     const int32_t* __restrict__ cells, const double* __restrict__ y, double* __restrict__ sd,
-    double* __restrict__ cval, int nr, int parts, uint64_t seed, uint64_t step, uint32_t ens,
-    float* __restrict__ xi, float* __restrict__ nu, double* __restrict__ part_dots,
+    float* __restrict__ sdf, int ne4, double* __restrict__ cval, int nr, int parts, uint64_t seed,
+    uint64_t step, uint32_t ens, float* __restrict__ xi, float* __restrict__ nu, double* __restrict__ part_dots,
     const uint64_t* __restrict__ dyn) {
   __shared__ double sh[kThreads];
   if ((int)blockIdx.x == parts)
-    innovation_body(blockIdx.y, n_obs, max_obs, nx, ny, H, S, 1.0, psi, cells, y, sd, cval, sh);
+    innovation_body(blockIdx.y, n_obs, max_obs, nx, ny, H, S, 1.0, psi, cells, y, sd, sdf, ne4,
+                    cval, sh);
   else
     rand_dots_body(blockIdx.y, blockIdx.x, nr, parts, seed, step, ens, xi, nu, part_dots, dyn, sh);
 }
@@ -600,11 +607,13 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(int n, int nrhs, const 
 
 // SD[p][r] = sum_c S[r][c] D[p][c] for every particle p and row r of the full S [n][n]
 // (rows of D and SD are `stride` apart): 16 x 16 tiles of (row, particle), c in chunks of 32
-// staged in LDS, each sum in increasing c.
-__global__ __launch_bounds__(256) void sd_gemm_kernel(int n, int ne, int stride,
+// staged in LDS, each sum in increasing c.  SDf receives the same values in float32,
+// observation-major ([r / 2][ne4][2]).
+__global__ __launch_bounds__(256) void sd_gemm_kernel(int n, int ne, int stride, int ne4,
                                                       const double* __restrict__ S,
                                                       const double* __restrict__ D,
-                                                      double* __restrict__ SD) {
+                                                      double* __restrict__ SD,
+                                                      float* __restrict__ SDf) {
   __shared__ double Ts[16][33], Td[16][33];
   const int tr = threadIdx.x & 15, tp = threadIdx.x >> 4;
   const int r0 = blockIdx.x * 16, p0 = blockIdx.y * 16;
@@ -620,7 +629,11 @@ __global__ __launch_bounds__(256) void sd_gemm_kernel(int n, int ne, int stride,
     for (int cc = 0; cc < 32; ++cc) acc += Ts[tr][cc] * Td[tp][cc];
     __syncthreads();
   }
-  if (r0 + tr < n && p0 + tp < ne) SD[(size_t)(p0 + tp) * stride + r0 + tr] = acc;
+  if (r0 + tr < n && p0 + tp < ne) {
+    const int r = r0 + tr, p = p0 + tp;
+    SD[(size_t)p * stride + r] = acc;
+    SDf[((size_t)(r >> 1) * ne4 + p) * 2 + (r & 1)] = static_cast<float>(acc);
+  }
 }
 
 // c_p = d_p^T (S d_p), one workgroup per particle, fixed-order sum.
@@ -890,10 +903,10 @@ __global__ void gather_kernel(size_t per_particle4, const int32_t* __restrict__ 
 
 void launch_innovation(int ne, int n_obs, int max_obs, int nx, int ny, double H, const double S[4],
                        const float* psi, const int32_t* cells, const double* y, double* sd,
-                       double* cval, hipStream_t s, double out_scale) {
+                       float* sdf, double* cval, hipStream_t s, double out_scale) {
   Mat2 M{{S[0], S[1], S[2], S[3]}};
   hipLaunchKernelGGL(innovation_kernel, dim3(ne), dim3(kThreads), 0, s, n_obs, max_obs, nx, ny, H,
-                     M, out_scale, psi, cells, y, sd, cval);
+                     M, out_scale, psi, cells, y, sd, sdf, sd_float_stride(ne), cval);
 }
 
 void launch_sir_normalise(int ne, const double* logw, double* w, hipStream_t s) {
@@ -924,14 +937,14 @@ void launch_rand_dots(int ne, int nr, uint64_t seed, uint64_t step, uint32_t ens
 
 void launch_innov_draws(int ne, int n_obs, int max_obs, int nx, int ny, double H,
                         const double S[4], const float* psi, const int32_t* cells, const double* y,
-                        double* sd, double* cval, int nr, uint64_t seed, uint64_t step,
+                        double* sd, float* sdf, double* cval, int nr, uint64_t seed, uint64_t step,
                         uint32_t ens, float* xi, float* nu, double* part_dots, hipStream_t s,
                         const uint64_t* dyn) {
   Mat2 M{{S[0], S[1], S[2], S[3]}};
   const int parts = rand_dots_parts_for(nr);
   hipLaunchKernelGGL(innov_draws_kernel, dim3(parts + 1, ne), dim3(kThreads), 0, s, n_obs, max_obs,
-                     nx, ny, H, M, psi, cells, y, sd, cval, nr, parts, seed, step, ens, xi, nu,
-                     part_dots, dyn);
+                     nx, ny, H, M, psi, cells, y, sd, sdf, sd_float_stride(ne), cval, nr, parts,
+                     seed, step, ens, xi, nu, part_dots, dyn);
 }
 
 void launch_sync(int ne, int nr, double n_psi, int one_stage, const double* cval,
@@ -972,9 +985,9 @@ void launch_chol_factor(int n, double* A, int32_t* status, hipStream_t s) {
 }
 
 void launch_sd_full(int n, int ne, int stride, const double* S, const double* D, double* SD,
-                    double* cval, hipStream_t s) {
+                    float* sdf, double* cval, hipStream_t s) {
   hipLaunchKernelGGL(sd_gemm_kernel, dim3((n + 15) / 16, (ne + 15) / 16), dim3(256), 0, s, n, ne,
-                     stride, S, D, SD);
+                     stride, sd_float_stride(ne), S, D, SD, sdf);
   hipLaunchKernelGGL(dot_rows_kernel, dim3(ne), dim3(kThreads), 0, s, n, stride, D, SD, cval);
 }
 

@@ -115,7 +115,7 @@ void free_ctx(iewpf_ctx* c) {
                   c->coarse, c->coarse2, c->windows,
                   c->dmat,    c->sd,     c->cval,   c->dots,   c->alpha,   c->cstar,
                   c->scal,    c->d_stage, c->dk1,    c->dpstar, c->dobs,   c->cflmax,  c->dparents,
-                  c->dcum,    c->sir_parents, c->dobs_cells};
+                  c->dcum,    c->sir_parents, c->dobs_cells, c->sdf};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
@@ -152,7 +152,7 @@ StageLayout stage_layout(const iewpf_ctx& c) {
   L.pt_off = o; o = align16(o + sizeof(int32_t) * (c.nr + 1));
   L.pt_ent = o; o = align16(o + sizeof(int32_t) * (size_t)c.max_obs * kBlockN);
   L.st_off = o; o = align16(o + sizeof(int32_t) * (c.n_upd_strips + 1));
-  L.st_ent = o; o = align16(o + sizeof(int32_t) * (size_t)c.n_upd_strips * c.max_obs);
+  L.st_ent = o; o = align16(o + sizeof(int32_t) * 4 * (size_t)c.n_upd_strips * c.max_obs);
   L.total = o;
   return L;
 }
@@ -256,7 +256,16 @@ int upload_observations(iewpf_ctx* c, int n_obs, bool with_y, hipStream_t s) {
         const bool in_x = c->rx < 0 || circ_interval_dist(cells[2 * o], j0, lenj, c->nx) <= c->rx;
         const bool in_y =
             c->ry < 0 || circ_interval_dist(cells[2 * o + 1], k0, lenk, c->ny) <= c->ry;
-        if (in_x && in_y) st_ent[t++] = o;
+        if (in_x && in_y) {
+          // the window's first column and row on the torus (a window folded onto the whole
+          // period starts at the observed cell)
+          const int jo = cells[2 * o], ko = cells[2 * o + 1];
+          int32_t* e = st_ent + 4 * (size_t)t++;
+          e[0] = c->rx < 0 ? jo : ((jo - c->rx) % c->nx + c->nx) % c->nx;
+          e[1] = c->ry < 0 ? ko : ((ko - c->ry) % c->ny + c->ny) % c->ny;
+          e[2] = o;
+          e[3] = 0;
+        }
       }
       st_off[sy * nsx + sx + 1] = t;
     }
@@ -265,7 +274,7 @@ int upload_observations(iewpf_ctx* c, int n_obs, bool with_y, hipStream_t s) {
   // same layout): small transfers each cost a fixed latency on the stream, so one copy of
   // the whole prefix beats six copies of the used parts.  Without y, the y block is skipped
   // (the caller uploads y itself) with a second copy from pt_off on.
-  const size_t end = L.st_ent + sizeof(int32_t) * (size_t)t;
+  const size_t end = L.st_ent + sizeof(int32_t) * 4 * (size_t)t;
   if (with_y) {
     IEWPF_HIP_TRY(hipMemcpyAsync(c->d_stage, c->h_stage, end, hipMemcpyHostToDevice, s));
   } else {
@@ -330,7 +339,7 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
     const double r = c->cfg.obs_sigma * c->cfg.obs_sigma;
     const double Rinv[4] = {1.0 / r, 0.0, 0.0, 1.0 / r};
     launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, Rinv, state, c->obs_cells,
-                      c->obs_y, c->sd, c->cval, s, -0.5);
+                      c->obs_y, c->sd, nullptr, c->cval, s, -0.5);
     launch_resample(c->ne, c->cfg.seed, analysis_index, c->cfg.ensemble_id, c->cval, c->sir_parents,
                     c->dparents, c->dcum, s, c->scal);
     const size_t per = 3 * c->ncell;
@@ -346,8 +355,8 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
       TraceScope tr(c, kTrInnov, s);
       const double I2[4] = {1.0, 0.0, 0.0, 1.0};
       launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, I2, state, c->obs_cells,
-                        c->obs_y, c->dinn, c->cval, s);
-      launch_sd_full(2 * n_obs, c->ne, 2 * c->max_obs, c->fX, c->dinn, c->sd, c->cval, s);
+                        c->obs_y, c->dinn, nullptr, c->cval, s);
+      launch_sd_full(2 * n_obs, c->ne, 2 * c->max_obs, c->fX, c->dinn, c->sd, c->sdf, c->cval, s);
     }
     // stage 3: xi, nu~ and their dot products
     TraceScope tr(c, kTrRandDots, s);
@@ -357,7 +366,8 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
     // stages 1-3 in one launch: innovations, S d, c_i and the draws with their dot products
     TraceScope tr(c, kTrRandDots, s);
     launch_innov_draws(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, c->S, state,
-                       c->obs_cells, c->obs_y, c->sd, c->cval, c->nr, c->cfg.seed, analysis_index,
+                       c->obs_cells, c->obs_y, c->sd, c->sdf, c->cval, c->nr, c->cfg.seed,
+                       analysis_index,
                        c->cfg.ensemble_id, c->xi, c->nu, c->part_dots, s, dyn);
   }
   // stages 4-5: cbar, beta, c*, alpha (the one ensemble-wide step)
@@ -387,8 +397,8 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
   P.n_strip_y = (c->ny + c->upd_strip_h - 1) / c->upd_strip_h;
   {
     TraceScope tr(c, kTrUpdate, s);
-    launch_analysis_update(c->cc, P, c->ne, c->coarse, c->windows, c->sd, c->max_obs, c->obs_cells,
-                           c->st_off, c->st_ent, state, c->scal, s);
+    launch_analysis_update(c->cc, P, c->ne, c->coarse, c->windows, c->sdf, c->st_off, c->st_ent,
+                           state, c->scal, s);
   }
   IEWPF_HIP_TRY(hipGetLastError());
   return 0;
@@ -812,6 +822,11 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   rc |= dev_alloc(&c->windows, win.size());
   rc |= dev_alloc(&c->dmat, (size_t)kBlockN * kBlockN);
   rc |= dev_alloc(&c->sd, (size_t)c->ne * c->max_obs * 2);
+  rc |= dev_alloc(&c->sdf, (size_t)sd_float_stride(c->ne) * c->max_obs * 2);
+  // the padding particles' entries are read (and their sums dropped): keep them finite
+  if (rc == 0 && hipMemset(c->sdf, 0, sizeof(float) * sd_float_stride(c->ne) * c->max_obs * 2) !=
+                     hipSuccess)
+    rc = fail(IEWPF_E_HIP, "hipMemset(sdf)");
   rc |= dev_alloc(&c->cval, c->ne);
   rc |= dev_alloc(&c->dots, (size_t)3 * c->ne);
   rc |= dev_alloc(&c->part_dots, (size_t)3 * c->ne * rand_dots_parts());
@@ -1085,7 +1100,7 @@ int iewpf_sir_log_weights(iewpf_ctx* c, const float* state, const iewpf_obs* obs
   const double r = r_scale * c->cfg.obs_sigma * c->cfg.obs_sigma;
   const double Rinv[4] = {1.0 / r, 0.0, 0.0, 1.0 / r};
   launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, Rinv, state, c->obs_cells,
-                    c->obs_y, c->sd, logw, s, -0.5);
+                    c->obs_y, c->sd, nullptr, logw, s, -0.5);
   if (w_out) launch_sir_normalise(c->ne, logw, w_out, s);
   IEWPF_HIP_TRY(hipGetLastError());
   return 0;

@@ -91,6 +91,7 @@ struct iewpf_ctx {
   float* windows = nullptr;    // [6][wy][wx]: (s_u, s_v) x (eta, hu, hv)
   float* dmat = nullptr;       // A^{1/2} - I, float32 [49][49]
   double* sd = nullptr;        // [ne][max_obs][2]
+  float* sdf = nullptr;        // S d rounded to float32, [max_obs][sd_float_stride(ne)][2]
   double* cval = nullptr;      // [ne]
   double* dots = nullptr;      // [ne][3]
   double* part_dots = nullptr; // [ne][parts][3] partial dot products
@@ -102,7 +103,7 @@ struct iewpf_ctx {
   int32_t* pt_off = nullptr;     // coarse-point CSR offsets [nr + 1]
   int32_t* pt_ent = nullptr;     // entries (obs << 8 | block index) [max_obs * 49]
   int32_t* st_off = nullptr;     // strip CSR offsets [n_strips + 1]
-  int32_t* st_ent = nullptr;     // obs ids per strip [n_strips * max_obs]
+  int32_t* st_ent = nullptr;     // per strip (window column, window row, obs, 0) [n_strips * max_obs][4]
   int n_upd_strips = 0;
   int upd_strip_h = 16;
   double* dk1 = nullptr;         // drifter k1 [ne][max_obs][2]
@@ -246,15 +247,19 @@ void launch_soar(const CoarseConst& C, const float* w25, int ne, const float* in
 // psi (+)= Q_GB I_Omega z  [+ pull];  base != nullptr: psi = base + ...
 void launch_gb_add(const CoarseConst& C, int ne, const float* z, const float* base, float* psi,
                    int strip_h, hipStream_t s);
+// Particles per wave of the analysis update; sdf pads the particle count to a multiple of it.
+constexpr int kUpdParticles = 4;
+inline int sd_float_stride(int ne) {
+  return (ne + kUpdParticles - 1) / kUpdParticles * kUpdParticles;
+}
 void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, const float* z,
-                            const float* windows, const double* sd, int max_obs,
-                            const int32_t* obs_cells, const int32_t* st_off,
+                            const float* windows, const float* sdf, const int32_t* st_off,
                             const int32_t* st_ent, float* psi, double* scal, hipStream_t s);
 // c_i = out_scale * sum_o d^T S d (out_scale = -1/2 and S = R^{-1} give the log-weights of
-// the standard particle filter)
+// the standard particle filter); sdf (may be null) receives S d in float32, observation-major
 void launch_innovation(int ne, int n_obs, int max_obs, int nx, int ny, double H, const double S[4],
                        const float* psi, const int32_t* cells, const double* y, double* sd,
-                       double* cval, hipStream_t s, double out_scale = 1.0);
+                       float* sdf, double* cval, hipStream_t s, double out_scale = 1.0);
 void launch_sir_normalise(int ne, const double* logw, double* w, hipStream_t s);
 void launch_observe_drifters(int n, int nx, int ny, double dx, double dy, double H, double sigma,
                              double dt_obs, uint64_t seed, uint64_t step, uint32_t ens,
@@ -264,7 +269,7 @@ int rand_dots_parts();
 // innovations, S d, c_i and the draws with their per-part dot products in one launch
 void launch_innov_draws(int ne, int n_obs, int max_obs, int nx, int ny, double H,
                         const double S[4], const float* psi, const int32_t* cells, const double* y,
-                        double* sd, double* cval, int nr, uint64_t seed, uint64_t step,
+                        double* sd, float* sdf, double* cval, int nr, uint64_t seed, uint64_t step,
                         uint32_t ens, float* xi, float* nu, double* part_dots, hipStream_t s,
                         const uint64_t* dyn = nullptr);
 // xi, nu~ and their per-part dot products (summed by the sync kernel)
@@ -282,7 +287,7 @@ void launch_chol_factor(int n, double* A, int32_t* status, hipStream_t s);
 void launch_chol_solve(int n, int nrhs, const double* L, const double* rhs, int rhs_stride,
                        double* out, int out_stride, double* cval, hipStream_t s);
 void launch_sd_full(int n, int ne, int stride, const double* S, const double* D, double* SD,
-                    double* cval, hipStream_t s);
+                    float* sdf, double* cval, hipStream_t s);
 // Also writes the analysis status words (kScalStatus) that the posterior and update kernels
 // check before writing.
 void launch_sync(int ne, int nr, double n_psi, int one_stage, const double* cval,

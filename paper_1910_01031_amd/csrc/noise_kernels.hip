@@ -131,17 +131,11 @@ __device__ __forceinline__ float bicubic_at(const float* __restrict__ z, const C
 //   psi(k) = (base or psi)(k) + (d_eta, -gH/(2 f dy) (d_eta(k+1) - d_eta(k-1)),
 //                                 gH/(2 f dx) (d_eta(j+1) - d_eta(j-1)))  [+ pull windows]
 // with d_eta = I_Omega z.
-template <bool PULL>
-__global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, PullConst P, int strip_h,
-                                                     int n_strip_x, int n_strip_y, int total_waves,
+__global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, int strip_h, int n_strip_x,
+                                                     int n_strip_y, int total_waves,
                                                      const float* __restrict__ zall,
                                                      const float* __restrict__ base,
-                                                     float* __restrict__ psi,
-                                                     const float* __restrict__ windows,
-                                                     const double* __restrict__ sd, int max_obs,
-                                                     const int32_t* __restrict__ cells,
-                                                     const int32_t* __restrict__ st_off,
-                                                     const int32_t* __restrict__ st_ent) {
+                                                     float* __restrict__ psi) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
   if (wave >= total_waves) return;
@@ -174,11 +168,6 @@ __global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, PullConst P,
   float dm2 = 0.0f, dm1 = 0.0f;  // d_eta rows m-2, m-1
   CoarseWin win;
   win.init(z, C, cx, wx, k0 - 1);
-  int o_beg = 0, o_end = 0;
-  if (PULL) {
-    o_beg = st_off[strip];
-    o_end = st_off[strip + 1];
-  }
   for (int m = k0 - 1; m <= k_end; ++m) {
     const float d0 = win.at(z, C, cx, wx, m);
     if (m >= k0 + 1) {
@@ -187,42 +176,10 @@ __global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, PullConst P,
       const float dhu = -C.gb_y * (d0 - dm2);
       const float dhv = C.gb_x * (__shfl_down(dm1, 1, kWave) - __shfl_up(dm1, 1, kWave));
       if (writer) {
-        float pe = 0.0f, pu = 0.0f, pv = 0.0f;
-        if (PULL) {
-          for (int t = o_beg; t < o_end; ++t) {
-            const int o = st_ent[t];
-            const int jo = cells[2 * o], ko = cells[2 * o + 1];
-            int ix, iy;
-            if (P.rx >= 0) {
-              int dj = j - jo;
-              dj = dj > nx / 2 ? dj - nx : (dj < -(nx / 2) ? dj + nx : dj);
-              if (dj < -P.rx || dj > P.rx) continue;
-              ix = dj + P.rx;
-            } else {
-              ix = wrapi(j - jo, nx);
-            }
-            if (P.ry >= 0) {
-              int dk = k - ko;
-              dk = dk > ny / 2 ? dk - ny : (dk < -(ny / 2) ? dk + ny : dk);
-              if (dk < -P.ry || dk > P.ry) continue;
-              iy = dk + P.ry;
-            } else {
-              iy = wrapi(k - ko, ny);
-            }
-            const size_t plane = (size_t)P.wx * P.wy;
-            const size_t idx = (size_t)iy * P.wx + ix;
-            const double* s = sd + ((size_t)particle * max_obs + o) * 2;
-            const float su = static_cast<float>(s[0]), sv = static_cast<float>(s[1]);
-            pe += su * windows[idx] + sv * windows[3 * plane + idx];
-            pu += su * windows[plane + idx] + sv * windows[4 * plane + idx];
-            pv += su * windows[2 * plane + idx] + sv * windows[5 * plane + idx];
-          }
-        }
         const size_t o = (size_t)k * nx + j;
-        const size_t ob = o;  // base has the same [3][ny][nx] layout for one state
-        E[o] = B[ob] + (de + pe);
-        E[ncell + o] = B[ncell + ob] + (dhu + pu);
-        E[2 * ncell + o] = B[2 * ncell + ob] + (dhv + pv);
+        E[o] = B[o] + de;
+        E[ncell + o] = B[ncell + o] + dhu;
+        E[2 * ncell + o] = B[2 * ncell + o] + dhv;
       }
     }
     dm2 = dm1;
@@ -234,46 +191,17 @@ __global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, PullConst P,
 // pull of eq. detailedOPDUpdate): psi += sum_o (s_u,o W_u + s_v,o W_v)(x - x_o) + Q_GB I_Omega z
 // for kPB particles per wave, so every window value fetched from cache serves kPB
 // particles.  W_u, W_v: precomputed responses to the unit vectors (stored windows); the
-// observation list of the strip comes from the host; the row window test is wave-uniform.
-#ifndef IEWPF_UPD_PB
-#define IEWPF_UPD_PB 4
-#endif
-constexpr int kPB = IEWPF_UPD_PB;
-#ifndef IEWPF_UPD_OBS_BATCH
-#define IEWPF_UPD_OBS_BATCH 4
-#endif
-constexpr int kObsBatch = IEWPF_UPD_OBS_BATCH;
+// observation list of the strip comes from the host with each window's origin on the torus,
+// and S d in float32, both read with scalar loads; the row window test is wave-uniform.
+constexpr int kPB = kUpdParticles;
+constexpr int kObsBatch = 4;
 
-// Offset (ix, iy) of cell (j, k) in the stored window of the observation at (jo, ko);
-// false when the cell is outside the window (radius -1: the window covers the period).
-__device__ __forceinline__ bool window_offset(const PullConst& P, int nx, int ny, int j, int k,
-                                              int jo, int ko, int& ix, int& iy) {
-  bool in = true;
-  if (P.ry >= 0) {
-    int dk = k - ko;
-    dk = dk > ny / 2 ? dk - ny : (dk < -(ny / 2) ? dk + ny : dk);
-    in = dk >= -P.ry && dk <= P.ry;
-    iy = in ? dk + P.ry : 0;
-  } else {
-    iy = wrapi(k - ko, ny);
-  }
-  if (P.rx >= 0) {
-    int dj = j - jo;
-    dj = dj > nx / 2 ? dj - nx : (dj < -(nx / 2) ? dj + nx : dj);
-    const bool inx = dj >= -P.rx && dj <= P.rx;
-    ix = inx ? dj + P.rx : 0;
-    in = in && inx;
-  } else {
-    ix = wrapi(j - jo, nx);
-  }
-  return in;
-}
 
 __global__ __launch_bounds__(256) void analysis_update_kernel(
-    CoarseConst C, PullConst P, int ne, int total_waves, const float* __restrict__ zall,
-    float* __restrict__ psi, const float* __restrict__ windows, const double* __restrict__ sd,
-    int max_obs, const int32_t* __restrict__ cells, const int32_t* __restrict__ st_off,
-    const int32_t* __restrict__ st_ent, double* __restrict__ scal) {
+    CoarseConst C, PullConst P, int ne, int ne4, int total_waves, const float* __restrict__ zall,
+    float* __restrict__ psi, const float* __restrict__ windows, const float* __restrict__ sdf,
+    const int32_t* __restrict__ st_off, const int4* __restrict__ st_ent,
+    double* __restrict__ scal) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave));
@@ -318,33 +246,11 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
   }
   const int k0 = sy * P.strip_h;
   const int k_end = min(k0 + P.strip_h, ny);
+  // The strip's observation list: per entry the first column and row of the observation's
+  // window on the torus (the observed cell minus the radius; the cell itself for a window
+  // folded onto the whole period) and the observation; read with scalar loads (the index is
+  // wave-uniform), as are S d of the group's particles (float, observation-major).
   const int o_beg = st_off[strip], o_end = st_off[strip + 1];
-  // The strip's observation list, one entry per lane (first 64 entries): the first column
-  // and row of each observation's window on the torus (the observed cell minus the
-  // radius; the cell itself for a window folded onto the whole period) and S d of each
-  // particle of the group, so the row loop reads them with lane broadcasts.
-  int l_js = 0, l_ks = 0;
-  float l_su[kPB], l_sv[kPB];
-  {
-    const int t = o_beg + lane;
-    const int o = t < o_end ? st_ent[t] : -1;
-#pragma unroll
-    for (int p = 0; p < kPB; ++p) l_su[p] = l_sv[p] = 0.0f;
-    if (o >= 0) {
-      l_js = cells[2 * o] - (P.rx >= 0 ? P.rx : 0);  // radius < nx / 2
-      l_js += l_js < 0 ? nx : 0;
-      l_ks = cells[2 * o + 1] - (P.ry >= 0 ? P.ry : 0);
-      l_ks += l_ks < 0 ? ny : 0;
-#pragma unroll
-      for (int p = 0; p < kPB; ++p) {
-        if (p < np) {
-          const double* s2 = sd + ((size_t)(p0 + p) * max_obs + o) * 2;
-          l_su[p] = static_cast<float>(s2[0]);
-          l_sv[p] = static_cast<float>(s2[1]);
-        }
-      }
-    }
-  }
   float dm2[kPB], dm1[kPB];
   float chk[kPB];  // stays 0 while every written value is finite (x * 0 is NaN for inf, NaN)
   CoarseWin win[kPB];
@@ -376,32 +282,30 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
         au[p] = -C.gb_y * (d0[p] - dm2[p]);
         av[p] = C.gb_x * (__shfl_down(dm1[p], 1, kWave) - __shfl_up(dm1[p], 1, kWave));
       }
-      // observations held in lanes: kObsBatch at a time, all window loads of a batch issued
-      // before its multiply-adds
-      const int n_lane = min(o_end - o_beg, kWave);
-      for (int q0 = 0; q0 < n_lane; q0 += kObsBatch) {
+      // kObsBatch observations at a time: all window loads of a batch issued before its
+      // multiply-adds
+      for (int t0 = o_beg; t0 < o_end; t0 += kObsBatch) {
         float w[kObsBatch][6];
         float su[kObsBatch][kPB], sv[kObsBatch][kPB];
 #pragma unroll
         for (int u = 0; u < kObsBatch; ++u) {
-          const bool valid = q0 + u < n_lane;  // wave-uniform
-          const int q = valid ? q0 + u : n_lane - 1;
-          const int js = __builtin_amdgcn_readlane(l_js, q);
-          const int ks = __builtin_amdgcn_readlane(l_ks, q);
-          // window offset on the torus: 0 <= k, ks < ny and 0 <= jw, js < nx
-          int iy = k - ks;  // wave-uniform
+          const bool valid = t0 + u < o_end;  // wave-uniform
+          const int4 e = st_ent[valid ? t0 + u : o_end - 1];
+          // window offset on the torus: 0 <= k, e.y < ny and 0 <= jw, e.x < nx
+          int iy = k - e.y;  // wave-uniform
           iy += iy < 0 ? ny : 0;
-          int ix = jw - js;
+          int ix = jw - e.x;
           ix += ix < 0 ? nx : 0;
           const bool in_y = valid && iy < P.wy;
           const unsigned voff = in_y && ix < P.wx ? 4u * static_cast<unsigned>(ix) : kBufferOff;
           const unsigned soff = in_y ? 4u * static_cast<unsigned>(iy * P.wx) : 0u;
 #pragma unroll
           for (int f = 0; f < 6; ++f) w[u][f] = ld_buf(bw, voff, soff + f * plane_b);
+          const float* q = sdf + ((size_t)e.z * ne4 + p0) * 2;
 #pragma unroll
           for (int p = 0; p < kPB; ++p) {
-            su[u][p] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l_su[p]), q));
-            sv[u][p] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(l_sv[p]), q));
+            su[u][p] = q[2 * p];
+            sv[u][p] = q[2 * p + 1];
           }
         }
 #pragma unroll
@@ -411,26 +315,6 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
             ae[p] = fmaf(sv[u][p], w[u][3], fmaf(su[u][p], w[u][0], ae[p]));
             au[p] = fmaf(sv[u][p], w[u][4], fmaf(su[u][p], w[u][1], au[p]));
             av[p] = fmaf(sv[u][p], w[u][5], fmaf(su[u][p], w[u][2], av[p]));
-          }
-        }
-      }
-      // observations past the lanes: read from the list
-      for (int t = o_beg + kWave; t < o_end; ++t) {
-        const int o = st_ent[t];
-        int ix, iy;
-        if (!window_offset(P, nx, ny, j, k, cells[2 * o], cells[2 * o + 1], ix, iy)) continue;
-        const size_t idx = (size_t)iy * P.wx + ix;
-        float w[6];
-#pragma unroll
-        for (int f = 0; f < 6; ++f) w[f] = windows[f * plane + idx];
-#pragma unroll
-        for (int p = 0; p < kPB; ++p) {
-          if (p < np) {
-            const double* s2 = sd + ((size_t)(p0 + p) * max_obs + o) * 2;
-            const float su = static_cast<float>(s2[0]), sv = static_cast<float>(s2[1]);
-            ae[p] = fmaf(sv, w[3], fmaf(su, w[0], ae[p]));
-            au[p] = fmaf(sv, w[4], fmaf(su, w[1], au[p]));
-            av[p] = fmaf(sv, w[5], fmaf(su, w[2], av[p]));
           }
         }
       }
@@ -484,10 +368,8 @@ void launch_gb_add(const CoarseConst& C, int ne, const float* z, const float* ba
   const int nsx = (C.nx + kGbOut - 1) / kGbOut;
   const int nsy = (C.ny + strip_h - 1) / strip_h;
   const int total = ne * nsx * nsy;
-  PullConst P{};
-  hipLaunchKernelGGL(gb_add_kernel<false>, dim3((total + 3) / 4), dim3(256), 0, s, C, P, strip_h,
-                     nsx, nsy, total, z, base, psi, nullptr, nullptr, 0, nullptr, nullptr,
-                     nullptr);
+  hipLaunchKernelGGL(gb_add_kernel, dim3((total + 3) / 4), dim3(256), 0, s, C, strip_h, nsx, nsy,
+                     total, z, base, psi);
 }
 
 int update_waves_per_cu() {
@@ -500,13 +382,13 @@ int update_waves_per_cu() {
 int update_particle_group() { return kPB; }
 
 void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, const float* z,
-                            const float* windows, const double* sd, int max_obs,
-                            const int32_t* obs_cells, const int32_t* st_off,
+                            const float* windows, const float* sdf, const int32_t* st_off,
                             const int32_t* st_ent, float* psi, double* scal, hipStream_t s) {
   const int groups = (ne + kPB - 1) / kPB;
   const int total = groups * P.n_strip_x * P.n_strip_y;
-  hipLaunchKernelGGL(analysis_update_kernel, dim3((total + 3) / 4), dim3(256), 0, s, C, P, ne, total,
-                     z, psi, windows, sd, max_obs, obs_cells, st_off, st_ent, scal);
+  hipLaunchKernelGGL(analysis_update_kernel, dim3((total + 3) / 4), dim3(256), 0, s, C, P, ne,
+                     sd_float_stride(ne), total, z, psi, windows, sdf, st_off,
+                     reinterpret_cast<const int4*>(st_ent), scal);
 }
 
 }  // namespace iewpf
