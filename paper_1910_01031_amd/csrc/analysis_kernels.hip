@@ -649,53 +649,133 @@ __global__ __launch_bounds__(kThreads) void dot_rows_kernel(int n, int stride,
   if (threadIdx.x == 0) cval[blockIdx.x] = v;
 }
 
-// One workgroup per 16 x 16 coarse points of one particle: r at the tile and a 6-point halo
-// (how far a 7x7 block reaches from any of its points) is formed once in LDS, then every
-// point adds the rows of the blocks that contain it (ascending observations).
-constexpr int kPcTile = 16, kPcHalo = 6, kPcW = kPcTile + 2 * kPcHalo;
-__global__ __launch_bounds__(kPcTile * kPcTile) void posterior_coarse_kernel(
-    CoarseConst C, const float* __restrict__ xi, const float* __restrict__ nu,
-    const double* __restrict__ dots, const double* __restrict__ alpha,
-    const double* __restrict__ scal, const float* __restrict__ dmat,
-    const int32_t* __restrict__ pt_off, const int32_t* __restrict__ pt_ent,
-    float* __restrict__ rout) {
-  __shared__ double rl[kPcW * kPcW];
-  if (reinterpret_cast<const int32_t*>(scal + kScalStatus)[0] & kStatSkipUpdate) return;
-  const int nr = C.nrx * C.nry;
-  const int i = blockIdx.z;
-  const int tx0 = blockIdx.x * kPcTile, ty0 = blockIdx.y * kPcTile;
+// Posterior random field on the coarse grid, r_i + (A^{1/2} - I) r_i on each observation's
+// 7x7 block, in two passes: one wave per (observation, particle) forms the block product
+// v = (A^{1/2} - I) r_block (each row summed in increasing block index), then one work-item
+// per (coarse point, particle) adds the rows of the blocks that contain the point to r
+// (ascending observations).
+struct PostCoef {
+  double a, sb, sa;
+};
+__device__ __forceinline__ PostCoef post_coef(int i, const double* __restrict__ dots,
+                                              const double* __restrict__ alpha,
+                                              const double* __restrict__ scal) {
   const double xx = dots[3 * i], nn = dots[3 * i + 1], nxv = dots[3 * i + 2];
-  const double a = nxv / xx;
-  const double sperp = sqrt(nn / (nn - a * nxv));
+  PostCoef k;
+  k.a = nxv / xx;
+  const double sperp = sqrt(nn / (nn - k.a * nxv));
   const double beta = scal[1];
-  const double sb = sqrt(fmax(beta, 0.0)) * sperp, sa = sqrt(alpha[i]);
-  const float* X = xi + (size_t)i * nr;
-  const float* N = nu + (size_t)i * nr;
-  for (int e = threadIdx.x; e < kPcW * kPcW; e += kPcTile * kPcTile) {
-    const int ly = e / kPcW, lx = e - ly * kPcW;
-    const int q = wrapi(ty0 - kPcHalo + ly, C.nry) * C.nrx + wrapi(tx0 - kPcHalo + lx, C.nrx);
-    const double xv = X[q], nv = N[q];
-    rl[e] = sb * (nv - a * xv) + sa * xv;
+  k.sb = sqrt(fmax(beta, 0.0)) * sperp;
+  k.sa = sqrt(alpha[i]);
+  return k;
+}
+__device__ __forceinline__ double post_r(const PostCoef& k, float x, float n) {
+  const double xv = x, nv = n;
+  return k.sb * (nv - k.a * xv) + k.sa * xv;
+}
+
+// One wave per (observation, kPostGroup particles): lanes < kPostGroup form the particles'
+// coefficients (the group's first observation stores them for the point pass), lanes m < 49
+// then load r at block point m for every particle of the group, and lane m forms row m of
+// (A^{1/2} - I) r for all of them (independent sum chains, each in increasing block index).
+constexpr int kPostGroup = 16;
+__global__ __launch_bounds__(kWave) void posterior_blocks_kernel(
+    CoarseConst C, int ne, int n_obs, int max_obs, const int32_t* __restrict__ cells,
+    const float* __restrict__ xi, const float* __restrict__ nu, const double* __restrict__ dots,
+    const double* __restrict__ alpha, const double* __restrict__ scal,
+    const float* __restrict__ dmat, double* __restrict__ vblk, double* __restrict__ coef) {
+  __shared__ double rb[kPostGroup][kBlockN];
+  __shared__ double kc[kPostGroup][3];
+  if (reinterpret_cast<const int32_t*>(scal + kScalStatus)[0] & kStatSkipUpdate) return;
+  const int o = blockIdx.x;
+  const int i0 = blockIdx.y * kPostGroup;
+  const int ng = min(kPostGroup, ne - i0);
+  const int nr = C.nrx * C.nry;
+  const int m = threadIdx.x;
+  if (m < kPostGroup) {  // a short group repeats its last particle
+    const PostCoef k = post_coef(i0 + min(m, ng - 1), dots, alpha, scal);
+    kc[m][0] = k.a;
+    kc[m][1] = k.sb;
+    kc[m][2] = k.sa;
+    if (o == 0 && m < ng) {
+      coef[3 * (i0 + m)] = k.a;
+      coef[3 * (i0 + m) + 1] = k.sb;
+      coef[3 * (i0 + m) + 2] = k.sa;
+    }
   }
   __syncthreads();
-  const int lx = threadIdx.x % kPcTile, ly = threadIdx.x / kPcTile;
-  const int px = tx0 + lx, py = ty0 + ly;
-  if (px >= C.nrx || py >= C.nry) return;
-  const int p = py * C.nrx + px;
-  const int cl = (ly + kPcHalo) * kPcW + lx + kPcHalo;
-  double acc = rl[cl];
-  for (int t = pt_off[p]; t < pt_off[p + 1]; ++t) {
-    const int row = pt_ent[t] & 255;  // this point's position in the block
-    const float* drow = dmat + row * kBlockN;
-    const double* b0 = rl + cl - (row / 7) * kPcW - (row % 7);  // the block's corner
-    double s = 0.0;
+  const bool active = m < kBlockN && n_obs > 0;
+  if (active) {
+    // block point m: offset (m / 7 - 3, m % 7 - 3) from the observation's coarse cell
+    const int ao = cells[2 * o] / C.c, bo = cells[2 * o + 1] / C.c;
+    const int q = wrapi(bo + m / 7 - 3, C.nry) * C.nrx + wrapi(ao + m % 7 - 3, C.nrx);
+    float xv[kPostGroup], nv[kPostGroup];
 #pragma unroll
-    for (int dk = 0; dk < 7; ++dk)
+    for (int g = 0; g < kPostGroup; ++g) {
+      const int i = i0 + min(g, ng - 1);
+      xv[g] = xi[(size_t)i * nr + q];
+      nv[g] = nu[(size_t)i * nr + q];
+    }
 #pragma unroll
-      for (int dj = 0; dj < 7; ++dj) s += (double)drow[dk * 7 + dj] * b0[dk * kPcW + dj];
-    acc += s;
+    for (int g = 0; g < kPostGroup; ++g) {
+      PostCoef k;
+      k.a = kc[g][0];
+      k.sb = kc[g][1];
+      k.sa = kc[g][2];
+      rb[g][m] = post_r(k, xv[g], nv[g]);
+    }
   }
-  rout[(size_t)i * nr + p] = static_cast<float>(acc);
+  __syncthreads();
+  if (!active) return;
+  float d[kBlockN];
+#pragma unroll
+  for (int b = 0; b < kBlockN; ++b) d[b] = dmat[m * kBlockN + b];
+  double v[kPostGroup];
+#pragma unroll
+  for (int g = 0; g < kPostGroup; ++g) v[g] = 0.0;
+#pragma unroll
+  for (int b = 0; b < kBlockN; ++b) {
+    const double db = d[b];
+#pragma unroll
+    for (int g = 0; g < kPostGroup; ++g) v[g] += db * rb[g][b];
+  }
+  for (int g = 0; g < ng; ++g) vblk[((size_t)(i0 + g) * max_obs + o) * kBlockN + m] = v[g];
+}
+
+// One work-item per coarse point for kPtGroup particles: the point's block entries are read
+// once for the group.
+constexpr int kPtGroup = 8;
+__global__ __launch_bounds__(256) void posterior_points_kernel(
+    CoarseConst C, int ne, int max_obs, const float* __restrict__ xi,
+    const float* __restrict__ nu, const double* __restrict__ coef,
+    const double* __restrict__ scal, const int32_t* __restrict__ pt_off,
+    const int32_t* __restrict__ pt_ent, const double* __restrict__ vblk,
+    float* __restrict__ rout) {
+  if (reinterpret_cast<const int32_t*>(scal + kScalStatus)[0] & kStatSkipUpdate) return;
+  const int nr = C.nrx * C.nry;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i0 = blockIdx.y * kPtGroup;
+  if (p >= nr) return;
+  const int ng = min(kPtGroup, ne - i0);
+  double acc[kPtGroup];
+#pragma unroll
+  for (int g = 0; g < kPtGroup; ++g) {
+    const int i = i0 + min(g, ng - 1);
+    PostCoef k;
+    k.a = coef[3 * i];
+    k.sb = coef[3 * i + 1];
+    k.sa = coef[3 * i + 2];
+    acc[g] = post_r(k, xi[(size_t)i * nr + p], nu[(size_t)i * nr + p]);
+  }
+  const int t1 = pt_off[p + 1];
+  for (int t = pt_off[p]; t < t1; ++t) {
+    const int e = pt_ent[t];  // (observation << 8) | this point's position in the block
+    const size_t off = (size_t)(e >> 8) * kBlockN + (e & 255);
+#pragma unroll
+    for (int g = 0; g < kPtGroup; ++g)
+      acc[g] += vblk[(size_t)(i0 + min(g, ng - 1)) * max_obs * kBlockN + off];
+  }
+  for (int g = 0; g < ng; ++g) rout[(size_t)(i0 + g) * nr + p] = static_cast<float>(acc[g]);
 }
 
 __global__ void observe_kernel(int n_obs, int nx, int ny, double H, double sigma, uint64_t seed,
@@ -954,13 +1034,20 @@ void launch_sync(int ne, int nr, double n_psi, int one_stage, const double* cval
                      cval, part_dots, rand_dots_parts_for(nr), dots, alpha, cstar, scal);
 }
 
-void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,
+void launch_posterior_coarse(const CoarseConst& C, int ne, int n_obs, int max_obs,
+                             const int32_t* cells, const float* xi, const float* nu,
                              const double* dots, const double* alpha, const double* scal,
                              const float* dmat, const int32_t* pt_off, const int32_t* pt_ent,
-                             float* rout, hipStream_t s) {
-  const dim3 grid((C.nrx + kPcTile - 1) / kPcTile, (C.nry + kPcTile - 1) / kPcTile, ne);
-  hipLaunchKernelGGL(posterior_coarse_kernel, grid, dim3(kPcTile * kPcTile), 0, s, C, xi, nu,
-                     dots, alpha, scal, dmat, pt_off, pt_ent, rout);
+                             double* vblk, double* coef, float* rout, hipStream_t s) {
+  // the point pass reads the coefficients the block pass stores with its first observation:
+  // without observations one block pass column runs that only stores them
+  const dim3 grid(std::max(1, n_obs), (ne + kPostGroup - 1) / kPostGroup);
+  hipLaunchKernelGGL(posterior_blocks_kernel, grid, dim3(kWave), 0, s, C, ne, n_obs, max_obs,
+                     cells, xi, nu, dots, alpha, scal, dmat, vblk, coef);
+  const int nr = C.nrx * C.nry;
+  hipLaunchKernelGGL(posterior_points_kernel, dim3((nr + 255) / 256, (ne + kPtGroup - 1) / kPtGroup),
+                     dim3(256), 0, s, C, ne, max_obs, xi, nu, coef, scal, pt_off, pt_ent, vblk,
+                     rout);
 }
 
 void launch_hqht_full(int n_obs, int nx, int ny, int rx, int ry, int wx, int wy, const double* win,

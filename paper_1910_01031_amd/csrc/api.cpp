@@ -115,7 +115,7 @@ void free_ctx(iewpf_ctx* c) {
                   c->coarse, c->coarse2, c->windows,
                   c->dmat,    c->sd,     c->cval,   c->dots,   c->alpha,   c->cstar,
                   c->scal,    c->d_stage, c->dk1,    c->dpstar, c->dobs,   c->cflmax,  c->dparents,
-                  c->dcum,    c->sir_parents, c->dobs_cells, c->sdf};
+                  c->dcum,    c->sir_parents, c->dobs_cells, c->sdf, c->wcell, c->vblk, c->pcoef};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
@@ -141,7 +141,7 @@ int circ_interval_dist(int p, int a, int len, int n) {
 size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 struct StageLayout {
-  size_t cells, y, pt_off, pt_ent, st_off, st_ent, total;
+  size_t cells, y, pt_off, pt_ent, st_off, st_rows, st_ent, total;
 };
 
 StageLayout stage_layout(const iewpf_ctx& c) {
@@ -151,8 +151,9 @@ StageLayout stage_layout(const iewpf_ctx& c) {
   L.y = o; o = align16(o + sizeof(double) * 2 * c.max_obs);
   L.pt_off = o; o = align16(o + sizeof(int32_t) * (c.nr + 1));
   L.pt_ent = o; o = align16(o + sizeof(int32_t) * (size_t)c.max_obs * kBlockN);
-  L.st_off = o; o = align16(o + sizeof(int32_t) * (c.n_upd_strips + 1));
-  L.st_ent = o; o = align16(o + sizeof(int32_t) * 4 * (size_t)c.n_upd_strips * c.max_obs);
+  L.st_off = o; o = align16(o + sizeof(int32_t) * (c.n_upd_cols + 1));
+  L.st_rows = o; o = align16(o + sizeof(int32_t) * 2 * (size_t)c.n_upd_cols * c.ny);
+  L.st_ent = o; o = align16(o + sizeof(int32_t) * 4 * (1 + 2 * (size_t)c.n_upd_cols * c.max_obs));
   L.total = o;
   return L;
 }
@@ -193,7 +194,7 @@ void add_noise(iewpf_ctx* c, float* psi, uint64_t step, hipStream_t s) {
     launch_soar(c->cc, c->soar_me_f, c->ne, c->xi, c->coarse, s);
   }
   TraceScope t(c, kTrGbAdd, s);
-  launch_gb_add(c->cc, c->ne, c->coarse, nullptr, psi, c->upd_strip_h, s);
+  launch_gb_add(c->cc, c->ne, c->coarse, nullptr, psi, c->gb_strip_h, s);
 }
 
 // One model-error draw (stream `step`, tag 1) with the SOAR weights scaled by `scale`.
@@ -202,13 +203,13 @@ void add_scaled_noise(iewpf_ctx* c, float* psi, uint64_t step, double scale, hip
   for (int q = 0; q < 25; ++q) w[q] = (float)(scale * c->soar_me[q]);
   launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, step, kTagModelError, c->cfg.ensemble_id, s);
   launch_soar(c->cc, w, c->ne, c->xi, c->coarse, s);
-  launch_gb_add(c->cc, c->ne, c->coarse, nullptr, psi, c->upd_strip_h, s);
+  launch_gb_add(c->cc, c->ne, c->coarse, nullptr, psi, c->gb_strip_h, s);
 }
 
 // Builds the per-call observation index lists from the cells in the pinned staging area
 // and uploads cells (and y when with_y) and the lists on the stream.
 //   coarse point -> (observation, 7x7 block row) pairs, ascending observations per point
-//   fine update strip -> observations whose pull window reaches it
+//   update column strip and row -> observations whose pull window holds the row
 int upload_observations(iewpf_ctx* c, int n_obs, bool with_y, hipStream_t s) {
   const StageLayout L = stage_layout(*c);
   int32_t* cells = reinterpret_cast<int32_t*>(c->h_stage + L.cells);
@@ -240,34 +241,73 @@ int upload_observations(iewpf_ctx* c, int n_obs, bool with_y, hipStream_t s) {
     for (int o = 0; o < n_obs; ++o)
       for (int q = 0; q < kBlockN; ++q) pt_ent[fillp[block_point(o, q)]++] = (o << 8) | q;
   }
+  // Update lists, per column strip of the update kernel: the observations whose pull window
+  // reaches the strip's columns, sorted by the window's first row and listed twice (the
+  // second time one period further down), so that the windows holding a row k are the
+  // consecutive entries whose (unwrapped) first row lies in (k + ny - wy, k + ny]; st_rows
+  // holds that range for every row.  Entry 0 is a sentinel (zero S d row, no window column)
+  // that pads the kernel's last batch of a row.  An entry holds the window's column (with
+  // simple_x the byte offset of lane 0's cell in the strided window row, lane 0 sitting at
+  // column j0 - kGbHalo; else the window's first column), its first row, the byte offset of
+  // the observation's S d row, and with simple_x lane 0's byte offset in a cell-major row.
   const int nsx = (c->nx + kGbOut - 1) / kGbOut;
-  const int nsy = (c->ny + c->upd_strip_h - 1) / c->upd_strip_h;
+  const int ne4 = sd_float_stride(c->ne);
   int32_t* st_off = reinterpret_cast<int32_t*>(c->h_stage + L.st_off);
+  int32_t* st_rows = reinterpret_cast<int32_t*>(c->h_stage + L.st_rows);
   int32_t* st_ent = reinterpret_cast<int32_t*>(c->h_stage + L.st_ent);
-  st_off[0] = 0;
-  int t = 0;
-  for (int sy = 0; sy < nsy; ++sy) {
-    const int k0 = sy * c->upd_strip_h;
-    const int lenk = std::min(c->upd_strip_h, c->ny - k0);
-    for (int sx = 0; sx < nsx; ++sx) {
-      const int j0 = sx * kGbOut;
-      const int lenj = std::min(kGbOut, c->nx - j0);
-      for (int o = 0; o < n_obs; ++o) {
-        const bool in_x = c->rx < 0 || circ_interval_dist(cells[2 * o], j0, lenj, c->nx) <= c->rx;
-        const bool in_y =
-            c->ry < 0 || circ_interval_dist(cells[2 * o + 1], k0, lenk, c->ny) <= c->ry;
-        if (in_x && in_y) {
-          // the window's first column and row on the torus (a window folded onto the whole
-          // period starts at the observed cell)
-          const int jo = cells[2 * o], ko = cells[2 * o + 1];
-          int32_t* e = st_ent + 4 * (size_t)t++;
-          e[0] = c->rx < 0 ? jo : ((jo - c->rx) % c->nx + c->nx) % c->nx;
-          e[1] = c->ry < 0 ? ko : ((ko - c->ry) % c->ny + c->ny) % c->ny;
-          e[2] = o;
-          e[3] = 0;
+  st_ent[0] = c->simple_x ? 4 * c->wx : 0;
+  st_ent[1] = 0;
+  st_ent[2] = (int32_t)(sizeof(float) * 2 * (size_t)ne4 * c->max_obs);
+  st_ent[3] = 24 * c->wx;
+  int t = 1;
+  st_off[0] = t;
+  std::vector<std::pair<int, int>> col;  // (window row, observation)
+  for (int sx = 0; sx < nsx; ++sx) {
+    const int j0 = sx * kGbOut;
+    const int lenj = std::min(kGbOut, c->nx - j0);
+    col.clear();
+    for (int o = 0; o < n_obs; ++o) {
+      if (c->rx >= 0 && circ_interval_dist(cells[2 * o], j0, lenj, c->nx) > c->rx) continue;
+      // the window's first row on the torus (a window folded onto the whole period starts at
+      // the observed cell)
+      const int ko = cells[2 * o + 1];
+      col.emplace_back(c->ry < 0 ? ko : ((ko - c->ry) % c->ny + c->ny) % c->ny, o);
+    }
+    std::stable_sort(col.begin(), col.end(),
+                     [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+                       return a.first < b.first;
+                     });
+    const int n = (int)col.size(), base = t;
+    for (int rep = 0; rep < 2; ++rep)
+      for (const auto& q : col) {
+        const int jo = cells[2 * q.second];
+        const int js = c->rx < 0 ? jo : ((jo - c->rx) % c->nx + c->nx) % c->nx;
+        int32_t* e = st_ent + 4 * (size_t)t++;
+        e[0] = js;
+        e[3] = 0;
+        if (c->simple_x) {
+          // lane l's window column is (l + a) mod nx; no lane wraps when a + 63 < nx, and
+          // otherwise the lanes that do not wrap lie past the window (a > nx - 64 >= wx):
+          // lane 0's column offset a' in bytes of the strided window rows (4 a') and of
+          // the cell-major LDS rows (24 a')
+          const int a = ((j0 - kGbHalo - js) % c->nx + c->nx) % c->nx;
+          const int a1 = a + kWave - 1 < c->nx ? a : a - c->nx;
+          e[0] = 4 * a1;
+          e[3] = 24 * a1;
         }
+        e[1] = q.first;
+        e[2] = (int32_t)(sizeof(float) * 2 * (size_t)ne4 * q.second);
       }
-      st_off[sy * nsx + sx + 1] = t;
+    st_off[sx + 1] = t;
+    // unwrapped first row of doubled entry i
+    auto row_of = [&](int i) { return i < n ? col[i].first : col[i - n].first + c->ny; };
+    int lo = 0, hi = 0;
+    for (int k = 0; k < c->ny; ++k) {
+      const int kk = k + c->ny;
+      while (lo < 2 * n && row_of(lo) <= kk - c->wy) ++lo;
+      while (hi < 2 * n && row_of(hi) <= kk) ++hi;
+      st_rows[2 * ((size_t)sx * c->ny + k)] = base + lo;
+      st_rows[2 * ((size_t)sx * c->ny + k) + 1] = base + std::max(lo, hi);
     }
   }
   // One copy of the staging area up to the last used list entry (the device block has the
@@ -379,8 +419,9 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
   // stage 6: r' on the coarse grid, SOAR, then one fused pass over the state
   {
     TraceScope tr(c, kTrPosterior, s);
-    launch_posterior_coarse(c->cc, c->ne, c->xi, c->nu, c->dots, c->alpha, c->scal, c->dmat,
-                            c->pt_off, c->pt_ent, c->coarse2, s);
+    launch_posterior_coarse(c->cc, c->ne, n_obs, c->max_obs, c->obs_cells, c->xi, c->nu, c->dots,
+                            c->alpha, c->scal, c->dmat, c->pt_off, c->pt_ent, c->vblk,
+                            c->pcoef, c->coarse2, s);
   }
   {
     TraceScope tr(c, kTrSoar, s);
@@ -389,6 +430,8 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
   PullConst P;
   P.wx = c->wx;
   P.wy = c->wy;
+  P.ws = c->ws;
+  P.simple_x = c->simple_x ? 1 : 0;
   P.rx = c->rx;
   P.ry = c->ry;
   P.n_obs = n_obs;
@@ -397,8 +440,8 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
   P.n_strip_y = (c->ny + c->upd_strip_h - 1) / c->upd_strip_h;
   {
     TraceScope tr(c, kTrUpdate, s);
-    launch_analysis_update(c->cc, P, c->ne, c->coarse, c->windows, c->sdf, c->st_off, c->st_ent,
-                           state, c->scal, s);
+    launch_analysis_update(c->cc, P, c->ne, c->coarse, c->windows, c->wcell, c->sdf, c->st_rows,
+                           c->st_ent, state, c->scal, s);
   }
   IEWPF_HIP_TRY(hipGetLastError());
   return 0;
@@ -773,9 +816,15 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   c->ry = W > f.ny ? -1 : r;
   c->wx = W > f.nx ? f.nx : W;
   c->wy = W > f.ny ? f.ny : W;
-  if (24.0 * c->wx * c->wy >= 2147483648.0) {  // the update kernel reads the windows in 31-bit bytes
+  c->ws = window_stride(c->wx);
+  c->simple_x = c->rx >= 0 && f.nx >= c->wx + kWave;
+  if (24.0 * c->ws * c->wy >= 2147483648.0) {  // the update kernel reads the windows in 31-bit bytes
     free_ctx(c);
     return fail(IEWPF_E_SHAPE, "pull windows above 2^31 bytes are not supported");
+  }
+  if (8.0 * sd_float_stride(f.n_particles) * (c->max_obs + 1.0) >= 2147483648.0) {
+    free_ctx(c);  // the update lists address S d rows by 31-bit byte offsets
+    return fail(IEWPF_E_CAPACITY, "particles x observations too large for the update lists");
   }
   std::vector<double> win((size_t)6 * c->wx * c->wy);
   build_pull_windows(*c, win.data(), c->Mfine);
@@ -790,17 +839,21 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
     return fail(IEWPF_E_ARG, "coarse H Q H^T + R is not positive definite");
   }
   {
-    // 6-row strips: measured fastest for 100 x 500x300 (4..12 rows within 5 %; the
-    // occupancy-based choice below, used when IEWPF_UPD_STRIP=0, picked 24 rows, 7 % slower)
-    const int forced = env_int("IEWPF_UPD_STRIP", 6);
+    // Update strips: every row's observation range comes with the lists, so a strip's
+    // length costs only its two halo rows; the strips are sized for whole launch rounds
+    // (IEWPF_UPD_STRIP forces a height).  Model-error strips: 6 rows.
+    const int forced = env_int("IEWPF_UPD_STRIP", 0);
     const int groups = (c->ne + update_particle_group() - 1) / update_particle_group();
     const int nsx = (f.nx + kGbOut - 1) / kGbOut;
+    c->use_lds = update_lds_bytes(c->wx, c->wy) <= kUpdateLdsMax && env_int("IEWPF_UPD_LDS", 1) != 0;
+    const int slots =
+        device_slots(c->use_lds ? update_lds_waves_per_cu() : update_waves_per_cu());
     const int n_ys = forced > 0 ? (f.ny + forced - 1) / forced
-                                : choose_row_strips(nsx * groups, f.ny,
-                                                    device_slots(update_waves_per_cu()), 2, 4);
+                                : choose_row_strips(nsx * groups, f.ny, slots, 2, 4);
     c->upd_strip_h = (f.ny + n_ys - 1) / n_ys;
+    c->gb_strip_h = std::max(1, std::min(f.ny, env_int("IEWPF_GB_STRIP", 6)));
+    c->n_upd_cols = nsx;
   }
-  c->n_upd_strips = ((f.nx + kGbOut - 1) / kGbOut) * ((f.ny + c->upd_strip_h - 1) / c->upd_strip_h);
 
   int rc = 0;
   const size_t nstate = 3 * c->ncell * (size_t)c->ne;
@@ -819,13 +872,17 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   }
   rc |= dev_alloc(&c->me_xi, (size_t)c->me_chunk * c->ne * c->nr);
   rc |= dev_alloc(&c->me_coarse, (size_t)c->me_chunk * c->ne * c->nr);
-  rc |= dev_alloc(&c->windows, win.size());
+  rc |= dev_alloc(&c->windows, (size_t)c->wy * 6 * c->ws);
+  if (c->use_lds) rc |= dev_alloc(&c->wcell, (size_t)c->wy * 6 * c->wx);
   rc |= dev_alloc(&c->dmat, (size_t)kBlockN * kBlockN);
   rc |= dev_alloc(&c->sd, (size_t)c->ne * c->max_obs * 2);
-  rc |= dev_alloc(&c->sdf, (size_t)sd_float_stride(c->ne) * c->max_obs * 2);
-  // the padding particles' entries are read (and their sums dropped): keep them finite
-  if (rc == 0 && hipMemset(c->sdf, 0, sizeof(float) * sd_float_stride(c->ne) * c->max_obs * 2) !=
-                     hipSuccess)
+  rc |= dev_alloc(&c->vblk, (size_t)c->ne * std::max(1, c->max_obs) * kBlockN);
+  rc |= dev_alloc(&c->pcoef, (size_t)3 * c->ne);
+  rc |= dev_alloc(&c->sdf, (size_t)sd_float_stride(c->ne) * (c->max_obs + 1) * 2);
+  // the padding particles' entries are read (and their sums dropped): keep them finite; row
+  // max_obs stays zero
+  if (rc == 0 && hipMemset(c->sdf, 0, sizeof(float) * sd_float_stride(c->ne) * (c->max_obs + 1) *
+                                          2) != hipSuccess)
     rc = fail(IEWPF_E_HIP, "hipMemset(sdf)");
   rc |= dev_alloc(&c->cval, c->ne);
   rc |= dev_alloc(&c->dots, (size_t)3 * c->ne);
@@ -854,6 +911,7 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
     c->pt_off = reinterpret_cast<int32_t*>(c->d_stage + L.pt_off);
     c->pt_ent = reinterpret_cast<int32_t*>(c->d_stage + L.pt_ent);
     c->st_off = reinterpret_cast<int32_t*>(c->d_stage + L.st_off);
+    c->st_rows = reinterpret_cast<int32_t*>(c->d_stage + L.st_rows);
     c->st_ent = reinterpret_cast<int32_t*>(c->d_stage + L.st_ent);
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_stage), c->stage_bytes) != hipSuccess ||
@@ -865,13 +923,28 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
     return fail(IEWPF_E_HIP, "pinned host allocation failed");
   }
   c->h_win64 = win;
-  std::vector<float> winf(win.begin(), win.end());
+  // device layout [wy][6][ws]: the six fields of one window cell a fixed stride apart
+  std::vector<float> winf((size_t)c->wy * 6 * c->ws, 0.0f);
+  for (int fld = 0; fld < 6; ++fld)
+    for (int iy = 0; iy < c->wy; ++iy)
+      for (int ix = 0; ix < c->wx; ++ix)
+        winf[((size_t)iy * 6 + fld) * c->ws + ix] =
+            (float)win[((size_t)fld * c->wy + iy) * c->wx + ix];
+  std::vector<float> wcf(c->wcell ? (size_t)c->wy * c->wx * 6 : 0);
+  if (c->wcell)
+    for (int fld = 0; fld < 6; ++fld)
+      for (int iy = 0; iy < c->wy; ++iy)
+        for (int ix = 0; ix < c->wx; ++ix)
+          wcf[((size_t)iy * c->wx + ix) * 6 + fld] =
+              (float)win[((size_t)fld * c->wy + iy) * c->wx + ix];
   std::vector<float> dm((size_t)kBlockN * kBlockN);
   for (int i = 0; i < kBlockN; ++i)
     for (int j = 0; j < kBlockN; ++j)
       dm[i * kBlockN + j] = (float)(c->ahalf[i * kBlockN + j] - (i == j ? 1.0 : 0.0));
   if (hipMemcpy(c->windows, winf.data(), sizeof(float) * winf.size(), hipMemcpyHostToDevice) !=
           hipSuccess ||
+      (c->wcell && hipMemcpy(c->wcell, wcf.data(), sizeof(float) * wcf.size(),
+                             hipMemcpyHostToDevice) != hipSuccess) ||
       hipMemcpy(c->dmat, dm.data(), sizeof(float) * dm.size(), hipMemcpyHostToDevice) != hipSuccess) {
     free_ctx(c);
     return fail(IEWPF_E_HIP, "constant upload failed");
@@ -900,7 +973,7 @@ int iewpf_init_ensemble(iewpf_ctx* c, float* state, const float* base, uint64_t 
   if (!base) IEWPF_HIP_TRY(hipMemsetAsync(state, 0, sizeof(float) * 3 * c->ncell * c->ne, s));
   launch_normals(c->xi, c->nr, c->ne, c->cfg.seed, stream_index, kTagInit, c->cfg.ensemble_id, s);
   launch_soar(c->cc, c->soar_init_f, c->ne, c->xi, c->coarse, s);
-  launch_gb_add(c->cc, c->ne, c->coarse, base, state, c->upd_strip_h, s);
+  launch_gb_add(c->cc, c->ne, c->coarse, base, state, c->gb_strip_h, s);
   IEWPF_HIP_TRY(hipGetLastError());
   return 0;
 }
@@ -1512,7 +1585,16 @@ int iewpf_read_buffer(iewpf_ctx* c, int which, void* host_out, size_t bytes, voi
       return 0;
     case 6:
       if (!need(sizeof(float) * 6 * (size_t)c->wx * c->wy)) break;
-      IEWPF_HIP_TRY(hipMemcpy(host_out, c->windows, bytes, hipMemcpyDeviceToHost));
+      {
+        std::vector<float> dev((size_t)c->wy * 6 * c->ws);
+        IEWPF_HIP_TRY(hipMemcpy(dev.data(), c->windows, sizeof(float) * dev.size(),
+                                hipMemcpyDeviceToHost));
+        float* o = static_cast<float*>(host_out);
+        for (int fld = 0; fld < 6; ++fld)
+          for (int iy = 0; iy < c->wy; ++iy)
+            for (int ix = 0; ix < c->wx; ++ix)
+              o[((size_t)fld * c->wy + iy) * c->wx + ix] = dev[((size_t)iy * 6 + fld) * c->ws + ix];
+      }
       return 0;
     case 7: {
       if (!need(sizeof(double) * (size_t)c->ne * c->last_n_obs * 2)) break;

@@ -39,10 +39,17 @@ struct CoarseConst {
 // Observation / pull-window geometry for the analysis update.
 struct PullConst {
   int wx, wy;          // stored window extents
+  int ws;              // window row stride per field in floats (device layout [wy][6][ws])
   int rx, ry;          // window radii (-1: folded onto the whole period)
+  int simple_x;        // rx >= 0 and nx >= wx + kWave: update entries carry lane 0's offset
   int n_obs;
   int strip_h, n_strip_x, n_strip_y;
 };
+
+// Device window row stride per field for windows up to this wide (a compile-time stride lets
+// the six field loads of one window cell take immediate offsets).
+constexpr int kWinStride = 128;
+inline int window_stride(int wx) { return wx <= kWinStride ? kWinStride : wx; }
 
 // Analysis status words: int32 [4] at byte offset 8 * kScalStatus of the analysis scalars
 // (scal): [0] flags set by the sync kernel, [1] the first particle with a non-finite scalar
@@ -73,6 +80,8 @@ struct iewpf_ctx {
   double S[4], Sc[4], Mfine[4];
   double ahalf[iewpf::kBlockN * iewpf::kBlockN];
   int wx, wy, rx, ry;      // pull window geometry
+  int ws = 128;            // device window row stride per field (window_stride(wx))
+  bool simple_x = false;   // see PullConst::simple_x
   iewpf::SweConst swe;       // the scheme step's form for this context's launches
   iewpf::SweConst swe_halo;  // the strip form (batched launches use it)
   iewpf::CoarseConst cc;
@@ -88,10 +97,14 @@ struct iewpf_ctx {
   float* me_xi = nullptr;
   float* me_coarse = nullptr;
   int me_chunk = 1;
-  float* windows = nullptr;    // [6][wy][wx]: (s_u, s_v) x (eta, hu, hv)
+  float* windows = nullptr;    // [wy][6][window_stride(wx)]: (s_u, s_v) x (eta, hu, hv)
+  float* wcell = nullptr;      // the same, cell-major [wy][wx][6], when they fit in LDS
   float* dmat = nullptr;       // A^{1/2} - I, float32 [49][49]
   double* sd = nullptr;        // [ne][max_obs][2]
-  float* sdf = nullptr;        // S d rounded to float32, [max_obs][sd_float_stride(ne)][2]
+  double* vblk = nullptr;      // posterior block products [ne][max_obs][49]
+  double* pcoef = nullptr;     // posterior coefficients per particle [ne][3]
+  float* sdf = nullptr;        // S d rounded to float32, [max_obs + 1][sd_float_stride(ne)][2]
+                               // (row max_obs stays zero: the update lists' sentinel)
   double* cval = nullptr;      // [ne]
   double* dots = nullptr;      // [ne][3]
   double* part_dots = nullptr; // [ne][parts][3] partial dot products
@@ -102,10 +115,17 @@ struct iewpf_ctx {
   double* obs_y = nullptr;       // [max_obs][2]
   int32_t* pt_off = nullptr;     // coarse-point CSR offsets [nr + 1]
   int32_t* pt_ent = nullptr;     // entries (obs << 8 | block index) [max_obs * 49]
-  int32_t* st_off = nullptr;     // strip CSR offsets [n_strips + 1]
-  int32_t* st_ent = nullptr;     // per strip (window column, window row, obs, 0) [n_strips * max_obs][4]
-  int n_upd_strips = 0;
+  // update lists per column strip: entries (window column, window row, obs, 0), each
+  // column's observations sorted by window row and listed twice [n_upd_cols * 2 * max_obs][4];
+  // st_off [n_upd_cols + 1] their CSR offsets; st_rows [n_upd_cols][ny][2] per row the
+  // entry range whose windows hold the row
+  int32_t* st_off = nullptr;
+  int32_t* st_rows = nullptr;
+  int32_t* st_ent = nullptr;
+  int n_upd_cols = 0;
   int upd_strip_h = 16;
+  int gb_strip_h = 6;
+  bool use_lds = false;          // the update stages its windows in LDS (wcell)
   double* dk1 = nullptr;         // drifter k1 [ne][max_obs][2]
   double* dpstar = nullptr;      // drifter p*  [ne][max_obs][2]
   double* dobs = nullptr;        // observation synthesis output [max_obs][2]
@@ -248,13 +268,22 @@ void launch_soar(const CoarseConst& C, const float* w25, int ne, const float* in
 void launch_gb_add(const CoarseConst& C, int ne, const float* z, const float* base, float* psi,
                    int strip_h, hipStream_t s);
 // Particles per wave of the analysis update; sdf pads the particle count to a multiple of it.
-constexpr int kUpdParticles = 4;
+#ifndef IEWPF_UPD_PB
+#define IEWPF_UPD_PB 4
+#endif
+constexpr int kUpdParticles = IEWPF_UPD_PB;
 inline int sd_float_stride(int ne) {
   return (ne + kUpdParticles - 1) / kUpdParticles * kUpdParticles;
 }
+// wcell (cell-major windows [wy * wx][6], or null): stage the windows in LDS
 void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, const float* z,
-                            const float* windows, const float* sdf, const int32_t* st_off,
-                            const int32_t* st_ent, float* psi, double* scal, hipStream_t s);
+                            const float* windows, const float* wcell, const float* sdf,
+                            const int32_t* st_rows, const int32_t* st_ent, float* psi,
+                            double* scal, hipStream_t s);
+// LDS of the staged-window update (two workgroups fit one compute unit up to this size)
+constexpr size_t kUpdateLdsMax = 80 * 1024;
+size_t update_lds_bytes(int wx, int wy);
+int update_lds_waves_per_cu();
 // c_i = out_scale * sum_o d^T S d (out_scale = -1/2 and S = R^{-1} give the log-weights of
 // the standard particle filter); sdf (may be null) receives S d in float32, observation-major
 void launch_innovation(int ne, int n_obs, int max_obs, int nx, int ny, double H, const double S[4],
@@ -293,10 +322,13 @@ void launch_sd_full(int n, int ne, int stride, const double* S, const double* D,
 void launch_sync(int ne, int nr, double n_psi, int one_stage, const double* cval,
                  const double* part_dots, double* dots, double* alpha, double* cstar,
                  double* scal, hipStream_t s);
-void launch_posterior_coarse(const CoarseConst& C, int ne, const float* xi, const float* nu,
+// vblk: [ne][max_obs][49] block products (A^{1/2} - I) r of every observation's block;
+// coef: [ne][3] the coefficients of r per particle
+void launch_posterior_coarse(const CoarseConst& C, int ne, int n_obs, int max_obs,
+                             const int32_t* cells, const float* xi, const float* nu,
                              const double* dots, const double* alpha, const double* scal,
                              const float* dmat, const int32_t* pt_off, const int32_t* pt_ent,
-                             float* rout, hipStream_t s);
+                             double* vblk, double* coef, float* rout, hipStream_t s);
 void launch_observe(int n_obs, int nx, int ny, double H, double sigma, uint64_t seed,
                     uint64_t step, uint32_t ens, const float* truth, const int32_t* cells,
                     double* y, hipStream_t s);

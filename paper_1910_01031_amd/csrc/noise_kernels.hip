@@ -194,13 +194,22 @@ __global__ __launch_bounds__(256) void gb_add_kernel(CoarseConst C, int strip_h,
 // observation list of the strip comes from the host with each window's origin on the torus,
 // and S d in float32, both read with scalar loads; the row window test is wave-uniform.
 constexpr int kPB = kUpdParticles;
-constexpr int kObsBatch = 4;
+#ifndef IEWPF_UPD_OBS_BATCH
+#define IEWPF_UPD_OBS_BATCH 4
+#endif
+constexpr int kObsBatch = IEWPF_UPD_OBS_BATCH;
 
 
-__global__ __launch_bounds__(256) void analysis_update_kernel(
+// SIMPLE_X: the grid is at least a window plus a wave wide and the windows are not folded,
+// so a strip's lanes meet each window at most once and every entry carries the byte offset
+// of lane 0's window column (negative when the window starts to the left of the strip);
+// otherwise the entry carries the window's first column and every lane wraps its own offset.
+// WS: the window row stride per field in floats (0: runtime, P.ws).
+template <bool SIMPLE_X, int WS>
+__global__ __launch_bounds__(256, 5) void analysis_update_kernel(
     CoarseConst C, PullConst P, int ne, int ne4, int total_waves, const float* __restrict__ zall,
     float* __restrict__ psi, const float* __restrict__ windows, const float* __restrict__ sdf,
-    const int32_t* __restrict__ st_off, const int4* __restrict__ st_ent,
+    const int2* __restrict__ st_rows, const int4* __restrict__ st_ent,
     double* __restrict__ scal) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave =
@@ -217,10 +226,13 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
   const int np = min(kPB, ne - p0);
   const int nx = C.nx, ny = C.ny;
   const size_t ncell = (size_t)nx * ny;
-  const size_t plane = (size_t)P.wx * P.wy;
+  const unsigned ws4 = 4u * static_cast<unsigned>(WS > 0 ? WS : P.ws);  // field stride, bytes
+  const unsigned wrow4 = 6u * ws4;                                       // window row, bytes
+  const unsigned wx4 = 4u * static_cast<unsigned>(P.wx);
 
   const int j = sx * kGbOut + lane - kGbHalo;
   const int jw = wrapi(j, nx);
+  const unsigned lane4 = 4u * static_cast<unsigned>(lane);
   const bool writer = lane >= kGbHalo && lane < kWave - kGbHalo && j < nx;
   // State and windows as raw buffers (byte offsets < 2^31, checked when the context is
   // created): state rows by a scalar offset and one lane offset, which switches the lanes
@@ -233,8 +245,8 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
 #pragma unroll
   for (int p = 0; p < kPB; ++p)
     bs[p] = make_rsrc(psi + (size_t)min(p0 + p, ne - 1) * 3 * ncell, p < np ? 12 * ncell : 0);
-  const __amdgpu_buffer_rsrc_t bw = make_rsrc(windows, 24 * plane);
-  const unsigned plane_b = 4u * static_cast<unsigned>(plane);
+  const __amdgpu_buffer_rsrc_t bw = make_rsrc(windows, (size_t)P.wy * wrow4);
+  const char* sdf_g = reinterpret_cast<const char*>(sdf + 2 * (size_t)p0);
   int cx[4];
   float wx[4];
   {
@@ -246,11 +258,13 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
   }
   const int k0 = sy * P.strip_h;
   const int k_end = min(k0 + P.strip_h, ny);
-  // The strip's observation list: per entry the first column and row of the observation's
-  // window on the torus (the observed cell minus the radius; the cell itself for a window
-  // folded onto the whole period) and the observation; read with scalar loads (the index is
-  // wave-uniform), as are S d of the group's particles (float, observation-major).
-  const int o_beg = st_off[strip], o_end = st_off[strip + 1];
+  // Per row, the range of list entries whose windows hold the row (entry 0: a sentinel whose
+  // S d row is zero, which pads the last batch): per entry the window's column (see SIMPLE_X),
+  // its first row on the torus (the observed cell minus the radius; the cell itself for a
+  // window folded onto the whole period) and the byte offset of the observation's S d row;
+  // read with scalar loads (the index is wave-uniform), as are S d of the group's particles
+  // (float, observation-major).
+  const int2* rows = st_rows + (size_t)sx * ny;
   float dm2[kPB], dm1[kPB];
   float chk[kPB];  // stays 0 while every written value is finite (x * 0 is NaN for inf, NaN)
   CoarseWin win[kPB];
@@ -284,24 +298,31 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
       }
       // kObsBatch observations at a time: all window loads of a batch issued before its
       // multiply-adds
+      const int2 range = rows[k];
+      const int o_beg = range.x, o_end = range.y;
       for (int t0 = o_beg; t0 < o_end; t0 += kObsBatch) {
         float w[kObsBatch][6];
         float su[kObsBatch][kPB], sv[kObsBatch][kPB];
 #pragma unroll
         for (int u = 0; u < kObsBatch; ++u) {
-          const bool valid = t0 + u < o_end;  // wave-uniform
-          const int4 e = st_ent[valid ? t0 + u : o_end - 1];
-          // window offset on the torus: 0 <= k, e.y < ny and 0 <= jw, e.x < nx
-          int iy = k - e.y;  // wave-uniform
+          const int4 e = st_ent[t0 + u < o_end ? t0 + u : 0];  // wave-uniform
+          int iy = k - e.y;  // 0 <= k, e.y < ny: the window row on the torus
           iy += iy < 0 ? ny : 0;
-          int ix = jw - e.x;
-          ix += ix < 0 ? nx : 0;
-          const bool in_y = valid && iy < P.wy;
-          const unsigned voff = in_y && ix < P.wx ? 4u * static_cast<unsigned>(ix) : kBufferOff;
-          const unsigned soff = in_y ? 4u * static_cast<unsigned>(iy * P.wx) : 0u;
+          const unsigned soff = static_cast<unsigned>(iy) * wrow4;
+          unsigned voff;
+          if (SIMPLE_X) {
+            const unsigned v = lane4 + static_cast<unsigned>(e.x);
+            voff = v < wx4 ? v : kBufferOff;
+          } else {
+            int ix = jw - e.x;  // 0 <= jw, e.x < nx
+            ix += ix < 0 ? nx : 0;
+            voff = static_cast<unsigned>(ix) < static_cast<unsigned>(P.wx)
+                       ? 4u * static_cast<unsigned>(ix)
+                       : kBufferOff;
+          }
 #pragma unroll
-          for (int f = 0; f < 6; ++f) w[u][f] = ld_buf(bw, voff, soff + f * plane_b);
-          const float* q = sdf + ((size_t)e.z * ne4 + p0) * 2;
+          for (int f = 0; f < 6; ++f) w[u][f] = ld_buf(bw, voff + f * ws4, soff);
+          const float* q = reinterpret_cast<const float*>(sdf_g + static_cast<unsigned>(e.z));
 #pragma unroll
           for (int p = 0; p < kPB; ++p) {
             su[u][p] = q[2 * p];
@@ -345,6 +366,233 @@ __global__ __launch_bounds__(256) void analysis_update_kernel(
   }
 }
 
+// The same update with the pull windows staged in LDS once per workgroup, cell-major
+// ([wy * wx + 1][6], the last cell zero: the lanes a window misses read it).  Window reads then
+// wait only on the LDS counter, so the state rows can be loaded one row ahead and the coarse
+// rows of the random part one fine row ahead without the observation loop waiting on them;
+// the arithmetic is that of analysis_update_kernel, in the same order.
+constexpr int kLdsWaves = 8;
+
+template <bool SIMPLE_X>
+__global__ __launch_bounds__(kLdsWaves * kWave, 4) void analysis_update_lds_kernel(
+    CoarseConst C, PullConst P, int ne, int ne4, int total_waves, const float* __restrict__ zall,
+    float* __restrict__ psi, const float* __restrict__ wcell, const float* __restrict__ sdf,
+    const int2* __restrict__ st_rows, const int4* __restrict__ st_ent,
+    double* __restrict__ scal) {
+  extern __shared__ __align__(16) float lw[];
+  int32_t* status = reinterpret_cast<int32_t*>(scal + kScalStatus);
+  if (status[0] & kStatSkipUpdate) return;  // the same for every workgroup
+  const int ncw = P.wx * P.wy;
+  {
+    const float2* src = reinterpret_cast<const float2*>(wcell);
+    float2* dst = reinterpret_cast<float2*>(lw);
+    for (int i = threadIdx.x; i < 3 * ncw; i += blockDim.x) dst[i] = src[i];
+    if (threadIdx.x < 6) lw[6 * ncw + threadIdx.x] = 0.0f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave =
+      __builtin_amdgcn_readfirstlane(blockIdx.x * kLdsWaves + (threadIdx.x / kWave));
+  if (wave >= total_waves) return;
+  const int per_group = P.n_strip_x * P.n_strip_y;
+  const int group = wave / per_group;
+  const int strip = wave - group * per_group;
+  const int sy = strip / P.n_strip_x;
+  const int sx = strip - sy * P.n_strip_x;
+  const int p0 = group * kPB;
+  const int np = min(kPB, ne - p0);
+  const int nx = C.nx, ny = C.ny;
+  const size_t ncell = (size_t)nx * ny;
+  const int nrc = C.nrx * C.nry;
+
+  const int j = sx * kGbOut + lane - kGbHalo;
+  const int jw = wrapi(j, nx);
+  const bool writer = lane >= kGbHalo && lane < kWave - kGbHalo && j < nx;
+  const unsigned bj = writer ? 4u * static_cast<unsigned>(j) : kBufferOff;
+  const unsigned brow = 4u * static_cast<unsigned>(nx);
+  const unsigned fq = 4u * static_cast<unsigned>(ncell), fr = 2u * fq;
+  __amdgpu_buffer_rsrc_t bs[kPB], bz[kPB];
+#pragma unroll
+  for (int p = 0; p < kPB; ++p) {
+    const int q = min(p0 + p, ne - 1);
+    bs[p] = make_rsrc(psi + (size_t)q * 3 * ncell, p < np ? 12 * ncell : 0);
+    bz[p] = make_rsrc(zall + (size_t)q * nrc, 4 * (size_t)nrc);
+  }
+  const char* sdf_g = reinterpret_cast<const char*>(sdf + 2 * (size_t)p0);
+  const unsigned lane24 = 24u * static_cast<unsigned>(lane);
+  const unsigned wx24 = 24u * static_cast<unsigned>(P.wx);
+  const unsigned zero24 = 24u * static_cast<unsigned>(ncw);
+  int cx[4];
+  float wxw[4];
+  unsigned cxo[4];  // byte offsets of the lane's coarse columns
+  {
+    const int num = 2 * jw + 1 - C.c;
+    const int bx = floordiv(num, 2 * C.c);
+    cr_phase(C, num - 2 * C.c * bx, wxw);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      cx[m] = wrap1(bx + m - 1, C.nrx);
+      cxo[m] = 4u * static_cast<unsigned>(cx[m]);
+    }
+  }
+  const unsigned crow = 4u * static_cast<unsigned>(C.nrx);
+  auto coarse_row = [&](int b) { return static_cast<unsigned>(wrap1(b, C.nry)) * crow; };
+  auto brow_of = [&](int s) { return floordiv(2 * s + 1 - C.c, 2 * C.c); };
+  const int k0 = sy * P.strip_h;
+  const int k_end = min(k0 + P.strip_h, ny);
+  const int2* rows = st_rows + (size_t)sx * ny;
+
+  // x-interpolated coarse rows by-1 .. by+2 around fine row s (as CoarseWin), the raw taps of
+  // the next coarse row when one is pending
+  float xr[kPB][4];
+  float pre[kPB][4];
+  int by = brow_of(k0 - 1);
+#pragma unroll
+  for (int p = 0; p < kPB; ++p)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const unsigned ro = coarse_row(by + n - 1);
+      float v[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) v[a] = ld_buf(bz[p], cxo[a], ro);
+      xr[p][n] = wxw[0] * v[0] + wxw[1] * v[1] + wxw[2] * v[2] + wxw[3] * v[3];
+    }
+  // d at fine row s; the caller has issued the taps of row brow_of(s) + 2 into pre when
+  // brow_of(s) moves past by
+  auto d_at = [&](int s, float (&d)[kPB]) {
+    const int num = 2 * s + 1 - C.c;
+    const int b = floordiv(num, 2 * C.c);
+    if (b != by) {
+#pragma unroll
+      for (int p = 0; p < kPB; ++p) {
+        xr[p][0] = xr[p][1];
+        xr[p][1] = xr[p][2];
+        xr[p][2] = xr[p][3];
+        xr[p][3] = wxw[0] * pre[p][0] + wxw[1] * pre[p][1] + wxw[2] * pre[p][2] + wxw[3] * pre[p][3];
+      }
+      by = b;
+    }
+    float wy[4];
+    cr_phase(C, num - 2 * C.c * b, wy);
+#pragma unroll
+    for (int p = 0; p < kPB; ++p)
+      d[p] = wy[0] * xr[p][0] + wy[1] * xr[p][1] + wy[2] * xr[p][2] + wy[3] * xr[p][3];
+  };
+  // issue the taps fine row s will need (if it starts a new coarse row)
+  auto prefetch = [&](int s) {
+    const int b = brow_of(s);
+    if (b != by) {
+      const unsigned ro = coarse_row(b + 2);
+#pragma unroll
+      for (int p = 0; p < kPB; ++p)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) pre[p][a] = ld_buf(bz[p], cxo[a], ro);
+    }
+  };
+  float dm2[kPB], dm1[kPB];
+  float chk[kPB];
+#pragma unroll
+  for (int p = 0; p < kPB; ++p) chk[p] = 0.0f;
+  prefetch(k0 - 1);
+  d_at(k0 - 1, dm2);
+  prefetch(k0);
+  d_at(k0, dm1);
+  prefetch(k0 + 1);
+  float sa[3][kPB], sb[3][kPB];
+  auto load_row = [&](int k, float (&st)[3][kPB]) {
+    const unsigned srow = static_cast<unsigned>(k) * brow;
+#pragma unroll
+    for (int p = 0; p < kPB; ++p) {
+      st[0][p] = ld_buf(bs[p], bj, srow);
+      st[1][p] = ld_buf(bs[p], bj, srow + fq);
+      st[2][p] = ld_buf(bs[p], bj, srow + fr);
+    }
+  };
+  load_row(k0, sa);
+  // output row k from state row k (cur); issues the loads of row k + 1 (nxt) first
+  auto body = [&](int k, float (&cur)[3][kPB], float (&nxt)[3][kPB]) {
+    if (k + 1 < k_end) load_row(k + 1, nxt);
+    float d0[kPB];
+    d_at(k + 1, d0);
+    prefetch(k + 2);
+    float ae[kPB], au[kPB], av[kPB];
+#pragma unroll
+    for (int p = 0; p < kPB; ++p) {
+      ae[p] = dm1[p];
+      au[p] = -C.gb_y * (d0[p] - dm2[p]);
+      av[p] = C.gb_x * (__shfl_down(dm1[p], 1, kWave) - __shfl_up(dm1[p], 1, kWave));
+    }
+    const int2 range = rows[k];
+    const int o_beg = range.x, o_end = range.y;
+    for (int t0 = o_beg; t0 < o_end; t0 += kObsBatch) {
+      float w[kObsBatch][6];
+      float su[kObsBatch][kPB], sv[kObsBatch][kPB];
+#pragma unroll
+      for (int u = 0; u < kObsBatch; ++u) {
+        const int4 e = st_ent[t0 + u < o_end ? t0 + u : 0];  // wave-uniform
+        int iy = k - e.y;
+        iy += iy < 0 ? ny : 0;
+        const unsigned rbase = static_cast<unsigned>(iy) * wx24;
+        unsigned off;
+        if (SIMPLE_X) {
+          const unsigned v = lane24 + static_cast<unsigned>(e.w);
+          off = v < wx24 ? rbase + v : zero24;
+        } else {
+          int ix = jw - e.x;
+          ix += ix < 0 ? nx : 0;
+          off = ix < P.wx ? rbase + 24u * static_cast<unsigned>(ix) : zero24;
+        }
+        const float2* c2 = reinterpret_cast<const float2*>(reinterpret_cast<const char*>(lw) + off);
+        const float2 w01 = c2[0], w23 = c2[1], w45 = c2[2];
+        w[u][0] = w01.x;
+        w[u][1] = w01.y;
+        w[u][2] = w23.x;
+        w[u][3] = w23.y;
+        w[u][4] = w45.x;
+        w[u][5] = w45.y;
+        const float* q = reinterpret_cast<const float*>(sdf_g + static_cast<unsigned>(e.z));
+#pragma unroll
+        for (int p = 0; p < kPB; ++p) {
+          su[u][p] = q[2 * p];
+          sv[u][p] = q[2 * p + 1];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kObsBatch; ++u) {
+#pragma unroll
+        for (int p = 0; p < kPB; ++p) {
+          ae[p] = fmaf(sv[u][p], w[u][3], fmaf(su[u][p], w[u][0], ae[p]));
+          au[p] = fmaf(sv[u][p], w[u][4], fmaf(su[u][p], w[u][1], au[p]));
+          av[p] = fmaf(sv[u][p], w[u][5], fmaf(su[u][p], w[u][2], av[p]));
+        }
+      }
+    }
+    const unsigned srow = static_cast<unsigned>(k) * brow;
+#pragma unroll
+    for (int p = 0; p < kPB; ++p) {
+      const float oe = cur[0][p] + ae[p], ou = cur[1][p] + au[p], ov = cur[2][p] + av[p];
+      st_buf(bs[p], bj, srow, oe);
+      st_buf(bs[p], bj, srow + fq, ou);
+      st_buf(bs[p], bj, srow + fr, ov);
+      chk[p] = fmaf(ov, 0.0f, fmaf(ou, 0.0f, fmaf(oe, 0.0f, chk[p])));
+      dm2[p] = dm1[p];
+      dm1[p] = d0[p];
+    }
+  };
+  for (int k = k0; k < k_end; k += 2) {
+    body(k, sa, sb);
+    if (k + 1 < k_end) body(k + 1, sb, sa);
+  }
+#pragma unroll
+  for (int p = 0; p < kPB; ++p) {
+    const bool bad = writer && p < np && !isfinite(chk[p]);
+    if (__ballot(bad) != 0 && lane == 0) {
+      atomicOr(status + 2, kStatNonfiniteState);
+      atomicMin(status + 3, p0 + p);
+    }
+  }
+}
+
 }  // namespace
 
 void launch_normals(float* out, int n, int ne, uint64_t seed, uint64_t step, uint32_t tag,
@@ -374,21 +622,63 @@ void launch_gb_add(const CoarseConst& C, int ne, const float* z, const float* ba
 
 int update_waves_per_cu() {
   int a = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, analysis_update_kernel, 256, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, analysis_update_kernel<true, kWinStride>,
+                                                   256, 0) != hipSuccess)
     return 16;
   return 4 * (a > 0 ? a : 1);
 }
 
 int update_particle_group() { return kPB; }
 
+size_t update_lds_bytes(int wx, int wy) { return 24 * ((size_t)wx * wy + 1); }
+
+int update_lds_waves_per_cu() {
+  int a = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, analysis_update_lds_kernel<true>,
+                                                   kLdsWaves * kWave, 0) != hipSuccess)
+    return 16;
+  return kLdsWaves * (a > 0 ? a : 1);
+}
+
 void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, const float* z,
-                            const float* windows, const float* sdf, const int32_t* st_off,
-                            const int32_t* st_ent, float* psi, double* scal, hipStream_t s) {
+                            const float* windows, const float* wcell, const float* sdf,
+                            const int32_t* st_rows, const int32_t* st_ent, float* psi,
+                            double* scal, hipStream_t s) {
   const int groups = (ne + kPB - 1) / kPB;
   const int total = groups * P.n_strip_x * P.n_strip_y;
-  hipLaunchKernelGGL(analysis_update_kernel, dim3((total + 3) / 4), dim3(256), 0, s, C, P, ne,
-                     sd_float_stride(ne), total, z, psi, windows, sdf, st_off,
-                     reinterpret_cast<const int4*>(st_ent), scal);
+  const int2* rows = reinterpret_cast<const int2*>(st_rows);
+  const int4* ent = reinterpret_cast<const int4*>(st_ent);
+  const int ne4 = sd_float_stride(ne);
+  if (wcell) {
+    const size_t lds = update_lds_bytes(P.wx, P.wy);
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(analysis_update_lds_kernel<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kUpdateLdsMax);
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(analysis_update_lds_kernel<false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kUpdateLdsMax);
+      attr = true;
+    }
+    const dim3 grid((total + kLdsWaves - 1) / kLdsWaves), block(kLdsWaves * kWave);
+    if (P.simple_x)
+      hipLaunchKernelGGL((analysis_update_lds_kernel<true>), grid, block, lds, s, C, P, ne, ne4,
+                         total, z, psi, wcell, sdf, rows, ent, scal);
+    else
+      hipLaunchKernelGGL((analysis_update_lds_kernel<false>), grid, block, lds, s, C, P, ne, ne4,
+                         total, z, psi, wcell, sdf, rows, ent, scal);
+    return;
+  }
+  const dim3 grid((total + 3) / 4), block(256);
+  const bool fixed = P.ws == kWinStride;
+  if (P.simple_x && fixed)
+    hipLaunchKernelGGL((analysis_update_kernel<true, kWinStride>), grid, block, 0, s, C, P, ne, ne4,
+                       total, z, psi, windows, sdf, rows, ent, scal);
+  else if (fixed)
+    hipLaunchKernelGGL((analysis_update_kernel<false, kWinStride>), grid, block, 0, s, C, P, ne,
+                       ne4, total, z, psi, windows, sdf, rows, ent, scal);
+  else
+    hipLaunchKernelGGL((analysis_update_kernel<false, 0>), grid, block, 0, s, C, P, ne, ne4, total,
+                       z, psi, windows, sdf, rows, ent, scal);
 }
 
 }  // namespace iewpf
