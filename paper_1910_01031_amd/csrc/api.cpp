@@ -848,8 +848,11 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
     c->use_lds = update_lds_bytes(c->wx, c->wy) <= kUpdateLdsMax && env_int("IEWPF_UPD_LDS", 1) != 0;
     const int slots =
         device_slots(c->use_lds ? update_lds_waves_per_cu() : update_waves_per_cu());
-    const int n_ys = forced > 0 ? (f.ny + forced - 1) / forced
-                                : choose_row_strips(nsx * groups, f.ny, slots, 2, 4);
+    int n_ys = forced > 0 ? (f.ny + forced - 1) / forced
+                          : choose_row_strips(nsx * groups, f.ny, slots, 2, 4);
+    // staged windows: strips of at most 8 rows (6-8 measured fastest for 100 particles on
+    // 500x300, 12 % ahead of one launch round of 17-row strips)
+    if (forced <= 0 && c->use_lds) n_ys = std::max(n_ys, (f.ny + 7) / 8);
     c->upd_strip_h = (f.ny + n_ys - 1) / n_ys;
     c->gb_strip_h = std::max(1, std::min(f.ny, env_int("IEWPF_GB_STRIP", 6)));
     c->n_upd_cols = nsx;
@@ -873,7 +876,7 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
   rc |= dev_alloc(&c->me_xi, (size_t)c->me_chunk * c->ne * c->nr);
   rc |= dev_alloc(&c->me_coarse, (size_t)c->me_chunk * c->ne * c->nr);
   rc |= dev_alloc(&c->windows, (size_t)c->wy * 6 * c->ws);
-  if (c->use_lds) rc |= dev_alloc(&c->wcell, (size_t)c->wy * 6 * c->wx);
+  if (c->use_lds) rc |= dev_alloc(&c->wcell, 4 * (size_t)update_lds_float4s(c->wx, c->wy));
   rc |= dev_alloc(&c->dmat, (size_t)kBlockN * kBlockN);
   rc |= dev_alloc(&c->sd, (size_t)c->ne * c->max_obs * 2);
   rc |= dev_alloc(&c->vblk, (size_t)c->ne * std::max(1, c->max_obs) * kBlockN);
@@ -930,7 +933,8 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
       for (int ix = 0; ix < c->wx; ++ix)
         winf[((size_t)iy * 6 + fld) * c->ws + ix] =
             (float)win[((size_t)fld * c->wy + iy) * c->wx + ix];
-  std::vector<float> wcf(c->wcell ? (size_t)c->wy * c->wx * 6 : 0);
+  // cell-major copy staged in LDS by the update: the cells, one zero cell, zero padding
+  std::vector<float> wcf(c->wcell ? 4 * (size_t)update_lds_float4s(c->wx, c->wy) : 0, 0.0f);
   if (c->wcell)
     for (int fld = 0; fld < 6; ++fld)
       for (int iy = 0; iy < c->wy; ++iy)

@@ -283,6 +283,11 @@ void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, co
 // LDS of the staged-window update (two workgroups fit one compute unit up to this size)
 constexpr size_t kUpdateLdsMax = 80 * 1024;
 size_t update_lds_bytes(int wx, int wy);
+// cell-major windows plus one zero cell in float4s, padded to whole 64-float4 chunks (the
+// device copy has this length)
+__host__ __device__ inline int update_lds_float4s(int wx, int wy) {
+  return ((6 * (wx * wy + 1) + 3) / 4 + 63) / 64 * 64;
+}
 int update_lds_waves_per_cu();
 // c_i = out_scale * sum_o d^T S d (out_scale = -1/2 and S = R^{-1} give the log-weights of
 // the standard particle filter); sdf (may be null) receives S d in float32, observation-major

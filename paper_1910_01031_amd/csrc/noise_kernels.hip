@@ -371,10 +371,20 @@ __global__ __launch_bounds__(256, 5) void analysis_update_kernel(
 // wait only on the LDS counter, so the state rows can be loaded one row ahead and the coarse
 // rows of the random part one fine row ahead without the observation loop waiting on them;
 // the arithmetic is that of analysis_update_kernel, in the same order.
-constexpr int kLdsWaves = 8;
+#ifndef IEWPF_UPD_LDS_WAVES
+#define IEWPF_UPD_LDS_WAVES 8
+#endif
+#ifndef IEWPF_UPD_LDS_OCC
+#define IEWPF_UPD_LDS_OCC 4
+#endif
+constexpr int kLdsWaves = IEWPF_UPD_LDS_WAVES;
+#ifndef IEWPF_UPD_DEPTH
+#define IEWPF_UPD_DEPTH 1
+#endif
+constexpr int kUpdDepth = IEWPF_UPD_DEPTH;  // state rows loaded ahead
 
 template <bool SIMPLE_X>
-__global__ __launch_bounds__(kLdsWaves * kWave, 4) void analysis_update_lds_kernel(
+__global__ __launch_bounds__(kLdsWaves * kWave, IEWPF_UPD_LDS_OCC) void analysis_update_lds_kernel(
     CoarseConst C, PullConst P, int ne, int ne4, int total_waves, const float* __restrict__ zall,
     float* __restrict__ psi, const float* __restrict__ wcell, const float* __restrict__ sdf,
     const int2* __restrict__ st_rows, const int4* __restrict__ st_ent,
@@ -384,10 +394,15 @@ __global__ __launch_bounds__(kLdsWaves * kWave, 4) void analysis_update_lds_kern
   if (status[0] & kStatSkipUpdate) return;  // the same for every workgroup
   const int ncw = P.wx * P.wy;
   {
-    const float2* src = reinterpret_cast<const float2*>(wcell);
-    float2* dst = reinterpret_cast<float2*>(lw);
-    for (int i = threadIdx.x; i < 3 * ncw; i += blockDim.x) dst[i] = src[i];
-    if (threadIdx.x < 6) lw[6 * ncw + threadIdx.x] = 0.0f;
+    // stage the windows (padded to whole 1 KB chunks) with LDS-direct loads: each lane of a
+    // wave moves 16 bytes of a chunk straight into LDS, lane l to byte 16 l of the chunk
+    const int n4 = update_lds_float4s(P.wx, P.wy);
+    const float4* src = reinterpret_cast<const float4*>(wcell) + (threadIdx.x & (kWave - 1));
+    for (int ch = threadIdx.x / kWave; ch * kWave < n4; ch += kLdsWaves)
+      __builtin_amdgcn_global_load_lds(
+          (__attribute__((address_space(1))) void*)(const_cast<float4*>(src + ch * kWave)),
+          (__attribute__((address_space(3))) void*)(lw + ch * 4 * kWave), 16, 0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
   }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
@@ -442,8 +457,8 @@ __global__ __launch_bounds__(kLdsWaves * kWave, 4) void analysis_update_lds_kern
   const int k_end = min(k0 + P.strip_h, ny);
   const int2* rows = st_rows + (size_t)sx * ny;
 
-  // x-interpolated coarse rows by-1 .. by+2 around fine row s (as CoarseWin), the raw taps of
-  // the next coarse row when one is pending
+  // x-interpolated coarse rows by-1 .. by+2 around fine row s (as CoarseWin) and the raw taps
+  // of row by+3, loaded as soon as the previous row moved in (a coarse period ahead)
   float xr[kPB][4];
   float pre[kPB][4];
   int by = brow_of(k0 - 1);
@@ -457,8 +472,15 @@ __global__ __launch_bounds__(kLdsWaves * kWave, 4) void analysis_update_lds_kern
       for (int a = 0; a < 4; ++a) v[a] = ld_buf(bz[p], cxo[a], ro);
       xr[p][n] = wxw[0] * v[0] + wxw[1] * v[1] + wxw[2] * v[2] + wxw[3] * v[3];
     }
-  // d at fine row s; the caller has issued the taps of row brow_of(s) + 2 into pre when
-  // brow_of(s) moves past by
+  auto load_next_coarse = [&]() {
+    const unsigned ro = coarse_row(by + 3);
+#pragma unroll
+    for (int p = 0; p < kPB; ++p)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) pre[p][a] = ld_buf(bz[p], cxo[a], ro);
+  };
+  load_next_coarse();
+  // d at fine row s (s increasing by one per call)
   auto d_at = [&](int s, float (&d)[kPB]) {
     const int num = 2 * s + 1 - C.c;
     const int b = floordiv(num, 2 * C.c);
@@ -471,6 +493,7 @@ __global__ __launch_bounds__(kLdsWaves * kWave, 4) void analysis_update_lds_kern
         xr[p][3] = wxw[0] * pre[p][0] + wxw[1] * pre[p][1] + wxw[2] * pre[p][2] + wxw[3] * pre[p][3];
       }
       by = b;
+      load_next_coarse();
     }
     float wy[4];
     cr_phase(C, num - 2 * C.c * b, wy);
@@ -478,43 +501,31 @@ __global__ __launch_bounds__(kLdsWaves * kWave, 4) void analysis_update_lds_kern
     for (int p = 0; p < kPB; ++p)
       d[p] = wy[0] * xr[p][0] + wy[1] * xr[p][1] + wy[2] * xr[p][2] + wy[3] * xr[p][3];
   };
-  // issue the taps fine row s will need (if it starts a new coarse row)
-  auto prefetch = [&](int s) {
-    const int b = brow_of(s);
-    if (b != by) {
-      const unsigned ro = coarse_row(b + 2);
-#pragma unroll
-      for (int p = 0; p < kPB; ++p)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) pre[p][a] = ld_buf(bz[p], cxo[a], ro);
-    }
-  };
   float dm2[kPB], dm1[kPB];
   float chk[kPB];
 #pragma unroll
   for (int p = 0; p < kPB; ++p) chk[p] = 0.0f;
-  prefetch(k0 - 1);
   d_at(k0 - 1, dm2);
-  prefetch(k0);
   d_at(k0, dm1);
-  prefetch(k0 + 1);
-  float sa[3][kPB], sb[3][kPB];
-  auto load_row = [&](int k, float (&st)[3][kPB]) {
+  // state rows kUpdDepth rows ahead in a ring of kUpdDepth + 1 rows
+  float st[kUpdDepth + 1][3][kPB];
+  auto load_row = [&](int k, float (&sr)[3][kPB]) {
     const unsigned srow = static_cast<unsigned>(k) * brow;
 #pragma unroll
     for (int p = 0; p < kPB; ++p) {
-      st[0][p] = ld_buf(bs[p], bj, srow);
-      st[1][p] = ld_buf(bs[p], bj, srow + fq);
-      st[2][p] = ld_buf(bs[p], bj, srow + fr);
+      sr[0][p] = ld_buf(bs[p], bj, srow);
+      sr[1][p] = ld_buf(bs[p], bj, srow + fq);
+      sr[2][p] = ld_buf(bs[p], bj, srow + fr);
     }
   };
-  load_row(k0, sa);
-  // output row k from state row k (cur); issues the loads of row k + 1 (nxt) first
-  auto body = [&](int k, float (&cur)[3][kPB], float (&nxt)[3][kPB]) {
-    if (k + 1 < k_end) load_row(k + 1, nxt);
+#pragma unroll
+  for (int u = 0; u < kUpdDepth; ++u)
+    if (k0 + u < k_end) load_row(k0 + u, st[u]);
+  // output row k from state row k (cur); issues the loads of row k + kUpdDepth (ahead) first
+  auto body = [&](int k, float (&cur)[3][kPB], float (&ahead)[3][kPB]) {
+    if (k + kUpdDepth < k_end) load_row(k + kUpdDepth, ahead);
     float d0[kPB];
     d_at(k + 1, d0);
-    prefetch(k + 2);
     float ae[kPB], au[kPB], av[kPB];
 #pragma unroll
     for (int p = 0; p < kPB; ++p) {
@@ -579,9 +590,10 @@ __global__ __launch_bounds__(kLdsWaves * kWave, 4) void analysis_update_lds_kern
       dm1[p] = d0[p];
     }
   };
-  for (int k = k0; k < k_end; k += 2) {
-    body(k, sa, sb);
-    if (k + 1 < k_end) body(k + 1, sb, sa);
+  for (int kb = k0; kb < k_end; kb += kUpdDepth + 1) {
+#pragma unroll
+    for (int u = 0; u <= kUpdDepth; ++u)
+      if (kb + u < k_end) body(kb + u, st[u], st[(u + kUpdDepth) % (kUpdDepth + 1)]);
   }
 #pragma unroll
   for (int p = 0; p < kPB; ++p) {
@@ -630,7 +642,7 @@ int update_waves_per_cu() {
 
 int update_particle_group() { return kPB; }
 
-size_t update_lds_bytes(int wx, int wy) { return 24 * ((size_t)wx * wy + 1); }
+size_t update_lds_bytes(int wx, int wy) { return 16 * (size_t)update_lds_float4s(wx, wy); }
 
 int update_lds_waves_per_cu() {
   int a = 0;
