@@ -549,9 +549,25 @@ def main():
     torch.cuda.synchronize()
     tr = ctx.trace_read()
     ctx.set_trace(False)
-    analysis_ms = sum(tr[k][0] for k in ("innovation", "rand_dots", "beta_alpha",
-                                         "posterior_coarse", "analysis_update")) / args.steps
-    analysis_ms += tr["soar"][0] / max(tr["soar"][1], 1)  # one of the SOAR launches per cycle
+    stage_sum_ms = sum(tr[k][0] for k in ("innovation", "rand_dots", "beta_alpha",
+                                          "posterior_coarse", "analysis_update")) / args.steps
+    stage_sum_ms += tr["soar"][0] / max(tr["soar"][1], 1)  # one of the SOAR launches per cycle
+    # ms per analysis: one event pair around consecutive whole analyses (observation upload
+    # included, no per-stage events between the kernels), repeated on the last forecast
+    saved = ens.clone()
+    reps = 10
+    a0 = torch.cuda.Event(enable_timing=True)
+    a1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a0.record()
+    for r in range(reps):
+        ctx.assimilate(ens, cells, None, analysis_index=n_cycles + r, want_stats=False,
+                       obs=obs[-1])
+    a1.record()
+    torch.cuda.synchronize()
+    analysis_ms = a0.elapsed_time(a1) / reps
+    ens.copy_(saved)
+    del saved
     plain_ms = tr["scheme_step"][0] / max(tr["scheme_step"][1], 1)
     launch_cells = cfg.n_particles * cfg.nx * cfg.ny
     bytes_per_launch = BYTES_PER_CELL_STEP * launch_cells
@@ -589,6 +605,7 @@ def main():
                    "nx": cfg.nx, "ny": cfg.ny, "particles": cfg.n_particles,
                    "buoys": int(len(cells)), "scheme_steps_per_cycle": cfg.n_sub * steps_per_cycle},
         "iewpf_ms_per_analysis": analysis_ms,
+        "analysis_stage_event_sum_ms": stage_sum_ms,
         "analysis_stats_last": {"beta": last["beta"], "cbar": last["cbar"],
                                 "alpha_min": last["alpha_min"], "alpha_max": last["alpha_max"]},
         "state_finite": finite,

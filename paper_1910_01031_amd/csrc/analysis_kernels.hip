@@ -301,15 +301,24 @@ __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, do
   __shared__ double sh[kWavesPerBlock];
   __shared__ double shb[kWavesPerBlock];
   __shared__ int shi[kWavesPerBlock];
+  __shared__ double sh6[6][kWavesPerBlock];
   // the draws' dot products: the parts of each particle added in the fixed order q = 0..
   // (each thread sums and later reads only its own particles)
   for (int i = threadIdx.x; i < ne; i += kThreads) {
+    // all parts loaded before the sums (parts <= kDotParts; the missing ones add +0)
+    const double* o = part_dots + (size_t)i * parts * 3;
+    double v[kDotParts][3];
+#pragma unroll
+    for (int q = 0; q < kDotParts; ++q)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) v[q][r] = o[3 * min(q, parts - 1) + r];
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int q = 0; q < parts; ++q) {
-      const double* o = part_dots + ((size_t)i * parts + q) * 3;
-      a += o[0];
-      b += o[1];
-      c += o[2];
+#pragma unroll
+    for (int q = 0; q < kDotParts; ++q) {
+      const bool in = q < parts;
+      a += in ? v[q][0] : 0.0;
+      b += in ? v[q][1] : 0.0;
+      c += in ? v[q][2] : 0.0;
     }
     dots[3 * i] = a;
     dots[3 * i + 1] = b;
@@ -376,11 +385,21 @@ __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, do
                         isfinite(a);
     if (!finite) first_bad = fmin(first_bad, (double)i);
   }
-  // min / max reductions (order independent)
-  const double vals[6] = {amin, -amax, -csmax, cmin, -cmax, first_bad};
-  double outv[6];
+  // min / max reductions (order independent), all six in one exchange through LDS
+  double outv[6] = {amin, -amax, -csmax, cmin, -cmax, first_bad};
 #pragma unroll
-  for (int q = 0; q < 6; ++q) outv[q] = block_min(vals[q], sh);
+  for (int q = 0; q < 6; ++q) outv[q] = wave_min(outv[q]);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sh6[q][threadIdx.x >> 6] = outv[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    double r = sh6[q][0];
+#pragma unroll
+    for (int w = 1; w < kWavesPerBlock; ++w) r = fmin(r, sh6[q][w]);
+    outv[q] = r;
+  }
   if (threadIdx.x == 0) {
     // status words read by the posterior and update kernels (which write nothing when an
     // error bit is set) and by the host after the analysis
