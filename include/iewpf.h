@@ -344,9 +344,17 @@ int iewpf_net_train_step(iewpf_net* net, const float* x, const float* target, in
 /* Input of hidden layer `layer` (1..5) from the last forward or training call: BF16 bits
  * (round to nearest even of the ReLU output of layer `layer`-1), NHWC [cells][48], copied to
  * host uint16 [count]; count must equal 48 * cells of that call.  Waits for the stream.
- * For inspection and testing of the mixed-precision forward pass. */
+ * For inspection and testing of the mixed-precision forward pass.  iewpf_net_forward runs
+ * layers 0 and 1 as one fused pass and does not keep the input of layer 1; reading it after
+ * such a forward returns IEWPF_E_ARG unless iewpf_net_keep_activations set the
+ * layer-by-layer forward.  Training and gradient calls keep every layer. */
 int iewpf_net_read_activation(iewpf_net* net, int layer, uint16_t* host, size_t count,
                               void* stream);
+/* keep != 0: iewpf_net_forward runs layer by layer and writes every hidden activation to
+ * device memory (for iewpf_net_read_activation); 0 (the default): layers 0 and 1 fused, so
+ * layer 0's activation (1.44 GB of BF16 at 100 x 500x300 cells) stays on chip; the output is
+ * bit-identical.  IEWPF_E_ARG for a NULL net. */
+int iewpf_net_keep_activations(iewpf_net* net, int keep);
 /* Loss gradient with respect to every parameter (host float [num_params]), without an
  * update; also the loss and the raw network output y (host float [B*H*W][3], NHWC, or
  * NULL).  Keeps every layer's pre-activation gradient for iewpf_net_read_gradient_signal

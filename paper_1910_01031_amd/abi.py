@@ -35,6 +35,7 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_net_create", "iewpf_net_destroy", "iewpf_net_num_params",
             "iewpf_net_set_params", "iewpf_net_get_params", "iewpf_net_set_norm",
             "iewpf_net_forward", "iewpf_net_train_step", "iewpf_net_read_activation",
+            "iewpf_net_keep_activations",
             "iewpf_net_gradients",
             "iewpf_surrogate_window", "iewpf_forecast_drifters_surrogate",
             "iewpf_set_full_innovation", "iewpf_set_scheme", "iewpf_last_error",
@@ -132,6 +133,7 @@ def load(path: str = LIB_PATH):
     lib.iewpf_net_train_step.argtypes = [vp, vp, vp, i32, i32, i32, ctypes.c_float,
                                          ctypes.POINTER(ctypes.c_float), vp]
     lib.iewpf_net_read_activation.argtypes = [vp, i32, vp, ctypes.c_size_t, vp]
+    lib.iewpf_net_keep_activations.argtypes = [vp, i32]
     lib.iewpf_net_gradients.argtypes = [vp, vp, vp, i32, i32, i32, vp,
                                         ctypes.POINTER(ctypes.c_float), vp, vp]
     lib.iewpf_surrogate_window.argtypes = [vp, vp, vp, i32, u64, ctypes.c_double,
@@ -444,6 +446,10 @@ class Net:
                                            ctypes.byref(loss) if want_loss else None,
                                            _stream(stream)))
         return loss.value if want_loss else None
+
+    def keep_activations(self, keep: bool = True) -> None:
+        """Forward layer by layer, keeping every hidden activation (default: fused pairs)."""
+        _check(load().iewpf_net_keep_activations(self.h, 1 if keep else 0))
 
     def read_activation(self, layer: int, cells: int, stream=None) -> np.ndarray:
         """BF16 bits (uint16 [cells][48]) of the input of hidden layer `layer` (1..5)."""

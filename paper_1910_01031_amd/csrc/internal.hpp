@@ -218,6 +218,10 @@ struct ConvArgs {
   float mu[3], isig[3], s[3];
 };
 void launch_conv(const ConvArgs& A, int in_mode, int out_mode, hipStream_t s);
+// Two consecutive layers in one pass (A: -> 48 channels with ReLU, B: 48 -> ...); false when
+// the shapes have no fused kernel (the caller then runs them one by one).
+bool launch_conv_pair(const ConvArgs& LA, int in_mode, const ConvArgs& LB, int out_mode,
+                      hipStream_t s);
 int net_max_cells(const iewpf_net* n);
 int net_horizon(const iewpf_net* n);
 void launch_wgrad(const ConvArgs& A, int in_mode, const uint16_t* g, int gch, int cells_per_chunk,

@@ -44,6 +44,8 @@ struct iewpf_net {
   int loss_blocks = 256;
   float mu[3] = {0, 0, 0}, sig[3] = {1, 1, 1}, s[3] = {1, 1, 1};
   int horizon = 10;  // model steps one application of the network stands in for
+  int keep_act = 0;  // forward layer by layer, every hidden activation to HBM (inspection)
+  unsigned act_valid = 0;  // bit L: act[L] holds the last call's input of layer L
   // pre-activation gradients of layers 0..4 kept by iewpf_net_gradients ([cells][48] BF16
   // each, allocated on its first call for that call's cells); layer 5's is g5
   uint16_t* gkeep[kLayers - 1] = {};
@@ -100,6 +102,32 @@ void forward_hidden(iewpf_net* n, const float* state, int B, int H, int W, hipSt
     A.out = n->act[L + 1];
     launch_conv(A, L == 0 ? kInStateNorm : kInNhwcVec, kOutReluBf16, s);
   }
+  n->act_valid = 0x3Eu;  // layers 1..5
+}
+
+// Inference forward with layers 0 and 1 fused (layer 0's activation stays on chip), then
+// layers 2..5 one by one.  Returns false (nothing launched) when the first pair has no fused
+// kernel.
+bool forward_fused(iewpf_net* n, const float* state_in, float* state_out, int B, int H, int W,
+                   hipStream_t s) {
+  ConvArgs L0 = conv_args(n, 0, B, H, W), L1 = conv_args(n, 1, B, H, W);
+  L0.in = state_in;
+  L1.out = n->act[2];
+  if (!launch_conv_pair(L0, kInStateNorm, L1, kOutReluBf16, s)) return false;
+  for (int L = 2; L < 5; ++L) {
+    ConvArgs A = conv_args(n, L, B, H, W);
+    A.in = n->act[L];
+    A.out = n->act[L + 1];
+    launch_conv(A, kInNhwcVec, kOutReluBf16, s);
+  }
+  ConvArgs L5 = conv_args(n, 5, B, H, W);
+  L5.in = n->act[5];
+  L5.out = state_out;
+  L5.state_in = state_in;
+  launch_conv(L5, kInNhwcVec, kOutResidState, s);
+  n->last_cells = (long long)B * H * W;
+  n->act_valid = 0x3Cu;  // layers 2..5
+  return true;
 }
 
 void prep_all(iewpf_net* n, hipStream_t s) {
@@ -284,13 +312,21 @@ int iewpf_net_forward(iewpf_net* n, const float* state_in, float* state_out, int
   if (!n || !state_in || !state_out || B <= 0 || H < 1 || W < 1) return fail(IEWPF_E_ARG, "invalid argument");
   if ((long long)B * H * W > n->max_cells) return fail(IEWPF_E_CAPACITY, "more cells than max_cells");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  forward_hidden(n, state_in, B, H, W, s);
-  ConvArgs A5 = conv_args(n, 5, B, H, W);
-  A5.in = n->act[5];
-  A5.out = state_out;
-  A5.state_in = state_in;
-  launch_conv(A5, kInNhwcVec, kOutResidState, s);
+  if (n->keep_act || !forward_fused(n, state_in, state_out, B, H, W, s)) {
+    forward_hidden(n, state_in, B, H, W, s);
+    ConvArgs A5 = conv_args(n, 5, B, H, W);
+    A5.in = n->act[5];
+    A5.out = state_out;
+    A5.state_in = state_in;
+    launch_conv(A5, kInNhwcVec, kOutResidState, s);
+  }
   IEWPF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int iewpf_net_keep_activations(iewpf_net* n, int keep) {
+  if (!n) return fail(IEWPF_E_ARG, "invalid argument");
+  n->keep_act = keep != 0;
   return 0;
 }
 
@@ -320,6 +356,9 @@ int iewpf_net_read_activation(iewpf_net* n, int layer, uint16_t* host, size_t co
   if (!n || !host || layer < 1 || layer > 5) return fail(IEWPF_E_ARG, "invalid argument");
   if (count != (size_t)48 * n->last_cells || n->last_cells == 0)
     return fail(IEWPF_E_ARG, "count must be 48 x the cells of the last call");
+  if (!(n->act_valid >> layer & 1u))
+    return fail(IEWPF_E_ARG, "the last forward kept no input of layer " + std::to_string(layer) +
+                                 " (fused layer pairs); call iewpf_net_keep_activations first");
   IEWPF_HIP_TRY(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
   IEWPF_HIP_TRY(hipMemcpy(host, n->act[layer], count * 2, hipMemcpyDeviceToHost));
   return 0;

@@ -306,12 +306,13 @@ __device__ __forceinline__ void lane_bias(const ConvArgs& A, int kq, float (&bia
 template <int NT, int OUT, int kTM>
 __device__ __forceinline__ void tile_store(const ConvArgs& A, const f32x4 (&acc)[NT][kTM],
                                            const float (&bias)[NT][4], int b, int y, int x0,
-                                           int row, int kq) {
-  // lane: pixel x0 + 16 m + row, channels 16 q + 4 kq .. + 3
+                                           int row, int kq, int cols = 16 * kTM) {
+  // lane: pixel x0 + 16 m + row, channels 16 q + 4 kq .. + 3; only the tile's first `cols`
+  // columns are stored
 #pragma unroll
   for (int m = 0; m < kTM; ++m) {
     const int x = x0 + m * 16 + row;
-    if (x >= A.W) continue;
+    if (x >= A.W || m * 16 + row >= cols) continue;
     const size_t cell = ((size_t)b * A.H + y) * A.W + x;
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
@@ -453,6 +454,157 @@ __global__ __launch_bounds__(64 * kTH) void conv_tile_kernel(ConvArgs A, int nti
     }
     if (tn < ntiles) fetch(tn);  // in flight during the MFMAs below
     if (t >= 0) compute(tile, t);
+  }
+}
+
+// Two consecutive layers in one pass (forward only): layer A (C_in -> 48, ReLU, BF16) over a
+// (kPairTH + 2) x 32 region into an LDS tile, then layer B (48 -> 16 NT_B) over the kPairTH x
+// kPairTW output tile from it, so A's activation never goes to HBM.  Both layers use
+// tile_mfma (the same fragments, K order and accumulation as the one-layer kernel) and the
+// same epilogue arithmetic, so the outputs equal the layer-by-layer pass bit for bit.
+// Geometry: input tile (kPairTH + 4) x 34 pixels from (y0 - 2, x0 - 2), intermediate tile
+// (kPairTH + 2) rows x 34 pixels (32 written; the two past them feed only output columns 30
+// and 31, which are computed and dropped), output tile kPairTH x kPairTW (wave w computes
+// intermediate row w, then output row w for w < kPairTH).
+constexpr int kPairTW = 30, kPairCols = 32;
+
+template <int CIN, int NT>
+__device__ __forceinline__ void weights_to_lds(const ConvArgs& A, uint16_t* wl, int nthreads) {
+  using G = TileGeom<CIN>;
+  for (int i = threadIdx.x; i < NT * 16 * (G::KW / 8); i += nthreads) {
+    const int n = i / (G::KW / 8), kv = i - n * (G::KW / 8);
+    uint4 v;
+    if (CIN == 48) {
+      v = *reinterpret_cast<const uint4*>(A.wt + (size_t)n * A.Kpad + kv * 8);
+    } else {  // kv = tap; stored layout k = 3 tap + c
+      uint32_t e0 = 0, e1 = 0;
+      if (kv < 9) {
+        const uint16_t* src = A.wt + (size_t)n * A.Kpad + kv * 3;
+        e0 = (uint32_t)src[0] | ((uint32_t)src[1] << 16);
+        e1 = (uint32_t)src[2];
+      }
+      v = make_uint4(e0, e1, 0u, 0u);
+    }
+    *reinterpret_cast<uint4*>(wl + n * G::WS + kv * 8) = v;
+  }
+}
+
+template <int CIN_A, int kPairTH>
+constexpr int pair_lds_bytes(int nt_b) {
+  return 2 * ((kPairTH + 4) * (kPairCols + 2) * TileGeom<CIN_A>::CP +
+              (kPairTH + 2) * (kPairCols + 2) * 48 + 48 * TileGeom<CIN_A>::WS +
+              nt_b * 16 * TileGeom<48>::WS);
+}
+
+template <int CIN_A, int IN_A, int NT_B, int OUT_B, int kPairTH>
+__global__ __launch_bounds__(64 * (kPairTH + 2)) void conv_pair_kernel(ConvArgs LA, ConvArgs LB,
+                                                                       int ntiles) {
+  constexpr int kPairThreads = 64 * (kPairTH + 2);
+  using GA = TileGeom<CIN_A>;
+  using GB = TileGeom<48>;
+  constexpr int kInW = kPairCols + 2;                   // 34 pixels per tile row
+  constexpr int kInPix = (kPairTH + 4) * kInW;
+  extern __shared__ __align__(16) uint16_t lds[];
+  uint16_t* tin = lds;                                  // [(TH + 4) * 34][CP_A]
+  uint16_t* tmid = tin + kInPix * GA::CP;               // [(TH + 2) * 34][48]
+  uint16_t* wa = tmid + (kPairTH + 2) * kInW * 48;      // [48][WS_A]
+  uint16_t* wb = wa + 48 * GA::WS;                      // [16 NT_B][WS_B]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, kq = lane >> 4;
+  weights_to_lds<CIN_A, 3>(LA, wa, kPairThreads);
+  weights_to_lds<48, NT_B>(LB, wb, kPairThreads);
+  const int xt = (LB.W + kPairTW - 1) / kPairTW, yt = (LB.H + kPairTH - 1) / kPairTH;
+  float bias_a[3][4], bias_b[NT_B][4];
+  lane_bias<3>(LA, kq, bias_a);
+  lane_bias<NT_B>(LB, kq, bias_b);
+
+  constexpr int kVecs = IN_A == kInStateNorm ? kInPix : kInPix * GA::VPP;
+  constexpr int kPer = (kVecs + kPairThreads - 1) / kPairThreads;
+  u32x4 pre[IN_A == kInStateNorm ? 1 : kPer];
+  float pf[IN_A == kInStateNorm ? kPer : 1][3];
+  auto origin = [&](int t, int& b, int& y0, int& x0) {
+    b = t / (yt * xt);
+    const int r = t - b * yt * xt;
+    y0 = (r / xt) * kPairTH;
+    x0 = (r - (r / xt) * xt) * kPairTW;
+  };
+  auto fetch = [&](int tn) {  // tile tn's input (rows y0 - 2 .., columns x0 - 2 ..) -> registers
+    int b, y0, x0;
+    origin(tn, b, y0, x0);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int v = threadIdx.x + i * kPairThreads;
+      if (v < kVecs) {
+        if (IN_A == kInStateNorm) {
+          const int rr = v / kInW, cc = v - rr * kInW;
+          const int ys = wrapm(y0 - 2 + rr, LA.H), xs = wrapm(x0 - 2 + cc, LA.W);
+          const size_t plane = (size_t)LA.H * LA.W;
+          const float* st = static_cast<const float*>(LA.in) + (size_t)b * 3 * plane + (size_t)ys * LA.W + xs;
+          pf[i][0] = st[0];
+          pf[i][1] = st[plane];
+          pf[i][2] = st[2 * plane];
+        } else {
+          const int pix = v / GA::VPP, cv = v - pix * GA::VPP;
+          const int rr = pix / kInW, cc = pix - rr * kInW;
+          const int ys = wrapm(y0 - 2 + rr, LA.H), xs = wrapm(x0 - 2 + cc, LA.W);
+          pre[i] = *reinterpret_cast<const u32x4*>(static_cast<const uint16_t*>(LA.in) +
+                                                   (((size_t)b * LA.H + ys) * LA.W + xs) * CIN_A + cv * 8);
+        }
+      }
+    }
+  };
+  auto commit = [&]() {  // registers -> LDS input tile
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int v = threadIdx.x + i * kPairThreads;
+      if (v < kVecs) {
+        if (IN_A == kInStateNorm) {
+          uint32_t h[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) h[c] = f2bf((pf[i][c] - LA.mu[c]) * LA.isig[c]);
+          *reinterpret_cast<uint4*>(tin + v * GA::CP) = make_uint4(h[0] | (h[1] << 16), h[2], 0u, 0u);
+        } else {
+          const int pix = v / GA::VPP, cv = v - pix * GA::VPP;
+          *reinterpret_cast<u32x4*>(tin + pix * GA::CP + cv * 8) = pre[i];
+        }
+      }
+    }
+  };
+  auto compute = [&](int t) {
+    int b, y0, x0;
+    origin(t, b, y0, x0);
+    {  // layer A: intermediate row `wave` (global row y0 - 1 + wave, wrapped), 32 columns
+      f32x4 acc[3][2];
+      tile_mfma<CIN_A, 3, kPairCols>(tin, wa, wave, row, kq, acc);
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const int n0 = q * 16 + kq * 4;
+          uint32_t h[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) h[e] = f2bf(fmaxf(acc[q][m][e] + bias_a[q][e], 0.0f));
+          *reinterpret_cast<uint2*>(tmid + (wave * kInW + m * 16 + row) * 48 + n0) =
+              make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+        }
+    }
+    __syncthreads();
+    const int y = y0 + wave;
+    if (wave < kPairTH && y < LB.H) {  // layer B: output row `wave`, columns x0 .. x0 + 29
+      f32x4 acc[NT_B][2];
+      tile_mfma<48, NT_B, kPairCols>(tmid, wb, wave, row, kq, acc);
+      tile_store<NT_B, OUT_B, 2>(LB, acc, bias_b, b, y, x0, row, kq, kPairTW);
+    }
+  };
+  for (int t = (int)blockIdx.x - (int)gridDim.x; t < ntiles; t += gridDim.x) {
+    const int tn = t + (int)gridDim.x;
+    if (t >= 0) {  // uniform across the workgroup
+      __syncthreads();  // weights written / the previous tile's LDS reads are done
+      commit();
+      __syncthreads();
+    }
+    if (tn < ntiles) fetch(tn);  // in flight during the MFMAs below
+    if (t >= 0) compute(t);
   }
 }
 
@@ -753,6 +905,42 @@ void launch_conv(const ConvArgs& A, int in_mode, int out_mode, hipStream_t s) {
   IEWPF_CONV_CASE(kInNhwcVec, kOutMaskBf16, 3)
   IEWPF_CONV_CASE(kInNhwcSmall, kOutMaskBf16, 3)
 #undef IEWPF_CONV_CASE
+}
+
+template <int CIN_A, int IN_A, int NT_B, int OUT_B, int kPairTH>
+void launch_pair_t(const ConvArgs& LA, const ConvArgs& LB, hipStream_t s) {
+  constexpr int bytes = pair_lds_bytes<CIN_A, kPairTH>(NT_B);
+  constexpr int kPairThreads = 64 * (kPairTH + 2);
+  static_assert(bytes <= 160 * 1024, "the pair's tiles and weights exceed the LDS");
+  auto* kern = conv_pair_kernel<CIN_A, IN_A, NT_B, OUT_B, kPairTH>;
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(kern),
+                                                     kPairThreads, bytes) != hipSuccess || n < 1)
+      n = 1;
+    per_cu = n;
+  }
+  const int ntiles = LB.B * ((LB.H + kPairTH - 1) / kPairTH) * ((LB.W + kPairTW - 1) / kPairTW);
+  const int nb = ntiles < per_cu * cu_count() ? ntiles : per_cu * cu_count();
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(kPairThreads), bytes, s, LA, LB, ntiles);
+}
+
+bool launch_conv_pair(const ConvArgs& LA, int in_mode, const ConvArgs& LB, int out_mode,
+                      hipStream_t s) {
+  // Only the first pair (state -> 48 -> 48) has a fused kernel: its layer A is small (K = 27)
+  // and its weights small, so 16-row tiles (16 waves) fit.  Two 48-channel layers need both
+  // weight sets in LDS (83 KB), which leaves room for 8-row tiles only (10 waves, layer A on
+  // 1.33x the cells); measured, such pairs were slower than two one-layer passes.
+  if (LA.cout != 48 || LA.Npad != 48 || LB.cin != 48 || LB.Kpad != TileGeom<48>::KP) return false;
+  if (in_mode == kInStateNorm && LA.cin == 3 && LA.Kpad == 32 && LB.cout == 48 &&
+      LB.Npad == 48 && out_mode == kOutReluBf16) {
+    launch_pair_t<8, kInStateNorm, 3, kOutReluBf16, 14>(LA, LB, s);
+    return true;
+  }
+  return false;
 }
 
 void launch_wgrad(const ConvArgs& A, int in_mode, const uint16_t* g, int gch, int cells_per_chunk,

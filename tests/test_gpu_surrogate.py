@@ -125,6 +125,7 @@ def test_forward_layerwise_exact(B, H, W):
     net = Net(B * H * W)
     net.set_params(_flat(params).astype(np.float32))
     net.set_norm(*NORM)
+    net.keep_activations(True)  # layer by layer, every hidden activation kept
     d_in = torch.from_numpy(psi).cuda()
     d_out = torch.empty_like(d_in)
     net.forward(d_in, d_out)
@@ -601,3 +602,39 @@ def test_normalisation_statistics_match_their_definition():
     assert np.all(np.abs(mu - ref_mu) <= 1e-12 * amax), (mu, ref_mu)
     for got, ref in ((sigma, ref_sig), (scale, ref_sc)):
         assert np.all(np.abs(got - ref) <= 1e-10 * np.abs(ref)), (got, ref)
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 37, 70), (1, 5, 9), (1, 300, 500)])
+def test_fused_forward_equals_layer_by_layer(B, H, W):
+    """The inference forward runs layers 0 and 1 as one fused pass (layer 0's activation kept
+    on chip); its output, and the inputs of layers 2..5, equal the layer-by-layer forward bit
+    for bit: tiles ragged in both directions (37 x 70 against 14 x 30 tiles), a grid smaller
+    than one tile's halo (5 x 9, the halo wraps more than once), and the paper's grid.  After
+    the fused forward the input of layer 1 is not kept and reading it is refused."""
+    _need_gpu()
+    from paper_1910_01031_amd import IewpfError, Net, abi
+    params = _params(23 + W, last_scale=0.3)
+    psi = _states(B, H, W, 7 + H)
+    net = Net(B * H * W)
+    net.set_params(_flat(params).astype(np.float32))
+    net.set_norm(*NORM)
+    d_in = torch.from_numpy(psi).cuda()
+    ref = torch.empty_like(d_in)
+    got = torch.empty_like(d_in)
+    cells = B * H * W
+    net.keep_activations(True)
+    net.forward(d_in, ref)
+    torch.cuda.synchronize()
+    kept = {L: net.read_activation(L, cells) for L in (2, 3, 4, 5)}
+    net.keep_activations(False)
+    got.fill_(float("nan"))
+    net.forward(d_in, got)
+    torch.cuda.synchronize()
+    assert torch.equal(got.view(torch.int32), ref.view(torch.int32))
+    for L in (2, 3, 4, 5):
+        assert np.array_equal(net.read_activation(L, cells), kept[L]), L
+    for L in (1,):
+        with pytest.raises(IewpfError) as e:
+            net.read_activation(L, cells)
+        assert e.value.code == abi.IEWPF_E_ARG
+    net.close()
