@@ -297,7 +297,8 @@ __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, do
                                                         int parts, double* __restrict__ dots,
                                                         double* __restrict__ alpha,
                                                         double* __restrict__ cstar,
-                                                        double* __restrict__ scal) {
+                                                        double* __restrict__ scal,
+                                                        double* __restrict__ host_out) {
   __shared__ double sh[kWavesPerBlock];
   __shared__ double shb[kWavesPerBlock];
   __shared__ int shi[kWavesPerBlock];
@@ -419,6 +420,18 @@ __global__ __launch_bounds__(kThreads) void sync_kernel(int ne, double n_psi, do
     scal[5] = outv[3];
     scal[6] = -outv[4];
     scal[7] = static_cast<double>(argmin);
+    if (host_out) {
+      // the scalars and status words for the host (pinned, mapped): no copy after the
+      // analysis; the fifth int32 after the scalars is the update's "read the device
+      // status" flag
+      for (int q = 0; q < kScalStatus; ++q) host_out[q] = scal[q];
+      int32_t* hs = reinterpret_cast<int32_t*>(host_out + kScalStatus);
+      hs[0] = flags;
+      hs[1] = st[1];
+      hs[2] = 0;
+      hs[3] = 0x7fffffff;
+      hs[4] = 0;
+    }
   }
 }
 
@@ -1048,9 +1061,9 @@ void launch_innov_draws(int ne, int n_obs, int max_obs, int nx, int ny, double H
 
 void launch_sync(int ne, int nr, double n_psi, int one_stage, const double* cval,
                  const double* part_dots, double* dots, double* alpha, double* cstar,
-                 double* scal, hipStream_t s) {
+                 double* scal, double* host_out, hipStream_t s) {
   hipLaunchKernelGGL(sync_kernel, dim3(1), dim3(kThreads), 0, s, ne, n_psi, (double)nr, one_stage,
-                     cval, part_dots, rand_dots_parts_for(nr), dots, alpha, cstar, scal);
+                     cval, part_dots, rand_dots_parts_for(nr), dots, alpha, cstar, scal, host_out);
 }
 
 void launch_posterior_coarse(const CoarseConst& C, int ne, int n_obs, int max_obs,

@@ -120,6 +120,7 @@ void free_ctx(iewpf_ctx* c) {
     if (b) (void)hipFree(b);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->h_small) (void)hipHostFree(c->h_small);
+  if (c->h_sync) (void)hipHostFree(c->h_sync);
   if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
   if (c->trace_ev) {
     for (int i = 0; i < 2 * kTraceMax; ++i)
@@ -414,7 +415,7 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
   {
     TraceScope tr(c, kTrSync, s);
     launch_sync(c->ne, c->nr, c->n_psi, c->one_stage, c->cval, c->part_dots, c->dots, c->alpha,
-                c->cstar, c->scal, s);
+                c->cstar, c->scal, c->publish_host ? c->h_sync : nullptr, s);
   }
   // stage 6: r' on the coarse grid, SOAR, then one fused pass over the state
   {
@@ -440,8 +441,10 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
   P.n_strip_y = (c->ny + c->upd_strip_h - 1) / c->upd_strip_h;
   {
     TraceScope tr(c, kTrUpdate, s);
-    launch_analysis_update(c->cc, P, c->ne, c->coarse, c->windows, c->wcell, c->sdf, c->st_rows,
-                           c->st_ent, state, c->scal, s);
+    launch_analysis_update(
+        c->cc, P, c->ne, c->coarse, c->windows, c->wcell, c->sdf, c->st_rows, c->st_ent, state,
+        c->scal,
+        c->publish_host ? reinterpret_cast<int32_t*>(c->h_sync + kScalStatus) + 4 : nullptr, s);
   }
   IEWPF_HIP_TRY(hipGetLastError());
   return 0;
@@ -918,6 +921,7 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
     c->st_ent = reinterpret_cast<int32_t*>(c->d_stage + L.st_ent);
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_stage), c->stage_bytes) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_sync), sizeof(double) * 16) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_small),
                     sizeof(double) * std::max<size_t>(64, std::max<size_t>(2 * c->max_obs, 8 * (size_t)c->ne))) !=
           hipSuccess ||
@@ -1049,12 +1053,24 @@ int iewpf_assimilate(iewpf_ctx* c, float* state, const iewpf_obs* obs, int n_obs
   if (c->full_innov && !c->sir && n_obs > 0) {
     if (int rc = prepare_full_s(c, cells, n_obs, s)) return rc;
   }
-  if (int rc = launch_analysis(c, state, n_obs, analysis_index, nullptr, s)) return rc;
-  // scalars and status words of this analysis (one copy), then wait for it
-  IEWPF_HIP_TRY(hipMemcpyAsync(c->h_small, c->scal, sizeof(double) * (kScalStatus + 2),
-                               hipMemcpyDeviceToHost, s));
+  // the sync kernel publishes the scalars and status words to mapped host memory (the SIR
+  // path has no sync kernel: one copy back instead)
+  c->publish_host = !c->sir;
+  const int rc_launch = launch_analysis(c, state, n_obs, analysis_index, nullptr, s);
+  c->publish_host = false;
+  if (rc_launch) return rc_launch;
+  const double* v = c->h_sync;
+  if (c->sir) {
+    IEWPF_HIP_TRY(hipMemcpyAsync(c->h_small, c->scal, sizeof(double) * (kScalStatus + 2),
+                                 hipMemcpyDeviceToHost, s));
+    v = c->h_small;
+  }
   IEWPF_HIP_TRY(hipStreamSynchronize(s));
-  const double* v = c->h_small;
+  if (!c->sir && reinterpret_cast<const int32_t*>(c->h_sync + kScalStatus)[4] != 0) {
+    // the update found a non-finite value: its status words are on the device
+    IEWPF_HIP_TRY(hipMemcpy(c->h_sync + kScalStatus + 1, c->scal + kScalStatus + 1,
+                            sizeof(double), hipMemcpyDeviceToHost));
+  }
   if (stats_out) {
     stats_out->cbar = v[0];
     stats_out->beta = v[1];

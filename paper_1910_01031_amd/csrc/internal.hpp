@@ -143,6 +143,11 @@ struct iewpf_ctx {
   hipEvent_t stage_ev = nullptr;
   bool stage_pending = false;
   double* h_small = nullptr;     // small pinned readback buffer
+  // pinned, device-mapped: the sync kernel writes the analysis scalars and status words here
+  // (kScalStatus doubles, then 5 int32: the status words and the update's error flag) when
+  // publish_host is set, so a synchronous analysis needs no copy back
+  double* h_sync = nullptr;
+  bool publish_host = false;
   int last_n_obs = 0;
   // optional per-launch event trace
   bool trace = false;
@@ -283,7 +288,7 @@ inline int sd_float_stride(int ne) {
 void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, const float* z,
                             const float* windows, const float* wcell, const float* sdf,
                             const int32_t* st_rows, const int32_t* st_ent, float* psi,
-                            double* scal, hipStream_t s);
+                            double* scal, int32_t* host_flag, hipStream_t s);
 // LDS of the staged-window update (two workgroups fit one compute unit up to this size)
 constexpr size_t kUpdateLdsMax = 80 * 1024;
 size_t update_lds_bytes(int wx, int wy);
@@ -330,7 +335,7 @@ void launch_sd_full(int n, int ne, int stride, const double* S, const double* D,
 // check before writing.
 void launch_sync(int ne, int nr, double n_psi, int one_stage, const double* cval,
                  const double* part_dots, double* dots, double* alpha, double* cstar,
-                 double* scal, hipStream_t s);
+                 double* scal, double* host_out, hipStream_t s);
 // vblk: [ne][max_obs][49] block products (A^{1/2} - I) r of every observation's block;
 // coef: [ne][3] the coefficients of r per particle
 void launch_posterior_coarse(const CoarseConst& C, int ne, int n_obs, int max_obs,

@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256, 5) void analysis_update_kernel(
     CoarseConst C, PullConst P, int ne, int ne4, int total_waves, const float* __restrict__ zall,
     float* __restrict__ psi, const float* __restrict__ windows, const float* __restrict__ sdf,
     const int2* __restrict__ st_rows, const int4* __restrict__ st_ent,
-    double* __restrict__ scal) {
+    double* __restrict__ scal, int32_t* __restrict__ host_flag) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave));
@@ -362,6 +362,7 @@ __global__ __launch_bounds__(256, 5) void analysis_update_kernel(
     if (__ballot(bad) != 0 && lane == 0) {
       atomicOr(status + 2, kStatNonfiniteState);
       atomicMin(status + 3, p0 + p);
+      if (host_flag) *host_flag = 1;  // the host then reads the device status words
     }
   }
 }
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(kLdsWaves * kWave, IEWPF_UPD_LDS_OCC) void analysis
     CoarseConst C, PullConst P, int ne, int ne4, int total_waves, const float* __restrict__ zall,
     float* __restrict__ psi, const float* __restrict__ wcell, const float* __restrict__ sdf,
     const int2* __restrict__ st_rows, const int4* __restrict__ st_ent,
-    double* __restrict__ scal) {
+    double* __restrict__ scal, int32_t* __restrict__ host_flag) {
   extern __shared__ __align__(16) float lw[];
   int32_t* status = reinterpret_cast<int32_t*>(scal + kScalStatus);
   if (status[0] & kStatSkipUpdate) return;  // the same for every workgroup
@@ -601,6 +602,7 @@ __global__ __launch_bounds__(kLdsWaves * kWave, IEWPF_UPD_LDS_OCC) void analysis
     if (__ballot(bad) != 0 && lane == 0) {
       atomicOr(status + 2, kStatNonfiniteState);
       atomicMin(status + 3, p0 + p);
+      if (host_flag) *host_flag = 1;  // the host then reads the device status words
     }
   }
 }
@@ -655,7 +657,7 @@ int update_lds_waves_per_cu() {
 void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, const float* z,
                             const float* windows, const float* wcell, const float* sdf,
                             const int32_t* st_rows, const int32_t* st_ent, float* psi,
-                            double* scal, hipStream_t s) {
+                            double* scal, int32_t* host_flag, hipStream_t s) {
   const int groups = (ne + kPB - 1) / kPB;
   const int total = groups * P.n_strip_x * P.n_strip_y;
   const int2* rows = reinterpret_cast<const int2*>(st_rows);
@@ -674,23 +676,23 @@ void launch_analysis_update(const CoarseConst& C, const PullConst& P, int ne, co
     const dim3 grid((total + kLdsWaves - 1) / kLdsWaves), block(kLdsWaves * kWave);
     if (P.simple_x)
       hipLaunchKernelGGL((analysis_update_lds_kernel<true>), grid, block, lds, s, C, P, ne, ne4,
-                         total, z, psi, wcell, sdf, rows, ent, scal);
+                         total, z, psi, wcell, sdf, rows, ent, scal, host_flag);
     else
       hipLaunchKernelGGL((analysis_update_lds_kernel<false>), grid, block, lds, s, C, P, ne, ne4,
-                         total, z, psi, wcell, sdf, rows, ent, scal);
+                         total, z, psi, wcell, sdf, rows, ent, scal, host_flag);
     return;
   }
   const dim3 grid((total + 3) / 4), block(256);
   const bool fixed = P.ws == kWinStride;
   if (P.simple_x && fixed)
     hipLaunchKernelGGL((analysis_update_kernel<true, kWinStride>), grid, block, 0, s, C, P, ne, ne4,
-                       total, z, psi, windows, sdf, rows, ent, scal);
+                       total, z, psi, windows, sdf, rows, ent, scal, host_flag);
   else if (fixed)
     hipLaunchKernelGGL((analysis_update_kernel<false, kWinStride>), grid, block, 0, s, C, P, ne,
-                       ne4, total, z, psi, windows, sdf, rows, ent, scal);
+                       ne4, total, z, psi, windows, sdf, rows, ent, scal, host_flag);
   else
     hipLaunchKernelGGL((analysis_update_kernel<false, 0>), grid, block, 0, s, C, P, ne, ne4, total,
-                       z, psi, windows, sdf, rows, ent, scal);
+                       z, psi, windows, sdf, rows, ent, scal, host_flag);
 }
 
 }  // namespace iewpf
