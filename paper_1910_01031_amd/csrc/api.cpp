@@ -211,12 +211,20 @@ void add_scaled_noise(iewpf_ctx* c, float* psi, uint64_t step, double scale, hip
 // and uploads cells (and y when with_y) and the lists on the stream.
 //   coarse point -> (observation, 7x7 block row) pairs, ascending observations per point
 //   update column strip and row -> observations whose pull window holds the row
-int upload_observations(iewpf_ctx* c, int n_obs, bool with_y, hipStream_t s) {
+int upload_observations(iewpf_ctx* c, int n_obs, bool with_y, hipStream_t s,
+                        bool y_mapped = false) {
   const StageLayout L = stage_layout(*c);
   int32_t* cells = reinterpret_cast<int32_t*>(c->h_stage + L.cells);
   if (with_y && n_obs == c->list_n &&
       std::equal(cells, cells + 2 * n_obs, c->list_cells.begin())) {
-    // same cells as the lists on the device (moorings): only the values go up
+    // same cells as the lists on the device (moorings): only the values go up, or (y_mapped,
+    // a caller that waits for the analysis before it returns) the kernels read them from the
+    // pinned staging area
+    if (y_mapped && c->h_stage_dev) {
+      c->y_use = reinterpret_cast<const double*>(c->h_stage_dev + L.y);
+      c->last_n_obs = n_obs;
+      return 0;
+    }
     if (n_obs > 0)
       IEWPF_HIP_TRY(hipMemcpyAsync(c->d_stage + L.y, c->h_stage + L.y, sizeof(double) * 2 * n_obs,
                                    hipMemcpyHostToDevice, s));
@@ -380,7 +388,7 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
     const double r = c->cfg.obs_sigma * c->cfg.obs_sigma;
     const double Rinv[4] = {1.0 / r, 0.0, 0.0, 1.0 / r};
     launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, Rinv, state, c->obs_cells,
-                      c->obs_y, c->sd, nullptr, c->cval, s, -0.5);
+                      c->y_use ? c->y_use : c->obs_y, c->sd, nullptr, c->cval, s, -0.5);
     launch_resample(c->ne, c->cfg.seed, analysis_index, c->cfg.ensemble_id, c->cval, c->sir_parents,
                     c->dparents, c->dcum, s, c->scal);
     const size_t per = 3 * c->ncell;
@@ -396,7 +404,7 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
       TraceScope tr(c, kTrInnov, s);
       const double I2[4] = {1.0, 0.0, 0.0, 1.0};
       launch_innovation(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, I2, state, c->obs_cells,
-                        c->obs_y, c->dinn, nullptr, c->cval, s);
+                        c->y_use ? c->y_use : c->obs_y, c->dinn, nullptr, c->cval, s);
       launch_sd_full(2 * n_obs, c->ne, 2 * c->max_obs, c->fX, c->dinn, c->sd, c->sdf, c->cval, s);
     }
     // stage 3: xi, nu~ and their dot products
@@ -407,7 +415,8 @@ int launch_analysis(iewpf_ctx* c, float* state, int n_obs, uint64_t analysis_ind
     // stages 1-3 in one launch: innovations, S d, c_i and the draws with their dot products
     TraceScope tr(c, kTrRandDots, s);
     launch_innov_draws(c->ne, n_obs, c->max_obs, c->nx, c->ny, c->cfg.H, c->S, state,
-                       c->obs_cells, c->obs_y, c->sd, c->sdf, c->cval, c->nr, c->cfg.seed,
+                       c->obs_cells, c->y_use ? c->y_use : c->obs_y, c->sd, c->sdf, c->cval,
+                       c->nr, c->cfg.seed,
                        analysis_index,
                        c->cfg.ensemble_id, c->xi, c->nu, c->part_dots, s, dyn);
   }
@@ -929,6 +938,11 @@ int iewpf_create(const iewpf_config* cfg, iewpf_ctx** out) {
     free_ctx(c);
     return fail(IEWPF_E_HIP, "pinned host allocation failed");
   }
+  {
+    void* dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, c->h_stage, 0) == hipSuccess)
+      c->h_stage_dev = static_cast<unsigned char*>(dp);
+  }
   c->h_win64 = win;
   // device layout [wy][6][ws]: the six fields of one window cell a fixed stride apart
   std::vector<float> winf((size_t)c->wy * 6 * c->ws, 0.0f);
@@ -1049,23 +1063,30 @@ int iewpf_assimilate(iewpf_ctx* c, float* state, const iewpf_obs* obs, int n_obs
     y[2 * o + 1] = obs[o].y_hv;
   }
   if (int rc = check_cells(c, cells, n_obs)) return rc;
-  if (int rc = upload_observations(c, n_obs, true, s)) return rc;
-  if (c->full_innov && !c->sir && n_obs > 0) {
-    if (int rc = prepare_full_s(c, cells, n_obs, s)) return rc;
-  }
+  // unchanged cells: the kernels read y from the pinned staging area (this call waits for
+  // them before it returns, so the host writes it again only after they are done)
+  if (int rc = upload_observations(c, n_obs, true, s, true)) return rc;
+  int rc_launch = 0;
+  if (c->full_innov && !c->sir && n_obs > 0) rc_launch = prepare_full_s(c, cells, n_obs, s);
   // the sync kernel publishes the scalars and status words to mapped host memory (the SIR
   // path has no sync kernel: one copy back instead)
   c->publish_host = !c->sir;
-  const int rc_launch = launch_analysis(c, state, n_obs, analysis_index, nullptr, s);
+  if (rc_launch == 0) rc_launch = launch_analysis(c, state, n_obs, analysis_index, nullptr, s);
   c->publish_host = false;
-  if (rc_launch) return rc_launch;
+  if (rc_launch) {
+    (void)hipStreamSynchronize(s);  // nothing may still read the staging area
+    c->y_use = nullptr;
+    return rc_launch;
+  }
   const double* v = c->h_sync;
   if (c->sir) {
     IEWPF_HIP_TRY(hipMemcpyAsync(c->h_small, c->scal, sizeof(double) * (kScalStatus + 2),
                                  hipMemcpyDeviceToHost, s));
     v = c->h_small;
   }
-  IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  const hipError_t es = hipStreamSynchronize(s);
+  c->y_use = nullptr;
+  IEWPF_HIP_TRY(es);
   if (!c->sir && reinterpret_cast<const int32_t*>(c->h_sync + kScalStatus)[4] != 0) {
     // the update found a non-finite value: its status words are on the device
     IEWPF_HIP_TRY(hipMemcpy(c->h_sync + kScalStatus + 1, c->scal + kScalStatus + 1,

@@ -148,6 +148,11 @@ struct iewpf_ctx {
   // publish_host is set, so a synchronous analysis needs no copy back
   double* h_sync = nullptr;
   bool publish_host = false;
+  // device address of the pinned staging area (it is mapped); y_use: where the analysis reads
+  // the observation values when not from the device staging block (a synchronous analysis with
+  // unchanged cells reads them straight from the pinned staging area, no upload)
+  unsigned char* h_stage_dev = nullptr;
+  const double* y_use = nullptr;
   int last_n_obs = 0;
   // optional per-launch event trace
   bool trace = false;
