@@ -486,7 +486,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if args.batched_only:
-        print(json.dumps({"batched": batched_leg(torch, dev, 3)}), flush=True)
+        print(json.dumps({"batched": batched_leg(torch, dev, 10)}), flush=True)
         return
     n_cycles = args.warmup + args.steps
     steps_per_cycle = 10
@@ -637,7 +637,7 @@ def main():
     out["full_covariance"] = full_covariance_leg(torch, ctx, ens, cells, obs, n_cycles)
     out["side"] = side_legs(torch, dev, ctx, ens, cfg)
     if not args.no_batched:
-        out["batched"] = batched_leg(torch, dev, 3)
+        out["batched"] = batched_leg(torch, dev, 10)
     if not args.no_surrogate:
         out["surrogate"], net = surrogate_leg(torch, dev, ctx, ens, cfg, args.surrogate_train_steps,
                                               keep_net=True)

@@ -1001,6 +1001,20 @@ __global__ void resample_kernel(int ne, uint64_t seed, uint64_t step, uint32_t e
   for (; t < ne; ++t) parents[t] = ne - 1;  // unreachable when the counts sum to ne
 }
 
+// one workgroup per ensemble; workgroup 0 also copies the counters
+__global__ __launch_bounds__(256) void batch_stage_in_kernel(BatchStageIn a) {
+  const int e = blockIdx.x;
+  const double* __restrict__ src = a.y_src[e];
+  double* __restrict__ dst = a.y_dst[e];
+  for (int i = threadIdx.x; i < a.n_y[e]; i += blockDim.x) dst[i] = src[i];
+  if (e == 0 && a.dyn_src && threadIdx.x < 2) a.dyn_dst[threadIdx.x] = a.dyn_src[threadIdx.x];
+}
+
+__global__ __launch_bounds__(64) void batch_status_kernel(BatchStatusOut a, int n) {
+  const int t = threadIdx.x;
+  if (t < 4 * n) a.dst[t] = a.src[t >> 2][t & 3];
+}
+
 __global__ void gather_kernel(size_t per_particle4, const int32_t* __restrict__ parents,
                               const float4* __restrict__ in, float4* __restrict__ out) {
   const int i = blockIdx.y;
@@ -1161,6 +1175,14 @@ void launch_gather_particles(int ne, size_t per_particle, const int32_t* parents
   if (bx > 1024) bx = 1024;
   hipLaunchKernelGGL(gather_kernel, dim3((unsigned)bx, ne), dim3(256), 0, s, n4, parents,
                      reinterpret_cast<const float4*>(in), reinterpret_cast<float4*>(out));
+}
+
+void launch_batch_stage_in(const BatchStageIn& a, int n, hipStream_t s) {
+  hipLaunchKernelGGL(batch_stage_in_kernel, dim3(n), dim3(256), 0, s, a);
+}
+
+void launch_batch_status(const BatchStatusOut& a, int n, hipStream_t s) {
+  hipLaunchKernelGGL(batch_status_kernel, dim3(1), dim3(64), 0, s, a, n);
 }
 
 void launch_resample(int ne, uint64_t seed, uint64_t step, uint32_t ens, const double* logw,

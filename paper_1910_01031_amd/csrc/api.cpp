@@ -30,6 +30,11 @@ struct iewpf_batch {
   uint64_t* h_dyn = nullptr;      // pinned
   double* h_y = nullptr;          // pinned observation values
   int32_t* h_status = nullptr;    // pinned analysis status words, 4 per ensemble
+  // device addresses of the three pinned buffers (they are mapped): the cycle's first kernel
+  // reads the values and counters there, its last one writes the status words there
+  const double* h_y_dev = nullptr;
+  const uint64_t* h_dyn_dev = nullptr;
+  int32_t* h_status_dev = nullptr;
   size_t h_y_len = 0;
   hipEvent_t copy_ev = nullptr;
   bool copy_pending = false;
@@ -588,14 +593,37 @@ int batch_cycle_body(iewpf_batch* b, int n_steps, uint64_t first_step, uint64_t 
   });
 }
 
-// Status words of every ensemble's analysis after a cycle on s: copied to pinned host memory,
-// then waited for; returns the first ensemble's error (an ensemble whose analysis failed
-// before writing keeps its forecast state).
-int batch_status(iewpf_batch* b, hipStream_t s) {
+// A whole batched cycle on s: the observation values (and with dyn the counters) into the
+// device buffers, the model steps and analyses, then every ensemble's status words into the
+// pinned host buffer.  No copies: a captured cycle is kernels and stream joins only.
+int batch_cycle_all(iewpf_batch* b, int n_steps, uint64_t first_step, uint64_t analysis_index,
+                    bool dyn, hipStream_t s) {
+  BatchStageIn in{};
+  for (int e = 0; e < b->n; ++e) {
+    in.y_src[e] = b->h_y_dev + b->y_off[e];
+    in.y_dst[e] = b->ctx[e]->obs_y;
+    in.n_y[e] = 2 * b->n_obs[e];
+  }
+  in.dyn_src = dyn ? b->h_dyn_dev : nullptr;
+  in.dyn_dst = b->d_dyn;
+  launch_batch_stage_in(in, b->n, s);
+  if (int rc = batch_cycle_body(b, n_steps, first_step, analysis_index, dyn ? b->d_dyn : nullptr, s))
+    return rc;
+  BatchStatusOut out{};
   for (int e = 0; e < b->n; ++e)
-    IEWPF_HIP_TRY(hipMemcpyAsync(b->h_status + 4 * e, b->ctx[e]->scal + kScalStatus,
-                                 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    out.src[e] = reinterpret_cast<const int32_t*>(b->ctx[e]->scal + kScalStatus);
+  out.dst = b->h_status_dev;
+  launch_batch_status(out, b->n, s);
+  IEWPF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+// Waits for a cycle on s and returns the first ensemble's error from the status words the
+// cycle's last kernel wrote (an ensemble whose analysis failed before writing keeps its
+// forecast state).
+int batch_status(iewpf_batch* b, hipStream_t s) {
   IEWPF_HIP_TRY(hipStreamSynchronize(s));
+  b->copy_pending = false;
   for (int e = 0; e < b->n; ++e)
     if (int rc = analysis_status(b->h_status + 4 * e, "ensemble " + std::to_string(e) + ": "))
       return rc;
@@ -1367,7 +1395,20 @@ int iewpf_batch_create(iewpf_ctx* const* ctxs, float* const* states, int n, iewp
               return true;
             }() &&
             hipMemcpy(b->tab_plain, &plain, sizeof(SweJobTable), hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(b->tab_noise, &noise, sizeof(SweJobTable), hipMemcpyHostToDevice) == hipSuccess;
+            hipMemcpy(b->tab_noise, &noise, sizeof(SweJobTable), hipMemcpyHostToDevice) == hipSuccess &&
+            [&] {
+              void* py = nullptr;
+              void* pd = nullptr;
+              void* ps = nullptr;
+              if (hipHostGetDevicePointer(&py, b->h_y, 0) != hipSuccess ||
+                  hipHostGetDevicePointer(&pd, b->h_dyn, 0) != hipSuccess ||
+                  hipHostGetDevicePointer(&ps, b->h_status, 0) != hipSuccess)
+                return false;
+              b->h_y_dev = static_cast<const double*>(py);
+              b->h_dyn_dev = static_cast<const uint64_t*>(pd);
+              b->h_status_dev = static_cast<int32_t*>(ps);
+              return true;
+            }();
   if (!ok) {
     free_batch(b);
     return fail(IEWPF_E_HIP, "batch allocation failed");
@@ -1416,27 +1457,24 @@ int iewpf_batch_cycle(iewpf_batch* b, int n_model_steps, uint64_t first_step,
     IEWPF_HIP_TRY(hipEventRecord(b->in_ev, s));
     IEWPF_HIP_TRY(hipStreamWaitEvent(run, b->in_ev, 0));
   }
-  // observation values and counters: pinned host -> device, ahead of the cycle
+  // observation values and counters into the pinned buffers the cycle's first kernel reads:
+  // only once no earlier cycle can still read them (every cycle is waited for before this
+  // call returns, except one that failed part-way, whose event is waited for here)
+  for (int e = 0; e < b->n; ++e)
+    if (b->n_obs[e] > 0 && !y_host[e]) return fail(IEWPF_E_ARG, "missing observation values");
   if (b->copy_pending) {
     IEWPF_HIP_TRY(hipEventSynchronize(b->copy_ev));
     b->copy_pending = false;
   }
-  for (int e = 0; e < b->n; ++e) {
-    if (b->n_obs[e] > 0 && !y_host[e]) return fail(IEWPF_E_ARG, "missing observation values");
+  for (int e = 0; e < b->n; ++e)
     std::memcpy(b->h_y + b->y_off[e], y_host[e], sizeof(double) * 2 * b->n_obs[e]);
-    if (b->n_obs[e] > 0)
-      IEWPF_HIP_TRY(hipMemcpyAsync(b->ctx[e]->obs_y, b->h_y + b->y_off[e],
-                                   sizeof(double) * 2 * b->n_obs[e], hipMemcpyHostToDevice, run));
-  }
-  if (use_graph) {
-    b->h_dyn[0] = first_step;
-    b->h_dyn[1] = analysis_index;
-    IEWPF_HIP_TRY(hipMemcpyAsync(b->d_dyn, b->h_dyn, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, run));
-  }
-  IEWPF_HIP_TRY(hipEventRecord(b->copy_ev, run));
-  b->copy_pending = true;
+  b->h_dyn[0] = first_step;
+  b->h_dyn[1] = analysis_index;
   if (!use_graph) {
-    if (int rc = batch_cycle_body(b, n_model_steps, first_step, analysis_index, nullptr, s)) return rc;
+    const int rc = batch_cycle_all(b, n_model_steps, first_step, analysis_index, false, s);
+    IEWPF_HIP_TRY(hipEventRecord(b->copy_ev, s));
+    b->copy_pending = true;
+    if (rc) return rc;
     return batch_status(b, s);
   }
 
@@ -1453,7 +1491,7 @@ int iewpf_batch_cycle(iewpf_batch* b, int n_model_steps, uint64_t first_step,
       b->ctx[e]->trace = false;  // no event records inside a capture
     }
     IEWPF_HIP_TRY(hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal));
-    const int rc = batch_cycle_body(b, n_model_steps, 0, 0, b->d_dyn, run);
+    const int rc = batch_cycle_all(b, n_model_steps, 0, 0, true, run);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(run, &g);
     for (int e = 0; e < b->n; ++e) b->ctx[e]->trace = tr[e];
@@ -1467,6 +1505,8 @@ int iewpf_batch_cycle(iewpf_batch* b, int n_model_steps, uint64_t first_step,
     b->graph_steps = n_model_steps;
   }
   IEWPF_HIP_TRY(hipGraphLaunch(b->exec, run));
+  IEWPF_HIP_TRY(hipEventRecord(b->copy_ev, run));
+  b->copy_pending = true;
   IEWPF_HIP_TRY(hipEventRecord(b->out_ev, run));
   IEWPF_HIP_TRY(hipStreamWaitEvent(s, b->out_ev, 0));
   return batch_status(b, run);

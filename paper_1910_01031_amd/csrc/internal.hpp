@@ -365,4 +365,22 @@ void launch_resample(int ne, uint64_t seed, uint64_t step, uint32_t ens, const d
                      double* scal = nullptr);
 void launch_gather_particles(int ne, size_t per_particle, const int32_t* parents, const float* in,
                              float* out, hipStream_t s);
+
+// Batched cycles: the per-cycle inputs (observation values of every ensemble, the step and
+// analysis counters) copied by one kernel from pinned, device-mapped host memory into the
+// contexts' device buffers, and the ensembles' analysis status words gathered by one kernel
+// into pinned host memory; so a captured cycle holds no copy nodes.
+struct BatchStageIn {
+  const double* y_src[kMaxBatch];  // device-mapped pinned values, 2 n_obs per ensemble
+  double* y_dst[kMaxBatch];        // the contexts' device observation values
+  int n_y[kMaxBatch];              // doubles per ensemble
+  const uint64_t* dyn_src;         // 2 counters (device-mapped) or nullptr
+  uint64_t* dyn_dst;
+};
+void launch_batch_stage_in(const BatchStageIn& a, int n, hipStream_t s);
+struct BatchStatusOut {
+  const int32_t* src[kMaxBatch];  // each ensemble's 4 status words
+  int32_t* dst;                   // device-mapped pinned [n][4]
+};
+void launch_batch_status(const BatchStatusOut& a, int n, hipStream_t s);
 }  // namespace iewpf
