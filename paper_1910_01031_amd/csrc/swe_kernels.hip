@@ -63,7 +63,6 @@ __device__ __forceinline__ void cu_flux(float eL, float nL, float tL, float eR, 
                                         const SweConst& C, float& F0, float& F1, float& F2) {
   const float hL = C.H + eL, hR = C.H + eR;
   const float qL = hL * nL, qR = hR * nR;
-  const float pL = hL * tL, pR = hR * tR;
   const float cL = sqrtf_fast(C.g * hL), cR = sqrtf_fast(C.g * hR);
   const float ap = fmaxf(fmaxf(nL + cL, nR + cR), 0.0f);
   const float am = fminf(fminf(nL - cL, nR - cR), 0.0f);
@@ -78,7 +77,10 @@ __device__ __forceinline__ void cu_flux(float eL, float nL, float tL, float eR, 
   const float MR = qR * nR + eR * (gH + hg * eR);
   F0 = (wqL - wqR) + apam * (eR - eL);
   F1 = wL * ML - wR * MR + apam * (qR - qL);
-  F2 = (wqL * tL - wqR * tR) + apam * (pR - pL);
+  // tangential momentum (p = h t): wL qL tL - wR qR tR + apam (pR - pL), grouped by side as
+  // tL (wL qL - apam hL) - tR (wR qR - apam hR) (two multiplies and a subtraction fewer)
+  const float bL = wqL - apam * hL, bR = wqR - apam * hR;
+  F2 = tL * bL - tR * bR;
 }
 
 // x-direction flux divergence F_{j+1/2} - F_{j-1/2} of one row (mass, hu, hv).
