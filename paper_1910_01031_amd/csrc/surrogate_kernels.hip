@@ -300,6 +300,13 @@ __device__ __forceinline__ void lane_bias(const ConvArgs& A, int kq, float (&bia
       const int n = NT == 1 ? e : q * 16 + kq * 4 + e;
       bias[q][e] = (A.bias && n < A.cout) ? A.bias[n] : 0.0f;
     }
+  // The loads are waited for here, once.  Left to their first use inside the persistent tile
+  // loop, the wait there would also cover every load issued after them (the next tile's
+  // prefetch), on every tile.
+#pragma unroll
+  for (int q = 0; q < NT; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) asm volatile("" ::"v"(bias[q][e]));
 }
 
 // Epilogue of one tile row: bias, activation / mask / residual, stores.
