@@ -357,8 +357,16 @@ __device__ __forceinline__ void tile_store(const ConvArgs& A, const f32x4 (&acc)
   }
 }
 
+// The 48 -> 3 layer (NT = 1) is bound by memory latency, not by the matrix cores: its
+// 32-column tiles are asked to fit more waves per SIMD, so that more workgroups (more tiles in
+// flight) share a compute unit: three of 8 rows (6 waves per SIMD) or two of 16 rows (8).
+template <int NT, int kTH, int kTW>
+constexpr int conv_min_waves() {
+  return (NT == 1 && kTW == 32) ? (kTH == 8 ? 6 : 8) : 1;
+}
 template <int CIN, int NT, int IN, int OUT, int kTH, int kTW>
-__global__ __launch_bounds__(64 * kTH) void conv_tile_kernel(ConvArgs A, int ntiles) {
+__global__ __launch_bounds__(64 * kTH, (conv_min_waves<NT, kTH, kTW>())) void conv_tile_kernel(
+    ConvArgs A, int ntiles) {
   constexpr int kTM = kTW / 16;
   constexpr int kTThreads = 64 * kTH;
   using G = TileGeom<CIN>;
