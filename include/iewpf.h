@@ -160,7 +160,8 @@ int iewpf_set_full_innovation(iewpf_ctx* ctx, int on);
  * posterior update.  obs_host: n_obs host records (copied; the pointer may be reused
  * when the call returns).  The per-call observation index lists are built on the host
  * and uploaded with the values in one copy; when the cells equal the previous call's
- * (moorings), only the values are uploaded.  stats_out: host pointer or NULL (filled when
+ * (moorings), nothing is uploaded: the kernels read the values from the library's pinned,
+ * device-mapped staging area (the call waits for them).  stats_out: host pointer or NULL (filled when
  * non-NULL).  The call waits for the analysis to finish and checks its status words:
  *   IEWPF_E_BETA       beta <= 0 (eq. betaTwoStage: the ensemble violates N_psi >> N_y);
  *                      the state is left untouched (stats_out still holds beta)
@@ -293,8 +294,9 @@ int iewpf_batch_set_cells(iewpf_batch* b, int e, const int32_t* cells_host, int 
  * ensemble (stream analysis_index) with observation values y_host[e] (host float64
  * [n_obs_e][2] for the cells set above).  use_graph != 0: the first call captures the whole
  * cycle into one hipGraph (on an internal stream ordered after `stream`) and later calls
- * replay it; the step and analysis indices are then read from device memory and y is
- * copied in before each replay.  A different n_model_steps recaptures.  The call waits for
+ * replay it; the cycle's first kernel copies the step and analysis indices and y from the
+ * library's pinned, device-mapped buffers (written by the host before each replay) into
+ * device memory, and its last kernel writes every ensemble's status words back there.  A different n_model_steps recaptures.  The call waits for
  * the cycle and returns the first ensemble's analysis error as iewpf_assimilate does
  * (IEWPF_E_BETA, IEWPF_E_NONFINITE; the message names the ensemble; an ensemble whose
  * analysis stopped before writing keeps its forecast). */
