@@ -161,8 +161,8 @@ int iewpf_set_full_innovation(iewpf_ctx* ctx, int on);
  * when the call returns).  The per-call observation index lists are built on the host
  * and uploaded with the values in one copy; when the cells equal the previous call's
  * (moorings), nothing is uploaded: the kernels read the values from the library's pinned,
- * device-mapped staging area (the call waits for them).  stats_out: host pointer or NULL (filled when
- * non-NULL).  The call waits for the analysis to finish and checks its status words:
+ * device-mapped staging area (the call waits for them).  stats_out: host pointer or NULL
+ * (filled when non-NULL).  The call waits for the analysis to finish and checks its status words:
  *   IEWPF_E_BETA       beta <= 0 (eq. betaTwoStage: the ensemble violates N_psi >> N_y);
  *                      the state is left untouched (stats_out still holds beta)
  *   IEWPF_E_NONFINITE  a non-finite c_i, gamma_i, zeta_i, c*_i or alpha_i (the state is left
@@ -296,9 +296,9 @@ int iewpf_batch_set_cells(iewpf_batch* b, int e, const int32_t* cells_host, int 
  * cycle into one hipGraph (on an internal stream ordered after `stream`) and later calls
  * replay it; the cycle's first kernel copies the step and analysis indices and y from the
  * library's pinned, device-mapped buffers (written by the host before each replay) into
- * device memory, and its last kernel writes every ensemble's status words back there.  A different n_model_steps recaptures.  The call waits for
- * the cycle and returns the first ensemble's analysis error as iewpf_assimilate does
- * (IEWPF_E_BETA, IEWPF_E_NONFINITE; the message names the ensemble; an ensemble whose
+ * device memory, and its last kernel writes every ensemble's status words back there.  A
+ * different n_model_steps recaptures.  The call waits for the cycle and returns the first
+ * ensemble's analysis error as iewpf_assimilate does (IEWPF_E_BETA, IEWPF_E_NONFINITE; the message names the ensemble; an ensemble whose
  * analysis stopped before writing keeps its forecast). */
 int iewpf_batch_cycle(iewpf_batch* b, int n_model_steps, uint64_t first_step,
                       uint64_t analysis_index, const double* const* y_host, int use_graph,
@@ -404,10 +404,10 @@ int iewpf_forecast_drifters_surrogate(iewpf_ctx* ctx, iewpf_net* net, float* sta
  * iewpf_trace_read waits for the recorded events and returns, per kernel kind, the total
  * milliseconds and launch count since the last start.  Kinds: 0 scheme step (both RK
  * stages), 1 model-error normals, 2 SOAR, 3 geostrophic add (model error / initial state),
- * 4 innovations (full-covariance path), 5 innovations (other paths) + xi/nu draws + dot products, 6 beta/alpha, 7 coarse posterior field,
- * 8 analysis update pass, 9 scheme step with the model error of its model step fused in.
- * n_kinds <= 16.  At most 8192 launches are recorded; later
- * launches are not timed. */
+ * 4 innovations (full-covariance path), 5 innovations (other paths) + xi/nu draws + dot
+ * products, 6 beta/alpha, 7 coarse posterior field, 8 analysis update pass, 9 scheme step
+ * with the model error of its model step fused in.  n_kinds <= 16.  At most 8192 launches
+ * are recorded; later launches are not timed. */
 int iewpf_set_trace(iewpf_ctx* ctx, int on);
 int iewpf_trace_read(iewpf_ctx* ctx, double* ms_out, int32_t* count_out, int n_kinds);
 
