@@ -298,8 +298,9 @@ int iewpf_batch_set_cells(iewpf_batch* b, int e, const int32_t* cells_host, int 
  * library's pinned, device-mapped buffers (written by the host before each replay) into
  * device memory, and its last kernel writes every ensemble's status words back there.  A
  * different n_model_steps recaptures.  The call waits for the cycle and returns the first
- * ensemble's analysis error as iewpf_assimilate does (IEWPF_E_BETA, IEWPF_E_NONFINITE; the message names the ensemble; an ensemble whose
- * analysis stopped before writing keeps its forecast). */
+ * ensemble's analysis error as iewpf_assimilate does (IEWPF_E_BETA, IEWPF_E_NONFINITE; the
+ * message names the ensemble; an ensemble whose analysis stopped before writing keeps its
+ * forecast). */
 int iewpf_batch_cycle(iewpf_batch* b, int n_model_steps, uint64_t first_step,
                       uint64_t analysis_index, const double* const* y_host, int use_graph,
                       void* stream);
