@@ -385,6 +385,16 @@ int iewpf_net_read_gradient_signal(iewpf_net* net, int layer, uint16_t* host, si
 int iewpf_surrogate_window(iewpf_ctx* ctx, iewpf_net* net, float* state, int n_model_steps,
                            uint64_t first_step, double drift_tol, double noise_scale,
                            int32_t* n_fallback_out, double* drift_out, void* stream);
+/* The same window without host waits, so it can be captured in a graph or queued behind
+ * other work: the flagged particles are re-stepped in place by plain scheme launches over
+ * all particles in which the unflagged particles' workgroups return at once (the state
+ * equals iewpf_surrogate_window's bit for bit).  n_fallback_dev: device int32, receives the
+ * number of re-stepped particles; drift_dev: device double [n_particles] or NULL.  Does not
+ * wait for the stream.  Its work buffers are those of iewpf_surrogate_window, allocated by
+ * the first call of either form on the context: make that call outside a graph capture. */
+int iewpf_surrogate_window_async(iewpf_ctx* ctx, iewpf_net* net, float* state, int n_model_steps,
+                                 uint64_t first_step, double drift_tol, double noise_scale,
+                                 int32_t* n_fallback_dev, double* drift_dev, void* stream);
 
 /* Drifter forecast with the surrogate standing in for the model: n_windows windows of
  * steps_per_window model steps, each one iewpf_surrogate_window (plain re-step of the

@@ -5,7 +5,7 @@ this package is its ctypes binding (`abi`) and the in-tree build step (`build`).
 """
 from . import abi
 from .abi import (Batch, Context, IewpfError, Net, forecast_drifters_surrogate, load,
-                  surrogate_window)
+                  surrogate_window, surrogate_window_async)
 
 __all__ = ["abi", "Batch", "Context", "IewpfError", "Net", "forecast_drifters_surrogate", "load",
-           "surrogate_window"]
+           "surrogate_window", "surrogate_window_async"]

@@ -37,7 +37,8 @@ EXPORTED = ("iewpf_create", "iewpf_destroy", "iewpf_init_ensemble", "iewpf_step_
             "iewpf_net_forward", "iewpf_net_train_step", "iewpf_net_read_activation",
             "iewpf_net_keep_activations",
             "iewpf_net_gradients",
-            "iewpf_surrogate_window", "iewpf_forecast_drifters_surrogate",
+            "iewpf_surrogate_window", "iewpf_surrogate_window_async",
+            "iewpf_forecast_drifters_surrogate",
             "iewpf_set_full_innovation", "iewpf_set_scheme", "iewpf_last_error",
             "iewpf_observe_drifters", "iewpf_sir_log_weights", "iewpf_net_set_horizon",
             "iewpf_resample_noalloc", "iewpf_net_read_gradient_signal", "iewpf_norm_stats")
@@ -139,6 +140,8 @@ def load(path: str = LIB_PATH):
     lib.iewpf_surrogate_window.argtypes = [vp, vp, vp, i32, u64, ctypes.c_double,
                                            ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
                                            vp, vp]
+    lib.iewpf_surrogate_window_async.argtypes = [vp, vp, vp, i32, u64, ctypes.c_double,
+                                                 ctypes.c_double, vp, vp, vp]
     lib.iewpf_forecast_drifters_surrogate.argtypes = [vp, vp, vp, vp, i32, i32, i32, u64,
                                                       ctypes.c_double, ctypes.c_double, vp,
                                                       ctypes.POINTER(ctypes.c_int32), vp]
@@ -505,6 +508,17 @@ def surrogate_window(ctx, net, state, n_model_steps: int, first_step: int, drift
                                          drift_tol, noise_scale, ctypes.byref(nf),
                                          drift.ctypes.data, _stream(stream)))
     return nf.value, drift
+
+
+def surrogate_window_async(ctx, net, state, n_model_steps: int, first_step: int,
+                           drift_tol: float, noise_scale: float, n_fallback_dev, drift_dev=None,
+                           stream=None):
+    """The window without host waits (capturable): n_fallback_dev is a device int32 tensor
+    of one element, drift_dev a device float64 tensor [n_particles] or None."""
+    _check(load().iewpf_surrogate_window_async(
+        ctx.h, net.h, _ptr(state), n_model_steps, first_step, drift_tol, noise_scale,
+        _ptr(n_fallback_dev), _ptr(drift_dev) if drift_dev is not None else None,
+        _stream(stream)))
 
 
 def forecast_drifters_surrogate(ctx, net, state, pos, n_windows: int, steps_per_window: int,

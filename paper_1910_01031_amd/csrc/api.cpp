@@ -1512,32 +1512,47 @@ int iewpf_batch_cycle(iewpf_batch* b, int n_model_steps, uint64_t first_step,
   return batch_status(b, run);
 }
 
-int iewpf_surrogate_window(iewpf_ctx* c, iewpf_net* net, float* state, int n_model_steps,
-                           uint64_t first_step, double drift_tol, double noise_scale,
-                           int32_t* n_fallback_out, double* drift_out, void* stream) {
-  if (!c || !net || !state || !n_fallback_out || n_model_steps < 1 || !(drift_tol >= 0))
+}  // extern "C"
+
+namespace {
+// The guarded window up to the drift flags: the inputs saved, the network applied (in as many
+// particles at a time as its workspaces hold), each particle's relative mass drift and flag.
+int window_forward(iewpf_ctx* c, iewpf_net* net, float* state, int n_model_steps,
+                   double drift_tol, hipStream_t s) {
+  if (!c || !net || !state || n_model_steps < 1 || !(drift_tol >= 0))
     return fail(IEWPF_E_ARG, "invalid argument");
   if (n_model_steps != net_horizon(net))
     return fail(IEWPF_E_ARG, "n_model_steps (" + std::to_string(n_model_steps) +
                                  ") differs from the network's horizon (" +
                                  std::to_string(net_horizon(net)) + " model steps)");
-  hipStream_t s = as_stream(stream);
   const size_t per = 3 * c->ncell;
   // each buffer on its own, so a call after a failed allocation retries what is missing
   if (!c->saved) IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->saved), sizeof(float) * per * c->ne));
   if (!c->sdrift) IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->sdrift), sizeof(double) * c->ne));
   if (!c->sflags) IEWPF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&c->sflags), sizeof(int32_t) * c->ne));
   IEWPF_HIP_TRY(hipMemcpyAsync(c->saved, state, sizeof(float) * per * c->ne, hipMemcpyDeviceToDevice, s));
-  // the network runs on as many particles at a time as its workspaces hold
   const int chunk = net_max_cells(net) / (int)std::min<size_t>(c->ncell, (size_t)INT32_MAX);
   if (chunk < 1) return fail(IEWPF_E_CAPACITY, "the network holds fewer cells than one particle");
   for (int p0 = 0; p0 < c->ne; p0 += chunk) {
     const int nb = std::min(chunk, c->ne - p0);
-    if (int rc = iewpf_net_forward(net, c->saved + per * p0, state + per * p0, nb, c->ny, c->nx, stream))
+    if (int rc = iewpf_net_forward(net, c->saved + per * p0, state + per * p0, nb, c->ny, c->nx, s))
       return rc;
   }
   launch_mass_drift(c->saved, state, c->ne, (int)c->ncell, c->cfg.H, drift_tol, c->sdrift, c->sflags, s);
   IEWPF_HIP_TRY(hipGetLastError());
+  return 0;
+}
+}  // namespace
+
+extern "C" {
+
+int iewpf_surrogate_window(iewpf_ctx* c, iewpf_net* net, float* state, int n_model_steps,
+                           uint64_t first_step, double drift_tol, double noise_scale,
+                           int32_t* n_fallback_out, double* drift_out, void* stream) {
+  if (!n_fallback_out) return fail(IEWPF_E_ARG, "invalid argument");
+  hipStream_t s = as_stream(stream);
+  if (int rc = window_forward(c, net, state, n_model_steps, drift_tol, s)) return rc;
+  const size_t per = 3 * c->ncell;
   std::vector<int32_t> flags(c->ne);
   std::vector<double> drift(c->ne);
   IEWPF_HIP_TRY(hipStreamSynchronize(s));
@@ -1570,6 +1585,33 @@ int iewpf_surrogate_window(iewpf_ctx* c, iewpf_net* net, float* state, int n_mod
   IEWPF_HIP_TRY(hipStreamSynchronize(s));
   *n_fallback_out = nf;
   if (drift_out) std::memcpy(drift_out, drift.data(), sizeof(double) * c->ne);
+  return 0;
+}
+
+int iewpf_surrogate_window_async(iewpf_ctx* c, iewpf_net* net, float* state, int n_model_steps,
+                                 uint64_t first_step, double drift_tol, double noise_scale,
+                                 int32_t* n_fallback_dev, double* drift_dev, void* stream) {
+  if (!n_fallback_dev) return fail(IEWPF_E_ARG, "invalid argument");
+  hipStream_t s = as_stream(stream);
+  if (int rc = window_forward(c, net, state, n_model_steps, drift_tol, s)) return rc;
+  const size_t per = 3 * c->ncell;
+  // the flagged particles re-stepped in place from their saved inputs: every particle's
+  // workgroups are launched and the unflagged ones return at once, so the host need not know
+  // which particles drifted
+  float* cur = c->saved;
+  float* other = c->scratch;
+  for (int st = 0; st < n_model_steps; ++st)
+    for (int sub = 0; sub < c->cfg.n_sub; ++sub) {
+      launch_swe_substep(c->swe, c->ne, cur, other, nullptr, s, c->sflags);
+      std::swap(cur, other);
+    }
+  launch_copy_flagged(cur, state, c->sflags, c->ne, per, s);
+  if (noise_scale > 0.0) add_scaled_noise(c, state, first_step + n_model_steps - 1, noise_scale, s);
+  launch_count_flags(c->sflags, c->ne, n_fallback_dev, s);
+  if (drift_dev)
+    IEWPF_HIP_TRY(hipMemcpyAsync(drift_dev, c->sdrift, sizeof(double) * c->ne,
+                                 hipMemcpyDeviceToDevice, s));
+  IEWPF_HIP_TRY(hipGetLastError());
   return 0;
 }
 

@@ -248,6 +248,11 @@ void launch_prep_weights(const float* w, int cin, int cout, int Kf, int Npf, int
                          uint16_t* wf, uint16_t* wd, hipStream_t s);
 void launch_mass_drift(const float* before, const float* after, int ne, int ncell, double H,
                        double tol, double* drift, int32_t* flags, hipStream_t s);
+// out[0] = number of nonzero flags[0 .. n)
+void launch_count_flags(const int32_t* flags, int n, int32_t* out, hipStream_t s);
+// dst particle i = src particle i for every i with flags[i] != 0 (per floats per particle)
+void launch_copy_flagged(const float* src, float* dst, const int32_t* flags, int ne, size_t per,
+                         hipStream_t s);
 // per-channel normalisation statistics of training pairs: out = {mu[3], sigma[3], scale[3]}
 // (float64, device); part holds channel_stats_parts() doubles
 int channel_stats_parts();
@@ -270,9 +275,11 @@ int choose_row_strips(int columns, int ny, int slots, int halo_rows, int min_row
 // noise: each job adds the model-error field zstep of its chunk (job.z + zstep job.z_field)
 void launch_swe_batch(const SweJobTable* tab, int total_waves, int parity, bool noise, int zstep,
                       hipStream_t s);
-// z != nullptr: also add the model error Q_GB I_Omega z (z: [ne][nry][nrx] SOAR field)
+// z != nullptr: also add the model error Q_GB I_Omega z (z: [ne][nry][nrx] SOAR field);
+// mask != nullptr: only particles i with mask[i] != 0 are stepped (the others' workgroups
+// return at once and their output is not written)
 void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, const float* z,
-                        hipStream_t s);
+                        hipStream_t s, const int32_t* mask = nullptr);
 // n_steps fields [n_steps][ne][n], field t drawn for step index step + t
 void launch_normals(float* out, int n, int ne, uint64_t seed, uint64_t step, uint32_t tag,
                     uint32_t ens, hipStream_t s, const uint64_t* dyn = nullptr, int n_steps = 1);

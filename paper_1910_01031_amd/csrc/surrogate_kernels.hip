@@ -833,6 +833,28 @@ __global__ void mass_drift_kernel(const float* __restrict__ before, const float*
   }
 }
 
+// one wave: the flags summed lane by lane, then across the wave
+__global__ __launch_bounds__(64) void count_flags_kernel(const int32_t* __restrict__ flags, int n,
+                                                         int32_t* __restrict__ out) {
+  int c = 0;
+  for (int i = threadIdx.x; i < n; i += 64) c += flags[i] != 0 ? 1 : 0;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if (threadIdx.x == 0) out[0] = c;
+}
+
+// grid (chunks, particles): particle blockIdx.y copied if flagged
+__global__ __launch_bounds__(256) void copy_flagged_kernel(const float* __restrict__ src,
+                                                           float* __restrict__ dst,
+                                                           const int32_t* __restrict__ flags,
+                                                           size_t per) {
+  const int i = blockIdx.y;
+  if (flags[i] == 0) return;
+  const float* a = src + (size_t)i * per;
+  float* b = dst + (size_t)i * per;
+  for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < per; k += (size_t)gridDim.x * 256)
+    b[k] = a[k];
+}
+
 template <int IN, int OUT, int NT>
 void launch_conv_t(const ConvArgs& A, hipStream_t s) {
   const int xt = (A.W + 16 * kMT - 1) / (16 * kMT);
@@ -1012,6 +1034,18 @@ void launch_channel_stats(const float* x, const float* t, int B, int hw, double*
                      part);
   hipLaunchKernelGGL(channel_moments_finish_kernel, dim3(1), dim3(64), 0, s, part,
                      (double)B * hw, out);
+}
+
+void launch_count_flags(const int32_t* flags, int n, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(count_flags_kernel, dim3(1), dim3(64), 0, s, flags, n, out);
+}
+
+void launch_copy_flagged(const float* src, float* dst, const int32_t* flags, int ne, size_t per,
+                         hipStream_t s) {
+  size_t bx = (per + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(copy_flagged_kernel, dim3((unsigned)bx, ne), dim3(256), 0, s, src, dst, flags,
+                     per);
 }
 
 void launch_mass_drift(const float* before, const float* after, int ne, int ncell, double H,

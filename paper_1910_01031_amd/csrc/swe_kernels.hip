@@ -425,11 +425,12 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
 template <bool NOISE>
 __global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_substep_kernel(
     const float* __restrict__ in, float* __restrict__ out, const float* __restrict__ zall,
-    SweConst C, int total_waves) {
+    SweConst C, int total_waves, const int32_t* __restrict__ mask) {
   // wave-uniform: held in scalar registers, so the strip and particle offsets are scalar
   const int wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave));
   if (wave >= total_waves) return;  // whole wave exits together
+  if (mask && mask[wave / (C.n_strip_x * C.n_strip_y)] == 0) return;  // particle not stepped
   substep_wave<NOISE>(in, out, zall, C, wave);
 }
 
@@ -736,24 +737,26 @@ __device__ __forceinline__ void row_strip(const float* __restrict__ in, float* _
 template <bool NOISE, int STRIDE>
 __global__ __launch_bounds__(STRIDE, IEWPF_ROW_MIN_WAVES) void swe_row_kernel(
     const float* __restrict__ in, float* __restrict__ out, const float* __restrict__ zall,
-    SweConst C) {
+    SweConst C, const int32_t* __restrict__ mask) {
   __shared__ float xl[3 * 7 * STRIDE];
   const int b = blockIdx.x;
   const int particle = b / C.n_strip_y;
   const int sy = b - particle * C.n_strip_y;
+  if (mask && mask[particle] == 0) return;  // the whole workgroup: particle not stepped
   row_strip<NOISE, STRIDE>(in, out, zall, C, particle, sy, xl);
 }
 
 template <int STRIDE>
 void launch_row(const SweConst& C, int ne, const float* in, float* out, const float* z,
-                hipStream_t s) {
+                hipStream_t s, const int32_t* mask) {
   const int threads = ((C.nx + 63) / 64) * 64;
   const int blocks = ne * C.n_strip_y;
   if (z)
-    hipLaunchKernelGGL((swe_row_kernel<true, STRIDE>), dim3(blocks), dim3(threads), 0, s, in, out, z, C);
+    hipLaunchKernelGGL((swe_row_kernel<true, STRIDE>), dim3(blocks), dim3(threads), 0, s, in, out, z, C,
+                       mask);
   else
     hipLaunchKernelGGL((swe_row_kernel<false, STRIDE>), dim3(blocks), dim3(threads), 0, s, in, out, z,
-                       C);
+                       C, mask);
 }
 
 }  // namespace
@@ -791,21 +794,22 @@ void launch_swe_batch(const SweJobTable* tab, int total_waves, int parity, bool 
 }
 
 void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, const float* z,
-                        hipStream_t s) {
+                        hipStream_t s, const int32_t* mask) {
   if (C.row) {  // full-row form (nx <= 512)
     if (C.nx <= 256)
-      launch_row<256>(C, ne, in, out, z, s);
+      launch_row<256>(C, ne, in, out, z, s, mask);
     else
-      launch_row<512>(C, ne, in, out, z, s);
+      launch_row<512>(C, ne, in, out, z, s, mask);
     return;
   }
   const int total = ne * C.n_strip_x * C.n_strip_y;
   const int blocks = (total + 3) / 4;
   if (z)
-    hipLaunchKernelGGL(swe_substep_kernel<true>, dim3(blocks), dim3(256), 0, s, in, out, z, C, total);
+    hipLaunchKernelGGL(swe_substep_kernel<true>, dim3(blocks), dim3(256), 0, s, in, out, z, C, total,
+                       mask);
   else
     hipLaunchKernelGGL(swe_substep_kernel<false>, dim3(blocks), dim3(256), 0, s, in, out, z, C,
-                       total);
+                       total, mask);
 }
 
 }  // namespace iewpf

@@ -435,6 +435,76 @@ def test_forced_drift_falls_back_to_the_plain_solver():
     ctx.close()
 
 
+def _window_tolerances(ctx, net, x):
+    """Drift thresholds flagging no particle, about half of them, and all of them."""
+    from paper_1910_01031_amd import surrogate_window
+    st = x.clone()
+    _, d0 = surrogate_window(ctx, net, st, 10, 0, drift_tol=1e30, noise_scale=0.0)
+    return [1e30, float(np.median(d0)), 0.0]
+
+
+def test_async_window_equals_the_synchronous_window():
+    """The window without host waits (masked plain re-steps over all particles) leaves the
+    state of the synchronous window (flagged particles packed and re-stepped) bit for bit, and
+    reports the same fallback count and drifts, for no, some and all particles flagged."""
+    _need_gpu()
+    from paper_1910_01031_amd import surrogate_window, surrogate_window_async
+    cfg, ctx, net, params, x = _window_setup()
+    net.set_params(_flat(params).astype(np.float32))
+    net.set_norm(*NORM)
+    nfd = torch.zeros(1, dtype=torch.int32, device="cuda")
+    dd = torch.zeros(cfg.n_particles, dtype=torch.float64, device="cuda")
+    for tol in _window_tolerances(ctx, net, x):
+        for noise in (0.0, 1.0):
+            ref = x.clone()
+            nf, drift = surrogate_window(ctx, net, ref, 10, 40, drift_tol=tol, noise_scale=noise)
+            st = x.clone()
+            surrogate_window_async(ctx, net, st, 10, 40, tol, noise, nfd, dd)
+            torch.cuda.synchronize()
+            print(f"tol {tol:g} noise {noise}: {nf} re-stepped", flush=True)
+            assert int(nfd.item()) == nf
+            assert np.array_equal(dd.cpu().numpy(), drift)
+            assert torch.equal(st, ref)
+    net.close()
+    ctx.close()
+
+
+def test_async_window_replays_in_a_graph():
+    """The window without host waits captured once in a graph (about half the particles
+    flagged, noise on): every replay, with eager work and synchronisations between the
+    replays, equals the eager synchronous window."""
+    _need_gpu()
+    from paper_1910_01031_amd import surrogate_window, surrogate_window_async
+    cfg, ctx, net, params, x = _window_setup()
+    net.set_params(_flat(params).astype(np.float32))
+    net.set_norm(*NORM)
+    tol = _window_tolerances(ctx, net, x)[1]
+    ref = x.clone()
+    nf, drift = surrogate_window(ctx, net, ref, 10, 70, drift_tol=tol, noise_scale=1.0)
+    assert 0 < nf < cfg.n_particles
+    st = x.clone()
+    nfd = torch.zeros(1, dtype=torch.int32, device="cuda")
+    dd = torch.zeros(cfg.n_particles, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side, capture_error_mode="thread_local"):
+        surrogate_window_async(ctx, net, st, 10, 70, tol, 1.0, nfd, dd, stream=side)
+    for r in range(3):
+        st.copy_(x)
+        nfd.fill_(-1)
+        dd.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        print(f"replay {r}: {int(nfd.item())} re-stepped", flush=True)
+        assert int(nfd.item()) == nf
+        assert np.array_equal(dd.cpu().numpy(), drift)
+        assert torch.equal(st, ref)
+    del g
+    net.close()
+    ctx.close()
+
+
 def test_window_noise_is_one_scaled_model_error_draw():
     _need_gpu()
     from paper_1910_01031_amd import surrogate_window
