@@ -443,13 +443,18 @@ def _window_tolerances(ctx, net, x):
     return [1e30, float(np.median(d0)), 0.0]
 
 
-def test_async_window_equals_the_synchronous_window():
+@pytest.mark.parametrize("row_form", ["1", "0"])
+def test_async_window_equals_the_synchronous_window(row_form, monkeypatch):
     """The window without host waits (masked plain re-steps over all particles) leaves the
     state of the synchronous window (flagged particles packed and re-stepped) bit for bit, and
-    reports the same fallback count and drifts, for no, some and all particles flagged."""
+    reports the same fallback count and drifts, for no, some and all particles flagged; with
+    the scheme step in its full-row form (one workgroup per particle strip) and in its strip
+    form (one wave per strip), the two places the mask is read."""
     _need_gpu()
     from paper_1910_01031_amd import surrogate_window, surrogate_window_async
+    monkeypatch.setenv("IEWPF_SWE_ROW", row_form)
     cfg, ctx, net, params, x = _window_setup()
+    monkeypatch.delenv("IEWPF_SWE_ROW")
     net.set_params(_flat(params).astype(np.float32))
     net.set_norm(*NORM)
     nfd = torch.zeros(1, dtype=torch.int32, device="cuda")
