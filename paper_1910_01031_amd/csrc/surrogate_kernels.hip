@@ -33,6 +33,16 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// Two floats -> a packed pair of bf16 (a in the low half), rounded to nearest even by the
+// hardware conversion (v_cvt_pk_bf16_f32): the same bits as f2bf for every non-NaN value.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  bf16x2 v;
+  v[0] = (__bf16)a;
+  v[1] = (__bf16)b;
+  return __builtin_bit_cast(uint32_t, v);
+}
+
 }  // namespace
 
 namespace {
@@ -229,6 +239,15 @@ __device__ __forceinline__ int wrapm(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;
 }
+// A tile's input coordinate (from one before the image to one tile past its end) wrapped onto
+// [0, n): one correction each way covers images larger than a tile; the remainder, which
+// costs a division, runs only for the lanes of smaller images.
+__device__ __forceinline__ int wrap_tile(int i, int n) {
+  if (i < 0) i += n;
+  if (i >= n) i -= n;
+  if (i < 0 || i >= n) i = wrapm(i, n);
+  return i;
+}
 
 template <int kTH, int kTW>
 __device__ __forceinline__ void tile_origin(int t, int xt, int yt, int& b, int& y0, int& x0) {
@@ -324,20 +343,21 @@ __device__ __forceinline__ void tile_store(const ConvArgs& A, const f32x4 (&acc)
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
       const int n0 = q * 16 + kq * 4;
-      if (OUT == kOutReluBf16 || OUT == kOutMaskBf16) {
-        uint2 mk = make_uint2(0, 0);
-        if (OUT == kOutMaskBf16) mk = *reinterpret_cast<const uint2*>(A.mask + cell * A.cout + n0);
+      if (OUT == kOutReluBf16) {
+        float r[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[e] = fmaxf(acc[q][m][e] + bias[q][e], 0.0f);
+        *reinterpret_cast<uint2*>(static_cast<uint16_t*>(A.out) + cell * A.cout + n0) =
+            make_uint2(pack_bf16x2(r[0], r[1]), pack_bf16x2(r[2], r[3]));
+      } else if (OUT == kOutMaskBf16) {
+        const uint2 mk = *reinterpret_cast<const uint2*>(A.mask + cell * A.cout + n0);
         uint32_t h[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const float v = acc[q][m][e] + bias[q][e];
-          if (OUT == kOutReluBf16) {
-            h[e] = f2bf(fmaxf(v, 0.0f));
-          } else {
-            const uint32_t word = e < 2 ? mk.x : mk.y;
-            const uint16_t me = (uint16_t)(e & 1 ? word >> 16 : word & 0xFFFFu);
-            h[e] = f2bf(bf2f(me) > 0.0f ? v : 0.0f);
-          }
+          const uint32_t word = e < 2 ? mk.x : mk.y;
+          const uint16_t me = (uint16_t)(e & 1 ? word >> 16 : word & 0xFFFFu);
+          h[e] = f2bf(bf2f(me) > 0.0f ? v : 0.0f);
         }
         *reinterpret_cast<uint2*>(static_cast<uint16_t*>(A.out) + cell * A.cout + n0) =
             make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
@@ -412,20 +432,23 @@ __global__ __launch_bounds__(64 * kTH, (conv_min_waves<NT, kTH, kTW>())) void co
     for (int i = 0; i < kPer; ++i) {
       const int v = threadIdx.x + i * kTThreads;
       if (v < kVecs) {
+        // the image's base is wave-uniform, the pixel's offset 32-bit
         if (IN == kInStateNorm) {
           const int rr = v / (kTW + 2), cc = v - rr * (kTW + 2);
-          const int ys = wrapm(y0 - 1 + rr, A.H), xs = wrapm(x0 - 1 + cc, A.W);
+          const int ys = wrap_tile(y0 - 1 + rr, A.H), xs = wrap_tile(x0 - 1 + cc, A.W);
           const size_t plane = (size_t)A.H * A.W;
-          const float* st = static_cast<const float*>(A.in) + (size_t)b * 3 * plane + (size_t)ys * A.W + xs;
-          pf[i][0] = st[0];
-          pf[i][1] = st[plane];
-          pf[i][2] = st[2 * plane];
+          const float* img = static_cast<const float*>(A.in) + (size_t)b * 3 * plane;
+          const unsigned off = static_cast<unsigned>(ys) * A.W + xs;
+          pf[i][0] = img[off];
+          pf[i][1] = (img + plane)[off];
+          pf[i][2] = (img + 2 * plane)[off];
         } else {
           const int pix = v / G::VPP, cv = v - pix * G::VPP;
           const int rr = pix / (kTW + 2), cc = pix - rr * (kTW + 2);
-          const int ys = wrapm(y0 - 1 + rr, A.H), xs = wrapm(x0 - 1 + cc, A.W);
-          pre[i] = *reinterpret_cast<const u32x4*>(static_cast<const uint16_t*>(A.in) +
-                                                   (((size_t)b * A.H + ys) * A.W + xs) * CIN + cv * 8);
+          const int ys = wrap_tile(y0 - 1 + rr, A.H), xs = wrap_tile(x0 - 1 + cc, A.W);
+          const uint16_t* img = static_cast<const uint16_t*>(A.in) + (size_t)b * A.H * A.W * CIN;
+          const unsigned off = (static_cast<unsigned>(ys) * A.W + xs) * CIN + cv * 8;
+          pre[i] = *reinterpret_cast<const u32x4*>(img + off);
         }
       }
     }
@@ -459,16 +482,18 @@ __global__ __launch_bounds__(64 * kTH, (conv_min_waves<NT, kTH, kTW>())) void co
   };
 
   // Iteration t: write tile t (fetched in the previous iteration) to LDS, start fetching
-  // tile t + gridDim.x, compute tile t.  The first iteration only fetches.
-  for (int t = (int)blockIdx.x - (int)gridDim.x; t < ntiles; t += gridDim.x) {
+  // tile t + gridDim.x, compute tile t.  The first fetch is peeled off the loop (the grid is
+  // at most ntiles workgroups), so every fetch follows a commit that has waited for the
+  // previous one's loads and the fetch's own loads are not waited for one by one.
+  int t = (int)blockIdx.x;
+  fetch(t);
+  for (; t < ntiles; t += gridDim.x) {
     const int tn = t + (int)gridDim.x;
-    if (t >= 0) {  // uniform across the workgroup
-      __syncthreads();  // weights written / the previous tile's LDS reads are done
-      commit(tile);
-      __syncthreads();
-    }
+    __syncthreads();  // weights written / the previous tile's LDS reads are done
+    commit(tile);
+    __syncthreads();
     if (tn < ntiles) fetch(tn);  // in flight during the MFMAs below
-    if (t >= 0) compute(tile, t);
+    compute(tile, t);
   }
 }
 
@@ -550,20 +575,24 @@ __global__ __launch_bounds__(64 * (kPairTH + 2)) void conv_pair_kernel(ConvArgs 
     for (int i = 0; i < kPer; ++i) {
       const int v = threadIdx.x + i * kPairThreads;
       if (v < kVecs) {
+        // the image's base is wave-uniform, the pixel's offset 32-bit
         if (IN_A == kInStateNorm) {
           const int rr = v / kInW, cc = v - rr * kInW;
-          const int ys = wrapm(y0 - 2 + rr, LA.H), xs = wrapm(x0 - 2 + cc, LA.W);
+          const int ys = wrap_tile(y0 - 2 + rr, LA.H), xs = wrap_tile(x0 - 2 + cc, LA.W);
           const size_t plane = (size_t)LA.H * LA.W;
-          const float* st = static_cast<const float*>(LA.in) + (size_t)b * 3 * plane + (size_t)ys * LA.W + xs;
-          pf[i][0] = st[0];
-          pf[i][1] = st[plane];
-          pf[i][2] = st[2 * plane];
+          const float* img = static_cast<const float*>(LA.in) + (size_t)b * 3 * plane;
+          const unsigned off = static_cast<unsigned>(ys) * LA.W + xs;
+          pf[i][0] = img[off];
+          pf[i][1] = (img + plane)[off];
+          pf[i][2] = (img + 2 * plane)[off];
         } else {
           const int pix = v / GA::VPP, cv = v - pix * GA::VPP;
           const int rr = pix / kInW, cc = pix - rr * kInW;
-          const int ys = wrapm(y0 - 2 + rr, LA.H), xs = wrapm(x0 - 2 + cc, LA.W);
-          pre[i] = *reinterpret_cast<const u32x4*>(static_cast<const uint16_t*>(LA.in) +
-                                                   (((size_t)b * LA.H + ys) * LA.W + xs) * CIN_A + cv * 8);
+          const int ys = wrap_tile(y0 - 2 + rr, LA.H), xs = wrap_tile(x0 - 2 + cc, LA.W);
+          const uint16_t* img =
+              static_cast<const uint16_t*>(LA.in) + (size_t)b * LA.H * LA.W * CIN_A;
+          const unsigned off = (static_cast<unsigned>(ys) * LA.W + xs) * CIN_A + cv * 8;
+          pre[i] = *reinterpret_cast<const u32x4*>(img + off);
         }
       }
     }
@@ -596,11 +625,11 @@ __global__ __launch_bounds__(64 * (kPairTH + 2)) void conv_pair_kernel(ConvArgs 
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
           const int n0 = q * 16 + kq * 4;
-          uint32_t h[4];
+          float r[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) h[e] = f2bf(fmaxf(acc[q][m][e] + bias_a[q][e], 0.0f));
+          for (int e = 0; e < 4; ++e) r[e] = fmaxf(acc[q][m][e] + bias_a[q][e], 0.0f);
           *reinterpret_cast<uint2*>(tmid + (wave * kInW + m * 16 + row) * 48 + n0) =
-              make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+              make_uint2(pack_bf16x2(r[0], r[1]), pack_bf16x2(r[2], r[3]));
         }
     }
     __syncthreads();
@@ -611,15 +640,16 @@ __global__ __launch_bounds__(64 * (kPairTH + 2)) void conv_pair_kernel(ConvArgs 
       tile_store<NT_B, OUT_B, 2>(LB, acc, bias_b, b, y, x0, row, kq, kPairTW);
     }
   };
-  for (int t = (int)blockIdx.x - (int)gridDim.x; t < ntiles; t += gridDim.x) {
+  // the first fetch peeled off the loop, as in conv_tile_kernel
+  int t = (int)blockIdx.x;
+  fetch(t);
+  for (; t < ntiles; t += gridDim.x) {
     const int tn = t + (int)gridDim.x;
-    if (t >= 0) {  // uniform across the workgroup
-      __syncthreads();  // weights written / the previous tile's LDS reads are done
-      commit();
-      __syncthreads();
-    }
+    __syncthreads();  // weights written / the previous tile's LDS reads are done
+    commit();
+    __syncthreads();
     if (tn < ntiles) fetch(tn);  // in flight during the MFMAs below
-    if (t >= 0) compute(t);
+    compute(t);
   }
 }
 
