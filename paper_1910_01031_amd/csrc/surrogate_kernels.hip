@@ -258,8 +258,9 @@ __device__ __forceinline__ void tile_origin(int t, int xt, int yt, int& b, int& 
 }
 
 template <int CIN, int NT, int kTH, int kTW>
-constexpr int tile_lds_bytes() {
-  return 2 * ((kTH + 2) * (kTW + 2) * TileGeom<CIN>::CP + NT * 16 * TileGeom<CIN>::WS);
+constexpr int tile_lds_bytes() {  // input tile, weights, then the NT x 16 bias values (float)
+  return 2 * ((kTH + 2) * (kTW + 2) * TileGeom<CIN>::CP + NT * 16 * TileGeom<CIN>::WS) +
+         4 * NT * 16;
 }
 
 // MFMA part of one tile for output row `wave` of the tile held in LDS: acc = W x inputs.
@@ -416,9 +417,13 @@ __global__ __launch_bounds__(64 * kTH, (conv_min_waves<NT, kTH, kTW>())) void co
     *reinterpret_cast<uint4*>(wl + n * G::WS + kv * 8) = v;
   }
 
+  // bias -> LDS, read by the epilogue of every tile (so the bias values hold no registers
+  // across the tile loop)
+  float* lbias = reinterpret_cast<float*>(wl + NT * 16 * G::WS);
+  for (int i = threadIdx.x; i < NT * 16; i += kTThreads)
+    lbias[i] = (A.bias && i < A.cout) ? A.bias[i] : 0.0f;
+
   const int xt = (A.W + kTW - 1) / kTW, yt = (A.H + kTH - 1) / kTH;
-  float bias[NT][4];
-  lane_bias<NT>(A, kq, bias);
 
   // registers holding the next tile's input
   constexpr int kVecs = IN == kInStateNorm ? kPix : kPix * G::VPP;
@@ -428,6 +433,8 @@ __global__ __launch_bounds__(64 * kTH, (conv_min_waves<NT, kTH, kTW>())) void co
   auto fetch = [&](int tn) {  // tile tn's input -> registers
     int b, y0, x0;
     tile_origin<kTH, kTW>(tn, xt, yt, b, y0, x0);
+    // wave-uniform: the tile and its halo lie inside the image, no coordinate wraps
+    const bool inside = y0 >= 1 && y0 + kTH + 1 <= A.H && x0 >= 1 && x0 + kTW + 1 <= A.W;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int v = threadIdx.x + i * kTThreads;
@@ -445,7 +452,11 @@ __global__ __launch_bounds__(64 * kTH, (conv_min_waves<NT, kTH, kTW>())) void co
         } else {
           const int pix = v / G::VPP, cv = v - pix * G::VPP;
           const int rr = pix / (kTW + 2), cc = pix - rr * (kTW + 2);
-          const int ys = wrap_tile(y0 - 1 + rr, A.H), xs = wrap_tile(x0 - 1 + cc, A.W);
+          int ys = y0 - 1 + rr, xs = x0 - 1 + cc;
+          if (!inside) {
+            ys = wrap_tile(ys, A.H);
+            xs = wrap_tile(xs, A.W);
+          }
           const uint16_t* img = static_cast<const uint16_t*>(A.in) + (size_t)b * A.H * A.W * CIN;
           const unsigned off = (static_cast<unsigned>(ys) * A.W + xs) * CIN + cv * 8;
           pre[i] = *reinterpret_cast<const u32x4*>(img + off);
@@ -477,6 +488,16 @@ __global__ __launch_bounds__(64 * kTH, (conv_min_waves<NT, kTH, kTW>())) void co
     if (y < A.H) {  // wave-uniform
       f32x4 acc[NT][kTM];
       tile_mfma<CIN, NT, kTW>(src, wl, wave, row, kq, acc);
+      // this lane's bias values: channels 16 q + 4 kq .. + 3 (NT = 1: channels 0 .. 3)
+      float bias[NT][4];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const float4 bv = *reinterpret_cast<const float4*>(lbias + (NT == 1 ? 0 : q * 16 + kq * 4));
+        bias[q][0] = bv.x;
+        bias[q][1] = bv.y;
+        bias[q][2] = bv.z;
+        bias[q][3] = bv.w;
+      }
       tile_store<NT, OUT, kTM>(A, acc, bias, b, y, x0, row, kq);
     }
   };
