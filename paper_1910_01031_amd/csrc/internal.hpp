@@ -276,8 +276,8 @@ int choose_row_strips(int columns, int ny, int slots, int halo_rows, int min_row
 void launch_swe_batch(const SweJobTable* tab, int total_waves, int parity, bool noise, int zstep,
                       hipStream_t s);
 // z != nullptr: also add the model error Q_GB I_Omega z (z: [ne][nry][nrx] SOAR field);
-// mask != nullptr: only particles i with mask[i] != 0 are stepped (the others' workgroups
-// return at once and their output is not written)
+// mask != nullptr (plain steps only, z == nullptr): only particles i with mask[i] != 0 are
+// stepped (the others' workgroups return at once and their output is not written)
 void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, const float* z,
                         hipStream_t s, const int32_t* mask = nullptr);
 // n_steps fields [n_steps][ne][n], field t drawn for step index step + t

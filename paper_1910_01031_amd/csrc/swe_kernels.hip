@@ -422,7 +422,8 @@ __device__ __forceinline__ void substep_wave(const float* __restrict__ in, float
   for (; m <= k_end + 3; ++m) step(m, Full{}, Full{}, true);
 }
 
-template <bool NOISE>
+// MASKED: particles i with mask[i] == 0 are not stepped (their waves return at once)
+template <bool NOISE, bool MASKED = false>
 __global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_substep_kernel(
     const float* __restrict__ in, float* __restrict__ out, const float* __restrict__ zall,
     SweConst C, int total_waves, const int32_t* __restrict__ mask) {
@@ -430,7 +431,7 @@ __global__ __launch_bounds__(256, IEWPF_SWE_MIN_BLOCKS) void swe_substep_kernel(
   const int wave =
       __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave));
   if (wave >= total_waves) return;  // whole wave exits together
-  if (mask && mask[wave / (C.n_strip_x * C.n_strip_y)] == 0) return;  // particle not stepped
+  if (MASKED && mask[wave / (C.n_strip_x * C.n_strip_y)] == 0) return;
   substep_wave<NOISE>(in, out, zall, C, wave);
 }
 
@@ -733,8 +734,9 @@ __device__ __forceinline__ void row_strip(const float* __restrict__ in, float* _
 #define IEWPF_ROW_MIN_WAVES 4
 #endif
 
-// grid: n_particles x n_strip_y workgroups of W x 64 threads (W x 64 <= STRIDE)
-template <bool NOISE, int STRIDE>
+// grid: n_particles x n_strip_y workgroups of W x 64 threads (W x 64 <= STRIDE); MASKED:
+// particles i with mask[i] == 0 are not stepped (their workgroups return at once)
+template <bool NOISE, int STRIDE, bool MASKED = false>
 __global__ __launch_bounds__(STRIDE, IEWPF_ROW_MIN_WAVES) void swe_row_kernel(
     const float* __restrict__ in, float* __restrict__ out, const float* __restrict__ zall,
     SweConst C, const int32_t* __restrict__ mask) {
@@ -742,7 +744,7 @@ __global__ __launch_bounds__(STRIDE, IEWPF_ROW_MIN_WAVES) void swe_row_kernel(
   const int b = blockIdx.x;
   const int particle = b / C.n_strip_y;
   const int sy = b - particle * C.n_strip_y;
-  if (mask && mask[particle] == 0) return;  // the whole workgroup: particle not stepped
+  if (MASKED && mask[particle] == 0) return;  // the whole workgroup
   row_strip<NOISE, STRIDE>(in, out, zall, C, particle, sy, xl);
 }
 
@@ -753,10 +755,13 @@ void launch_row(const SweConst& C, int ne, const float* in, float* out, const fl
   const int blocks = ne * C.n_strip_y;
   if (z)
     hipLaunchKernelGGL((swe_row_kernel<true, STRIDE>), dim3(blocks), dim3(threads), 0, s, in, out, z, C,
-                       mask);
+                       nullptr);
+  else if (mask)  // masked steps are plain steps (the fallback of the surrogate window)
+    hipLaunchKernelGGL((swe_row_kernel<false, STRIDE, true>), dim3(blocks), dim3(threads), 0, s, in,
+                       out, z, C, mask);
   else
     hipLaunchKernelGGL((swe_row_kernel<false, STRIDE>), dim3(blocks), dim3(threads), 0, s, in, out, z,
-                       C, mask);
+                       C, nullptr);
 }
 
 }  // namespace
@@ -806,10 +811,13 @@ void launch_swe_substep(const SweConst& C, int ne, const float* in, float* out, 
   const int blocks = (total + 3) / 4;
   if (z)
     hipLaunchKernelGGL(swe_substep_kernel<true>, dim3(blocks), dim3(256), 0, s, in, out, z, C, total,
-                       mask);
+                       nullptr);
+  else if (mask)
+    hipLaunchKernelGGL((swe_substep_kernel<false, true>), dim3(blocks), dim3(256), 0, s, in, out, z,
+                       C, total, mask);
   else
     hipLaunchKernelGGL(swe_substep_kernel<false>, dim3(blocks), dim3(256), 0, s, in, out, z, C,
-                       total, mask);
+                       total, nullptr);
 }
 
 }  // namespace iewpf
